@@ -1,0 +1,281 @@
+"""Pins for the CPU oracle: what the paper and the mathematics fix, independent of the oracle's code.
+
+- structural counts printed by the paper (Kuhn, Leduc, the 11-node example);
+- the paper's Table 'tab:convergence' Kuhn row (exploitability after 1,000 iterations);
+- the Kuhn game value -1/18 from a sequence-form LP, and the LP equilibrium's exploitability ~ 0;
+- best response against brute force over all pure strategies;
+- CFR iterates against a terminal-path (non-recursive) CFR;
+- Proposition 1 (chance-folded root value = expected payoff) against terminal enumeration;
+- hand-derived first-iteration regrets of Kuhn.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import gamegen as gg
+import oracle
+from oracle import brute, lp
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def paper_counts(game):
+    """States (non-chance histories incl. terminals), paper-convention infosets
+    (distinct (player, own hand, public history) over those histories)."""
+    node_pair = game.meta["node_pair"]
+    h1, h2 = game.meta["pair_h1"], game.meta["pair_h2"]
+    m = (game.type != 0) & (node_pair >= 0)
+    states = int(m.sum())
+    pub = game.pub[m]
+    p = node_pair[m]
+    s1 = set(zip(h1[p].tolist(), pub.tolist()))
+    s2 = set(zip(h2[p].tolist(), pub.tolist()))
+    return states, len(s1) + len(s2)
+
+
+def sequences_per_player(lay):
+    so, pl = lay["slot_off"], lay["iset_player"]
+    out = {1: 1, 2: 1}
+    for i in range(len(pl)):
+        out[int(pl[i])] += int(so[i + 1] - so[i])
+    return out
+
+
+def test_kuhn_structure():
+    ref = json.load(open(os.path.join(GOLD, "structure_counts.json")))["kuhn"]
+    g = gg.kuhn()
+    o = oracle.Oracle(g)
+    states, pis = paper_counts(g)
+    assert states == ref["states"] and pis == ref["paper_infosets"]
+    assert o.D == ref["blocks"]
+    seqs = sequences_per_player(o.layout())
+    assert seqs[1] == seqs[2] == ref["sequences_per_player"]
+    assert (o.N, o.E, o.Z, o.Ndec, o.I, o.A) == (55, 54, 30, 24, 12, 24)
+
+
+def test_leduc_structure():
+    ref = json.load(open(os.path.join(GOLD, "structure_counts.json")))["leduc"]
+    g = gg.leduc(3, 2)
+    o = oracle.Oracle(g)
+    states, pis = paper_counts(g)
+    assert states == ref["states"]
+    assert pis == ref["paper_infosets"]
+    assert o.D == ref["blocks"]
+    seqs = sequences_per_player(o.layout())
+    assert seqs[1] == seqs[2] == ref["sequences_per_player"]
+
+
+def test_example11_layout():
+    ref = json.load(open(os.path.join(GOLD, "structure_counts.json")))["example11"]
+    o = oracle.Oracle(gg.example11())
+    lay = o.layout()
+    assert (o.N, o.E, o.Z, o.A, o.D) == (ref["nodes"], ref["edges"], ref["terminals"], ref["slots"], ref["blocks"])
+    assert lay["depth_off"].tolist() == ref["depth_off"]
+    # parent-before-child numbering, contiguous children
+    assert all(lay["parent"][c] < c for c in range(1, o.N))
+    # template = pi_c(z) u(z) at terminals only: chance root 0.4 / 0.6
+    t = lay["tmpl"]
+    assert t[4] == np.float32(0.4 * -1.0) and t[6] == np.float32(0.6 * 0.5)
+    assert t[7] == np.float32(0.4 * 2.0) and t[10] == np.float32(0.6 * -3.0)
+    assert np.all(t[:4] == 0) and t[5] == 0
+
+
+def test_c1_counts():
+    o = oracle.Oracle(gg.leduc(13, 2))
+    assert (o.N, o.E, o.Z, o.Ndec, o.I, o.A, o.D) == (1179777, 1179776, 704600, 471900, 19656, 45864, 11)
+
+
+@pytest.mark.parametrize("order,rule", [("simultaneous", "CFR+"), ("simultaneous", "CFR"),
+                                        ("alternating", "CFR+"), ("alternating", "CFR")])
+def test_paper_kuhn_update_rules(order, rule):
+    ref = json.load(open(os.path.join(GOLD, "kuhn_update_rules_t1000.json")))
+    want = ref["exploitability"][order][rule]
+    o = oracle.Oracle(gg.kuhn(), plus=(rule == "CFR+"), linear=True, alternating=(order == "alternating"))
+    o.iterate(1000)
+    e = o.exploitability()[0]
+    # three printed digits of a float32 run: allow half a unit in the third digit plus float32 drift
+    assert abs(e - want) <= 0.01 * want, (e, want)
+
+
+def test_kuhn_lp_value_and_equilibrium():
+    g = gg.kuhn()
+    o = oracle.Oracle(g)
+    lay = o.layout()
+    v, sig, (v1, v2) = lp.solve(lay, lp.folded_payoffs(lay, g))
+    assert abs(v1 + 1.0 / 18.0) < 1e-9 and abs(v2 + 1.0 / 18.0) < 1e-9
+    b1, _ = o.best_response(1, sig)
+    b2, _ = o.best_response(2, sig)
+    assert abs(0.5 * (b1 + b2)) < 1e-9
+    assert abs(o.profile_value(sig) + 1.0 / 18.0) < 1e-9
+
+
+@pytest.mark.parametrize("seed", [3, 7, 11])
+def test_lp_equilibrium_random_games(seed):
+    g = gg.random_game(seed, n_types1=2, n_types2=3, max_depth=5)
+    o = oracle.Oracle(g)
+    lay = o.layout()
+    if o.I == 0:
+        pytest.skip("no decisions")
+    v, sig, (v1, v2) = lp.solve(lay, lp.folded_payoffs(lay, g))
+    assert abs(v1 - v2) < 1e-8
+    b1, _ = o.best_response(1, sig)
+    b2, _ = o.best_response(2, sig)
+    assert abs(0.5 * (b1 + b2)) < 1e-8
+    # CFR+ converges to the LP value
+    o.iterate(2000)
+    e, _, _, val = o.exploitability()
+    assert e < 5e-3 and abs(val - v1) < 2 * e + 1e-9
+
+
+def _random_profile(o, rng):
+    lay = o.layout()
+    so = lay["slot_off"]
+    prof = rng.random(o.A) + 0.05
+    for i in range(o.I):
+        prof[so[i]:so[i + 1]] /= prof[so[i]:so[i + 1]].sum()
+    return prof
+
+
+@pytest.mark.parametrize("name", ["kuhn", "example11", "r5", "r9", "r13"])
+def test_best_response_brute_force(name):
+    g = {"kuhn": gg.kuhn, "example11": gg.example11}.get(name, lambda: gg.random_game(int(name[1:]), 2, 2, 4))()
+    o = oracle.Oracle(g)
+    if o.I == 0:
+        pytest.skip("no decisions")
+    P, isets, ns = brute.paths(g)
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        prof = _random_profile(o, rng)
+        for pl in (1, 2):
+            if not any(p == pl for p, _, _ in isets):
+                continue
+            want = brute.best_response(P, isets, pl, prof)
+            got, _ = o.best_response(pl, prof)
+            assert abs(got - want) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["kuhn", "example11", "r2", "r4", "r6", "r8"])
+@pytest.mark.parametrize("plus,linear", [(True, True), (True, False), (False, True), (False, False)])
+def test_cfr_against_terminal_sums(name, plus, linear):
+    g = {"kuhn": gg.kuhn, "example11": gg.example11}.get(name, lambda: gg.random_game(int(name[1:]), 2, 2, 5))()
+    o = oracle.Oracle(g, plus=plus, linear=linear)
+    if o.I == 0:
+        pytest.skip("no decisions")
+    P, isets, ns = brute.paths(g)
+    R_b, S_b = brute.cfr(P, isets, ns, 15, plus, linear)
+    o.iterate(15)
+    R, S, _, _ = o.state()
+    scale = max(1.0, np.abs(R_b).max())
+    assert np.abs(R - R_b).max() <= 1e-12 * scale
+    assert np.abs(S - S_b).max() <= 1e-12 * max(1.0, np.abs(S_b).max())
+
+
+@pytest.mark.parametrize("name", ["kuhn", "example11", "r2", "r6", "leduc"])
+def test_proposition1_folded_values(name):
+    g = {"kuhn": gg.kuhn, "example11": gg.example11, "leduc": lambda: gg.leduc(3, 2)}.get(
+        name, lambda: gg.random_game(int(name[1:]), 2, 2, 5))()
+    o = oracle.Oracle(g)
+    prof = _random_profile(o, np.random.default_rng(2))
+    vt, vf = o.node_values(prof)
+    lay = o.layout()
+    # chance reach per canonical node
+    pic = np.ones(o.N)
+    for c in range(1, o.N):
+        p = lay["parent"][c]
+        pic[c] = pic[p]
+    # recompute pi_c from the game's chance edges in canonical order
+    pf = lp.folded_payoffs(lay, g)
+    term = lay["node_type"] == 3
+    if name != "leduc":
+        P, isets, ns = brute.paths(g)
+        assert abs(vf[0] - brute.root_value(P, prof)) < 1e-12
+    # at terminals, the chance-weighted value is the template in float64
+    assert np.allclose(vf[term], pf[term], rtol=0, atol=1e-15)
+    assert abs(vf[0] - vt[0]) < 1e-15
+    assert abs(vf[0] - o.profile_value(prof)) < 1e-12
+
+
+def test_kuhn_first_iteration_closed_form():
+    """Uniform sigma^1.  P1 holding K at the root: pass -> P2 passes (+1) or bets, then P1 folds (-1) or
+    calls (+2): 0.5*1 + 0.5*(0.5*-1 + 0.5*2) = 0.75 per deal; bet -> P2 folds (+1) or calls (+2): 1.5.
+    Two deals of chance 1/6 each: v(pass) = 0.25, v(bet) = 0.5, v(I) = 0.375, regrets (-0.125, +0.125).
+    P1 holding J: pass = 0.5*-1 + 0.5*(0.5*-1 + 0.5*-2) = -1.25, bet = 0.5*1 + 0.5*-2 = -0.5 per deal,
+    v(pass) = -5/12, v(bet) = -1/6, regrets (-0.125, +0.125) as well."""
+    g = gg.kuhn()
+    for plus, want_pass in ((False, -0.125), (True, 0.0)):
+        o = oracle.Oracle(g, plus=plus)
+        o.iterate(1)
+        R, S, _, _ = o.state()
+        lay = o.layout()
+        # root-level P1 infosets are the three first-occurring ones; card = key//2 % KH
+        for i in range(o.I):
+            key = int(lay["iset_key"][i])
+            pub, hand, pl = key // 2 // 3, key // 2 % 3, key % 2 + 1
+            if pub == 0 and pl == 1 and hand in (0, 2):
+                s = lay["slot_off"][i]
+                assert R[s] == pytest.approx(want_pass, abs=1e-15)
+                assert R[s + 1] == pytest.approx(0.125, abs=1e-15)
+                # average after one iteration: w_1 = 1, own reach 1, uniform sigma
+                assert S[s] == S[s + 1] == 0.5
+
+
+def test_invariants_cfr_plus():
+    o = oracle.Oracle(gg.leduc(3, 2))
+    prev = None
+    for _ in range(5):
+        o.iterate(20)
+        R, S, sc, sa = o.state()
+        assert (R >= 0).all()
+        lay = o.layout()
+        so = lay["slot_off"]
+        sums = np.add.reduceat(sa, so[:-1])
+        assert np.allclose(sums, 1.0)
+        if prev is not None:
+            assert (S >= prev - 1e-15).all()
+        prev = S.copy()
+
+
+def test_exploitability_decreases_to_zero():
+    o = oracle.Oracle(gg.leduc(3, 2))
+    es = []
+    for _ in range(4):
+        o.iterate(250)
+        es.append(o.exploitability()[0])
+    assert es[-1] < es[0] and es[-1] < 1e-2
+
+
+def test_degenerate_games():
+    o = oracle.Oracle(gg.degenerate("root_terminal"))
+    assert (o.N, o.I, o.A, o.D) == (1, 0, 0, 0)
+    o.iterate(3)
+    e, b1, b2, v = o.exploitability()
+    assert e == 0.0 and v == 0.75
+    o = oracle.Oracle(gg.degenerate("all_chance"))
+    o.iterate(2)
+    e, b1, b2, v = o.exploitability()
+    assert e == 0.0 and abs(v - (0.3 * (0.5 * 2.0 + 0.5 * -1.0) + 0.7 * 1.0)) < 1e-15
+    o = oracle.Oracle(gg.degenerate("single_action"))
+    o.iterate(2)
+    e, _, _, v = o.exploitability()
+    assert e == 0.0 and v == 1.5
+
+
+@pytest.mark.parametrize("bad", ["cycle", "two_parents", "chance_sum", "mixed_players", "action_counts"])
+def test_oracle_rejects_invalid(bad):
+    T = 3
+    if bad == "cycle":
+        g = gg.from_arrays([1, 2, T], [[1], [0], []], [None] * 3, [1, 2, -1], [0, 0, 0])
+    elif bad == "two_parents":
+        g = gg.from_arrays([0, 1, T], [[1, 2], [2], []], [[0.5, 0.5], None, None], [-1, 1, -1], [0, 0, 0])
+    elif bad == "chance_sum":
+        g = gg.from_arrays([0, T, T], [[1, 2], [], []], [[0.5, 0.6], None, None], [-1] * 3, [0, 1, 2])
+    elif bad == "mixed_players":
+        g = gg.from_arrays([0, 1, 2, T, T, T, T], [[1, 2], [3, 4], [5, 6], [], [], [], []],
+                           [[0.5, 0.5]] + [None] * 6, [-1, 7, 7, -1, -1, -1, -1], [0] * 7)
+    else:
+        g = gg.from_arrays([0, 1, 1, T, T, T, T, T], [[1, 2], [3, 4], [5, 6, 7], [], [], [], [], []],
+                           [[0.5, 0.5]] + [None] * 7, [-1, 7, 7, -1, -1, -1, -1, -1], [0] * 8)
+    with pytest.raises(ValueError):
+        oracle.Oracle(g)
