@@ -297,6 +297,7 @@ static int emit_game(gg_game *g, const pubtree *t, int n1, const gg_hand *H1, in
     int64_t npairs = 0;
     for (int i = 0; i < n1; i++) for (int j = 0; j < n2; j++) if (!hands_clash(&H1[i], &H2[j])) npairs++;
     g->n_pairs = npairs;
+    if (npairs == 0) return -2;
     g->pair_h1 = (int32_t *)malloc((size_t)(npairs ? npairs : 1) * sizeof(int32_t));
     g->pair_h2 = (int32_t *)malloc((size_t)(npairs ? npairs : 1) * sizeof(int32_t));
     int64_t *pair_of = (int64_t *)malloc((size_t)n1 * n2 * sizeof(int64_t) + 8);
@@ -453,6 +454,7 @@ int gg_build_card(const gg_card_params *p, gg_game *out) {
     out->pot_at_root = p->contrib1 + p->contrib2;
     export_pub(out, &t);
     free(t.v);
+    if (rc == -2) { set_err(out, "no compatible pair of hands"); return 1; }
     if (rc) { set_err(out, "out of memory (game)"); return 2; }
     return 0;
 }

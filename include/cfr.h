@@ -1,0 +1,225 @@
+/* cfr.h -- C ABI of the MI355X compiled-CFR library.
+ *
+ * One CFR iteration over a two-player zero-sum perfect-recall game compiled
+ * to static, depth-sorted arrays (paper: Section 4 "Compiling CFR onto
+ * Accelerators", Algorithm 'alg:iteration'; compiler passes: Appendix H,
+ * Algorithm 'alg:compile'):
+ *   regret matching (eq. rm) -> forward reach pass per depth level (eqs.
+ *   reach, lanes) -> backward counterfactual-value pass per depth level
+ *   (eq. cfv with chance folded into a values template, eq. template) ->
+ *   per-information-set regret accumulation (eqs. regret, instregret) with
+ *   the CFR+ clamp -> FP64 average-strategy update (eq. rm, Proposition 4).
+ * All of it runs in hand-written gfx950 HIP kernels; one iteration (or k) is
+ * captured into a hipGraph and replayed.
+ *
+ * Conventions for every entry point:
+ *  - Every function returns cfr_status; nothing throws across the ABI.  On
+ *    failure a message is kept per thread and returned by cfr_last_error().
+ *  - Pointers are plain host or device pointers, as each argument states.
+ *    The caller owns every input; cfr_compile copies what it needs and keeps
+ *    no caller pointer.  The handle owns all device memory until
+ *    cfr_destroy.
+ *  - `stream` arguments are hipStream_t values passed as void* (NULL = the
+ *    null stream).  Work is enqueued asynchronously unless stated.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ *  - Slot order: every per-slot array crossing the ABI (strategies, regrets,
+ *    strategy sums) is in CANONICAL order: information sets numbered by first
+ *    occurrence in breadth-first node order (children in action order), the
+ *    actions of a set contiguous.  cfr_layout_host() returns that numbering.
+ */
+#ifndef CFR_H
+#define CFR_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CFR_OK = 0,
+    CFR_EINVAL = 1,         /* invalid argument or invalid game */
+    CFR_ENOMEM = 2,         /* host or device allocation failed */
+    CFR_EDEVICE = 3,        /* a HIP call failed */
+    CFR_EGRAPH = 4,         /* graph capture or launch failed */
+    CFR_ESTATE = 5,         /* handle state forbids the call (e.g. a persistent buffer was rebound) */
+    CFR_EUNSUPPORTED = 6    /* valid request this build does not support */
+} cfr_status;
+
+enum { CFR_NODE_CHANCE = 0, CFR_NODE_P1 = 1, CFR_NODE_P2 = 2, CFR_NODE_TERMINAL = 3 };
+
+/* Explicit game specification (paper Appendix H, "Input representation"):
+ * a node table with type, acting player, information-set key, children in
+ * action order and terminal payoff, plus the chance probability of every
+ * chance outcome.  All arrays are HOST memory and are only read.
+ *   num_nodes      number of nodes; ids 0..num_nodes-1 in any order
+ *   root           id of the root
+ *   node_type      [num_nodes] CFR_NODE_*
+ *   child_begin    [num_nodes] index into children[] of the node's first child
+ *   num_children   [num_nodes] 0 for terminals, >= 1 otherwise (<= 64 at decision nodes)
+ *   children       child ids, children[child_begin[n] + a] is the child after action a
+ *   chance_prob    aligned with children[]; read only below chance nodes; each chance
+ *                  node's probabilities must be >= 0 and sum to 1 within 1e-9
+ *   infoset_key    [num_nodes] information-set key of decision nodes (ignored elsewhere);
+ *                  members of one set must share player and action count
+ *   payoff         [num_nodes] payoff to player 1 at terminals (player 2 receives -payoff)
+ *   public_key     [num_nodes] optional (NULL): public-state id of every node; enables
+ *                  CFR_LAYOUT_PUBLIC
+ *   pot            exploitability unit (> 0) reported back by cfr_counts
+ * Validation (Algorithm 'alg:compile', first pass, plus perfect recall): a tree reachable
+ * from root with one parent per non-root node, valid types, chance sums, information sets
+ * owned by one player with equal action counts, and identical own-action sequences for all
+ * members of a set.  Violations return CFR_EINVAL. */
+typedef struct {
+    int64_t        num_nodes;
+    int64_t        root;
+    const int8_t  *node_type;
+    const int64_t *child_begin;
+    const int32_t *num_children;
+    const int64_t *children;
+    const double  *chance_prob;
+    const int64_t *infoset_key;
+    const double  *payoff;
+    const int64_t *public_key;
+    double         pot;
+} cfr_game_desc;
+
+enum { CFR_RULE_CFR_PLUS = 0, CFR_RULE_CFR = 1 };        /* CFR+ clamps regrets at 0 after the add */
+enum { CFR_AVG_LINEAR = 0, CFR_AVG_UNIFORM = 1 };       /* w_t = t or 1 */
+enum { CFR_ORDER_SIMULTANEOUS = 0, CFR_ORDER_ALTERNATING = 1 };
+enum { CFR_LAYOUT_BFS = 0, CFR_LAYOUT_PUBLIC = 1 };     /* device node order within a depth level */
+enum { CFR_STRATEGY_CURRENT = 0, CFR_STRATEGY_AVERAGE = 1 };
+enum { CFR_PRECISION_FP32 = 0, CFR_PRECISION_FP64 = 1 };
+
+typedef struct {
+    int rule;              /* CFR_RULE_* (default CFR+) */
+    int averaging;         /* CFR_AVG_* (default linear) */
+    int order;             /* CFR_ORDER_* (default simultaneous) */
+    int iters_per_graph;   /* k iterations captured per graph (default 1) */
+    int layout;            /* CFR_LAYOUT_* (default BFS) */
+    int use_graph;         /* 1: hipGraph replay (default); 0: direct kernel launches */
+    int device;            /* HIP device ordinal (default 0) */
+    int test_fail_capture; /* test hook: treat graph capture as failed (warns once, launches directly) */
+    int precision;         /* CFR_PRECISION_*: type of reach, values, regrets and strategy (default FP32);
+                              strategy sums are FP64 in both */
+} cfr_options;
+
+/* Sizes of a compiled game.  blocks = number of depth levels that hold edges (D of eq. blocks). */
+typedef struct {
+    int64_t nodes, edges, terminals, decision_nodes, infosets, slots;
+    int32_t max_depth, blocks, max_actions, br_supported;
+    int64_t device_bytes;          /* device memory held by the handle */
+    int64_t kernels_per_iteration; /* launches in one iteration (the operation-count gate) */
+    double  pot;
+} cfr_counts_t;
+
+/* Canonical compiled arrays (host copies), all in canonical numbering:
+ *   depth_off [max_depth+2]  nodes of depth d are [depth_off[d], depth_off[d+1])
+ *   parent    [nodes]        -1 at the root
+ *   child_off [nodes+1]      children of n are [child_off[n], child_off[n+1])
+ *   in_slot   [nodes]        slot of the edge into n, -1 below chance and at the root
+ *   node_infoset [nodes]     -1 at non-decision nodes
+ *   node_type [nodes]
+ *   tmpl      [nodes]        pi_c(z) u(z) at terminals, rounded once to float (eq. template), 0 elsewhere
+ *   slot_off  [infosets+1], mem_off [infosets+1], mem_node [decision_nodes] (ascending)
+ *   iset_player [infosets], iset_key [infosets] */
+typedef struct {
+    cfr_counts_t counts;
+    int32_t *depth_off, *parent, *child_off, *in_slot, *node_infoset;
+    int8_t  *node_type;
+    float   *tmpl;
+    int32_t *slot_off, *mem_off, *mem_node;
+    int8_t  *iset_player;
+    int64_t *iset_key;
+} cfr_layout;
+
+typedef struct cfr_handle cfr_handle;
+
+/* Fill *opt with the defaults (CFR+, linear, simultaneous, k=1, BFS, graph on, device 0, FP32). */
+void cfr_default_options(cfr_options *opt);
+
+/* Host-only compile (no GPU touched): validate the game and return its canonical arrays
+ * in *out (library-allocated; release with cfr_layout_free). */
+cfr_status cfr_layout_host(const cfr_game_desc *game, cfr_layout *out);
+void cfr_layout_free(cfr_layout *layout);
+
+/* Compile a game onto the device (Algorithm 'alg:compile'): validate, number nodes
+ * breadth-first, build depth offsets, information sets and slots, the CSR arrays and
+ * member lists, fold chance into the values template, copy everything to the device once,
+ * and set R = 0, sbar = 0, t = 0, sigma = uniform.  opt may be NULL (defaults).
+ * On success *out receives a new handle. */
+cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_handle **out);
+
+/* Run n CFR iterations on `stream` (asynchronous).  The first call captures the iteration
+ * body into a hipGraph (after one direct iteration that counts toward n) and later calls
+ * replay it.  n == 0 is a no-op.  Returns CFR_ESTATE if a persistent buffer recorded at
+ * capture time has changed. */
+cfr_status cfr_iterate(cfr_handle *h, int64_t n, void *stream);
+
+/* Iterations completed so far (host count). */
+cfr_status cfr_iterations(cfr_handle *h, int64_t *t);
+
+/* Write the current strategy (regret matching of the latest regrets, i.e. the strategy
+ * the next iteration plays) or the normalised average strategy (uniform where the strategy
+ * sum is 0) as float32 into dst[len] in canonical slot order; len must equal the slot count.
+ * dst_on_device selects a device (1) or host (0) pointer; a host destination synchronises
+ * the stream. */
+cfr_status cfr_strategy(cfr_handle *h, int which, float *dst, int64_t len, int dst_on_device, void *stream);
+
+/* Exploitability of the average profile (eq. exploitability): expl = (BR_1 + BR_2)/2 in payoff
+ * units, with br1/br2 the best-response values and value_avg player 1's value of the average
+ * profile, all computed in FP64 on the device by a level-synchronous best response over the
+ * compiled arrays.  Synchronises `stream`.  Any output pointer may be NULL.
+ * CFR_EUNSUPPORTED if an information set spans several depths. */
+cfr_status cfr_exploitability(cfr_handle *h, void *stream, double *expl, double *br1, double *br2,
+                              double *value_avg);
+
+/* Zero regrets, strategy sums and the iteration counter, reset sigma to uniform; nothing is
+ * reallocated, so a captured graph stays valid (paper Appendix H, reset()).  Synchronous: waits
+ * for all queued device work first. */
+cfr_status cfr_reset(cfr_handle *h);
+
+/* Copy regrets and strategy sums to host float64 arrays of `len` slots (either pointer may be
+ * NULL), canonical order; FP32 regrets are widened exactly.  Synchronises `stream`. */
+cfr_status cfr_get_state(cfr_handle *h, double *regrets, double *strategy_sum, int64_t len, void *stream);
+
+/* Replace the cumulative regrets with r0[len] (canonical order; host or device pointer per
+ * src_on_device) and recompute the current strategy from them: a warm start.  Strategy sums and
+ * the counter are left as they are (call cfr_reset first for a fresh solve). */
+cfr_status cfr_set_regrets(cfr_handle *h, const float *r0, int64_t len, int src_on_device, void *stream);
+
+/* Sizes and per-iteration launch count of a compiled game. */
+cfr_status cfr_counts(cfr_handle *h, cfr_counts_t *out);
+
+/* Per-kernel measurement.  Runs n iterations with direct launches on `stream`, recording a HIP
+ * event before and after every launch, and reports for each kernel of the iteration body:
+ *   name                  the kernel's symbol name (as profilers list it, without namespace)
+ *   launches_per_iteration
+ *   bytes_per_iteration   algorithmic bytes of all its launches in one iteration: each index,
+ *                         state and value element the kernel must read or write counted once
+ *   ms_per_iteration      mean over the n iterations of the summed durations of its launches
+ * The iterations advance the solver like cfr_iterate.  Writes up to max_out entries to out and
+ * their number to *n_out.  Synchronises `stream`. */
+typedef struct {
+    char    name[32];
+    int64_t launches_per_iteration;
+    double  bytes_per_iteration;
+    double  ms_per_iteration;
+} cfr_kernel_stat;
+cfr_status cfr_profile(cfr_handle *h, int64_t n, void *stream, cfr_kernel_stat *out, int32_t max_out,
+                       int32_t *n_out);
+
+/* Test hook: shift one persistent device pointer by `delta` elements (0 restores), so that
+ * the rebinding guard can be exercised.  which: 0 regrets, 1 strategy sums, 2 strategy. */
+cfr_status cfr_debug_rebind(cfr_handle *h, int which, int64_t delta);
+
+/* Release the handle and all its device memory after the device has finished all queued work.
+ * NULL is ignored. */
+void cfr_destroy(cfr_handle *h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *cfr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -20,27 +20,30 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
+_SO = {False: os.path.join(_HERE, "liboracle.so"), True: os.path.join(_HERE, "liboracle_f32state.so")}
 
 
-def build_lib(force: bool = False) -> str:
-    """Compile liboracle.so in place (plain C99, gcc -O2, single-threaded)."""
+def build_lib(force: bool = False, f32_state: bool = False) -> str:
+    """Compile liboracle.so in place (plain C99, gcc -O2, single-threaded).  f32_state builds the
+    FP32-state control variant (strategy sums stay FP64)."""
     src = os.path.join(_HERE, "oracle.c")
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
-        tmp = _SO + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-o", tmp, src, "-lm"])
-        os.replace(tmp, _SO)
-    return _SO
+    so = _SO[f32_state]
+    if force or not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(src):
+        tmp = so + ".tmp"
+        extra = ["-DORACLE_STATE_FLOAT"] if f32_state else []
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall"] + extra +
+                              ["-o", tmp, src, "-lm"])
+        os.replace(tmp, so)
+    return so
 
 
-_lib = None
+_libs = {}
 _P = ctypes.c_void_p
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        lib = ctypes.CDLL(build_lib())
+def _load(f32_state: bool = False):
+    if f32_state not in _libs:
+        lib = ctypes.CDLL(build_lib(f32_state=f32_state))
         lib.or_create.restype = _P
         lib.or_create.argtypes = [ctypes.c_int64, ctypes.c_int64, _P, _P, _P, _P, _P, _P, _P, ctypes.c_char_p,
                                   ctypes.c_int]
@@ -62,8 +65,8 @@ def _load():
         lib.or_exploitability.argtypes = [_P, _P, _P, _P]
         lib.or_exploitability.restype = ctypes.c_double
         lib.or_node_values.argtypes = [_P, _P, _P, _P]
-        _lib = lib
-    return _lib
+        _libs[f32_state] = lib
+    return _libs[f32_state]
 
 
 def _ptr(a):
@@ -71,10 +74,12 @@ def _ptr(a):
 
 
 class Oracle:
-    """FP64 CFR oracle over one explicit game (a ``gamegen.Game``-like object)."""
+    """FP64 CFR oracle over one explicit game (a ``gamegen.Game``-like object).
+    f32_state=True selects the FP32-state control build."""
 
-    def __init__(self, game, plus: bool = True, linear: bool = True, alternating: bool = False):
-        lib = _load()
+    def __init__(self, game, plus: bool = True, linear: bool = True, alternating: bool = False,
+                 f32_state: bool = False):
+        self._lib = lib = _load(f32_state)
         self._keep = [np.ascontiguousarray(game.type, np.int8), np.ascontiguousarray(game.child_begin, np.int64),
                       np.ascontiguousarray(game.n_children, np.int32), np.ascontiguousarray(game.children, np.int64),
                       np.ascontiguousarray(game.prob, np.float64), np.ascontiguousarray(game.key, np.int64),
@@ -94,12 +99,12 @@ class Oracle:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h and _lib is not None:
-            _lib.or_destroy(h)
+        if h:
+            self._lib.or_destroy(h)
             self._h = None
 
     def set_options(self, plus=True, linear=True, alternating=False):
-        _load().or_set_options(self._h, int(plus), int(linear), int(alternating))
+        self._lib.or_set_options(self._h, int(plus), int(linear), int(alternating))
 
     def layout(self) -> dict:
         """Canonical compiled arrays (breadth-first numbering; see oracle.c)."""
@@ -112,7 +117,7 @@ class Oracle:
             mem_node=np.zeros(max(self.Ndec, 1), np.int32), iset_player=np.zeros(max(I, 1), np.int8),
             iset_key=np.zeros(max(I, 1), np.int64),
         )
-        _load().or_layout(self._h, *[_ptr(d[k]) for k in ("depth_off", "parent", "child_off", "in_slot",
+        self._lib.or_layout(self._h, *[_ptr(d[k]) for k in ("depth_off", "parent", "child_off", "in_slot",
                                                           "node_infoset", "node_type", "tmpl", "slot_off",
                                                           "mem_off", "mem_node", "iset_player", "iset_key")])
         d["mem_node"] = d["mem_node"][: self.Ndec]
@@ -121,48 +126,48 @@ class Oracle:
         return d
 
     def reset(self):
-        _load().or_reset(self._h)
+        self._lib.or_reset(self._h)
 
     def iterate(self, T: int) -> float:
-        return float(_load().or_iterate(self._h, int(T)))
+        return float(self._lib.or_iterate(self._h, int(T)))
 
     @property
     def t(self) -> int:
-        return int(_load().or_iterations(self._h))
+        return int(self._lib.or_iterations(self._h))
 
     def state(self):
         """(R, sbar, sigma_current_next, sigma_avg) in canonical slot order (float64)."""
         A = max(self.A, 1)
         R, S, sc, sa = (np.zeros(A) for _ in range(4))
-        _load().or_get(self._h, _ptr(R), _ptr(S), _ptr(sc), _ptr(sa))
+        self._lib.or_get(self._h, _ptr(R), _ptr(S), _ptr(sc), _ptr(sa))
         return R[: self.A], S[: self.A], sc[: self.A], sa[: self.A]
 
     def set_state(self, R=None, sbar=None, t=0):
         R = None if R is None else np.ascontiguousarray(R, np.float64)
         sbar = None if sbar is None else np.ascontiguousarray(sbar, np.float64)
-        _load().or_set_state(self._h, _ptr(R), _ptr(sbar), int(t))
+        self._lib.or_set_state(self._h, _ptr(R), _ptr(sbar), int(t))
 
     def best_response(self, player: int, profile) -> tuple[float, np.ndarray]:
         prof = np.ascontiguousarray(profile, np.float64)
         ast = np.zeros(max(self.I, 1), np.int32)
-        v = _load().or_best_response(self._h, int(player), _ptr(prof), _ptr(ast))
+        v = self._lib.or_best_response(self._h, int(player), _ptr(prof), _ptr(ast))
         return float(v), ast[: self.I]
 
     def profile_value(self, profile) -> float:
         prof = np.ascontiguousarray(profile, np.float64)
-        return float(_load().or_profile_value(self._h, _ptr(prof)))
+        return float(self._lib.or_profile_value(self._h, _ptr(prof)))
 
     def exploitability(self):
         """(expl, BR_1, BR_2, value of the average profile), expl = (BR_1 + BR_2) / 2 in payoff units."""
         b1, b2, v = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        e = _load().or_exploitability(self._h, ctypes.byref(b1), ctypes.byref(b2), ctypes.byref(v))
+        e = self._lib.or_exploitability(self._h, ctypes.byref(b1), ctypes.byref(b2), ctypes.byref(v))
         return float(e), b1.value, b2.value, v.value
 
     def node_values(self, profile):
         """(textbook, chance-weighted) per-node values of a profile, canonical node order."""
         prof = np.ascontiguousarray(profile, np.float64)
         vt, vf = np.zeros(self.N), np.zeros(self.N)
-        _load().or_node_values(self._h, _ptr(prof), _ptr(vt), _ptr(vf))
+        self._lib.or_node_values(self._h, _ptr(prof), _ptr(vt), _ptr(vf))
         return vt, vf
 
     def uniform_profile(self) -> np.ndarray:

@@ -30,8 +30,13 @@
  *    (exploitability), by an exact recursive best response with
  *    information-set argmax (ties to the lowest action index).
  *
- * Everything is in double precision.  The public entry points take the game
- * as plain arrays (node type, children, chance probabilities, keys, payoffs).
+ * Everything is in double precision by default.  Built with
+ * -DORACLE_STATE_FLOAT, the state the paper keeps in its configured compute
+ * dtype (reach, values, regrets, strategy) is float while strategy sums stay
+ * double (paper, Table 'tab:memplan' and Proposition 4): a control build that
+ * measures how far any FP32-state run drifts from the FP64 iterates.  The
+ * public entry points take the game as plain arrays (node type, children,
+ * chance probabilities, keys, payoffs).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -40,6 +45,12 @@
 #include <math.h>
 
 enum { CH = 0, PL1 = 1, PL2 = 2, TERM = 3 };
+
+#ifdef ORACLE_STATE_FLOAT
+typedef float st_t;
+#else
+typedef double st_t;
+#endif
 
 typedef struct {
     int64_t key;
@@ -72,7 +83,8 @@ typedef struct {
     int64_t hcap;
     int64_t *hkey, *hval;
     /* solver state (per slot) */
-    double *R, *sbar, *sigma, *rinst;
+    st_t *R, *sigma, *rinst;
+    double *sbar;
     int64_t *avg_stamp;           /* per infoset: last (iteration, player) stamp the average was added */
     int plus, linear, alternating;
     int64_t t;                    /* iterations done */
@@ -233,10 +245,10 @@ oracle *or_create(int64_t n, int64_t root, const int8_t *type, const int64_t *ch
     }
     free(count);
     int64_t A = o->na ? o->na : 1;
-    o->R = (double *)calloc((size_t)A, 8);
+    o->R = (st_t *)calloc((size_t)A, sizeof(st_t));
     o->sbar = (double *)calloc((size_t)A, 8);
-    o->sigma = (double *)calloc((size_t)A, 8);
-    o->rinst = (double *)calloc((size_t)A, 8);
+    o->sigma = (st_t *)calloc((size_t)A, sizeof(st_t));
+    o->rinst = (st_t *)calloc((size_t)A, sizeof(st_t));
     o->avg_stamp = (int64_t *)malloc((size_t)(o->ni ? o->ni : 1) * 8);
     for (int64_t i = 0; i < o->ni; i++) o->avg_stamp[i] = -1;
     o->memo = (double *)malloc((size_t)n * 8);
@@ -300,17 +312,17 @@ void or_set_options(oracle *o, int plus, int linear, int alternating) {
 
 void or_reset(oracle *o) {
     int64_t A = o->na;
-    memset(o->R, 0, (size_t)(A ? A : 1) * 8);
+    memset(o->R, 0, (size_t)(A ? A : 1) * sizeof(st_t));
     memset(o->sbar, 0, (size_t)(A ? A : 1) * 8);
     for (int64_t i = 0; i < o->ni; i++) o->avg_stamp[i] = -1;
     o->t = 0;
 }
 
 /* regret matching for one infoset: proportional to positive regret, uniform if none (eq. rm) */
-static void regret_match(const double *R, double *sig, int nA) {
-    double tot = 0.0;
-    for (int a = 0; a < nA; a++) tot += R[a] > 0.0 ? R[a] : 0.0;
-    for (int a = 0; a < nA; a++) sig[a] = tot > 0.0 ? (R[a] > 0.0 ? R[a] : 0.0) / tot : 1.0 / nA;
+static void regret_match(const st_t *R, st_t *sig, int nA) {
+    st_t tot = 0;
+    for (int a = 0; a < nA; a++) tot += R[a] > 0 ? R[a] : 0;
+    for (int a = 0; a < nA; a++) sig[a] = tot > 0 ? (R[a] > 0 ? R[a] : (st_t)0) / tot : (st_t)1 / (st_t)nA;
 }
 
 static void regret_match_player(oracle *o, int player) {
@@ -325,36 +337,36 @@ static void regret_match_player(oracle *o, int player) {
  * pi1, pi2: players' own reach; pic: chance reach.  Regrets of `upd` players
  * (bit 1 = P1, bit 2 = P2) are accumulated into rinst and their average into
  * sbar with weight w (once per infoset and stamp). */
-static double walk(oracle *o, int64_t h, double pi1, double pi2, double pic, int upd, double w, int64_t stamp) {
+static st_t walk(oracle *o, int64_t h, st_t pi1, st_t pi2, st_t pic, int upd, double w, int64_t stamp) {
     int ty = o->type[h];
-    if (ty == TERM) return o->payoff[h];
+    if (ty == TERM) return (st_t)o->payoff[h];
     if (ty == CH) {
-        double v = 0.0;
+        st_t v = 0;
         for (int32_t a = 0; a < o->nk[h]; a++) {
-            double p = o->prob[o->kb[h] + a];
+            st_t p = (st_t)o->prob[o->kb[h] + a];
             v += p * walk(o, o->kids[o->kb[h] + a], pi1, pi2, pic * p, upd, w, stamp);
         }
         return v;
     }
     int64_t Ii = o->iset[h];
     oinfo *I = &o->info[Ii];
-    const double *sig = o->sigma + I->slot;
-    double va[64];
-    double v = 0.0;
+    const st_t *sig = o->sigma + I->slot;
+    st_t va[64];
+    st_t v = 0;
     for (int32_t a = 0; a < I->nA; a++) {
-        double c1 = ty == PL1 ? pi1 * sig[a] : pi1;
-        double c2 = ty == PL2 ? pi2 * sig[a] : pi2;
+        st_t c1 = ty == PL1 ? pi1 * sig[a] : pi1;
+        st_t c2 = ty == PL2 ? pi2 * sig[a] : pi2;
         va[a] = walk(o, o->kids[o->kb[h] + a], c1, c2, pic, upd, w, stamp);
         v += sig[a] * va[a];
     }
     if (upd & ty) {
-        double s = ty == PL1 ? 1.0 : -1.0;
-        double cf = (ty == PL1 ? pi2 : pi1) * pic;
+        st_t s = ty == PL1 ? 1 : -1;
+        st_t cf = (ty == PL1 ? pi2 : pi1) * pic;
         for (int32_t a = 0; a < I->nA; a++) o->rinst[I->slot + a] += s * cf * (va[a] - v);
         if (o->avg_stamp[Ii] != stamp) {
             o->avg_stamp[Ii] = stamp;
-            double own = ty == PL1 ? pi1 : pi2;
-            for (int32_t a = 0; a < I->nA; a++) o->sbar[I->slot + a] += w * own * sig[a];
+            double own = ty == PL1 ? (double)pi1 : (double)pi2;
+            for (int32_t a = 0; a < I->nA; a++) o->sbar[I->slot + a] += w * own * (double)sig[a];
         }
     }
     return v;
@@ -367,15 +379,15 @@ static void apply_regrets(oracle *o, int player) {
         for (int a = 0; a < I->nA; a++) {
             int64_t q = I->slot + a;
             o->R[q] += o->rinst[q];
-            o->rinst[q] = 0.0;
-            if (o->plus && o->R[q] < 0.0) o->R[q] = 0.0;
+            o->rinst[q] = 0;
+            if (o->plus && o->R[q] < 0) o->R[q] = 0;
         }
     }
 }
 
 /* T iterations; returns the root value of the last traversal (player-1 expected payoff under sigma^t) */
 double or_iterate(oracle *o, int64_t T) {
-    double v = 0.0;
+    st_t v = 0;
     for (int64_t it = 0; it < T; it++) {
         int64_t t = o->t + 1;
         double w = o->linear ? (double)t : 1.0;
@@ -393,7 +405,7 @@ double or_iterate(oracle *o, int64_t T) {
         }
         o->t = t;
     }
-    return v;
+    return (double)v;
 }
 
 int64_t or_iterations(const oracle *o) { return o->t; }
@@ -402,12 +414,12 @@ int64_t or_iterations(const oracle *o) { return o->t; }
 void or_get(const oracle *o, double *R, double *sbar, double *sigma_cur, double *sigma_avg) {
     for (int64_t i = 0; i < o->ni; i++) {
         const oinfo *I = &o->info[i];
-        double tmp[64];
-        if (R) for (int a = 0; a < I->nA; a++) R[I->slot + a] = o->R[I->slot + a];
+        st_t tmp[64];
+        if (R) for (int a = 0; a < I->nA; a++) R[I->slot + a] = (double)o->R[I->slot + a];
         if (sbar) for (int a = 0; a < I->nA; a++) sbar[I->slot + a] = o->sbar[I->slot + a];
         if (sigma_cur) {
             regret_match(o->R + I->slot, tmp, I->nA);
-            for (int a = 0; a < I->nA; a++) sigma_cur[I->slot + a] = tmp[a];
+            for (int a = 0; a < I->nA; a++) sigma_cur[I->slot + a] = (double)tmp[a];
         }
         if (sigma_avg) {
             double s = 0.0;
@@ -418,7 +430,7 @@ void or_get(const oracle *o, double *R, double *sbar, double *sigma_cur, double 
 }
 
 void or_set_state(oracle *o, const double *R, const double *sbar, int64_t t) {
-    if (R) memcpy(o->R, R, (size_t)o->na * 8);
+    if (R) for (int64_t q = 0; q < o->na; q++) o->R[q] = (st_t)R[q];
     if (sbar) memcpy(o->sbar, sbar, (size_t)o->na * 8);
     o->t = t;
 }

@@ -1,0 +1,332 @@
+"""Python binding of the MI355X compiled-CFR library (``include/cfr.h``).
+
+Argument marshalling only: every step of an iteration runs in the HIP kernels
+of ``libcfr.so``.  The library must have been built (``python -m
+paper_2609_11923_amd.build`` or ``__graft_entry__.build()``); importing the
+functions raises if it is missing.  There is no CPU fallback.
+
+The C entry points are exposed under their own names (``cfr_compile``,
+``cfr_iterate`` ...).  ``Solver`` wraps a handle with numpy/torch-friendly
+helpers; torch is used only for device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcfr.so")
+
+CFR_OK, CFR_EINVAL, CFR_ENOMEM, CFR_EDEVICE, CFR_EGRAPH, CFR_ESTATE, CFR_EUNSUPPORTED = range(7)
+CFR_RULE_CFR_PLUS, CFR_RULE_CFR = 0, 1
+CFR_AVG_LINEAR, CFR_AVG_UNIFORM = 0, 1
+CFR_ORDER_SIMULTANEOUS, CFR_ORDER_ALTERNATING = 0, 1
+CFR_LAYOUT_BFS, CFR_LAYOUT_PUBLIC = 0, 1
+CFR_STRATEGY_CURRENT, CFR_STRATEGY_AVERAGE = 0, 1
+CFR_PRECISION_FP32, CFR_PRECISION_FP64 = 0, 1
+
+_STATUS = {0: "CFR_OK", 1: "CFR_EINVAL", 2: "CFR_ENOMEM", 3: "CFR_EDEVICE", 4: "CFR_EGRAPH", 5: "CFR_ESTATE",
+           6: "CFR_EUNSUPPORTED"}
+
+_P = ctypes.c_void_p
+
+
+class cfr_game_desc(ctypes.Structure):
+    _fields_ = [("num_nodes", ctypes.c_int64), ("root", ctypes.c_int64), ("node_type", _P), ("child_begin", _P),
+                ("num_children", _P), ("children", _P), ("chance_prob", _P), ("infoset_key", _P), ("payoff", _P),
+                ("public_key", _P), ("pot", ctypes.c_double)]
+
+
+class cfr_options(ctypes.Structure):
+    _fields_ = [("rule", ctypes.c_int), ("averaging", ctypes.c_int), ("order", ctypes.c_int),
+                ("iters_per_graph", ctypes.c_int), ("layout", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("device", ctypes.c_int), ("test_fail_capture", ctypes.c_int), ("precision", ctypes.c_int)]
+
+
+class cfr_counts_t(ctypes.Structure):
+    _fields_ = [("nodes", ctypes.c_int64), ("edges", ctypes.c_int64), ("terminals", ctypes.c_int64),
+                ("decision_nodes", ctypes.c_int64), ("infosets", ctypes.c_int64), ("slots", ctypes.c_int64),
+                ("max_depth", ctypes.c_int32), ("blocks", ctypes.c_int32), ("max_actions", ctypes.c_int32),
+                ("br_supported", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
+                ("kernels_per_iteration", ctypes.c_int64), ("pot", ctypes.c_double)]
+
+
+class cfr_layout(ctypes.Structure):
+    _fields_ = [("counts", cfr_counts_t)] + [(n, _P) for n in (
+        "depth_off", "parent", "child_off", "in_slot", "node_infoset", "node_type", "tmpl", "slot_off", "mem_off",
+        "mem_node", "iset_player", "iset_key")]
+
+
+class cfr_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches_per_iteration", ctypes.c_int64),
+                ("bytes_per_iteration", ctypes.c_double), ("ms_per_iteration", ctypes.c_double)]
+
+
+class CfrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+# exported symbols of include/cfr.h (the ABI tests check the library exports each one)
+EXPORTS = ["cfr_default_options", "cfr_layout_host", "cfr_layout_free", "cfr_compile", "cfr_iterate",
+           "cfr_iterations", "cfr_strategy", "cfr_exploitability", "cfr_reset", "cfr_get_state", "cfr_set_regrets",
+           "cfr_counts", "cfr_profile", "cfr_debug_rebind", "cfr_destroy", "cfr_last_error"]
+
+
+def load():
+    """Load libcfr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2609_11923_amd.build` "
+                          f"(there is no CPU fallback)")
+    # torch ships its own HIP runtime under the same soname; load it first (when installed) so that
+    # one runtime serves the process and torch streams/memory stay usable next to this library
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(LIB_PATH)
+    S = ctypes.c_int
+    sig = {
+        "cfr_default_options": (None, [ctypes.POINTER(cfr_options)]),
+        "cfr_layout_host": (S, [ctypes.POINTER(cfr_game_desc), ctypes.POINTER(cfr_layout)]),
+        "cfr_layout_free": (None, [ctypes.POINTER(cfr_layout)]),
+        "cfr_compile": (S, [ctypes.POINTER(cfr_game_desc), ctypes.POINTER(cfr_options), ctypes.POINTER(_P)]),
+        "cfr_iterate": (S, [_P, ctypes.c_int64, _P]),
+        "cfr_iterations": (S, [_P, ctypes.POINTER(ctypes.c_int64)]),
+        "cfr_strategy": (S, [_P, ctypes.c_int, _P, ctypes.c_int64, ctypes.c_int, _P]),
+        "cfr_exploitability": (S, [_P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+        "cfr_reset": (S, [_P]),
+        "cfr_get_state": (S, [_P, _P, _P, ctypes.c_int64, _P]),
+        "cfr_set_regrets": (S, [_P, _P, ctypes.c_int64, ctypes.c_int, _P]),
+        "cfr_counts": (S, [_P, ctypes.POINTER(cfr_counts_t)]),
+        "cfr_profile": (S, [_P, ctypes.c_int64, _P, ctypes.POINTER(cfr_kernel_stat), ctypes.c_int32,
+                            ctypes.POINTER(ctypes.c_int32)]),
+        "cfr_debug_rebind": (S, [_P, ctypes.c_int, ctypes.c_int64]),
+        "cfr_destroy": (None, [_P]),
+        "cfr_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != CFR_OK:
+        raise CfrError(status, load().cfr_last_error().decode())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_P)
+
+
+class GameDesc:
+    """cfr_game_desc built from any object with the gamegen.Game array attributes; keeps the arrays alive."""
+
+    def __init__(self, game, with_public_key: bool = True):
+        self.arrays = dict(
+            node_type=np.ascontiguousarray(game.type, np.int8),
+            child_begin=np.ascontiguousarray(game.child_begin, np.int64),
+            num_children=np.ascontiguousarray(game.n_children, np.int32),
+            children=np.ascontiguousarray(game.children, np.int64),
+            chance_prob=np.ascontiguousarray(game.prob, np.float64),
+            infoset_key=np.ascontiguousarray(game.key, np.int64),
+            payoff=np.ascontiguousarray(game.payoff, np.float64),
+        )
+        pk = getattr(game, "pub", None)
+        if with_public_key and pk is not None:
+            self.arrays["public_key"] = np.ascontiguousarray(pk, np.int64)
+        d = cfr_game_desc()
+        d.num_nodes = len(self.arrays["node_type"])
+        d.root = int(getattr(game, "root", 0))
+        for k, v in self.arrays.items():
+            setattr(d, k, _ptr(v))
+        d.pot = float(getattr(game, "pot", 1.0))
+        self.desc = d
+
+
+def cfr_default_options() -> cfr_options:
+    o = cfr_options()
+    load().cfr_default_options(ctypes.byref(o))
+    return o
+
+
+def cfr_layout_host(game) -> dict:
+    """Host-only compile; returns the canonical arrays as numpy copies."""
+    gd = game if isinstance(game, GameDesc) else GameDesc(game)
+    lay = cfr_layout()
+    _check(load().cfr_layout_host(ctypes.byref(gd.desc), ctypes.byref(lay)))
+    try:
+        c = lay.counts
+        N, I, A, Nd = c.nodes, c.infosets, c.slots, c.decision_nodes
+
+        def arr(ptr, n, dt):
+            if n == 0:
+                return np.zeros(0, dt)
+            return np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(np.ctypeslib.as_ctypes_type(dt))),
+                                         shape=(n,)).copy()
+
+        out = dict(
+            depth_off=arr(lay.depth_off, c.max_depth + 2, np.int32), parent=arr(lay.parent, N, np.int32),
+            child_off=arr(lay.child_off, N + 1, np.int32), in_slot=arr(lay.in_slot, N, np.int32),
+            node_infoset=arr(lay.node_infoset, N, np.int32), node_type=arr(lay.node_type, N, np.int8),
+            tmpl=arr(lay.tmpl, N, np.float32), slot_off=arr(lay.slot_off, I + 1, np.int32),
+            mem_off=arr(lay.mem_off, I + 1, np.int32), mem_node=arr(lay.mem_node, Nd, np.int32),
+            iset_player=arr(lay.iset_player, I, np.int8), iset_key=arr(lay.iset_key, I, np.int64),
+        )
+        out["counts"] = {f: getattr(c, f) for f, _ in cfr_counts_t._fields_}
+        return out
+    finally:
+        load().cfr_layout_free(ctypes.byref(lay))
+
+
+def cfr_compile(game, options: cfr_options | None = None):
+    gd = game if isinstance(game, GameDesc) else GameDesc(game)
+    h = _P()
+    _check(load().cfr_compile(ctypes.byref(gd.desc), ctypes.byref(options) if options is not None else None,
+                              ctypes.byref(h)))
+    return h
+
+
+def cfr_iterate(h, n: int, stream=None):
+    _check(load().cfr_iterate(h, int(n), stream))
+
+
+def cfr_iterations(h) -> int:
+    t = ctypes.c_int64()
+    _check(load().cfr_iterations(h, ctypes.byref(t)))
+    return t.value
+
+
+def cfr_strategy(h, which: int, dst_ptr, length: int, dst_on_device: bool, stream=None):
+    _check(load().cfr_strategy(h, int(which), dst_ptr, int(length), int(dst_on_device), stream))
+
+
+def cfr_exploitability(h, stream=None):
+    e, b1, b2, v = (ctypes.c_double() for _ in range(4))
+    _check(load().cfr_exploitability(h, stream, ctypes.byref(e), ctypes.byref(b1), ctypes.byref(b2),
+                                     ctypes.byref(v)))
+    return e.value, b1.value, b2.value, v.value
+
+
+def cfr_reset(h):
+    _check(load().cfr_reset(h))
+
+
+def cfr_get_state(h, length: int, stream=None):
+    R = np.zeros(max(length, 1), np.float64)
+    S = np.zeros(max(length, 1), np.float64)
+    _check(load().cfr_get_state(h, _ptr(R), _ptr(S), int(length), stream))
+    return R[:length], S[:length]
+
+
+def cfr_set_regrets(h, src_ptr, length: int, src_on_device: bool, stream=None):
+    _check(load().cfr_set_regrets(h, src_ptr, int(length), int(src_on_device), stream))
+
+
+def cfr_counts(h) -> dict:
+    c = cfr_counts_t()
+    _check(load().cfr_counts(h, ctypes.byref(c)))
+    return {f: getattr(c, f) for f, _ in cfr_counts_t._fields_}
+
+
+def cfr_profile(h, n: int, stream=None) -> list[dict]:
+    arr = (cfr_kernel_stat * 16)()
+    k = ctypes.c_int32()
+    _check(load().cfr_profile(h, int(n), stream, arr, 16, ctypes.byref(k)))
+    return [dict(name=arr[i].name.decode(), launches_per_iteration=arr[i].launches_per_iteration,
+                 bytes_per_iteration=arr[i].bytes_per_iteration, ms_per_iteration=arr[i].ms_per_iteration)
+            for i in range(k.value)]
+
+
+def cfr_debug_rebind(h, which: int, delta: int):
+    _check(load().cfr_debug_rebind(h, int(which), int(delta)))
+
+
+def cfr_destroy(h):
+    if h:
+        load().cfr_destroy(h)
+
+
+class Solver:
+    """Owns one compiled game.  ``stream`` may be a torch.cuda.Stream, a raw hipStream_t int, or None."""
+
+    def __init__(self, game, rule=CFR_RULE_CFR_PLUS, averaging=CFR_AVG_LINEAR, order=CFR_ORDER_SIMULTANEOUS,
+                 iters_per_graph=1, layout=CFR_LAYOUT_BFS, use_graph=True, device=0, test_fail_capture=False,
+                 precision=CFR_PRECISION_FP32):
+        o = cfr_default_options()
+        o.rule, o.averaging, o.order = rule, averaging, order
+        o.iters_per_graph, o.layout, o.use_graph = iters_per_graph, layout, int(use_graph)
+        o.device, o.test_fail_capture = device, int(test_fail_capture)
+        o.precision = precision
+        self.options = o
+        self.h = cfr_compile(game, o)
+        self.counts = cfr_counts(self.h)
+        self.A = int(self.counts["slots"])
+
+    @staticmethod
+    def _stream(stream):
+        if stream is None:
+            return None
+        if hasattr(stream, "cuda_stream"):
+            return ctypes.c_void_p(stream.cuda_stream)
+        return ctypes.c_void_p(int(stream))
+
+    def iterate(self, n: int, stream=None):
+        cfr_iterate(self.h, n, self._stream(stream))
+
+    @property
+    def iterations(self) -> int:
+        return cfr_iterations(self.h)
+
+    def strategy(self, average: bool = False, stream=None) -> np.ndarray:
+        out = np.zeros(max(self.A, 1), np.float32)
+        cfr_strategy(self.h, CFR_STRATEGY_AVERAGE if average else CFR_STRATEGY_CURRENT, _ptr(out), self.A, False,
+                     self._stream(stream))
+        return out[: self.A]
+
+    def strategy_into(self, tensor, average: bool = False, stream=None):
+        """Write into a device tensor (float32, slot count elements)."""
+        cfr_strategy(self.h, CFR_STRATEGY_AVERAGE if average else CFR_STRATEGY_CURRENT,
+                     ctypes.c_void_p(tensor.data_ptr()), self.A, True, self._stream(stream))
+
+    def state(self, stream=None):
+        return cfr_get_state(self.h, self.A, self._stream(stream))
+
+    def set_regrets(self, r0, stream=None):
+        if hasattr(r0, "data_ptr"):
+            cfr_set_regrets(self.h, ctypes.c_void_p(r0.data_ptr()), self.A, True, self._stream(stream))
+        else:
+            a = np.ascontiguousarray(r0, np.float32)
+            cfr_set_regrets(self.h, _ptr(a), self.A, False, self._stream(stream))
+
+    def profile(self, n: int, stream=None) -> list[dict]:
+        return cfr_profile(self.h, n, self._stream(stream))
+
+    def exploitability(self, stream=None):
+        return cfr_exploitability(self.h, self._stream(stream))
+
+    def reset(self):
+        cfr_reset(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            cfr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

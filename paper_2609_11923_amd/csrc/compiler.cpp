@@ -1,0 +1,234 @@
+// compiler.cpp -- host-side game compiler (paper Appendix H, Algorithm 'alg:compile',
+// passes 1-7: validate, slots, node arrays, edge arrays, depth schedule, chance
+// folding, index emission).  See compiler.hpp for the produced arrays.
+#include "compiler.hpp"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+namespace cfrx {
+namespace {
+
+inline uint64_t mix(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+// open-addressing map int64 key -> int32 index
+struct KeyMap {
+    std::vector<int64_t> keys;
+    std::vector<int32_t> vals;
+    uint64_t mask = 0;
+    explicit KeyMap(int64_t expect) {
+        uint64_t cap = 16;
+        while (cap < (uint64_t)expect * 2 + 16) cap <<= 1;
+        keys.assign(cap, 0);
+        vals.assign(cap, -1);
+        mask = cap - 1;
+    }
+    // returns existing index, or inserts `fresh` and returns it
+    int32_t find_or_insert(int64_t key, int32_t fresh) {
+        uint64_t h = mix((uint64_t)key) & mask;
+        for (;;) {
+            if (vals[h] < 0) { keys[h] = key; vals[h] = fresh; return fresh; }
+            if (keys[h] == key) return vals[h];
+            h = (h + 1) & mask;
+        }
+    }
+};
+
+}  // namespace
+
+cfr_status build_layout(const cfr_game_desc *g, Layout &L, std::string &err) {
+    try {
+        if (!g) { err = "game description is NULL"; return CFR_EINVAL; }
+        const int64_t N = g->num_nodes;
+        if (N <= 0 || N > 0x7fffffffLL) { err = "num_nodes must be in [1, 2^31)"; return CFR_EINVAL; }
+        if (g->root < 0 || g->root >= N) { err = "root out of range"; return CFR_EINVAL; }
+        if (!g->node_type || !g->child_begin || !g->num_children || !g->payoff || !g->infoset_key) {
+            err = "missing node array"; return CFR_EINVAL;
+        }
+        if (!(g->pot > 0.0)) { err = "pot must be > 0"; return CFR_EINVAL; }
+        int64_t E = 0;
+        for (int64_t n = 0; n < N; n++) {
+            int t = g->node_type[n];
+            int32_t k = g->num_children[n];
+            if (t < 0 || t > 3) { err = "invalid node type at node " + std::to_string(n); return CFR_EINVAL; }
+            if (k < 0) { err = "negative child count"; return CFR_EINVAL; }
+            if (t == CFR_NODE_TERMINAL && k != 0) { err = "terminal node with children"; return CFR_EINVAL; }
+            if (t != CFR_NODE_TERMINAL && k == 0) { err = "non-terminal node without children"; return CFR_EINVAL; }
+            if ((t == CFR_NODE_P1 || t == CFR_NODE_P2) && k > 64) {
+                err = "decision node with more than 64 actions"; return CFR_EINVAL;
+            }
+            E += k;
+        }
+        if (E > 0 && !g->children) { err = "children array is NULL"; return CFR_EINVAL; }
+        for (int64_t n = 0; n < N; n++) {
+            int32_t k = g->num_children[n];
+            if (k == 0) continue;
+            if (g->child_begin[n] < 0) { err = "negative child_begin"; return CFR_EINVAL; }
+            for (int32_t a = 0; a < k; a++) {
+                int64_t c = g->children[g->child_begin[n] + a];
+                if (c < 0 || c >= N) { err = "child id out of range"; return CFR_EINVAL; }
+            }
+            if (g->node_type[n] == CFR_NODE_CHANCE) {
+                if (!g->chance_prob) { err = "chance_prob array is NULL"; return CFR_EINVAL; }
+                double s = 0.0;
+                for (int32_t a = 0; a < k; a++) {
+                    double p = g->chance_prob[g->child_begin[n] + a];
+                    if (!(p >= 0.0) || !std::isfinite(p)) { err = "invalid chance probability"; return CFR_EINVAL; }
+                    s += p;
+                }
+                if (std::fabs(s - 1.0) > 1e-9) { err = "chance probabilities do not sum to 1"; return CFR_EINVAL; }
+            }
+        }
+        // ---- pass 3/5: breadth-first numbering (parent before child) and depths
+        std::vector<int32_t> canon((size_t)N, -1);
+        std::vector<int32_t> order((size_t)N);
+        std::vector<int32_t> depth((size_t)N);
+        int64_t tail = 0;
+        order[tail++] = (int32_t)g->root;
+        canon[g->root] = 0;
+        depth[0] = 0;
+        int max_depth = 0;
+        for (int64_t k = 0; k < tail; k++) {
+            int64_t h = order[k];
+            int32_t nk = g->num_children[h];
+            for (int32_t a = 0; a < nk; a++) {
+                int64_t c = g->children[g->child_begin[h] + a];
+                if (canon[c] >= 0) { err = "not a tree: node " + std::to_string(c) + " reached twice"; return CFR_EINVAL; }
+                canon[c] = (int32_t)tail;
+                depth[tail] = depth[k] + 1;
+                if (depth[tail] > max_depth) max_depth = depth[tail];
+                order[tail++] = (int32_t)c;
+            }
+        }
+        if (tail != N) { err = "not a tree: " + std::to_string(N - tail) + " node(s) unreachable from the root"; return CFR_EINVAL; }
+        L.N = N; L.E = E; L.max_depth = max_depth; L.D = N > 1 ? max_depth : 0;
+        L.depth_off.assign((size_t)max_depth + 2, 0);
+        for (int64_t k = 0; k < N; k++) L.depth_off[depth[k] + 1]++;
+        for (int d = 0; d <= max_depth; d++) L.depth_off[d + 1] += L.depth_off[d];
+        // ---- pass 2: information sets by first occurrence, slots
+        L.node_type.resize((size_t)N);
+        L.node_infoset.assign((size_t)N, -1);
+        std::vector<int32_t> iset_nA, iset_depth;
+        KeyMap km(1024);
+        {
+            int64_t ndec = 0;
+            for (int64_t n = 0; n < N; n++) ndec += (g->node_type[n] == CFR_NODE_P1 || g->node_type[n] == CFR_NODE_P2);
+            km = KeyMap(ndec);
+        }
+        int64_t Z = 0, Ndec = 0;
+        int max_actions = 0;
+        for (int64_t k = 0; k < N; k++) {
+            int64_t h = order[k];
+            int t = g->node_type[h];
+            L.node_type[k] = (int8_t)t;
+            if (t == CFR_NODE_TERMINAL) { Z++; continue; }
+            if (t == CFR_NODE_CHANCE) continue;
+            Ndec++;
+            int32_t nk = g->num_children[h];
+            if (nk > max_actions) max_actions = nk;
+            int32_t fresh = (int32_t)L.iset_player.size();
+            int32_t idx = km.find_or_insert(g->infoset_key[h], fresh);
+            if (idx == fresh) {
+                L.iset_player.push_back((int8_t)t);
+                L.iset_key.push_back(g->infoset_key[h]);
+                iset_nA.push_back(nk);
+                iset_depth.push_back(depth[k]);
+            } else {
+                if (L.iset_player[idx] != t) { err = "information set spans players (key " + std::to_string(g->infoset_key[h]) + ")"; return CFR_EINVAL; }
+                if (iset_nA[idx] != nk) { err = "information set members differ in action count (key " + std::to_string(g->infoset_key[h]) + ")"; return CFR_EINVAL; }
+                if (iset_depth[idx] != depth[k]) L.br_ok = false;
+            }
+            L.node_infoset[k] = idx;
+        }
+        const int64_t I = (int64_t)L.iset_player.size();
+        L.I = I; L.Z = Z; L.Ndec = Ndec; L.max_actions = max_actions;
+        L.slot_off.assign((size_t)I + 1, 0);
+        for (int64_t i = 0; i < I; i++) L.slot_off[i + 1] = L.slot_off[i] + iset_nA[i];
+        L.A = L.slot_off[I];
+        if (L.A > (1LL << 28)) { err = "more than 2^28 information-set actions"; return CFR_EINVAL; }
+        // ---- pass 4/6: edge arrays in canonical numbering, chance folding, perfect recall
+        L.parent.assign((size_t)N, -1);
+        L.child_off.assign((size_t)N + 1, 0);
+        L.in_slot.assign((size_t)N, -1);
+        L.tmpl.assign((size_t)N, 0.0f);
+        L.tmpl64.assign((size_t)N, 0.0);
+        std::vector<double> pic((size_t)N);
+        std::vector<uint64_t> seq1((size_t)N), seq2((size_t)N);
+        std::vector<uint64_t> iset_seq((size_t)I, 0);
+        std::vector<uint8_t> iset_seen((size_t)I, 0);
+        pic[0] = 1.0; seq1[0] = 0; seq2[0] = 0;
+        int32_t next = 1;
+        for (int64_t k = 0; k < N; k++) {
+            int64_t h = order[k];
+            int t = L.node_type[k];
+            L.child_off[k] = next;
+            int32_t nk = g->num_children[h];
+            int32_t I_h = L.node_infoset[k];
+            if (I_h >= 0) {
+                uint64_t own = t == CFR_NODE_P1 ? seq1[k] : seq2[k];
+                if (!iset_seen[I_h]) { iset_seen[I_h] = 1; iset_seq[I_h] = own; }
+                else if (iset_seq[I_h] != own) {
+                    err = "not perfect recall: members of information set (key " + std::to_string(L.iset_key[I_h]) +
+                          ") have different own-action histories";
+                    return CFR_EINVAL;
+                }
+            }
+            for (int32_t a = 0; a < nk; a++) {
+                int32_t ck = next++;
+                L.parent[ck] = (int32_t)k;
+                seq1[ck] = seq1[k]; seq2[ck] = seq2[k];
+                if (t == CFR_NODE_CHANCE) {
+                    pic[ck] = pic[k] * g->chance_prob[g->child_begin[h] + a];
+                } else {
+                    pic[ck] = pic[k];
+                    int32_t q = L.slot_off[I_h] + a;
+                    L.in_slot[ck] = q;
+                    uint64_t &s = t == CFR_NODE_P1 ? seq1[ck] : seq2[ck];
+                    s = mix(s ^ ((uint64_t)q + 1) * 0x100000001B3ull);
+                }
+            }
+            if (t == CFR_NODE_TERMINAL) {
+                double v = pic[k] * g->payoff[h];
+                L.tmpl64[k] = v;
+                L.tmpl[k] = (float)v;
+            }
+        }
+        L.child_off[N] = next;
+        // ---- pass 7: member lists (ascending canonical id) and per-depth infoset ranges
+        L.mem_off.assign((size_t)I + 1, 0);
+        for (int64_t k = 0; k < N; k++) if (L.node_infoset[k] >= 0) L.mem_off[L.node_infoset[k] + 1]++;
+        for (int64_t i = 0; i < I; i++) L.mem_off[i + 1] += L.mem_off[i];
+        L.mem_node.assign((size_t)Ndec, 0);
+        {
+            std::vector<int32_t> fill(L.mem_off.begin(), L.mem_off.end() - 1);
+            for (int64_t k = 0; k < N; k++) {
+                int32_t i = L.node_infoset[k];
+                if (i >= 0) L.mem_node[fill[i]++] = (int32_t)k;
+            }
+        }
+        L.iset_depth_off.assign((size_t)max_depth + 2, (int32_t)I);
+        {
+            int32_t i = 0;
+            for (int d = 0; d <= max_depth + 1; d++) {
+                while (i < I && iset_depth[i] < d) i++;
+                L.iset_depth_off[d] = i;
+            }
+        }
+        if (g->public_key) {
+            L.public_key.resize((size_t)N);
+            for (int64_t k = 0; k < N; k++) L.public_key[k] = g->public_key[order[k]];
+        }
+        return CFR_OK;
+    } catch (const std::bad_alloc &) {
+        err = "host allocation failed while compiling the game";
+        return CFR_ENOMEM;
+    }
+}
+
+}  // namespace cfrx

@@ -1,0 +1,68 @@
+// device.hpp -- device-side data of a compiled game and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace cfrx {
+
+// Edge code stored with every node for the edge into it:
+//   bits 0-1  owner of the parent (0 chance / root, 1 player 1, 2 player 2)
+//   bit  2    the node is internal (has children); terminals carry no reach
+//   bits 3-30 slot of the edge (decision parents only)
+constexpr int CODE_OWNER_MASK = 3;
+constexpr int CODE_INTERNAL = 4;
+constexpr int CODE_SLOT_SHIFT = 3;
+
+struct DevGame {
+    int32_t N = 0, I = 0, A = 0, Ndec = 0, max_depth = 0, max_actions = 0;
+    int fp64 = 0;                 // state type: 0 float (paper's configured dtype), 1 double
+    // structure (read-only after compile)
+    int2 *up = nullptr;           // [N]   (parent, edge code)
+    int32_t *child_off = nullptr; // [N+1] children of n are [child_off[n], child_off[n+1])
+    int32_t *node_slot = nullptr; // [N]   first slot of a decision node, -1 otherwise
+    int32_t *node_iset = nullptr; // [N]   information set of a decision node, -1 otherwise
+    int32_t *slot_off = nullptr;  // [I+1]
+    int32_t *mem_off = nullptr;   // [I+1]
+    int32_t *mem_node = nullptr;  // [Ndec]
+    int8_t *iset_player = nullptr;// [I]
+    // iteration state, element type float or double (fp64)
+    void *v = nullptr;            // [N]   player-1 chance-weighted values; terminals hold the template
+    void *reach = nullptr;        // [2N]  lane 0: player 1 reach, lane 1: player 2 reach
+    void *sigma = nullptr;        // [A]   current strategy
+    void *R = nullptr;            // [A]   cumulative regrets
+    double *sbar = nullptr;       // [A]   strategy sums (FP64)
+    int32_t *t = nullptr;         // [1]   iterations started (device counter)
+    // evaluation scratch (best response, FP64)
+    double *vbr = nullptr;        // [N]   terminals hold pi_c(z) u(z) in double
+    double *qbr = nullptr;        // [N]   opponent reach of the best responder
+    double *sigbar = nullptr;     // [A]   normalised average strategy
+    int32_t *astar = nullptr;     // [I]   best-response action
+    float *out = nullptr;         // [A]   staging for strategy output
+};
+
+struct IterFlags {
+    int plus;     // CFR+ clamp
+    int linear;   // w_t = t
+};
+
+// one level of the forward reach pass: nodes [lo, hi) of one depth; tick != nullptr bumps the counter
+hipError_t launch_forward(const DevGame &g, int32_t lo, int32_t hi, int32_t *tick, hipStream_t s);
+// one level of the backward value pass: nodes [lo, hi) of one depth
+hipError_t launch_backward(const DevGame &g, int32_t lo, int32_t hi, hipStream_t s);
+// regrets, clamp, average, and regret matching of the next strategy, all information sets
+hipError_t launch_update(const DevGame &g, IterFlags f, hipStream_t s);
+// sigma <- regret matching of R (all information sets)
+hipError_t launch_regret_matching(const DevGame &g, hipStream_t s);
+// counter bump for games without edges
+hipError_t launch_tick(const DevGame &g, hipStream_t s);
+// out[q] <- normalised average strategy (float), sigbar[q] <- same in double
+hipError_t launch_average(const DevGame &g, hipStream_t s);
+// out-of-band conversions: dst[A] <- sigma as float; R <- src[A] (float)
+hipError_t launch_sigma_to_float(const DevGame &g, float *dst, hipStream_t s);
+hipError_t launch_regrets_from_float(const DevGame &g, const float *src, hipStream_t s);
+// best response pieces (FP64); br = 1 or 2 selects the best responder, 0 evaluates the average profile
+hipError_t launch_br_forward(const DevGame &g, int32_t lo, int32_t hi, int br, hipStream_t s);
+hipError_t launch_br_argmax(const DevGame &g, int32_t ilo, int32_t ihi, int br, hipStream_t s);
+hipError_t launch_br_backward(const DevGame &g, int32_t lo, int32_t hi, int br, hipStream_t s);
+
+}  // namespace cfrx

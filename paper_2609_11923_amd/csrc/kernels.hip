@@ -1,0 +1,334 @@
+// kernels.hip -- gfx950 kernels of one compiled CFR iteration and of the FP64
+// best-response evaluator.
+//
+// Iteration (paper Algorithm 'alg:iteration', Table 'tab:opsteps'):
+//   forward  : per depth level, pi_i(c) = pi_i(parent) * (owner(parent) == i ? sigma(slot) : 1)
+//              (eqs. reach, lanes; chance multiplies by 1 because its probabilities
+//              live in the values template, eq. template)
+//   backward : per depth level, v(h) = sum_children m(c) v(c), m = sigma(slot) below decisions,
+//              1 below chance (eqs. cfv, opbwd); terminal entries of v hold the template and
+//              are never overwritten, so no per-iteration template copy is needed
+//   update   : per information set I of player i with members h,
+//              r(I,a) = sum_h s_i pi_{-i}(h) (v(h.a) - v(h))         (eqs. regret, instregret)
+//              R <- R + r, CFR+ clamps at 0; sbar += w_t pi_i(I) sigma^t (FP64, Prop. 4);
+//              then sigma^{t+1} = regret matching of R (eq. rm) for the next iteration.
+// The state type T (reach, values, regrets, strategy) is float -- the paper's
+// configured dtype -- or double; strategy sums are double in both.  Every
+// reduction runs in a fixed order inside one thread, so results are bitwise
+// reproducible run to run (no float atomics).
+#include "device.hpp"
+
+namespace cfrx {
+
+constexpr int BLOCK = 256;
+
+static inline unsigned grid_for(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
+
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float max_t(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ double max_t(double a, double b) { return fmax(a, b); }
+
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_forward(int32_t lo, int32_t hi, const int2 *__restrict__ up,
+                                                   const T *__restrict__ sigma, T *__restrict__ r1,
+                                                   T *__restrict__ r2, int32_t *tick) {
+    if (tick && blockIdx.x == 0 && threadIdx.x == 0) tick[0] += 1;
+    int32_t c = lo + (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
+    if (c >= hi) return;
+    int2 u = up[c];
+    if (!(u.y & CODE_INTERNAL)) return;
+    int owner = u.y & CODE_OWNER_MASK;
+    T s = owner ? sigma[u.y >> CODE_SLOT_SHIFT] : T(1);
+    T a = r1[u.x], b = r2[u.x];
+    r1[c] = owner == 1 ? a * s : a;
+    r2[c] = owner == 2 ? b * s : b;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_backward(int32_t lo, int32_t hi, const int32_t *__restrict__ child_off,
+                                                    const int32_t *__restrict__ node_slot,
+                                                    const T *__restrict__ sigma, T *__restrict__ v) {
+    int32_t h = lo + (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
+    if (h >= hi) return;
+    int32_t b = child_off[h], e = child_off[h + 1];
+    if (b == e) return;
+    int32_t s = node_slot[h];
+    T acc = T(0);
+    if (s < 0) {
+        for (int32_t c = b; c < e; c++) acc += v[c];
+    } else {
+        for (int32_t c = b; c < e; c++) acc = fma_t(sigma[s + (c - b)], v[c], acc);
+    }
+    v[h] = acc;
+}
+
+template <typename T, int MAXA>
+__global__ void __launch_bounds__(BLOCK) k_update(int32_t I, const int32_t *__restrict__ slot_off,
+                                                  const int32_t *__restrict__ mem_off,
+                                                  const int32_t *__restrict__ mem_node,
+                                                  const int8_t *__restrict__ iset_player,
+                                                  const int32_t *__restrict__ child_off,
+                                                  const T *__restrict__ v, const T *__restrict__ r1,
+                                                  const T *__restrict__ r2, T *__restrict__ R,
+                                                  double *__restrict__ sbar, T *__restrict__ sigma,
+                                                  const int32_t *__restrict__ tcount, int plus, int linear) {
+    int32_t i = (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
+    if (i >= I) return;
+    int32_t s0 = slot_off[i], nA = slot_off[i + 1] - s0;
+    int32_t m0 = mem_off[i], m1 = mem_off[i + 1];
+    int pl = iset_player[i];
+    const T *opp = pl == 1 ? r2 : r1;
+    const T *own = pl == 1 ? r1 : r2;
+    T r[MAXA];
+#pragma unroll
+    for (int a = 0; a < MAXA; a++) r[a] = T(0);
+    for (int32_t m = m0; m < m1; m++) {
+        int32_t h = mem_node[m];
+        int32_t cb = child_off[h];
+        T vh = v[h], po = opp[h];
+#pragma unroll
+        for (int a = 0; a < MAXA; a++)
+            if (a < nA) r[a] = fma_t(po, v[cb + a] - vh, r[a]);
+    }
+    const T sign = pl == 1 ? T(1) : T(-1);
+    const double w = linear ? (double)tcount[0] : 1.0;
+    const double pown = (double)own[mem_node[m0]];
+    T tot = T(0);
+    T Rn[MAXA];
+#pragma unroll
+    for (int a = 0; a < MAXA; a++) {
+        if (a < nA) {
+            int32_t q = s0 + a;
+            sbar[q] += w * pown * (double)sigma[q];
+            T x = fma_t(sign, r[a], R[q]);
+            if (plus) x = max_t(x, T(0));
+            R[q] = x;
+            Rn[a] = max_t(x, T(0));
+            tot += Rn[a];
+        }
+    }
+    const T inv = tot > T(0) ? T(1) / tot : T(0);
+    const T uni = T(1) / (T)nA;
+#pragma unroll
+    for (int a = 0; a < MAXA; a++)
+        if (a < nA) sigma[s0 + a] = tot > T(0) ? Rn[a] * inv : uni;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_regret_matching(int32_t I, const int32_t *__restrict__ slot_off,
+                                                           const T *__restrict__ R, T *__restrict__ sigma) {
+    int32_t i = (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
+    if (i >= I) return;
+    int32_t s0 = slot_off[i], s1 = slot_off[i + 1];
+    T tot = T(0);
+    for (int32_t q = s0; q < s1; q++) tot += max_t(R[q], T(0));
+    const T inv = tot > T(0) ? T(1) / tot : T(0);
+    const T uni = T(1) / (T)(s1 - s0);
+    for (int32_t q = s0; q < s1; q++) sigma[q] = tot > T(0) ? max_t(R[q], T(0)) * inv : uni;
+}
+
+__global__ void k_tick(int32_t *t) {
+    if (threadIdx.x == 0) t[0] += 1;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_average(int32_t I, const int32_t *__restrict__ slot_off,
+                                                   const double *__restrict__ sbar, double *__restrict__ sigbar,
+                                                   float *__restrict__ out) {
+    int32_t i = (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
+    if (i >= I) return;
+    int32_t s0 = slot_off[i], s1 = slot_off[i + 1];
+    double tot = 0.0;
+    for (int32_t q = s0; q < s1; q++) tot += sbar[q];
+    const double uni = 1.0 / (double)(s1 - s0);
+    for (int32_t q = s0; q < s1; q++) {
+        double x = tot > 0.0 ? sbar[q] / tot : uni;
+        sigbar[q] = x;
+        out[q] = (float)x;
+    }
+}
+
+template <typename S, typename D>
+__global__ void __launch_bounds__(BLOCK) k_convert(int32_t n, const S *__restrict__ src, D *__restrict__ dst) {
+    int32_t i = (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
+    if (i < n) dst[i] = (D)src[i];
+}
+
+// ---- best response (FP64) -------------------------------------------------
+
+__global__ void __launch_bounds__(BLOCK) k_br_forward(int32_t lo, int32_t hi, const int2 *__restrict__ up,
+                                                      const double *__restrict__ sigbar, double *__restrict__ q,
+                                                      int br) {
+    int32_t c = lo + (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
+    if (c >= hi) return;
+    int2 u = up[c];
+    if (!(u.y & CODE_INTERNAL)) return;
+    int owner = u.y & CODE_OWNER_MASK;
+    double m = (owner != 0 && owner != br) ? sigbar[u.y >> CODE_SLOT_SHIFT] : 1.0;
+    q[c] = q[u.x] * m;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_br_argmax(int32_t ilo, int32_t ihi, const int32_t *__restrict__ slot_off,
+                                                     const int32_t *__restrict__ mem_off,
+                                                     const int32_t *__restrict__ mem_node,
+                                                     const int8_t *__restrict__ iset_player,
+                                                     const int32_t *__restrict__ child_off,
+                                                     const double *__restrict__ vbr, const double *__restrict__ q,
+                                                     int32_t *__restrict__ astar, int br) {
+    int32_t i = ilo + (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
+    if (i >= ihi) return;
+    if (iset_player[i] != br) return;
+    int32_t nA = slot_off[i + 1] - slot_off[i];
+    int32_t m0 = mem_off[i], m1 = mem_off[i + 1];
+    const double sign = br == 1 ? 1.0 : -1.0;
+    int best = 0;
+    double bq = 0.0;
+    for (int a = 0; a < nA; a++) {
+        double Q = 0.0;
+        for (int32_t m = m0; m < m1; m++) {
+            int32_t h = mem_node[m];
+            Q += q[h] * (sign * vbr[child_off[h] + a]);
+        }
+        if (a == 0 || Q > bq) { bq = Q; best = a; }
+    }
+    astar[i] = best;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_br_backward(int32_t lo, int32_t hi, const int32_t *__restrict__ child_off,
+                                                       const int32_t *__restrict__ node_slot,
+                                                       const int32_t *__restrict__ node_iset,
+                                                       const int8_t *__restrict__ iset_player,
+                                                       const double *__restrict__ sigbar,
+                                                       const int32_t *__restrict__ astar, double *__restrict__ vbr,
+                                                       int br) {
+    int32_t h = lo + (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
+    if (h >= hi) return;
+    int32_t b = child_off[h], e = child_off[h + 1];
+    if (b == e) return;
+    int32_t s = node_slot[h];
+    double acc = 0.0;
+    if (s < 0) {
+        for (int32_t c = b; c < e; c++) acc += vbr[c];
+    } else {
+        int32_t i = node_iset[h];
+        if (iset_player[i] == br) {
+            acc = vbr[b + astar[i]];
+        } else {
+            for (int32_t c = b; c < e; c++) acc += sigbar[s + (c - b)] * vbr[c];
+        }
+    }
+    vbr[h] = acc;
+}
+
+// ---- launchers ------------------------------------------------------------
+
+template <typename T>
+static hipError_t forward_t(const DevGame &g, int32_t lo, int32_t hi, int32_t *tick, hipStream_t s) {
+    T *r = (T *)g.reach;
+    hipLaunchKernelGGL(k_forward<T>, dim3(grid_for(hi - lo)), dim3(BLOCK), 0, s, lo, hi, g.up, (const T *)g.sigma, r,
+                       r + g.N, tick);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward(const DevGame &g, int32_t lo, int32_t hi, int32_t *tick, hipStream_t s) {
+    if (hi <= lo) return hipSuccess;
+    return g.fp64 ? forward_t<double>(g, lo, hi, tick, s) : forward_t<float>(g, lo, hi, tick, s);
+}
+
+template <typename T>
+static hipError_t backward_t(const DevGame &g, int32_t lo, int32_t hi, hipStream_t s) {
+    hipLaunchKernelGGL(k_backward<T>, dim3(grid_for(hi - lo)), dim3(BLOCK), 0, s, lo, hi, g.child_off, g.node_slot,
+                       (const T *)g.sigma, (T *)g.v);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward(const DevGame &g, int32_t lo, int32_t hi, hipStream_t s) {
+    if (hi <= lo) return hipSuccess;
+    return g.fp64 ? backward_t<double>(g, lo, hi, s) : backward_t<float>(g, lo, hi, s);
+}
+
+template <typename T, int MAXA>
+static hipError_t update_t(const DevGame &g, IterFlags f, hipStream_t s) {
+    const T *r = (const T *)g.reach;
+    hipLaunchKernelGGL((k_update<T, MAXA>), dim3(grid_for(g.I)), dim3(BLOCK), 0, s, g.I, g.slot_off, g.mem_off,
+                       g.mem_node, g.iset_player, g.child_off, (const T *)g.v, r, r + g.N, (T *)g.R, g.sbar,
+                       (T *)g.sigma, g.t, f.plus, f.linear);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t update_dispatch(const DevGame &g, IterFlags f, hipStream_t s) {
+    if (g.max_actions <= 4) return update_t<T, 4>(g, f, s);
+    if (g.max_actions <= 16) return update_t<T, 16>(g, f, s);
+    return update_t<T, 64>(g, f, s);
+}
+
+hipError_t launch_update(const DevGame &g, IterFlags f, hipStream_t s) {
+    if (g.I == 0) return hipSuccess;
+    return g.fp64 ? update_dispatch<double>(g, f, s) : update_dispatch<float>(g, f, s);
+}
+
+hipError_t launch_regret_matching(const DevGame &g, hipStream_t s) {
+    if (g.I == 0) return hipSuccess;
+    if (g.fp64)
+        hipLaunchKernelGGL(k_regret_matching<double>, dim3(grid_for(g.I)), dim3(BLOCK), 0, s, g.I, g.slot_off,
+                           (const double *)g.R, (double *)g.sigma);
+    else
+        hipLaunchKernelGGL(k_regret_matching<float>, dim3(grid_for(g.I)), dim3(BLOCK), 0, s, g.I, g.slot_off,
+                           (const float *)g.R, (float *)g.sigma);
+    return hipGetLastError();
+}
+
+hipError_t launch_tick(const DevGame &g, hipStream_t s) {
+    hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, g.t);
+    return hipGetLastError();
+}
+
+hipError_t launch_average(const DevGame &g, hipStream_t s) {
+    if (g.I == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_average, dim3(grid_for(g.I)), dim3(BLOCK), 0, s, g.I, g.slot_off, g.sbar, g.sigbar, g.out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sigma_to_float(const DevGame &g, float *dst, hipStream_t s) {
+    if (g.A == 0) return hipSuccess;
+    if (g.fp64)
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A,
+                           (const double *)g.sigma, dst);
+    else
+        hipLaunchKernelGGL((k_convert<float, float>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A,
+                           (const float *)g.sigma, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_regrets_from_float(const DevGame &g, const float *src, hipStream_t s) {
+    if (g.A == 0) return hipSuccess;
+    if (g.fp64)
+        hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, src,
+                           (double *)g.R);
+    else
+        hipLaunchKernelGGL((k_convert<float, float>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, src, (float *)g.R);
+    return hipGetLastError();
+}
+
+hipError_t launch_br_forward(const DevGame &g, int32_t lo, int32_t hi, int br, hipStream_t s) {
+    if (hi <= lo) return hipSuccess;
+    hipLaunchKernelGGL(k_br_forward, dim3(grid_for(hi - lo)), dim3(BLOCK), 0, s, lo, hi, g.up, g.sigbar, g.qbr, br);
+    return hipGetLastError();
+}
+
+hipError_t launch_br_argmax(const DevGame &g, int32_t ilo, int32_t ihi, int br, hipStream_t s) {
+    if (ihi <= ilo) return hipSuccess;
+    hipLaunchKernelGGL(k_br_argmax, dim3(grid_for(ihi - ilo)), dim3(BLOCK), 0, s, ilo, ihi, g.slot_off, g.mem_off,
+                       g.mem_node, g.iset_player, g.child_off, g.vbr, g.qbr, g.astar, br);
+    return hipGetLastError();
+}
+
+hipError_t launch_br_backward(const DevGame &g, int32_t lo, int32_t hi, int br, hipStream_t s) {
+    if (hi <= lo) return hipSuccess;
+    hipLaunchKernelGGL(k_br_backward, dim3(grid_for(hi - lo)), dim3(BLOCK), 0, s, lo, hi, g.child_off, g.node_slot,
+                       g.node_iset, g.iset_player, g.sigbar, g.astar, g.vbr, br);
+    return hipGetLastError();
+}
+
+}  // namespace cfrx

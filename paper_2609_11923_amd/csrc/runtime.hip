@@ -1,0 +1,600 @@
+// runtime.hip -- handle, device memory, hipGraph capture/replay and the C ABI
+// declared in include/cfr.h.
+//
+// One iteration is a fixed sequence of launches (paper Proposition 3 (iii):
+// c1 + c2 D operations): D forward levels (the first also bumps the device
+// iteration counter), D backward levels and one fused update.  The first
+// cfr_iterate call runs one iteration with direct launches, then captures
+// the body once into a hipGraph (k iterations per graph optional) and replays
+// it (paper Section 4.3).  The pointers the graph bakes in are recorded at
+// capture time and checked before every replay; a failed capture warns once
+// and the handle keeps launching the same kernels directly.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cfr.h"
+#include "compiler.hpp"
+#include "device.hpp"
+
+using namespace cfrx;
+
+namespace {
+thread_local std::string g_err;
+
+cfr_status fail(cfr_status s, const std::string &m) {
+    g_err = m;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                                   \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess) return fail(CFR_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+}  // namespace
+
+struct cfr_handle {
+    cfr_options opt{};
+    DevGame g{};
+    // host copies of the schedule
+    std::vector<int32_t> depth_off, iset_depth_off;
+    int32_t D = 0;
+    bool br_ok = true;
+    int64_t E = 0, Z = 0;
+    double pot = 1.0;
+    int64_t device_bytes = 0;
+    std::vector<void *> allocs;
+    // graph state
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph1 = nullptr, graphk = nullptr;
+    hipGraphExec_t exec1 = nullptr, execk = nullptr;
+    bool captured = false, use_graph = true, warned = false;
+    std::vector<const void *> pinned;  // pointers baked into the graph
+    int64_t rebind[3] = {0, 0, 0};     // test hook offsets
+    char *R_base = nullptr, *sigma_base = nullptr, *sbar_base = nullptr;
+    size_t es = 4;                     // bytes per state element
+    int64_t iters = 0;
+    int64_t launches = 0;
+    // algorithmic bytes per iteration of each kernel (traffic model, see model_bytes)
+    double bytes_fwd = 0, bytes_bwd = 0, bytes_upd = 0;
+};
+
+// Per-launch event timing for cfr_profile: class 0 tick, 1 forward, 2 backward, 3 update.
+struct LaunchTimer {
+    std::vector<hipEvent_t> ev;   // pairs (before, after)
+    std::vector<int> cls;
+    size_t next = 0;
+};
+
+namespace {
+
+template <typename T>
+cfr_status dev_alloc(cfr_handle *h, T **p, int64_t count) {
+    size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return fail(CFR_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    h->allocs.push_back(q);
+    h->device_bytes += (int64_t)bytes;
+    *p = (T *)q;
+    return CFR_OK;
+}
+
+template <typename T>
+cfr_status upload(T *dst, const std::vector<T> &src) {
+    if (src.empty()) return CFR_OK;
+    HIP_TRY(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return CFR_OK;
+}
+
+// The addresses a captured graph bakes in.  The rebinding test hook shifts the reported
+// address only; no kernel or copy ever sees a shifted pointer.
+std::vector<const void *> persistent_ptrs(const cfr_handle *h) {
+    return {h->R_base + h->rebind[0] * (int64_t)h->es, h->sbar_base + h->rebind[1] * 8,
+            h->sigma_base + h->rebind[2] * (int64_t)h->es, h->g.v, h->g.reach, h->g.t, h->g.up, h->g.child_off,
+            h->g.mem_node};
+}
+
+// one iteration, direct launches, in a fixed order; tm != nullptr brackets every launch with events
+cfr_status enqueue_iteration(cfr_handle *h, hipStream_t s, int64_t *count, LaunchTimer *tm = nullptr) {
+    const DevGame &g = h->g;
+    int64_t n = 0;
+    auto mark = [&](int cls) -> hipError_t {
+        if (!tm) return hipSuccess;
+        if (tm->next + 1 >= tm->ev.size()) return hipErrorInvalidValue;
+        tm->cls.push_back(cls);
+        return hipEventRecord(tm->ev[tm->next++], s);
+    };
+    if (h->D == 0) {
+        HIP_TRY(mark(0)); HIP_TRY(launch_tick(g, s)); HIP_TRY(mark(-1)); n++;
+    }
+    for (int d = 1; d <= g.max_depth; d++) {
+        HIP_TRY(mark(1));
+        HIP_TRY(launch_forward(g, h->depth_off[d], h->depth_off[d + 1], d == 1 ? g.t : nullptr, s));
+        HIP_TRY(mark(-1));
+        n++;
+    }
+    for (int d = g.max_depth - 1; d >= 0; d--) {
+        HIP_TRY(mark(2));
+        HIP_TRY(launch_backward(g, h->depth_off[d], h->depth_off[d + 1], s));
+        HIP_TRY(mark(-1));
+        n++;
+    }
+    IterFlags f{h->opt.rule == CFR_RULE_CFR_PLUS ? 1 : 0, h->opt.averaging == CFR_AVG_LINEAR ? 1 : 0};
+    if (g.I > 0) { HIP_TRY(mark(3)); HIP_TRY(launch_update(g, f, s)); HIP_TRY(mark(-1)); n++; }
+    if (count) *count = n;
+    return CFR_OK;
+}
+
+// Algorithmic bytes of one iteration per kernel: every index, state and value element a
+// kernel must touch, counted once (sigma gathers count once per slot and pass).
+void model_bytes(cfr_handle *h, const Layout &L) {
+    const int md = L.max_depth;
+    std::vector<double> Nd(md + 2, 0), Nint(md + 2, 0), Ad(md + 2, 0);
+    for (int d = 0; d <= md; d++) {
+        Nd[d] = L.depth_off[d + 1] - L.depth_off[d];
+        for (int32_t n = L.depth_off[d]; n < L.depth_off[d + 1]; n++) Nint[d] += L.child_off[n + 1] > L.child_off[n];
+        for (int32_t i = L.iset_depth_off[d]; i < L.iset_depth_off[d + 1]; i++) Ad[d] += L.slot_off[i + 1] - L.slot_off[i];
+    }
+    const double es = (double)h->es;
+    double f = 0, b = 0;
+    for (int d = 1; d <= md; d++) f += 8 * Nd[d] + 2 * es * Nint[d - 1] + 2 * es * Nint[d] + es * Ad[d - 1];
+    for (int d = 0; d < md; d++) b += 4 * (Nd[d] + 1) + 4 * Nd[d] + es * Nint[d] + es * Nd[d + 1] + es * Ad[d];
+    double edec = 0;
+    for (int64_t i = 0; i < L.I; i++)
+        edec += (double)(L.mem_off[i + 1] - L.mem_off[i]) * (L.slot_off[i + 1] - L.slot_off[i]);
+    h->bytes_fwd = f;
+    h->bytes_bwd = b;
+    // per set: two offsets pairs and the player (17 B) plus the own reach of one member; per member:
+    // its id, child offset, v(h), opponent reach; per decision edge: the child value; per slot:
+    // sigma read and write, R read and write, sbar read and write (FP64)
+    h->bytes_upd = (17.0 + es) * L.I + (8.0 + 2 * es) * L.Ndec + es * edec + (4 * es + 16.0) * L.A;
+}
+
+cfr_status capture(cfr_handle *h, int iters, hipGraph_t *graph, hipGraphExec_t *exec) {
+    hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(CFR_EGRAPH, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    cfr_status st = CFR_OK;
+    for (int k = 0; k < iters && st == CFR_OK; k++) st = enqueue_iteration(h, h->cap_stream, nullptr);
+    hipGraph_t gr = nullptr;
+    e = hipStreamEndCapture(h->cap_stream, &gr);
+    if (st != CFR_OK) { if (gr) (void)hipGraphDestroy(gr); return st; }
+    if (e != hipSuccess || !gr) return fail(CFR_EGRAPH, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) { (void)hipGraphDestroy(gr); return fail(CFR_EGRAPH, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)); }
+    *graph = gr;
+    *exec = ex;
+    return CFR_OK;
+}
+
+void free_handle(cfr_handle *h) {
+    if (!h) return;
+    if (h->exec1) (void)hipGraphExecDestroy(h->exec1);
+    if (h->execk) (void)hipGraphExecDestroy(h->execk);
+    if (h->graph1) (void)hipGraphDestroy(h->graph1);
+    if (h->graphk) (void)hipGraphDestroy(h->graphk);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    for (void *p : h->allocs) (void)hipFree(p);
+    delete h;
+}
+
+void fill_counts(const Layout &L, cfr_counts_t *c, double pot) {
+    std::memset(c, 0, sizeof *c);
+    c->nodes = L.N; c->edges = L.E; c->terminals = L.Z; c->decision_nodes = L.Ndec;
+    c->infosets = L.I; c->slots = L.A; c->max_depth = L.max_depth; c->blocks = L.D;
+    c->max_actions = L.max_actions; c->br_supported = L.br_ok ? 1 : 0; c->pot = pot;
+}
+
+template <typename T>
+T *copy_out(const std::vector<T> &v) {
+    T *p = (T *)std::malloc((v.size() ? v.size() : 1) * sizeof(T));
+    if (p && !v.empty()) std::memcpy(p, v.data(), v.size() * sizeof(T));
+    return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+void cfr_default_options(cfr_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->rule = CFR_RULE_CFR_PLUS;
+    o->averaging = CFR_AVG_LINEAR;
+    o->order = CFR_ORDER_SIMULTANEOUS;
+    o->iters_per_graph = 1;
+    o->layout = CFR_LAYOUT_BFS;
+    o->use_graph = 1;
+    o->device = 0;
+    o->test_fail_capture = 0;
+    o->precision = CFR_PRECISION_FP32;
+}
+
+const char *cfr_last_error(void) { return g_err.c_str(); }
+
+cfr_status cfr_layout_host(const cfr_game_desc *game, cfr_layout *out) {
+    if (!out) return fail(CFR_EINVAL, "out is NULL");
+    std::memset(out, 0, sizeof *out);
+    Layout L;
+    std::string err;
+    cfr_status st = build_layout(game, L, err);
+    if (st != CFR_OK) return fail(st, err);
+    fill_counts(L, &out->counts, game->pot);
+    out->depth_off = copy_out(L.depth_off);
+    out->parent = copy_out(L.parent);
+    out->child_off = copy_out(L.child_off);
+    out->in_slot = copy_out(L.in_slot);
+    out->node_infoset = copy_out(L.node_infoset);
+    out->node_type = copy_out(L.node_type);
+    out->tmpl = copy_out(L.tmpl);
+    out->slot_off = copy_out(L.slot_off);
+    out->mem_off = copy_out(L.mem_off);
+    out->mem_node = copy_out(L.mem_node);
+    out->iset_player = copy_out(L.iset_player);
+    out->iset_key = copy_out(L.iset_key);
+    if (!out->depth_off || !out->parent || !out->child_off || !out->in_slot || !out->node_infoset ||
+        !out->node_type || !out->tmpl || !out->slot_off || !out->mem_off || !out->mem_node || !out->iset_player ||
+        !out->iset_key) {
+        cfr_layout_free(out);
+        return fail(CFR_ENOMEM, "host allocation failed");
+    }
+    return CFR_OK;
+}
+
+void cfr_layout_free(cfr_layout *l) {
+    if (!l) return;
+    std::free(l->depth_off); std::free(l->parent); std::free(l->child_off); std::free(l->in_slot);
+    std::free(l->node_infoset); std::free(l->node_type); std::free(l->tmpl); std::free(l->slot_off);
+    std::free(l->mem_off); std::free(l->mem_node); std::free(l->iset_player); std::free(l->iset_key);
+    std::memset(l, 0, sizeof *l);
+}
+
+cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_handle **out) {
+    if (!out) return fail(CFR_EINVAL, "out is NULL");
+    *out = nullptr;
+    cfr_options o;
+    cfr_default_options(&o);
+    if (opt) o = *opt;
+    if (o.rule != CFR_RULE_CFR_PLUS && o.rule != CFR_RULE_CFR) return fail(CFR_EINVAL, "unknown rule");
+    if (o.averaging != CFR_AVG_LINEAR && o.averaging != CFR_AVG_UNIFORM) return fail(CFR_EINVAL, "unknown averaging");
+    if (o.order != CFR_ORDER_SIMULTANEOUS) return fail(CFR_EUNSUPPORTED, "alternating updates are not built yet");
+    if (o.layout != CFR_LAYOUT_BFS) return fail(CFR_EUNSUPPORTED, "only the breadth-first layout is built yet");
+    if (o.iters_per_graph < 1 || o.iters_per_graph > 1000) return fail(CFR_EINVAL, "iters_per_graph must be in [1, 1000]");
+    if (o.precision != CFR_PRECISION_FP32 && o.precision != CFR_PRECISION_FP64) return fail(CFR_EINVAL, "unknown precision");
+    Layout L;
+    std::string err;
+    cfr_status st = build_layout(game, L, err);
+    if (st != CFR_OK) return fail(st, err);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(CFR_EDEVICE, "no HIP device available");
+    if (o.device < 0 || o.device >= ndev) return fail(CFR_EINVAL, "device ordinal out of range");
+    HIP_TRY(hipSetDevice(o.device));
+
+    cfr_handle *h = new cfr_handle();
+    h->opt = o;
+    h->use_graph = o.use_graph != 0;
+    h->depth_off = L.depth_off;
+    h->iset_depth_off = L.iset_depth_off;
+    h->D = L.D;
+    h->br_ok = L.br_ok;
+    h->E = L.E; h->Z = L.Z; h->pot = game->pot;
+    DevGame &g = h->g;
+    g.N = (int32_t)L.N; g.I = (int32_t)L.I; g.A = (int32_t)L.A; g.Ndec = (int32_t)L.Ndec;
+    g.max_depth = L.max_depth; g.max_actions = L.max_actions;
+    g.fp64 = o.precision == CFR_PRECISION_FP64 ? 1 : 0;
+    h->es = g.fp64 ? 8 : 4;
+    const int64_t N = L.N, I = L.I, A = L.A;
+
+    // node arrays: (parent, edge code), child offsets, per-node first slot and infoset
+    std::vector<int2> up((size_t)N);
+    std::vector<int32_t> node_slot((size_t)N, -1);
+    for (int64_t n = 0; n < N; n++) {
+        int32_t p = L.parent[n];
+        int owner = p >= 0 && (L.node_type[p] == CFR_NODE_P1 || L.node_type[p] == CFR_NODE_P2) ? L.node_type[p] : 0;
+        int internal = L.child_off[n + 1] > L.child_off[n] ? CODE_INTERNAL : 0;
+        int slot = owner ? L.in_slot[n] : 0;
+        up[n] = make_int2(p, (slot << CODE_SLOT_SHIFT) | internal | owner);
+        if (L.node_infoset[n] >= 0) node_slot[n] = L.slot_off[L.node_infoset[n]];
+    }
+    // values: terminals hold the template, internal entries are overwritten every iteration
+    std::vector<double> vbr0(L.tmpl64);
+
+#define ALLOC(ptr, n) do { st = dev_alloc(h, &(ptr), (n)); if (st != CFR_OK) { free_handle(h); return st; } } while (0)
+    ALLOC(g.up, N);
+    ALLOC(g.child_off, N + 1);
+    ALLOC(g.node_slot, N);
+    ALLOC(g.node_iset, N);
+    ALLOC(g.slot_off, I + 1);
+    ALLOC(g.mem_off, I + 1);
+    ALLOC(g.mem_node, L.Ndec);
+    ALLOC(g.iset_player, I);
+    {
+        char *pv = nullptr, *pr = nullptr, *ps = nullptr, *pR = nullptr;
+        ALLOC(pv, N * (int64_t)h->es);
+        ALLOC(pr, 2 * N * (int64_t)h->es);
+        ALLOC(ps, (A > 0 ? A : 1) * (int64_t)h->es);
+        ALLOC(pR, (A > 0 ? A : 1) * (int64_t)h->es);
+        g.v = pv; g.reach = pr; g.sigma = ps; g.R = pR;
+    }
+    ALLOC(g.sbar, A);
+    ALLOC(g.t, 1);
+    ALLOC(g.vbr, N);
+    ALLOC(g.qbr, N);
+    ALLOC(g.sigbar, A);
+    ALLOC(g.astar, I);
+    ALLOC(g.out, A);
+#undef ALLOC
+    h->R_base = (char *)g.R; h->sbar_base = (char *)g.sbar; h->sigma_base = (char *)g.sigma;
+#define UP(dst, src) do { st = upload(dst, src); if (st != CFR_OK) { free_handle(h); return st; } } while (0)
+    UP(g.up, up);
+    UP(g.child_off, L.child_off);
+    UP(g.node_slot, node_slot);
+    UP(g.node_iset, L.node_infoset);
+    UP(g.slot_off, L.slot_off);
+    UP(g.mem_off, L.mem_off);
+    UP(g.mem_node, L.mem_node);
+    UP(g.iset_player, L.iset_player);
+    if (g.fp64) { UP((double *)g.v, L.tmpl64); } else { UP((float *)g.v, L.tmpl); }
+    UP(g.vbr, vbr0);
+#undef UP
+    {
+        // root reach = 1 in both lanes and in the best-response lane; written once, never overwritten
+        float one = 1.0f;
+        double oned = 1.0;
+        const void *src = g.fp64 ? (const void *)&oned : (const void *)&one;
+        char *r = (char *)g.reach;
+        hipError_t e = hipMemcpy(r, src, h->es, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(r + N * (int64_t)h->es, src, h->es, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(g.qbr, &oned, sizeof oned, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) { free_handle(h); return fail(CFR_EDEVICE, std::string("setup: ") + hipGetErrorString(e)); }
+    }
+    int64_t nl = 0;
+    {
+        // count launches per iteration without launching anything
+        nl = (h->D == 0 ? 1 : 0) + 2 * (int64_t)g.max_depth + (g.I > 0 ? 1 : 0);
+    }
+    h->launches = nl;
+    model_bytes(h, L);
+    st = cfr_reset(h);
+    if (st != CFR_OK) { free_handle(h); return st; }
+    *out = h;
+    return CFR_OK;
+}
+
+cfr_status cfr_reset(cfr_handle *h) {
+    if (!h) return fail(CFR_EINVAL, "handle is NULL");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    // iterations may still be queued on a caller's stream: finish them before clearing
+    HIP_TRY(hipDeviceSynchronize());
+    const DevGame &g = h->g;
+    hipStream_t s = h->cap_stream;
+    HIP_TRY(hipMemsetAsync(g.R, 0, (size_t)(g.A > 0 ? g.A : 1) * h->es, s));
+    HIP_TRY(hipMemsetAsync(g.sbar, 0, (size_t)(g.A > 0 ? g.A : 1) * sizeof(double), s));
+    HIP_TRY(hipMemsetAsync(g.t, 0, sizeof(int32_t), s));
+    HIP_TRY(launch_regret_matching(g, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    h->iters = 0;
+    return CFR_OK;
+}
+
+cfr_status cfr_iterate(cfr_handle *h, int64_t n, void *stream) {
+    if (!h) return fail(CFR_EINVAL, "handle is NULL");
+    if (n < 0) return fail(CFR_EINVAL, "n must be >= 0");
+    if (n == 0) return CFR_OK;
+    HIP_TRY(hipSetDevice(h->opt.device));
+    hipStream_t s = (hipStream_t)stream;
+    if (h->captured && h->pinned != persistent_ptrs(h))
+        return fail(CFR_ESTATE, "a persistent buffer changed since graph capture; refusing to replay");
+    if (!h->use_graph) {
+        for (int64_t k = 0; k < n; k++) {
+            cfr_status st = enqueue_iteration(h, s, nullptr);
+            if (st != CFR_OK) return st;
+            h->iters++;
+        }
+        return CFR_OK;
+    }
+    if (!h->captured) {
+        // one direct iteration first (loads every kernel), then capture
+        cfr_status st = enqueue_iteration(h, s, nullptr);
+        if (st != CFR_OK) return st;
+        h->iters++;
+        n--;
+        if (h->opt.test_fail_capture) st = fail(CFR_EGRAPH, "capture failure injected by test hook");
+        else st = capture(h, 1, &h->graph1, &h->exec1);
+        if (st == CFR_OK && h->opt.iters_per_graph > 1) st = capture(h, h->opt.iters_per_graph, &h->graphk, &h->execk);
+        if (st != CFR_OK) {
+            if (!h->warned) {
+                std::fprintf(stderr, "cfr: graph capture failed (%s); launching the same kernels directly\n",
+                             g_err.c_str());
+                h->warned = true;
+            }
+            h->use_graph = false;
+            return cfr_iterate(h, n, stream);
+        }
+        h->captured = true;
+        h->pinned = persistent_ptrs(h);
+    }
+    const int64_t k = h->opt.iters_per_graph;
+    while (k > 1 && n >= k) {
+        hipError_t e = hipGraphLaunch(h->execk, s);
+        if (e != hipSuccess) return fail(CFR_EGRAPH, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+        h->iters += k;
+        n -= k;
+    }
+    for (; n > 0; n--) {
+        hipError_t e = hipGraphLaunch(h->exec1, s);
+        if (e != hipSuccess) return fail(CFR_EGRAPH, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+        h->iters++;
+    }
+    return CFR_OK;
+}
+
+cfr_status cfr_iterations(cfr_handle *h, int64_t *t) {
+    if (!h || !t) return fail(CFR_EINVAL, "NULL argument");
+    *t = h->iters;
+    return CFR_OK;
+}
+
+cfr_status cfr_strategy(cfr_handle *h, int which, float *dst, int64_t len, int dst_on_device, void *stream) {
+    if (!h || (!dst && len > 0)) return fail(CFR_EINVAL, "NULL argument");
+    if (len != h->g.A) return fail(CFR_EINVAL, "len must equal the slot count " + std::to_string(h->g.A));
+    if (which != CFR_STRATEGY_CURRENT && which != CFR_STRATEGY_AVERAGE) return fail(CFR_EINVAL, "unknown strategy kind");
+    if (len == 0) return CFR_OK;
+    HIP_TRY(hipSetDevice(h->opt.device));
+    hipStream_t s = (hipStream_t)stream;
+    const float *src = h->g.out;
+    if (which == CFR_STRATEGY_AVERAGE) HIP_TRY(launch_average(h->g, s));
+    else HIP_TRY(launch_sigma_to_float(h->g, h->g.out, s));
+    HIP_TRY(hipMemcpyAsync(dst, src, (size_t)len * sizeof(float),
+                           dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    if (!dst_on_device) HIP_TRY(hipStreamSynchronize(s));
+    return CFR_OK;
+}
+
+cfr_status cfr_get_state(cfr_handle *h, double *regrets, double *strategy_sum, int64_t len, void *stream) {
+    if (!h) return fail(CFR_EINVAL, "handle is NULL");
+    if (len != h->g.A) return fail(CFR_EINVAL, "len must equal the slot count " + std::to_string(h->g.A));
+    HIP_TRY(hipSetDevice(h->opt.device));
+    hipStream_t s = (hipStream_t)stream;
+    if (len == 0) return CFR_OK;
+    std::vector<float> tmp;
+    if (regrets) {
+        if (h->g.fp64) {
+            HIP_TRY(hipMemcpyAsync(regrets, h->g.R, (size_t)len * 8, hipMemcpyDeviceToHost, s));
+        } else {
+            tmp.resize((size_t)len);
+            HIP_TRY(hipMemcpyAsync(tmp.data(), h->g.R, (size_t)len * 4, hipMemcpyDeviceToHost, s));
+        }
+    }
+    if (strategy_sum)
+        HIP_TRY(hipMemcpyAsync(strategy_sum, h->g.sbar, (size_t)len * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (regrets && !h->g.fp64)
+        for (int64_t q = 0; q < len; q++) regrets[q] = (double)tmp[(size_t)q];
+    return CFR_OK;
+}
+
+cfr_status cfr_set_regrets(cfr_handle *h, const float *r0, int64_t len, int src_on_device, void *stream) {
+    if (!h || (!r0 && len > 0)) return fail(CFR_EINVAL, "NULL argument");
+    if (len != h->g.A) return fail(CFR_EINVAL, "len must equal the slot count " + std::to_string(h->g.A));
+    if (len == 0) return CFR_OK;
+    HIP_TRY(hipSetDevice(h->opt.device));
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(h->g.out, r0, (size_t)len * sizeof(float),
+                           src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_regrets_from_float(h->g, h->g.out, s));
+    HIP_TRY(launch_regret_matching(h->g, s));
+    if (!src_on_device) HIP_TRY(hipStreamSynchronize(s));
+    return CFR_OK;
+}
+
+cfr_status cfr_exploitability(cfr_handle *h, void *stream, double *expl, double *br1, double *br2,
+                              double *value_avg) {
+    if (!h) return fail(CFR_EINVAL, "handle is NULL");
+    if (!h->br_ok) return fail(CFR_EUNSUPPORTED, "an information set spans several depths; the level-synchronous best response needs one depth per set");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    hipStream_t s = (hipStream_t)stream;
+    const DevGame &g = h->g;
+    double vals[3] = {0, 0, 0};
+    HIP_TRY(launch_average(g, s));
+    const int order[3] = {1, 2, 0};
+    for (int k = 0; k < 3; k++) {
+        const int br = order[k];
+        if (br != 0)
+            for (int d = 1; d <= g.max_depth; d++) HIP_TRY(launch_br_forward(g, h->depth_off[d], h->depth_off[d + 1], br, s));
+        for (int d = g.max_depth - 1; d >= 0; d--) {
+            if (br != 0) HIP_TRY(launch_br_argmax(g, h->iset_depth_off[d], h->iset_depth_off[d + 1], br, s));
+            HIP_TRY(launch_br_backward(g, h->depth_off[d], h->depth_off[d + 1], br, s));
+        }
+        double root = 0.0;
+        HIP_TRY(hipMemcpyAsync(&root, g.vbr, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        vals[br] = root;
+    }
+    double b1 = vals[1], b2 = -vals[2];
+    if (br1) *br1 = b1;
+    if (br2) *br2 = b2;
+    if (value_avg) *value_avg = vals[0];
+    if (expl) *expl = 0.5 * (b1 + b2);
+    return CFR_OK;
+}
+
+cfr_status cfr_counts(cfr_handle *h, cfr_counts_t *c) {
+    if (!h || !c) return fail(CFR_EINVAL, "NULL argument");
+    std::memset(c, 0, sizeof *c);
+    c->nodes = h->g.N; c->edges = h->E; c->terminals = h->Z; c->decision_nodes = h->g.Ndec;
+    c->infosets = h->g.I; c->slots = h->g.A; c->max_depth = h->g.max_depth; c->blocks = h->D;
+    c->max_actions = h->g.max_actions; c->br_supported = h->br_ok ? 1 : 0;
+    c->device_bytes = h->device_bytes; c->kernels_per_iteration = h->launches; c->pot = h->pot;
+    return CFR_OK;
+}
+
+cfr_status cfr_profile(cfr_handle *h, int64_t n, void *stream, cfr_kernel_stat *out, int32_t max_out,
+                       int32_t *n_out) {
+    if (!h || !out || !n_out || n <= 0 || max_out < 0) return fail(CFR_EINVAL, "bad argument");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    hipStream_t s = (hipStream_t)stream;
+    LaunchTimer tm;
+    tm.ev.resize((size_t)(2 * h->launches * n + 2));
+    for (auto &e : tm.ev) HIP_TRY(hipEventCreate(&e));
+    cfr_status st = CFR_OK;
+    for (int64_t k = 0; k < n && st == CFR_OK; k++) {
+        st = enqueue_iteration(h, s, nullptr, &tm);
+        if (st == CFR_OK) h->iters++;
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    double ms[4] = {0, 0, 0, 0};
+    int64_t cnt[4] = {0, 0, 0, 0};
+    if (st == CFR_OK && e == hipSuccess) {
+        for (size_t i = 0; i + 1 < tm.next; i += 2) {
+            float x = 0.0f;
+            e = hipEventElapsedTime(&x, tm.ev[i], tm.ev[i + 1]);
+            if (e != hipSuccess) break;
+            ms[tm.cls[i]] += x;
+            cnt[tm.cls[i]]++;
+        }
+    }
+    for (auto &ev : tm.ev) (void)hipEventDestroy(ev);
+    if (st != CFR_OK) return st;
+    if (e != hipSuccess) return fail(CFR_EDEVICE, std::string("profiling events: ") + hipGetErrorString(e));
+    const char *names[4] = {"k_tick", "k_forward", "k_backward", "k_update"};
+    const double bytes[4] = {0.0, h->bytes_fwd, h->bytes_bwd, h->bytes_upd};
+    int32_t k = 0;
+    for (int c = 0; c < 4; c++) {
+        if (cnt[c] == 0) continue;
+        if (k < max_out) {
+            cfr_kernel_stat &o = out[k];
+            std::memset(&o, 0, sizeof o);
+            std::snprintf(o.name, sizeof o.name, "%s", names[c]);
+            o.launches_per_iteration = cnt[c] / n;
+            o.bytes_per_iteration = bytes[c];
+            o.ms_per_iteration = ms[c] / (double)n;
+        }
+        k++;
+    }
+    *n_out = k < max_out ? k : max_out;
+    return CFR_OK;
+}
+
+cfr_status cfr_debug_rebind(cfr_handle *h, int which, int64_t delta) {
+    if (!h || which < 0 || which > 2) return fail(CFR_EINVAL, "bad argument");
+    h->rebind[which] = delta;
+    return CFR_OK;
+}
+
+void cfr_destroy(cfr_handle *h) {
+    if (!h) return;
+    (void)hipSetDevice(h->opt.device);
+    // work queued on any stream may still read the handle's buffers
+    (void)hipDeviceSynchronize();
+    free_handle(h);
+}
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+"""CPU tests of the library boundary: the shared library loads, exports every symbol the header
+declares, and its host compiler emits the canonical arrays bit-exactly as the oracle's
+independent compiler does; invalid games are rejected with CFR_EINVAL and a message."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gamegen as gg
+import oracle
+import paper_2609_11923_amd as cfr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "cfr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cfr_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = cfr.load()
+    names = header_functions()
+    assert "cfr_compile" in names and "cfr_iterate" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(cfr.EXPORTS) == names
+
+
+def _games():
+    yield "kuhn", gg.kuhn()
+    yield "example11", gg.example11()
+    yield "leduc3x2", gg.leduc(3, 2)
+    yield "leduc13x2", gg.leduc(13, 2)
+    for s in (0, 2, 7, 11, 12, 13):
+        yield f"random{s}", gg.random_game(s, 3, 2, 6)
+    yield "large_K1", gg.large(1, seed=0)
+    for k in ("root_terminal", "all_chance", "single_action"):
+        yield k, gg.degenerate(k)
+
+
+@pytest.mark.parametrize("name,game", list(_games()), ids=lambda x: x if isinstance(x, str) else "")
+def test_layout_bit_exact_against_oracle(name, game):
+    a = cfr.cfr_layout_host(game)
+    o = oracle.Oracle(game)
+    b = o.layout()
+    for k in b:
+        assert a[k].dtype == b[k].dtype, k
+        assert np.array_equal(a[k], b[k]), k
+    c = a["counts"]
+    assert (c["nodes"], c["edges"], c["terminals"], c["decision_nodes"], c["infosets"], c["slots"], c["blocks"]) == \
+        (o.N, o.E, o.Z, o.Ndec, o.I, o.A, o.D)
+
+
+def test_layout_any_input_numbering():
+    """The canonical arrays do not depend on how the input numbers its nodes."""
+    g = gg.leduc(3, 2)
+    rng = np.random.default_rng(0)
+    N = g.n_nodes
+    perm = rng.permutation(N)            # new id of old node
+    inv = np.argsort(perm)
+    g2 = gg.Game(type=g.type[inv].copy(), child_begin=np.zeros(N, np.int64), n_children=g.n_children[inv].copy(),
+                 children=np.zeros(g.n_edges, np.int64), prob=np.zeros(g.n_edges), key=g.key[inv].copy(),
+                 payoff=g.payoff[inv].copy(), pub=g.pub[inv].copy(), root=int(perm[g.root]), pot=g.pot)
+    # children lists stored in reverse node order to scramble child_begin as well
+    pos = 0
+    for new in range(N - 1, -1, -1):
+        old = inv[new]
+        b, n = int(g.child_begin[old]), int(g.n_children[old])
+        g2.child_begin[new] = pos
+        g2.children[pos:pos + n] = perm[g.children[b:b + n]]
+        g2.prob[pos:pos + n] = g.prob[b:b + n]
+        pos += n
+    a, b = cfr.cfr_layout_host(g), cfr.cfr_layout_host(g2)
+    for k in ("depth_off", "parent", "child_off", "in_slot", "node_infoset", "tmpl", "slot_off", "mem_node"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+T = 3
+
+
+@pytest.mark.parametrize("bad,needle", [
+    ("cycle", "tree"), ("two_parents", "tree"), ("unreachable", "unreachable"), ("chance_sum", "sum to 1"),
+    ("mixed_players", "spans players"), ("action_counts", "action count"), ("bad_type", "type"),
+    ("terminal_children", "terminal"), ("no_children", "without children"), ("child_range", "out of range"),
+    ("imperfect_recall", "perfect recall"), ("pot", "pot"),
+])
+def test_invalid_games_rejected(bad, needle):
+    pot = 1.0
+    if bad == "cycle":
+        g = gg.from_arrays([1, 2, T], [[1], [0], []], [None] * 3, [1, 2, -1], [0, 0, 0])
+    elif bad == "two_parents":
+        g = gg.from_arrays([0, 1, T], [[1, 2], [2], []], [[0.5, 0.5], None, None], [-1, 1, -1], [0, 0, 0])
+    elif bad == "unreachable":
+        g = gg.from_arrays([1, T, T], [[1], [], []], [None] * 3, [1, -1, -1], [0, 0, 0])
+    elif bad == "chance_sum":
+        g = gg.from_arrays([0, T, T], [[1, 2], [], []], [[0.5, 0.6], None, None], [-1] * 3, [0, 1, 2])
+    elif bad == "mixed_players":
+        g = gg.from_arrays([0, 1, 2, T, T, T, T], [[1, 2], [3, 4], [5, 6], [], [], [], []],
+                           [[0.5, 0.5]] + [None] * 6, [-1, 7, 7, -1, -1, -1, -1], [0] * 7)
+    elif bad == "action_counts":
+        g = gg.from_arrays([0, 1, 1, T, T, T, T, T], [[1, 2], [3, 4], [5, 6, 7], [], [], [], [], []],
+                           [[0.5, 0.5]] + [None] * 7, [-1, 7, 7, -1, -1, -1, -1, -1], [0] * 8)
+    elif bad == "bad_type":
+        g = gg.from_arrays([7, T], [[1], []], [None, None], [1, -1], [0, 0])
+    elif bad == "terminal_children":
+        g = gg.from_arrays([T, T], [[1], []], [None, None], [-1, -1], [0, 0])
+    elif bad == "no_children":
+        g = gg.from_arrays([1], [[]], [None], [1], [0])
+    elif bad == "child_range":
+        g = gg.from_arrays([1, T], [[5], []], [None, None], [1, -1], [0, 0])
+    elif bad == "imperfect_recall":
+        # player 1 acts, then acts again at one information set from both of its actions
+        g = gg.from_arrays([1, 1, 1, T, T, T, T], [[1, 2], [3, 4], [5, 6], [], [], [], []], [None] * 7,
+                           [1, 2, 2, -1, -1, -1, -1], [0, 0, 0, 1, 2, 3, 4])
+    else:
+        g = gg.kuhn()
+        g.pot = 0.0
+    with pytest.raises(cfr.CfrError) as e:
+        cfr.cfr_layout_host(g)
+    assert e.value.status == cfr.CFR_EINVAL
+    assert needle in str(e.value)
+
+
+def test_options_rejected_before_device():
+    o = cfr.cfr_default_options()
+    o.iters_per_graph = 0
+    with pytest.raises(cfr.CfrError) as e:
+        cfr.cfr_compile(gg.kuhn(), o)
+    assert e.value.status == cfr.CFR_EINVAL
+
+
+def test_default_options():
+    o = cfr.cfr_default_options()
+    assert (o.rule, o.averaging, o.order, o.iters_per_graph, o.layout, o.use_graph) == (0, 0, 0, 1, 0, 1)
