@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--iters-per-graph", type=int, default=1)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--direct", action="store_true", help="launch kernels directly instead of replaying a graph")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of this many MiB (counter calibration for profilers)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU design is "
@@ -99,7 +102,7 @@ def main():
     log(f"[bench] generated {args.workload}: {game.n_nodes} nodes in {t_gen:.1f} s")
     t0 = time.perf_counter()
     prec = cfr.CFR_PRECISION_FP64 if args.precision == "fp64" else cfr.CFR_PRECISION_FP32
-    solver = cfr.Solver(game, iters_per_graph=args.iters_per_graph, precision=prec)
+    solver = cfr.Solver(game, iters_per_graph=args.iters_per_graph, precision=prec, use_graph=not args.direct)
     t_compile = time.perf_counter() - t0
     c = solver.counts
     log(f"[bench] compiled in {t_compile:.1f} s: {c}")
@@ -135,6 +138,16 @@ def main():
     per_launch_ms = dom["ms_per_iteration"] / dom["launches_per_iteration"]
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
     log(f"[bench] kernels: {kernels}")
+
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calibrate_copy} MiB done")
+        del src, dst
 
     e, b1, b2, v = solver.exploitability(stream=stream)
     out = {

@@ -86,7 +86,10 @@ typedef struct {
 enum { CFR_RULE_CFR_PLUS = 0, CFR_RULE_CFR = 1 };        /* CFR+ clamps regrets at 0 after the add */
 enum { CFR_AVG_LINEAR = 0, CFR_AVG_UNIFORM = 1 };       /* w_t = t or 1 */
 enum { CFR_ORDER_SIMULTANEOUS = 0, CFR_ORDER_ALTERNATING = 1 };
-enum { CFR_LAYOUT_BFS = 0, CFR_LAYOUT_PUBLIC = 1 };     /* device node order within a depth level */
+/* Device node order within a depth level.  BFS: the canonical order.  PUBLIC: internal nodes
+ * first, then terminals, each grouped by public state (first occurrence), canonical order
+ * inside a group; this keeps an information set's members and each level's writes together. */
+enum { CFR_LAYOUT_BFS = 0, CFR_LAYOUT_PUBLIC = 1 };
 enum { CFR_STRATEGY_CURRENT = 0, CFR_STRATEGY_AVERAGE = 1 };
 enum { CFR_PRECISION_FP32 = 0, CFR_PRECISION_FP64 = 1 };
 
@@ -95,7 +98,8 @@ typedef struct {
     int averaging;         /* CFR_AVG_* (default linear) */
     int order;             /* CFR_ORDER_* (default simultaneous) */
     int iters_per_graph;   /* k iterations captured per graph (default 1) */
-    int layout;            /* CFR_LAYOUT_* (default BFS) */
+    int layout;            /* CFR_LAYOUT_* (default PUBLIC; without public keys it orders internal
+                              nodes before terminals inside each depth) */
     int use_graph;         /* 1: hipGraph replay (default); 0: direct kernel launches */
     int device;            /* HIP device ordinal (default 0) */
     int test_fail_capture; /* test hook: treat graph capture as failed (warns once, launches directly) */
@@ -134,7 +138,8 @@ typedef struct {
 
 typedef struct cfr_handle cfr_handle;
 
-/* Fill *opt with the defaults (CFR+, linear, simultaneous, k=1, BFS, graph on, device 0, FP32). */
+/* Fill *opt with the defaults (CFR+, linear, simultaneous, k=1, PUBLIC layout, graph on, device 0,
+ * FP32). */
 void cfr_default_options(cfr_options *opt);
 
 /* Host-only compile (no GPU touched): validate the game and return its canonical arrays

@@ -263,7 +263,7 @@ class Solver:
     """Owns one compiled game.  ``stream`` may be a torch.cuda.Stream, a raw hipStream_t int, or None."""
 
     def __init__(self, game, rule=CFR_RULE_CFR_PLUS, averaging=CFR_AVG_LINEAR, order=CFR_ORDER_SIMULTANEOUS,
-                 iters_per_graph=1, layout=CFR_LAYOUT_BFS, use_graph=True, device=0, test_fail_capture=False,
+                 iters_per_graph=1, layout=CFR_LAYOUT_PUBLIC, use_graph=True, device=0, test_fail_capture=False,
                  precision=CFR_PRECISION_FP32):
         o = cfr_default_options()
         o.rule, o.averaging, o.order = rule, averaging, order

@@ -231,4 +231,164 @@ cfr_status build_layout(const cfr_game_desc *g, Layout &L, std::string &err) {
     }
 }
 
+namespace {
+// edge code: owner of the parent in bits 0-1, internal flag in bit 2, slot from bit 3
+inline int32_t edge_code(int owner, bool internal, int32_t slot) {
+    return (int32_t)(((uint32_t)slot << 3) | (internal ? 4u : 0u) | (uint32_t)owner);
+}
+}  // namespace
+
+cfr_status build_device_layout(const Layout &L, int kind, DeviceLayout &D, std::string &err) {
+    try {
+        const int64_t N = L.N, I = L.I, A = L.A;
+        const int md = L.max_depth;
+        const bool pub = kind == CFR_LAYOUT_PUBLIC;
+        std::vector<int32_t> perm((size_t)N), inv((size_t)N);
+        D.depth_off = L.depth_off;
+        D.int_end.assign((size_t)md + 1, 0);
+        auto internal = [&](int64_t k) { return L.child_off[k + 1] > L.child_off[k]; };
+        if (!pub) {
+            for (int64_t k = 0; k < N; k++) perm[k] = inv[k] = (int32_t)k;
+            for (int d = 0; d <= md; d++) D.int_end[d] = L.depth_off[d + 1];
+        } else {
+            const bool have_keys = !L.public_key.empty();
+            std::vector<int32_t> rank;
+            std::vector<int64_t> count;
+            for (int d = 0; d <= md; d++) {
+                const int32_t lo = L.depth_off[d], hi = L.depth_off[d + 1];
+                const int64_t n = hi - lo;
+                // rank public states by first occurrence inside this depth
+                rank.assign((size_t)n, 0);
+                int32_t R = 1;
+                if (have_keys) {
+                    KeyMap km(n);
+                    R = 0;
+                    for (int64_t j = 0; j < n; j++) {
+                        int32_t r = km.find_or_insert(L.public_key[lo + j], R);
+                        if (r == R) R++;
+                        rank[j] = r;
+                    }
+                }
+                // stable counting sort by (terminal, rank)
+                count.assign((size_t)2 * R + 1, 0);
+                for (int64_t j = 0; j < n; j++) count[(internal(lo + j) ? 0 : R) + rank[j] + 1]++;
+                for (int64_t b = 0; b < 2 * R; b++) count[b + 1] += count[b];
+                int64_t n_int = 0;
+                for (int64_t j = 0; j < n; j++) {
+                    bool in = internal(lo + j);
+                    n_int += in;
+                    int64_t pos = count[(in ? 0 : R) + rank[j]]++;
+                    perm[lo + j] = (int32_t)(lo + pos);
+                    inv[lo + pos] = (int32_t)(lo + j);
+                }
+                D.int_end[d] = (int32_t)(lo + n_int);
+            }
+        }
+        D.explicit_kids = pub;
+        // information sets renumbered by first member in device order
+        std::vector<int32_t> iset_dev((size_t)I, -1), iset_canon;
+        iset_canon.reserve((size_t)I);
+        for (int64_t x = 0; x < N; x++) {
+            int32_t ci = L.node_infoset[inv[x]];
+            if (ci >= 0 && iset_dev[ci] < 0) { iset_dev[ci] = (int32_t)iset_canon.size(); iset_canon.push_back(ci); }
+        }
+        D.slot_off.assign((size_t)I + 1, 0);
+        D.iset_player.resize((size_t)I);
+        for (int64_t i = 0; i < I; i++) {
+            int32_t ci = iset_canon[i];
+            D.slot_off[i + 1] = D.slot_off[i] + (L.slot_off[ci + 1] - L.slot_off[ci]);
+            D.iset_player[i] = L.iset_player[ci];
+        }
+        std::vector<int32_t> slot_map((size_t)A);
+        for (int64_t ci = 0; ci < I; ci++)
+            for (int32_t a = 0; a < L.slot_off[ci + 1] - L.slot_off[ci]; a++)
+                slot_map[L.slot_off[ci] + a] = D.slot_off[iset_dev[ci]] + a;
+        if (pub) D.slot_canon_to_dev = slot_map; else D.slot_canon_to_dev.clear();
+        // members ascending in device order
+        D.mem_off.assign((size_t)I + 1, 0);
+        for (int64_t x = 0; x < N; x++) {
+            int32_t ci = L.node_infoset[inv[x]];
+            if (ci >= 0) D.mem_off[iset_dev[ci] + 1]++;
+        }
+        for (int64_t i = 0; i < I; i++) D.mem_off[i + 1] += D.mem_off[i];
+        D.mem_node.assign((size_t)L.Ndec, 0);
+        {
+            std::vector<int32_t> fill(D.mem_off.begin(), D.mem_off.end() - 1);
+            for (int64_t x = 0; x < N; x++) {
+                int32_t ci = L.node_infoset[inv[x]];
+                if (ci >= 0) {
+                    // bit 31 marks members of player-2 sets (kernels mask it off)
+                    uint32_t tag = L.iset_player[ci] == CFR_NODE_P2 ? 0x80000000u : 0u;
+                    D.mem_node[fill[iset_dev[ci]]++] = (int32_t)((uint32_t)x | tag);
+                }
+            }
+        }
+        D.iset_depth_off.assign((size_t)md + 2, (int32_t)I);
+        {
+            int32_t i = 0;
+            for (int d = 0; d <= md + 1; d++) {
+                while (i < I) {
+                    int32_t x = D.mem_node[D.mem_off[i]] & 0x7fffffff;
+                    int dep = 0;
+                    while (dep <= md && x >= L.depth_off[dep + 1]) dep++;
+                    if (dep >= d) break;
+                    i++;
+                }
+                D.iset_depth_off[d] = i;
+            }
+        }
+        // node arrays in device order
+        D.up_parent.assign((size_t)N, -1);
+        D.up_code.assign((size_t)N, 0);
+        D.node_slot.assign((size_t)N, -1);
+        D.node_iset.assign((size_t)N, -1);
+        D.tmpl.assign((size_t)N, 0.0f);
+        D.tmpl64.assign((size_t)N, 0.0);
+        D.kid_off.assign((size_t)N + 1, 0);
+        if (pub) D.kid.assign((size_t)L.E, 0);
+        int32_t e = 0;
+        for (int64_t x = 0; x < N; x++) {
+            int64_t k = inv[x];
+            int32_t p = L.parent[k];
+            int owner = 0;
+            if (p >= 0 && (L.node_type[p] == CFR_NODE_P1 || L.node_type[p] == CFR_NODE_P2)) owner = L.node_type[p];
+            int32_t slot = owner ? slot_map[L.in_slot[k]] : 0;
+            D.up_parent[x] = p >= 0 ? perm[p] : -1;
+            D.up_code[x] = edge_code(owner, internal(k), slot);
+            int32_t ci = L.node_infoset[k];
+            if (ci >= 0) {
+                D.node_iset[x] = iset_dev[ci];
+                D.node_slot[x] = D.slot_off[iset_dev[ci]];
+            }
+            D.tmpl[x] = L.tmpl[k];
+            D.tmpl64[x] = L.tmpl64[k];
+            if (pub) {
+                D.kid_off[x] = e;
+                for (int32_t c = L.child_off[k]; c < L.child_off[k + 1]; c++) D.kid[e++] = perm[c];
+            } else {
+                D.kid_off[x] = L.child_off[k];
+            }
+        }
+        D.kid_off[N] = pub ? e : L.child_off[N];
+        // update groups in device information-set order
+        D.grp_iset_off.assign(1, 0);
+        {
+            int32_t members = 0, sets = 0;
+            for (int64_t i = 0; i < I; i++) {
+                int32_t m = D.mem_off[i + 1] - D.mem_off[i];
+                if (sets > 0 && (members + m > GROUP_MEMBERS || sets + 1 > GROUP_SETS)) {
+                    D.grp_iset_off.push_back((int32_t)i);
+                    members = 0; sets = 0;
+                }
+                members += m; sets++;
+            }
+            if (sets > 0) D.grp_iset_off.push_back((int32_t)I);
+        }
+        return CFR_OK;
+    } catch (const std::bad_alloc &) {
+        err = "host allocation failed while building the device layout";
+        return CFR_ENOMEM;
+    }
+}
+
 }  // namespace cfrx

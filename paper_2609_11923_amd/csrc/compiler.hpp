@@ -39,4 +39,42 @@ struct Layout {
 // Validate and compile.  Returns CFR_OK or CFR_EINVAL / CFR_ENOMEM with a message in err.
 cfr_status build_layout(const cfr_game_desc *g, Layout &out, std::string &err);
 
+// The node order the kernels run on.  Depth ranges are those of the canonical layout; inside
+// each depth the nodes are permuted:
+//   BFS     canonical order (children of a node are consecutive ids, so child lists stay
+//           implicit: child a of h is kid_off[h] + a)
+//   PUBLIC  internal nodes first, then terminals; each part grouped by public state (states
+//           ranked by first occurrence in canonical order), canonical order inside a group.
+//           Members of an information set then sit in one public-state block, children of a
+//           block's nodes sit in the child states' blocks at the same rank, and every write of
+//           a level pass lands in one dense range.  Child lists are explicit (kid[]).
+// Information sets are renumbered by first member in device order (hence depth-sorted) and
+// slots follow them; slot_canon_to_dev maps the canonical slot numbering of the ABI.
+struct DeviceLayout {
+    bool explicit_kids = false;
+    std::vector<int32_t> depth_off;      // [max_depth + 2]
+    std::vector<int32_t> int_end;        // [max_depth + 1] internal nodes of depth d: [depth_off[d], int_end[d])
+    std::vector<int32_t> up_parent;      // [N] parent (device id), -1 at the root
+    std::vector<int32_t> up_code;        // [N] edge code (see device.hpp), slot in device numbering
+    std::vector<int32_t> kid_off;        // [N + 1]
+    std::vector<int32_t> kid;            // [E] when explicit_kids
+    std::vector<int32_t> node_slot;      // [N] first device slot of a decision node, -1 otherwise
+    std::vector<int32_t> node_iset;      // [N] device information set, -1 otherwise
+    std::vector<int32_t> slot_off, mem_off, mem_node;
+    std::vector<int8_t> iset_player;
+    std::vector<int32_t> iset_depth_off; // [max_depth + 2]
+    std::vector<float> tmpl;             // [N]
+    std::vector<double> tmpl64;          // [N]
+    std::vector<int32_t> slot_canon_to_dev; // [A], empty when identical
+    // update groups: runs of consecutive information sets with at most GROUP_MEMBERS members and
+    // at most GROUP_SETS sets in total (a set with more members forms a group of its own);
+    // group g holds sets [grp_iset_off[g], grp_iset_off[g + 1])
+    std::vector<int32_t> grp_iset_off;
+};
+
+constexpr int GROUP_MEMBERS = 256;
+constexpr int GROUP_SETS = 256;
+
+cfr_status build_device_layout(const Layout &L, int layout_kind, DeviceLayout &out, std::string &err);
+
 }  // namespace cfrx

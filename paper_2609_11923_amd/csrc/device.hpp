@@ -12,19 +12,27 @@ namespace cfrx {
 constexpr int CODE_OWNER_MASK = 3;
 constexpr int CODE_INTERNAL = 4;
 constexpr int CODE_SLOT_SHIFT = 3;
+// Member-list entries: node id in bits 0-30, bit 31 set when the set belongs to player 2.
+constexpr int32_t MEMBER_NODE_MASK = 0x7fffffff;
+constexpr int32_t MEMBER_P2 = (int32_t)0x80000000u;
 
 struct DevGame {
     int32_t N = 0, I = 0, A = 0, Ndec = 0, max_depth = 0, max_actions = 0;
     int fp64 = 0;                 // state type: 0 float (paper's configured dtype), 1 double
     // structure (read-only after compile)
+    int explicit_kids = 0;        // 1: child a of n is kid[kid_off[n] + a]; 0: it is kid_off[n] + a
     int2 *up = nullptr;           // [N]   (parent, edge code)
-    int32_t *child_off = nullptr; // [N+1] children of n are [child_off[n], child_off[n+1])
+    int32_t *kid_off = nullptr;   // [N+1] edges of n are [kid_off[n], kid_off[n+1])
+    int32_t *kid = nullptr;       // [E]   child of each edge (explicit layouts only)
+    int32_t *slot_map = nullptr;  // [A]   canonical slot -> device slot (nullptr: identity)
     int32_t *node_slot = nullptr; // [N]   first slot of a decision node, -1 otherwise
     int32_t *node_iset = nullptr; // [N]   information set of a decision node, -1 otherwise
     int32_t *slot_off = nullptr;  // [I+1]
     int32_t *mem_off = nullptr;   // [I+1]
     int32_t *mem_node = nullptr;  // [Ndec]
     int8_t *iset_player = nullptr;// [I]
+    int32_t G = 0;                // update groups
+    int32_t *grp_iset_off = nullptr; // [G+1]
     // iteration state, element type float or double (fp64)
     void *v = nullptr;            // [N]   player-1 chance-weighted values; terminals hold the template
     void *reach = nullptr;        // [2N]  lane 0: player 1 reach, lane 1: player 2 reach
@@ -37,7 +45,8 @@ struct DevGame {
     double *qbr = nullptr;        // [N]   opponent reach of the best responder
     double *sigbar = nullptr;     // [A]   normalised average strategy
     int32_t *astar = nullptr;     // [I]   best-response action
-    float *out = nullptr;         // [A]   staging for strategy output
+    float *out = nullptr;         // [A]   staging for strategy output (canonical order)
+    float *out2 = nullptr;        // [A]   staging in device order
 };
 
 struct IterFlags {
@@ -55,10 +64,12 @@ hipError_t launch_update(const DevGame &g, IterFlags f, hipStream_t s);
 hipError_t launch_regret_matching(const DevGame &g, hipStream_t s);
 // counter bump for games without edges
 hipError_t launch_tick(const DevGame &g, hipStream_t s);
-// out[q] <- normalised average strategy (float), sigbar[q] <- same in double
+// out2[q] <- normalised average strategy (float, device order), sigbar[q] <- same in double
 hipError_t launch_average(const DevGame &g, hipStream_t s);
-// out-of-band conversions: dst[A] <- sigma as float; R <- src[A] (float)
+// out-of-band conversions between device slot order and canonical order:
+// dst[q] <- sigma[map q] as float; dst[q] <- src[map q]; R[map q] <- src[q]
 hipError_t launch_sigma_to_float(const DevGame &g, float *dst, hipStream_t s);
+hipError_t launch_gather_float(const DevGame &g, const float *src, float *dst, hipStream_t s);
 hipError_t launch_regrets_from_float(const DevGame &g, const float *src, hipStream_t s);
 // best response pieces (FP64); br = 1 or 2 selects the best responder, 0 evaluates the average profile
 hipError_t launch_br_forward(const DevGame &g, int32_t lo, int32_t hi, int br, hipStream_t s);

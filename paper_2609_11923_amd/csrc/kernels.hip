@@ -29,6 +29,13 @@ __device__ __forceinline__ double fma_t(double a, double b, double c) { return f
 __device__ __forceinline__ float max_t(float a, float b) { return fmaxf(a, b); }
 __device__ __forceinline__ double max_t(double a, double b) { return fmax(a, b); }
 
+// child a of node n: explicit layouts list children, the breadth-first layout numbers them
+template <bool EXPLICIT>
+__device__ __forceinline__ int32_t child_of(const int32_t *__restrict__ kid, int32_t edge) {
+    if constexpr (EXPLICIT) return kid[edge];
+    else return edge;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_forward(int32_t lo, int32_t hi, const int2 *__restrict__ up,
                                                    const T *__restrict__ sigma, T *__restrict__ r1,
@@ -45,30 +52,32 @@ __global__ void __launch_bounds__(BLOCK) k_forward(int32_t lo, int32_t hi, const
     r2[c] = owner == 2 ? b * s : b;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(BLOCK) k_backward(int32_t lo, int32_t hi, const int32_t *__restrict__ child_off,
+template <typename T, bool EXPLICIT>
+__global__ void __launch_bounds__(BLOCK) k_backward(int32_t lo, int32_t hi, const int32_t *__restrict__ kid_off,
+                                                    const int32_t *__restrict__ kid,
                                                     const int32_t *__restrict__ node_slot,
                                                     const T *__restrict__ sigma, T *__restrict__ v) {
     int32_t h = lo + (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
     if (h >= hi) return;
-    int32_t b = child_off[h], e = child_off[h + 1];
+    int32_t b = kid_off[h], e = kid_off[h + 1];
     if (b == e) return;
     int32_t s = node_slot[h];
     T acc = T(0);
     if (s < 0) {
-        for (int32_t c = b; c < e; c++) acc += v[c];
+        for (int32_t c = b; c < e; c++) acc += v[child_of<EXPLICIT>(kid, c)];
     } else {
-        for (int32_t c = b; c < e; c++) acc = fma_t(sigma[s + (c - b)], v[c], acc);
+        for (int32_t c = b; c < e; c++) acc = fma_t(sigma[s + (c - b)], v[child_of<EXPLICIT>(kid, c)], acc);
     }
     v[h] = acc;
 }
 
-template <typename T, int MAXA>
+template <typename T, int MAXA, bool EXPLICIT>
 __global__ void __launch_bounds__(BLOCK) k_update(int32_t I, const int32_t *__restrict__ slot_off,
                                                   const int32_t *__restrict__ mem_off,
                                                   const int32_t *__restrict__ mem_node,
                                                   const int8_t *__restrict__ iset_player,
-                                                  const int32_t *__restrict__ child_off,
+                                                  const int32_t *__restrict__ kid_off,
+                                                  const int32_t *__restrict__ kid,
                                                   const T *__restrict__ v, const T *__restrict__ r1,
                                                   const T *__restrict__ r2, T *__restrict__ R,
                                                   double *__restrict__ sbar, T *__restrict__ sigma,
@@ -84,16 +93,100 @@ __global__ void __launch_bounds__(BLOCK) k_update(int32_t I, const int32_t *__re
 #pragma unroll
     for (int a = 0; a < MAXA; a++) r[a] = T(0);
     for (int32_t m = m0; m < m1; m++) {
-        int32_t h = mem_node[m];
-        int32_t cb = child_off[h];
+        int32_t h = mem_node[m] & MEMBER_NODE_MASK;
+        int32_t cb = kid_off[h];
         T vh = v[h], po = opp[h];
 #pragma unroll
         for (int a = 0; a < MAXA; a++)
-            if (a < nA) r[a] = fma_t(po, v[cb + a] - vh, r[a]);
+            if (a < nA) r[a] = fma_t(po, v[child_of<EXPLICIT>(kid, cb + a)] - vh, r[a]);
     }
     const T sign = pl == 1 ? T(1) : T(-1);
     const double w = linear ? (double)tcount[0] : 1.0;
-    const double pown = (double)own[mem_node[m0]];
+    const double pown = (double)own[mem_node[m0] & MEMBER_NODE_MASK];
+    T tot = T(0);
+    T Rn[MAXA];
+#pragma unroll
+    for (int a = 0; a < MAXA; a++) {
+        if (a < nA) {
+            int32_t q = s0 + a;
+            sbar[q] += w * pown * (double)sigma[q];
+            T x = fma_t(sign, r[a], R[q]);
+            if (plus) x = max_t(x, T(0));
+            R[q] = x;
+            Rn[a] = max_t(x, T(0));
+            tot += Rn[a];
+        }
+    }
+    const T inv = tot > T(0) ? T(1) / tot : T(0);
+    const T uni = T(1) / (T)nA;
+#pragma unroll
+    for (int a = 0; a < MAXA; a++)
+        if (a < nA) sigma[s0 + a] = tot > T(0) ? Rn[a] * inv : uni;
+}
+
+// Grouped update: one workgroup per group of consecutive information sets (at most BLOCK members
+// and BLOCK sets).  Phase 1 stages, for every member h (one thread each, coalesced over the
+// member list), the opponent reach pi_{-i}(h) and the value differences v(h.a) - v(h) in LDS.
+// Phase 2 gives each set one thread that reduces its members from LDS in ascending member order
+// -- the same fused multiply-add chain as a per-set loop -- and then applies the regret, clamp,
+// average and regret-matching step to the set's slots.  Sets with more than BLOCK members are
+// streamed through LDS in chunks.  Member entries carry the owner in bit 31 (MEMBER_P2).
+template <typename T, int MAXA, bool EXPLICIT>
+__global__ void __launch_bounds__(BLOCK) k_update_grouped(
+    const int32_t *__restrict__ grp_iset_off, const int32_t *__restrict__ slot_off,
+    const int32_t *__restrict__ mem_off, const int32_t *__restrict__ mem_node, const int8_t *__restrict__ iset_player,
+    const int32_t *__restrict__ kid_off, const int32_t *__restrict__ kid, const T *__restrict__ v,
+    const T *__restrict__ r1, const T *__restrict__ r2, T *__restrict__ R, double *__restrict__ sbar,
+    T *__restrict__ sigma, const int32_t *__restrict__ tcount, int plus, int linear) {
+    __shared__ T s_po[BLOCK];
+    __shared__ T s_diff[BLOCK * MAXA];
+    const int32_t g = blockIdx.x;
+    const int32_t i0 = grp_iset_off[g], i1 = grp_iset_off[g + 1];
+    const int32_t mbeg = mem_off[i0], mend = mem_off[i1];
+    const int tid = threadIdx.x;
+    const int32_t my = i0 + tid;
+    const bool has_set = my < i1;
+    int32_t s0 = 0, nA = 0, m0 = 0, m1 = 0, pl = 1;
+    if (has_set) {
+        s0 = slot_off[my];
+        nA = slot_off[my + 1] - s0;
+        m0 = mem_off[my];
+        m1 = mem_off[my + 1];
+        pl = iset_player[my];
+    }
+    T r[MAXA];
+#pragma unroll
+    for (int a = 0; a < MAXA; a++) r[a] = T(0);
+    for (int32_t cbeg = mbeg; cbeg < mend; cbeg += BLOCK) {
+        const int32_t cend = min(cbeg + BLOCK, mend);
+        const int32_t m = cbeg + tid;
+        if (m < cend) {
+            const int32_t x = mem_node[m];
+            const int32_t h = x & MEMBER_NODE_MASK;
+            const int32_t e0 = kid_off[h], na = kid_off[h + 1] - e0;
+            const T vh = v[h];
+            s_po[tid] = (x & MEMBER_P2) ? r1[h] : r2[h];
+#pragma unroll
+            for (int a = 0; a < MAXA; a++)
+                if (a < na) s_diff[tid * MAXA + a] = v[child_of<EXPLICIT>(kid, e0 + a)] - vh;
+        }
+        __syncthreads();
+        if (has_set) {
+            const int32_t lo = max(m0, cbeg), hi = min(m1, cend);
+            for (int32_t k = lo - cbeg; k < hi - cbeg; k++) {
+                const T po = s_po[k];
+#pragma unroll
+                for (int a = 0; a < MAXA; a++)
+                    if (a < nA) r[a] = fma_t(po, s_diff[k * MAXA + a], r[a]);
+            }
+        }
+        __syncthreads();
+    }
+    if (!has_set) return;
+    const T *own = pl == 1 ? r1 : r2;
+    const T sign = pl == 1 ? T(1) : T(-1);
+    const double w = linear ? (double)tcount[0] : 1.0;
+    const double pown = (double)own[mem_node[m0] & MEMBER_NODE_MASK];
     T tot = T(0);
     T Rn[MAXA];
 #pragma unroll
@@ -148,10 +241,20 @@ __global__ void __launch_bounds__(BLOCK) k_average(int32_t I, const int32_t *__r
     }
 }
 
+// dst[i] = src[map i] (map == nullptr: identity)
 template <typename S, typename D>
-__global__ void __launch_bounds__(BLOCK) k_convert(int32_t n, const S *__restrict__ src, D *__restrict__ dst) {
+__global__ void __launch_bounds__(BLOCK) k_gather(int32_t n, const int32_t *__restrict__ map,
+                                                  const S *__restrict__ src, D *__restrict__ dst) {
     int32_t i = (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
-    if (i < n) dst[i] = (D)src[i];
+    if (i < n) dst[i] = (D)src[map ? map[i] : i];
+}
+
+// dst[map i] = src[i] (map == nullptr: identity)
+template <typename S, typename D>
+__global__ void __launch_bounds__(BLOCK) k_scatter(int32_t n, const int32_t *__restrict__ map,
+                                                   const S *__restrict__ src, D *__restrict__ dst) {
+    int32_t i = (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
+    if (i < n) dst[map ? map[i] : i] = (D)src[i];
 }
 
 // ---- best response (FP64) -------------------------------------------------
@@ -168,11 +271,13 @@ __global__ void __launch_bounds__(BLOCK) k_br_forward(int32_t lo, int32_t hi, co
     q[c] = q[u.x] * m;
 }
 
+template <bool EXPLICIT>
 __global__ void __launch_bounds__(BLOCK) k_br_argmax(int32_t ilo, int32_t ihi, const int32_t *__restrict__ slot_off,
                                                      const int32_t *__restrict__ mem_off,
                                                      const int32_t *__restrict__ mem_node,
                                                      const int8_t *__restrict__ iset_player,
-                                                     const int32_t *__restrict__ child_off,
+                                                     const int32_t *__restrict__ kid_off,
+                                                     const int32_t *__restrict__ kid,
                                                      const double *__restrict__ vbr, const double *__restrict__ q,
                                                      int32_t *__restrict__ astar, int br) {
     int32_t i = ilo + (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
@@ -186,15 +291,17 @@ __global__ void __launch_bounds__(BLOCK) k_br_argmax(int32_t ilo, int32_t ihi, c
     for (int a = 0; a < nA; a++) {
         double Q = 0.0;
         for (int32_t m = m0; m < m1; m++) {
-            int32_t h = mem_node[m];
-            Q += q[h] * (sign * vbr[child_off[h] + a]);
+            int32_t h = mem_node[m] & MEMBER_NODE_MASK;
+            Q += q[h] * (sign * vbr[child_of<EXPLICIT>(kid, kid_off[h] + a)]);
         }
         if (a == 0 || Q > bq) { bq = Q; best = a; }
     }
     astar[i] = best;
 }
 
-__global__ void __launch_bounds__(BLOCK) k_br_backward(int32_t lo, int32_t hi, const int32_t *__restrict__ child_off,
+template <bool EXPLICIT>
+__global__ void __launch_bounds__(BLOCK) k_br_backward(int32_t lo, int32_t hi, const int32_t *__restrict__ kid_off,
+                                                       const int32_t *__restrict__ kid,
                                                        const int32_t *__restrict__ node_slot,
                                                        const int32_t *__restrict__ node_iset,
                                                        const int8_t *__restrict__ iset_player,
@@ -203,18 +310,18 @@ __global__ void __launch_bounds__(BLOCK) k_br_backward(int32_t lo, int32_t hi, c
                                                        int br) {
     int32_t h = lo + (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
     if (h >= hi) return;
-    int32_t b = child_off[h], e = child_off[h + 1];
+    int32_t b = kid_off[h], e = kid_off[h + 1];
     if (b == e) return;
     int32_t s = node_slot[h];
     double acc = 0.0;
     if (s < 0) {
-        for (int32_t c = b; c < e; c++) acc += vbr[c];
+        for (int32_t c = b; c < e; c++) acc += vbr[child_of<EXPLICIT>(kid, c)];
     } else {
         int32_t i = node_iset[h];
         if (iset_player[i] == br) {
-            acc = vbr[b + astar[i]];
+            acc = vbr[child_of<EXPLICIT>(kid, b + astar[i])];
         } else {
-            for (int32_t c = b; c < e; c++) acc += sigbar[s + (c - b)] * vbr[c];
+            for (int32_t c = b; c < e; c++) acc += sigbar[s + (c - b)] * vbr[child_of<EXPLICIT>(kid, c)];
         }
     }
     vbr[h] = acc;
@@ -235,32 +342,47 @@ hipError_t launch_forward(const DevGame &g, int32_t lo, int32_t hi, int32_t *tic
     return g.fp64 ? forward_t<double>(g, lo, hi, tick, s) : forward_t<float>(g, lo, hi, tick, s);
 }
 
-template <typename T>
+template <typename T, bool EX>
 static hipError_t backward_t(const DevGame &g, int32_t lo, int32_t hi, hipStream_t s) {
-    hipLaunchKernelGGL(k_backward<T>, dim3(grid_for(hi - lo)), dim3(BLOCK), 0, s, lo, hi, g.child_off, g.node_slot,
-                       (const T *)g.sigma, (T *)g.v);
+    hipLaunchKernelGGL((k_backward<T, EX>), dim3(grid_for(hi - lo)), dim3(BLOCK), 0, s, lo, hi, g.kid_off, g.kid,
+                       g.node_slot, (const T *)g.sigma, (T *)g.v);
     return hipGetLastError();
 }
 
 hipError_t launch_backward(const DevGame &g, int32_t lo, int32_t hi, hipStream_t s) {
     if (hi <= lo) return hipSuccess;
-    return g.fp64 ? backward_t<double>(g, lo, hi, s) : backward_t<float>(g, lo, hi, s);
+    if (g.explicit_kids) return g.fp64 ? backward_t<double, true>(g, lo, hi, s) : backward_t<float, true>(g, lo, hi, s);
+    return g.fp64 ? backward_t<double, false>(g, lo, hi, s) : backward_t<float, false>(g, lo, hi, s);
 }
 
-template <typename T, int MAXA>
+template <typename T, int MAXA, bool EX>
 static hipError_t update_t(const DevGame &g, IterFlags f, hipStream_t s) {
     const T *r = (const T *)g.reach;
-    hipLaunchKernelGGL((k_update<T, MAXA>), dim3(grid_for(g.I)), dim3(BLOCK), 0, s, g.I, g.slot_off, g.mem_off,
-                       g.mem_node, g.iset_player, g.child_off, (const T *)g.v, r, r + g.N, (T *)g.R, g.sbar,
+    hipLaunchKernelGGL((k_update<T, MAXA, EX>), dim3(grid_for(g.I)), dim3(BLOCK), 0, s, g.I, g.slot_off, g.mem_off,
+                       g.mem_node, g.iset_player, g.kid_off, g.kid, (const T *)g.v, r, r + g.N, (T *)g.R, g.sbar,
                        (T *)g.sigma, g.t, f.plus, f.linear);
     return hipGetLastError();
 }
 
+template <typename T, int MAXA, bool EX>
+static hipError_t update_grouped_t(const DevGame &g, IterFlags f, hipStream_t s) {
+    const T *r = (const T *)g.reach;
+    hipLaunchKernelGGL((k_update_grouped<T, MAXA, EX>), dim3(g.G), dim3(BLOCK), 0, s, g.grp_iset_off, g.slot_off,
+                       g.mem_off, g.mem_node, g.iset_player, g.kid_off, g.kid, (const T *)g.v, r, r + g.N, (T *)g.R,
+                       g.sbar, (T *)g.sigma, g.t, f.plus, f.linear);
+    return hipGetLastError();
+}
+
+template <typename T, bool EX>
+static hipError_t update_dispatch_ex(const DevGame &g, IterFlags f, hipStream_t s) {
+    if (g.max_actions <= 4) return update_grouped_t<T, 4, EX>(g, f, s);
+    if (g.max_actions <= 16) return update_grouped_t<T, 16, EX>(g, f, s);
+    return update_t<T, 64, EX>(g, f, s);
+}
+
 template <typename T>
 static hipError_t update_dispatch(const DevGame &g, IterFlags f, hipStream_t s) {
-    if (g.max_actions <= 4) return update_t<T, 4>(g, f, s);
-    if (g.max_actions <= 16) return update_t<T, 16>(g, f, s);
-    return update_t<T, 64>(g, f, s);
+    return g.explicit_kids ? update_dispatch_ex<T, true>(g, f, s) : update_dispatch_ex<T, false>(g, f, s);
 }
 
 hipError_t launch_update(const DevGame &g, IterFlags f, hipStream_t s) {
@@ -286,28 +408,35 @@ hipError_t launch_tick(const DevGame &g, hipStream_t s) {
 
 hipError_t launch_average(const DevGame &g, hipStream_t s) {
     if (g.I == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_average, dim3(grid_for(g.I)), dim3(BLOCK), 0, s, g.I, g.slot_off, g.sbar, g.sigbar, g.out);
+    hipLaunchKernelGGL(k_average, dim3(grid_for(g.I)), dim3(BLOCK), 0, s, g.I, g.slot_off, g.sbar, g.sigbar, g.out2);
     return hipGetLastError();
 }
 
 hipError_t launch_sigma_to_float(const DevGame &g, float *dst, hipStream_t s) {
     if (g.A == 0) return hipSuccess;
     if (g.fp64)
-        hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A,
+        hipLaunchKernelGGL((k_gather<double, float>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, g.slot_map,
                            (const double *)g.sigma, dst);
     else
-        hipLaunchKernelGGL((k_convert<float, float>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A,
+        hipLaunchKernelGGL((k_gather<float, float>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, g.slot_map,
                            (const float *)g.sigma, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_float(const DevGame &g, const float *src, float *dst, hipStream_t s) {
+    if (g.A == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_gather<float, float>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, g.slot_map, src, dst);
     return hipGetLastError();
 }
 
 hipError_t launch_regrets_from_float(const DevGame &g, const float *src, hipStream_t s) {
     if (g.A == 0) return hipSuccess;
     if (g.fp64)
-        hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, src,
+        hipLaunchKernelGGL((k_scatter<float, double>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, g.slot_map, src,
                            (double *)g.R);
     else
-        hipLaunchKernelGGL((k_convert<float, float>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, src, (float *)g.R);
+        hipLaunchKernelGGL((k_scatter<float, float>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, g.slot_map, src,
+                           (float *)g.R);
     return hipGetLastError();
 }
 
@@ -319,15 +448,23 @@ hipError_t launch_br_forward(const DevGame &g, int32_t lo, int32_t hi, int br, h
 
 hipError_t launch_br_argmax(const DevGame &g, int32_t ilo, int32_t ihi, int br, hipStream_t s) {
     if (ihi <= ilo) return hipSuccess;
-    hipLaunchKernelGGL(k_br_argmax, dim3(grid_for(ihi - ilo)), dim3(BLOCK), 0, s, ilo, ihi, g.slot_off, g.mem_off,
-                       g.mem_node, g.iset_player, g.child_off, g.vbr, g.qbr, g.astar, br);
+    if (g.explicit_kids)
+        hipLaunchKernelGGL(k_br_argmax<true>, dim3(grid_for(ihi - ilo)), dim3(BLOCK), 0, s, ilo, ihi, g.slot_off,
+                           g.mem_off, g.mem_node, g.iset_player, g.kid_off, g.kid, g.vbr, g.qbr, g.astar, br);
+    else
+        hipLaunchKernelGGL(k_br_argmax<false>, dim3(grid_for(ihi - ilo)), dim3(BLOCK), 0, s, ilo, ihi, g.slot_off,
+                           g.mem_off, g.mem_node, g.iset_player, g.kid_off, g.kid, g.vbr, g.qbr, g.astar, br);
     return hipGetLastError();
 }
 
 hipError_t launch_br_backward(const DevGame &g, int32_t lo, int32_t hi, int br, hipStream_t s) {
     if (hi <= lo) return hipSuccess;
-    hipLaunchKernelGGL(k_br_backward, dim3(grid_for(hi - lo)), dim3(BLOCK), 0, s, lo, hi, g.child_off, g.node_slot,
-                       g.node_iset, g.iset_player, g.sigbar, g.astar, g.vbr, br);
+    if (g.explicit_kids)
+        hipLaunchKernelGGL(k_br_backward<true>, dim3(grid_for(hi - lo)), dim3(BLOCK), 0, s, lo, hi, g.kid_off, g.kid,
+                           g.node_slot, g.node_iset, g.iset_player, g.sigbar, g.astar, g.vbr, br);
+    else
+        hipLaunchKernelGGL(k_br_backward<false>, dim3(grid_for(hi - lo)), dim3(BLOCK), 0, s, lo, hi, g.kid_off, g.kid,
+                           g.node_slot, g.node_iset, g.iset_player, g.sigbar, g.astar, g.vbr, br);
     return hipGetLastError();
 }
 

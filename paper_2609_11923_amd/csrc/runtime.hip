@@ -42,7 +42,8 @@ struct cfr_handle {
     cfr_options opt{};
     DevGame g{};
     // host copies of the schedule
-    std::vector<int32_t> depth_off, iset_depth_off;
+    std::vector<int32_t> depth_off, int_end, iset_depth_off;
+    std::vector<int32_t> slot_map;     // canonical slot -> device slot (empty: identity)
     int32_t D = 0;
     bool br_ok = true;
     int64_t E = 0, Z = 0;
@@ -96,7 +97,7 @@ cfr_status upload(T *dst, const std::vector<T> &src) {
 // address only; no kernel or copy ever sees a shifted pointer.
 std::vector<const void *> persistent_ptrs(const cfr_handle *h) {
     return {h->R_base + h->rebind[0] * (int64_t)h->es, h->sbar_base + h->rebind[1] * 8,
-            h->sigma_base + h->rebind[2] * (int64_t)h->es, h->g.v, h->g.reach, h->g.t, h->g.up, h->g.child_off,
+            h->sigma_base + h->rebind[2] * (int64_t)h->es, h->g.v, h->g.reach, h->g.t, h->g.up, h->g.kid_off,
             h->g.mem_node};
 }
 
@@ -115,13 +116,13 @@ cfr_status enqueue_iteration(cfr_handle *h, hipStream_t s, int64_t *count, Launc
     }
     for (int d = 1; d <= g.max_depth; d++) {
         HIP_TRY(mark(1));
-        HIP_TRY(launch_forward(g, h->depth_off[d], h->depth_off[d + 1], d == 1 ? g.t : nullptr, s));
+        HIP_TRY(launch_forward(g, h->depth_off[d], h->int_end[d], d == 1 ? g.t : nullptr, s));
         HIP_TRY(mark(-1));
         n++;
     }
     for (int d = g.max_depth - 1; d >= 0; d--) {
         HIP_TRY(mark(2));
-        HIP_TRY(launch_backward(g, h->depth_off[d], h->depth_off[d + 1], s));
+        HIP_TRY(launch_backward(g, h->depth_off[d], h->int_end[d], s));
         HIP_TRY(mark(-1));
         n++;
     }
@@ -132,28 +133,32 @@ cfr_status enqueue_iteration(cfr_handle *h, hipStream_t s, int64_t *count, Launc
 }
 
 // Algorithmic bytes of one iteration per kernel: every index, state and value element a
-// kernel must touch, counted once (sigma gathers count once per slot and pass).
-void model_bytes(cfr_handle *h, const Layout &L) {
+// kernel must touch in the device layout, counted once (sigma gathers count once per slot
+// and pass).  Launch ranges: a level's forward/backward launch covers [depth_off, int_end).
+void model_bytes(cfr_handle *h, const Layout &L, const DeviceLayout &D) {
     const int md = L.max_depth;
-    std::vector<double> Nd(md + 2, 0), Nint(md + 2, 0), Ad(md + 2, 0);
-    for (int d = 0; d <= md; d++) {
-        Nd[d] = L.depth_off[d + 1] - L.depth_off[d];
-        for (int32_t n = L.depth_off[d]; n < L.depth_off[d + 1]; n++) Nint[d] += L.child_off[n + 1] > L.child_off[n];
-        for (int32_t i = L.iset_depth_off[d]; i < L.iset_depth_off[d + 1]; i++) Ad[d] += L.slot_off[i + 1] - L.slot_off[i];
-    }
     const double es = (double)h->es;
+    const double kb = D.explicit_kids ? 4.0 : 0.0;
+    std::vector<double> Nr(md + 2, 0), Nint(md + 2, 0), Ad(md + 2, 0), Nd(md + 2, 0);
+    for (int d = 0; d <= md; d++) {
+        Nd[d] = D.depth_off[d + 1] - D.depth_off[d];
+        Nr[d] = D.int_end[d] - D.depth_off[d];
+        for (int32_t n = D.depth_off[d]; n < D.int_end[d]; n++) Nint[d] += D.kid_off[n + 1] > D.kid_off[n];
+        for (int32_t i = D.iset_depth_off[d]; i < D.iset_depth_off[d + 1]; i++) Ad[d] += D.slot_off[i + 1] - D.slot_off[i];
+    }
     double f = 0, b = 0;
-    for (int d = 1; d <= md; d++) f += 8 * Nd[d] + 2 * es * Nint[d - 1] + 2 * es * Nint[d] + es * Ad[d - 1];
-    for (int d = 0; d < md; d++) b += 4 * (Nd[d] + 1) + 4 * Nd[d] + es * Nint[d] + es * Nd[d + 1] + es * Ad[d];
+    for (int d = 1; d <= md; d++) f += 8 * Nr[d] + 2 * es * Nint[d - 1] + 2 * es * Nint[d] + es * Ad[d - 1];
+    for (int d = 0; d < md; d++) b += 8 * Nr[d] + 4 + (kb + es) * Nd[d + 1] + es * Nint[d] + es * Ad[d];
     double edec = 0;
     for (int64_t i = 0; i < L.I; i++)
         edec += (double)(L.mem_off[i + 1] - L.mem_off[i]) * (L.slot_off[i + 1] - L.slot_off[i]);
     h->bytes_fwd = f;
     h->bytes_bwd = b;
-    // per set: two offsets pairs and the player (17 B) plus the own reach of one member; per member:
-    // its id, child offset, v(h), opponent reach; per decision edge: the child value; per slot:
-    // sigma read and write, R read and write, sbar read and write (FP64)
-    h->bytes_upd = (17.0 + es) * L.I + (8.0 + 2 * es) * L.Ndec + es * edec + (4 * es + 16.0) * L.A;
+    // per set: slot and member offsets and the player (17 B) plus the own reach of one member;
+    // per member: its id, edge offset, v(h) and opponent reach; per decision edge: the child
+    // value (and its child index in explicit layouts); per slot: sigma read and write, R read and
+    // write, sbar read and write (FP64)
+    h->bytes_upd = (17.0 + es) * L.I + (8.0 + 2 * es) * L.Ndec + (es + kb) * edec + (4 * es + 16.0) * L.A;
 }
 
 cfr_status capture(cfr_handle *h, int iters, hipGraph_t *graph, hipGraphExec_t *exec) {
@@ -209,7 +214,7 @@ void cfr_default_options(cfr_options *o) {
     o->averaging = CFR_AVG_LINEAR;
     o->order = CFR_ORDER_SIMULTANEOUS;
     o->iters_per_graph = 1;
-    o->layout = CFR_LAYOUT_BFS;
+    o->layout = CFR_LAYOUT_PUBLIC;
     o->use_graph = 1;
     o->device = 0;
     o->test_fail_capture = 0;
@@ -264,7 +269,7 @@ cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_ha
     if (o.rule != CFR_RULE_CFR_PLUS && o.rule != CFR_RULE_CFR) return fail(CFR_EINVAL, "unknown rule");
     if (o.averaging != CFR_AVG_LINEAR && o.averaging != CFR_AVG_UNIFORM) return fail(CFR_EINVAL, "unknown averaging");
     if (o.order != CFR_ORDER_SIMULTANEOUS) return fail(CFR_EUNSUPPORTED, "alternating updates are not built yet");
-    if (o.layout != CFR_LAYOUT_BFS) return fail(CFR_EUNSUPPORTED, "only the breadth-first layout is built yet");
+    if (o.layout != CFR_LAYOUT_BFS && o.layout != CFR_LAYOUT_PUBLIC) return fail(CFR_EINVAL, "unknown layout");
     if (o.iters_per_graph < 1 || o.iters_per_graph > 1000) return fail(CFR_EINVAL, "iters_per_graph must be in [1, 1000]");
     if (o.precision != CFR_PRECISION_FP32 && o.precision != CFR_PRECISION_FP64) return fail(CFR_EINVAL, "unknown precision");
     Layout L;
@@ -279,8 +284,13 @@ cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_ha
     cfr_handle *h = new cfr_handle();
     h->opt = o;
     h->use_graph = o.use_graph != 0;
-    h->depth_off = L.depth_off;
-    h->iset_depth_off = L.iset_depth_off;
+    DeviceLayout DL;
+    st = build_device_layout(L, o.layout, DL, err);
+    if (st != CFR_OK) { delete h; return fail(st, err); }
+    h->depth_off = DL.depth_off;
+    h->int_end = DL.int_end;
+    h->iset_depth_off = DL.iset_depth_off;
+    h->slot_map = DL.slot_canon_to_dev;
     h->D = L.D;
     h->br_ok = L.br_ok;
     h->E = L.E; h->Z = L.Z; h->pot = game->pot;
@@ -288,32 +298,26 @@ cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_ha
     g.N = (int32_t)L.N; g.I = (int32_t)L.I; g.A = (int32_t)L.A; g.Ndec = (int32_t)L.Ndec;
     g.max_depth = L.max_depth; g.max_actions = L.max_actions;
     g.fp64 = o.precision == CFR_PRECISION_FP64 ? 1 : 0;
+    g.explicit_kids = DL.explicit_kids ? 1 : 0;
     h->es = g.fp64 ? 8 : 4;
     const int64_t N = L.N, I = L.I, A = L.A;
 
-    // node arrays: (parent, edge code), child offsets, per-node first slot and infoset
     std::vector<int2> up((size_t)N);
-    std::vector<int32_t> node_slot((size_t)N, -1);
-    for (int64_t n = 0; n < N; n++) {
-        int32_t p = L.parent[n];
-        int owner = p >= 0 && (L.node_type[p] == CFR_NODE_P1 || L.node_type[p] == CFR_NODE_P2) ? L.node_type[p] : 0;
-        int internal = L.child_off[n + 1] > L.child_off[n] ? CODE_INTERNAL : 0;
-        int slot = owner ? L.in_slot[n] : 0;
-        up[n] = make_int2(p, (slot << CODE_SLOT_SHIFT) | internal | owner);
-        if (L.node_infoset[n] >= 0) node_slot[n] = L.slot_off[L.node_infoset[n]];
-    }
-    // values: terminals hold the template, internal entries are overwritten every iteration
-    std::vector<double> vbr0(L.tmpl64);
+    for (int64_t n = 0; n < N; n++) up[n] = make_int2(DL.up_parent[n], DL.up_code[n]);
 
 #define ALLOC(ptr, n) do { st = dev_alloc(h, &(ptr), (n)); if (st != CFR_OK) { free_handle(h); return st; } } while (0)
     ALLOC(g.up, N);
-    ALLOC(g.child_off, N + 1);
+    ALLOC(g.kid_off, N + 1);
+    if (g.explicit_kids) ALLOC(g.kid, L.E);
+    if (!h->slot_map.empty()) ALLOC(g.slot_map, A);
     ALLOC(g.node_slot, N);
     ALLOC(g.node_iset, N);
     ALLOC(g.slot_off, I + 1);
     ALLOC(g.mem_off, I + 1);
     ALLOC(g.mem_node, L.Ndec);
     ALLOC(g.iset_player, I);
+    g.G = (int32_t)DL.grp_iset_off.size() - 1;
+    ALLOC(g.grp_iset_off, (int64_t)DL.grp_iset_off.size());
     {
         char *pv = nullptr, *pr = nullptr, *ps = nullptr, *pR = nullptr;
         ALLOC(pv, N * (int64_t)h->es);
@@ -329,19 +333,23 @@ cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_ha
     ALLOC(g.sigbar, A);
     ALLOC(g.astar, I);
     ALLOC(g.out, A);
+    ALLOC(g.out2, A);
 #undef ALLOC
     h->R_base = (char *)g.R; h->sbar_base = (char *)g.sbar; h->sigma_base = (char *)g.sigma;
 #define UP(dst, src) do { st = upload(dst, src); if (st != CFR_OK) { free_handle(h); return st; } } while (0)
     UP(g.up, up);
-    UP(g.child_off, L.child_off);
-    UP(g.node_slot, node_slot);
-    UP(g.node_iset, L.node_infoset);
-    UP(g.slot_off, L.slot_off);
-    UP(g.mem_off, L.mem_off);
-    UP(g.mem_node, L.mem_node);
-    UP(g.iset_player, L.iset_player);
-    if (g.fp64) { UP((double *)g.v, L.tmpl64); } else { UP((float *)g.v, L.tmpl); }
-    UP(g.vbr, vbr0);
+    UP(g.kid_off, DL.kid_off);
+    if (g.explicit_kids) UP(g.kid, DL.kid);
+    if (g.slot_map) UP(g.slot_map, h->slot_map);
+    UP(g.node_slot, DL.node_slot);
+    UP(g.node_iset, DL.node_iset);
+    UP(g.slot_off, DL.slot_off);
+    UP(g.mem_off, DL.mem_off);
+    UP(g.mem_node, DL.mem_node);
+    UP(g.iset_player, DL.iset_player);
+    UP(g.grp_iset_off, DL.grp_iset_off);
+    if (g.fp64) { UP((double *)g.v, DL.tmpl64); } else { UP((float *)g.v, DL.tmpl); }
+    UP(g.vbr, DL.tmpl64);
 #undef UP
     {
         // root reach = 1 in both lanes and in the best-response lane; written once, never overwritten
@@ -361,7 +369,7 @@ cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_ha
         nl = (h->D == 0 ? 1 : 0) + 2 * (int64_t)g.max_depth + (g.I > 0 ? 1 : 0);
     }
     h->launches = nl;
-    model_bytes(h, L);
+    model_bytes(h, L, DL);
     st = cfr_reset(h);
     if (st != CFR_OK) { free_handle(h); return st; }
     *out = h;
@@ -450,8 +458,12 @@ cfr_status cfr_strategy(cfr_handle *h, int which, float *dst, int64_t len, int d
     HIP_TRY(hipSetDevice(h->opt.device));
     hipStream_t s = (hipStream_t)stream;
     const float *src = h->g.out;
-    if (which == CFR_STRATEGY_AVERAGE) HIP_TRY(launch_average(h->g, s));
-    else HIP_TRY(launch_sigma_to_float(h->g, h->g.out, s));
+    if (which == CFR_STRATEGY_AVERAGE) {
+        HIP_TRY(launch_average(h->g, s));                    // device order into out2
+        HIP_TRY(launch_gather_float(h->g, h->g.out2, h->g.out, s));
+    } else {
+        HIP_TRY(launch_sigma_to_float(h->g, h->g.out, s));   // gathers into canonical order
+    }
     HIP_TRY(hipMemcpyAsync(dst, src, (size_t)len * sizeof(float),
                            dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
     if (!dst_on_device) HIP_TRY(hipStreamSynchronize(s));
@@ -464,20 +476,25 @@ cfr_status cfr_get_state(cfr_handle *h, double *regrets, double *strategy_sum, i
     HIP_TRY(hipSetDevice(h->opt.device));
     hipStream_t s = (hipStream_t)stream;
     if (len == 0) return CFR_OK;
-    std::vector<float> tmp;
+    std::vector<double> rd((size_t)len), sd((size_t)len);
+    std::vector<float> rf;
     if (regrets) {
         if (h->g.fp64) {
-            HIP_TRY(hipMemcpyAsync(regrets, h->g.R, (size_t)len * 8, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(rd.data(), h->g.R, (size_t)len * 8, hipMemcpyDeviceToHost, s));
         } else {
-            tmp.resize((size_t)len);
-            HIP_TRY(hipMemcpyAsync(tmp.data(), h->g.R, (size_t)len * 4, hipMemcpyDeviceToHost, s));
+            rf.resize((size_t)len);
+            HIP_TRY(hipMemcpyAsync(rf.data(), h->g.R, (size_t)len * 4, hipMemcpyDeviceToHost, s));
         }
     }
     if (strategy_sum)
-        HIP_TRY(hipMemcpyAsync(strategy_sum, h->g.sbar, (size_t)len * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(sd.data(), h->g.sbar, (size_t)len * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (regrets && !h->g.fp64)
-        for (int64_t q = 0; q < len; q++) regrets[q] = (double)tmp[(size_t)q];
+    const bool ident = h->slot_map.empty();
+    for (int64_t q = 0; q < len; q++) {
+        const size_t dq = ident ? (size_t)q : (size_t)h->slot_map[(size_t)q];
+        if (regrets) regrets[q] = h->g.fp64 ? rd[dq] : (double)rf[dq];
+        if (strategy_sum) strategy_sum[q] = sd[dq];
+    }
     return CFR_OK;
 }
 
@@ -508,10 +525,10 @@ cfr_status cfr_exploitability(cfr_handle *h, void *stream, double *expl, double 
     for (int k = 0; k < 3; k++) {
         const int br = order[k];
         if (br != 0)
-            for (int d = 1; d <= g.max_depth; d++) HIP_TRY(launch_br_forward(g, h->depth_off[d], h->depth_off[d + 1], br, s));
+            for (int d = 1; d <= g.max_depth; d++) HIP_TRY(launch_br_forward(g, h->depth_off[d], h->int_end[d], br, s));
         for (int d = g.max_depth - 1; d >= 0; d--) {
             if (br != 0) HIP_TRY(launch_br_argmax(g, h->iset_depth_off[d], h->iset_depth_off[d + 1], br, s));
-            HIP_TRY(launch_br_backward(g, h->depth_off[d], h->depth_off[d + 1], br, s));
+            HIP_TRY(launch_br_backward(g, h->depth_off[d], h->int_end[d], br, s));
         }
         double root = 0.0;
         HIP_TRY(hipMemcpyAsync(&root, g.vbr, sizeof(double), hipMemcpyDeviceToHost, s));

@@ -134,4 +134,5 @@ def test_options_rejected_before_device():
 
 def test_default_options():
     o = cfr.cfr_default_options()
-    assert (o.rule, o.averaging, o.order, o.iters_per_graph, o.layout, o.use_graph) == (0, 0, 0, 1, 0, 1)
+    assert (o.rule, o.averaging, o.order, o.iters_per_graph, o.layout, o.use_graph, o.precision) == \
+        (0, 0, 0, 1, cfr.CFR_LAYOUT_PUBLIC, 1, cfr.CFR_PRECISION_FP32)

@@ -96,28 +96,35 @@ def check(game, s, o, T, plus=True, linear=True, precision="fp64", current=True)
         assert (R >= 0).all()
 
 
+LAYOUTS = {"public": cfr.CFR_LAYOUT_PUBLIC, "bfs": cfr.CFR_LAYOUT_BFS}
+
+
+@pytest.mark.parametrize("layout", list(LAYOUTS))
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("name", list(GAMES))
 @pytest.mark.parametrize("plus,linear", [(True, True), (True, False), (False, True), (False, False)])
-def test_parity_small(name, plus, linear, precision):
+def test_parity_small(name, plus, linear, precision, layout):
     game = GAMES[name]()
-    s, o = run_pair(game, 100, plus, linear, precision)
+    s, o = run_pair(game, 100, plus, linear, precision, layout=LAYOUTS[layout])
     check(game, s, o, 100, plus, linear, precision)
 
 
+@pytest.mark.parametrize("layout", list(LAYOUTS))
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_parity_c1_full_size(precision):
+def test_parity_c1_full_size(precision, layout):
     """The mid game at its full size: 13 ranks x 2 suits, 1,179,777 nodes."""
     game = gg.leduc(13, 2)
-    s, o = run_pair(game, 100, precision=precision)
+    s, o = run_pair(game, 100, precision=precision, layout=LAYOUTS[layout])
     check(game, s, o, 100, precision=precision, current=False)
 
 
+@pytest.mark.parametrize("layout", list(LAYOUTS))
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_parity_large_one_pair(precision):
-    """The large game's generator at one hand pair (2.5M nodes, 13 levels)."""
-    game = gg.large(1, seed=0)
-    s, o = run_pair(game, 100, precision=precision)
+def test_parity_large_small_hands(precision, layout):
+    """The large game's generator at two hands per player (about 10M nodes, 13 levels; several hand
+    pairs, so information sets have several members)."""
+    game = gg.large(2, seed=0)
+    s, o = run_pair(game, 100, precision=precision, layout=LAYOUTS[layout])
     check(game, s, o, 100, precision=precision, current=False)
 
 
@@ -136,10 +143,11 @@ def _state(s):
     return R.copy(), S.copy(), s.strategy().copy()
 
 
-def test_graph_equals_direct_bitwise():
+@pytest.mark.parametrize("layout", list(LAYOUTS))
+def test_graph_equals_direct_bitwise(layout):
     game = gg.leduc(3, 2)
-    a = cfr.Solver(game, use_graph=True)
-    b = cfr.Solver(game, use_graph=False)
+    a = cfr.Solver(game, use_graph=True, layout=LAYOUTS[layout])
+    b = cfr.Solver(game, use_graph=False, layout=LAYOUTS[layout])
     a.iterate(30)
     b.iterate(30)
     for x, y in zip(_state(a), _state(b)):
@@ -237,12 +245,13 @@ def test_launch_count_gate():
         assert c["kernels_per_iteration"] <= 40 + 10 * c["blocks"]
 
 
-def test_warm_start_regrets():
+@pytest.mark.parametrize("layout", list(LAYOUTS))
+def test_warm_start_regrets(layout):
     game = gg.leduc(3, 2)
     o = oracle.Oracle(game)
     rng = np.random.default_rng(5)
     R0 = np.round(rng.random(o.A) * 4.0, 3).astype(np.float32)
-    s = cfr.Solver(game, precision=cfr.CFR_PRECISION_FP64)
+    s = cfr.Solver(game, precision=cfr.CFR_PRECISION_FP64, layout=LAYOUTS[layout])
     s.set_regrets(R0)
     o.set_state(R=R0.astype(np.float64), sbar=np.zeros(o.A), t=0)
     s.iterate(50)
@@ -253,13 +262,18 @@ def test_warm_start_regrets():
     assert rel_err(s.strategy(average=True), sao) <= TOL
 
 
-def test_device_strategy_output():
+@pytest.mark.parametrize("layout", list(LAYOUTS))
+def test_device_strategy_output(layout):
     torch = pytest.importorskip("torch")
     game = gg.leduc(3, 2)
-    s = cfr.Solver(game)
+    s = cfr.Solver(game, layout=LAYOUTS[layout])
     stream = torch.cuda.Stream()
     s.iterate(10, stream=stream)
     out = torch.empty(s.A, dtype=torch.float32, device="cuda")
     s.strategy_into(out, average=True, stream=stream)
     stream.synchronize()
     assert np.array_equal(out.cpu().numpy(), s.strategy(average=True))
+    cur = torch.empty(s.A, dtype=torch.float32, device="cuda")
+    s.strategy_into(cur, average=False, stream=stream)
+    stream.synchronize()
+    assert np.array_equal(cur.cpu().numpy(), s.strategy(average=False))
