@@ -269,15 +269,18 @@ cfr_status build_device_layout(const Layout &L, int kind, DeviceLayout &D, std::
                         rank[j] = r;
                     }
                 }
-                // stable counting sort by (terminal, rank)
-                count.assign((size_t)2 * R + 1, 0);
-                for (int64_t j = 0; j < n; j++) count[(internal(lo + j) ? 0 : R) + rank[j] + 1]++;
-                for (int64_t b = 0; b < 2 * R; b++) count[b + 1] += count[b];
+                // stable counting sort by (class, rank): decision, chance, terminal
+                auto cls = [&](int64_t k) -> int64_t {
+                    int t = L.node_type[k];
+                    return t == CFR_NODE_TERMINAL ? 2 : (t == CFR_NODE_CHANCE ? 1 : 0);
+                };
+                count.assign((size_t)3 * R + 1, 0);
+                for (int64_t j = 0; j < n; j++) count[cls(lo + j) * R + rank[j] + 1]++;
+                for (int64_t b = 0; b < 3 * R; b++) count[b + 1] += count[b];
                 int64_t n_int = 0;
                 for (int64_t j = 0; j < n; j++) {
-                    bool in = internal(lo + j);
-                    n_int += in;
-                    int64_t pos = count[(in ? 0 : R) + rank[j]]++;
+                    n_int += internal(lo + j);
+                    int64_t pos = count[cls(lo + j) * R + rank[j]]++;
                     perm[lo + j] = (int32_t)(lo + pos);
                     inv[lo + pos] = (int32_t)(lo + j);
                 }
@@ -370,19 +373,29 @@ cfr_status build_device_layout(const Layout &L, int kind, DeviceLayout &D, std::
             }
         }
         D.kid_off[N] = pub ? e : L.child_off[N];
-        // update groups in device information-set order
+        // update groups in device information-set order, never spanning two depths
         D.grp_iset_off.assign(1, 0);
-        {
+        D.grp_depth_off.assign((size_t)md + 2, 0);
+        for (int d = 0; d <= md; d++) {
             int32_t members = 0, sets = 0;
-            for (int64_t i = 0; i < I; i++) {
+            for (int32_t i = D.iset_depth_off[d]; i < D.iset_depth_off[d + 1]; i++) {
                 int32_t m = D.mem_off[i + 1] - D.mem_off[i];
                 if (sets > 0 && (members + m > GROUP_MEMBERS || sets + 1 > GROUP_SETS)) {
-                    D.grp_iset_off.push_back((int32_t)i);
+                    D.grp_iset_off.push_back(i);
                     members = 0; sets = 0;
                 }
                 members += m; sets++;
             }
-            if (sets > 0) D.grp_iset_off.push_back((int32_t)I);
+            if (sets > 0) D.grp_iset_off.push_back(D.iset_depth_off[d + 1]);
+            D.grp_depth_off[d + 1] = (int32_t)D.grp_iset_off.size() - 1;
+        }
+        // internal chance nodes by depth
+        D.chance_off.assign((size_t)md + 2, 0);
+        D.chance_node.clear();
+        for (int d = 0; d <= md; d++) {
+            for (int32_t x = D.depth_off[d]; x < D.int_end[d]; x++)
+                if (L.node_type[inv[x]] == CFR_NODE_CHANCE && D.kid_off[x + 1] > D.kid_off[x]) D.chance_node.push_back(x);
+            D.chance_off[d + 1] = (int32_t)D.chance_node.size();
         }
         return CFR_OK;
     } catch (const std::bad_alloc &) {

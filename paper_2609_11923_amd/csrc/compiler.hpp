@@ -43,8 +43,9 @@ cfr_status build_layout(const cfr_game_desc *g, Layout &out, std::string &err);
 // each depth the nodes are permuted:
 //   BFS     canonical order (children of a node are consecutive ids, so child lists stay
 //           implicit: child a of h is kid_off[h] + a)
-//   PUBLIC  internal nodes first, then terminals; each part grouped by public state (states
-//           ranked by first occurrence in canonical order), canonical order inside a group.
+//   PUBLIC  decision nodes first, then chance nodes, then terminals; each part grouped by public
+//           state (states ranked by first occurrence in canonical order), canonical order inside
+//           a group.
 //           Members of an information set then sit in one public-state block, children of a
 //           block's nodes sit in the child states' blocks at the same rank, and every write of
 //           a level pass lands in one dense range.  Child lists are explicit (kid[]).
@@ -66,10 +67,15 @@ struct DeviceLayout {
     std::vector<float> tmpl;             // [N]
     std::vector<double> tmpl64;          // [N]
     std::vector<int32_t> slot_canon_to_dev; // [A], empty when identical
-    // update groups: runs of consecutive information sets with at most GROUP_MEMBERS members and
-    // at most GROUP_SETS sets in total (a set with more members forms a group of its own);
-    // group g holds sets [grp_iset_off[g], grp_iset_off[g + 1])
+    // update groups: runs of consecutive information sets of one depth with at most GROUP_MEMBERS
+    // members and at most GROUP_SETS sets in total (a set with more members forms a group of its
+    // own); group g holds sets [grp_iset_off[g], grp_iset_off[g + 1]); the groups of depth d are
+    // [grp_depth_off[d], grp_depth_off[d + 1])
     std::vector<int32_t> grp_iset_off;
+    std::vector<int32_t> grp_depth_off;  // [max_depth + 2]
+    // internal chance nodes by depth: chance_node[chance_off[d] .. chance_off[d + 1])
+    std::vector<int32_t> chance_node;
+    std::vector<int32_t> chance_off;     // [max_depth + 2]
 };
 
 constexpr int GROUP_MEMBERS = 256;

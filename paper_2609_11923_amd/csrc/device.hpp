@@ -33,6 +33,10 @@ struct DevGame {
     int8_t *iset_player = nullptr;// [I]
     int32_t G = 0;                // update groups
     int32_t *grp_iset_off = nullptr; // [G+1]
+    // host copies of per-depth ranges (launch parameters)
+    const int32_t *grp_depth_off = nullptr;  // [max_depth+2] groups of depth d
+    const int32_t *chance_off = nullptr;     // [max_depth+2] chance nodes of depth d
+    int32_t *chance_node = nullptr;          // device: internal chance nodes by depth
     // iteration state, element type float or double (fp64)
     void *v = nullptr;            // [N]   player-1 chance-weighted values; terminals hold the template
     void *reach = nullptr;        // [2N]  lane 0: player 1 reach, lane 1: player 2 reach
@@ -56,10 +60,9 @@ struct IterFlags {
 
 // one level of the forward reach pass: nodes [lo, hi) of one depth; tick != nullptr bumps the counter
 hipError_t launch_forward(const DevGame &g, int32_t lo, int32_t hi, int32_t *tick, hipStream_t s);
-// one level of the backward value pass: nodes [lo, hi) of one depth
-hipError_t launch_backward(const DevGame &g, int32_t lo, int32_t hi, hipStream_t s);
-// regrets, clamp, average, and regret matching of the next strategy, all information sets
-hipError_t launch_update(const DevGame &g, IterFlags f, hipStream_t s);
+// one level of the backward value pass fused with the update of the information sets on it
+// (regrets, clamp, average, regret matching of the next strategy)
+hipError_t launch_level(const DevGame &g, int d, IterFlags f, hipStream_t s);
 // sigma <- regret matching of R (all information sets)
 hipError_t launch_regret_matching(const DevGame &g, hipStream_t s);
 // counter bump for games without edges

@@ -52,128 +52,97 @@ __global__ void __launch_bounds__(BLOCK) k_forward(int32_t lo, int32_t hi, const
     r2[c] = owner == 2 ? b * s : b;
 }
 
-template <typename T, bool EXPLICIT>
-__global__ void __launch_bounds__(BLOCK) k_backward(int32_t lo, int32_t hi, const int32_t *__restrict__ kid_off,
-                                                    const int32_t *__restrict__ kid,
-                                                    const int32_t *__restrict__ node_slot,
-                                                    const T *__restrict__ sigma, T *__restrict__ v) {
-    int32_t h = lo + (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
-    if (h >= hi) return;
-    int32_t b = kid_off[h], e = kid_off[h + 1];
-    if (b == e) return;
-    int32_t s = node_slot[h];
-    T acc = T(0);
-    if (s < 0) {
-        for (int32_t c = b; c < e; c++) acc += v[child_of<EXPLICIT>(kid, c)];
-    } else {
-        for (int32_t c = b; c < e; c++) acc = fma_t(sigma[s + (c - b)], v[child_of<EXPLICIT>(kid, c)], acc);
-    }
-    v[h] = acc;
-}
-
+// One backward level fused with the regret / average / regret-matching update of the
+// information sets on that level.  Launched once per depth d (deepest first) with
+//   blocks [0, ngroups)            one update group each: consecutive information sets of depth d
+//                                  with at most BLOCK members and BLOCK sets in total
+//   blocks [ngroups, ...)          one thread per internal chance node of depth d
+// Group blocks, phase 1 (one thread per member h, coalesced over the member list):
+//   v(h) = sum_a sigma^t(I, a) v(h.a)   -- written to v, the backward value pass at h
+//   stage pi_{-i}(h) and v(h.a) - v(h) in LDS.
+// Phase 2 (one thread per set I): reduce the set's members from LDS in ascending member order,
+//   r(I,a) = sum_h s_i pi_{-i}(h) (v(h.a) - v(h)), then R <- R + r (CFR+: max(R, 0)),
+//   sbar += w_t pi_i(I) sigma^t (FP64), sigma^{t+1} = regret matching of R.
+// Only this block reads sigma(I) during the backward pass (all members of I are here), and the
+// forward pass has already consumed it, so overwriting sigma(I) with sigma^{t+1} is safe.
+// Sets with more than BLOCK members are streamed through LDS in chunks.
 template <typename T, int MAXA, bool EXPLICIT>
-__global__ void __launch_bounds__(BLOCK) k_update(int32_t I, const int32_t *__restrict__ slot_off,
-                                                  const int32_t *__restrict__ mem_off,
-                                                  const int32_t *__restrict__ mem_node,
-                                                  const int8_t *__restrict__ iset_player,
-                                                  const int32_t *__restrict__ kid_off,
-                                                  const int32_t *__restrict__ kid,
-                                                  const T *__restrict__ v, const T *__restrict__ r1,
-                                                  const T *__restrict__ r2, T *__restrict__ R,
-                                                  double *__restrict__ sbar, T *__restrict__ sigma,
-                                                  const int32_t *__restrict__ tcount, int plus, int linear) {
-    int32_t i = (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
-    if (i >= I) return;
-    int32_t s0 = slot_off[i], nA = slot_off[i + 1] - s0;
-    int32_t m0 = mem_off[i], m1 = mem_off[i + 1];
-    int pl = iset_player[i];
-    const T *opp = pl == 1 ? r2 : r1;
-    const T *own = pl == 1 ? r1 : r2;
-    T r[MAXA];
-#pragma unroll
-    for (int a = 0; a < MAXA; a++) r[a] = T(0);
-    for (int32_t m = m0; m < m1; m++) {
-        int32_t h = mem_node[m] & MEMBER_NODE_MASK;
-        int32_t cb = kid_off[h];
-        T vh = v[h], po = opp[h];
-#pragma unroll
-        for (int a = 0; a < MAXA; a++)
-            if (a < nA) r[a] = fma_t(po, v[child_of<EXPLICIT>(kid, cb + a)] - vh, r[a]);
-    }
-    const T sign = pl == 1 ? T(1) : T(-1);
-    const double w = linear ? (double)tcount[0] : 1.0;
-    const double pown = (double)own[mem_node[m0] & MEMBER_NODE_MASK];
-    T tot = T(0);
-    T Rn[MAXA];
-#pragma unroll
-    for (int a = 0; a < MAXA; a++) {
-        if (a < nA) {
-            int32_t q = s0 + a;
-            sbar[q] += w * pown * (double)sigma[q];
-            T x = fma_t(sign, r[a], R[q]);
-            if (plus) x = max_t(x, T(0));
-            R[q] = x;
-            Rn[a] = max_t(x, T(0));
-            tot += Rn[a];
-        }
-    }
-    const T inv = tot > T(0) ? T(1) / tot : T(0);
-    const T uni = T(1) / (T)nA;
-#pragma unroll
-    for (int a = 0; a < MAXA; a++)
-        if (a < nA) sigma[s0 + a] = tot > T(0) ? Rn[a] * inv : uni;
-}
-
-// Grouped update: one workgroup per group of consecutive information sets (at most BLOCK members
-// and BLOCK sets).  Phase 1 stages, for every member h (one thread each, coalesced over the
-// member list), the opponent reach pi_{-i}(h) and the value differences v(h.a) - v(h) in LDS.
-// Phase 2 gives each set one thread that reduces its members from LDS in ascending member order
-// -- the same fused multiply-add chain as a per-set loop -- and then applies the regret, clamp,
-// average and regret-matching step to the set's slots.  Sets with more than BLOCK members are
-// streamed through LDS in chunks.  Member entries carry the owner in bit 31 (MEMBER_P2).
-template <typename T, int MAXA, bool EXPLICIT>
-__global__ void __launch_bounds__(BLOCK) k_update_grouped(
+__global__ void __launch_bounds__(BLOCK) k_level(
+    int32_t gbeg, int32_t ngroups, const int32_t *__restrict__ chance_node, int32_t cbeg, int32_t nchance,
     const int32_t *__restrict__ grp_iset_off, const int32_t *__restrict__ slot_off,
     const int32_t *__restrict__ mem_off, const int32_t *__restrict__ mem_node, const int8_t *__restrict__ iset_player,
-    const int32_t *__restrict__ kid_off, const int32_t *__restrict__ kid, const T *__restrict__ v,
+    const int32_t *__restrict__ kid_off, const int32_t *__restrict__ kid, T *__restrict__ v,
     const T *__restrict__ r1, const T *__restrict__ r2, T *__restrict__ R, double *__restrict__ sbar,
     T *__restrict__ sigma, const int32_t *__restrict__ tcount, int plus, int linear) {
+    const int tid = threadIdx.x;
+    if ((int32_t)blockIdx.x >= ngroups) {
+        const int32_t j = ((int32_t)blockIdx.x - ngroups) * BLOCK + tid;
+        if (j >= nchance) return;
+        const int32_t h = chance_node[cbeg + j];
+        const int32_t b = kid_off[h], e = kid_off[h + 1];
+        T acc = T(0);
+        for (int32_t c = b; c < e; c++) acc += v[child_of<EXPLICIT>(kid, c)];
+        v[h] = acc;
+        return;
+    }
     __shared__ T s_po[BLOCK];
     __shared__ T s_diff[BLOCK * MAXA];
-    const int32_t g = blockIdx.x;
+    __shared__ int32_t s_moff[BLOCK + 1];
+    __shared__ int32_t s_slot[BLOCK];
+    const int32_t g = gbeg + (int32_t)blockIdx.x;
     const int32_t i0 = grp_iset_off[g], i1 = grp_iset_off[g + 1];
-    const int32_t mbeg = mem_off[i0], mend = mem_off[i1];
-    const int tid = threadIdx.x;
-    const int32_t my = i0 + tid;
-    const bool has_set = my < i1;
+    const int32_t nsets = i1 - i0;
+    if (tid < nsets) {
+        s_moff[tid] = mem_off[i0 + tid];
+        s_slot[tid] = slot_off[i0 + tid];
+    }
+    if (tid == 0) s_moff[nsets] = mem_off[i1];
+    __syncthreads();
+    const int32_t mbeg = s_moff[0], mend = s_moff[nsets];
+    const bool has_set = tid < nsets;
     int32_t s0 = 0, nA = 0, m0 = 0, m1 = 0, pl = 1;
     if (has_set) {
-        s0 = slot_off[my];
-        nA = slot_off[my + 1] - s0;
-        m0 = mem_off[my];
-        m1 = mem_off[my + 1];
-        pl = iset_player[my];
+        s0 = s_slot[tid];
+        nA = slot_off[i0 + tid + 1] - s0;
+        m0 = s_moff[tid];
+        m1 = s_moff[tid + 1];
+        pl = iset_player[i0 + tid];
     }
     T r[MAXA];
 #pragma unroll
     for (int a = 0; a < MAXA; a++) r[a] = T(0);
-    for (int32_t cbeg = mbeg; cbeg < mend; cbeg += BLOCK) {
-        const int32_t cend = min(cbeg + BLOCK, mend);
-        const int32_t m = cbeg + tid;
-        if (m < cend) {
+    for (int32_t cb = mbeg; cb < mend; cb += BLOCK) {
+        const int32_t ce = min(cb + BLOCK, mend);
+        const int32_t m = cb + tid;
+        if (m < ce) {
+            // the set of member m: the last j with s_moff[j] <= m
+            int32_t lo = 0, hi = nsets - 1;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (s_moff[mid] <= m) lo = mid; else hi = mid - 1;
+            }
+            const int32_t sb = s_slot[lo];
             const int32_t x = mem_node[m];
             const int32_t h = x & MEMBER_NODE_MASK;
             const int32_t e0 = kid_off[h], na = kid_off[h + 1] - e0;
-            const T vh = v[h];
+            T cv[MAXA];
+            T vh = T(0);
+#pragma unroll
+            for (int a = 0; a < MAXA; a++)
+                if (a < na) {
+                    cv[a] = v[child_of<EXPLICIT>(kid, e0 + a)];
+                    vh = fma_t(sigma[sb + a], cv[a], vh);
+                }
+            v[h] = vh;
             s_po[tid] = (x & MEMBER_P2) ? r1[h] : r2[h];
 #pragma unroll
             for (int a = 0; a < MAXA; a++)
-                if (a < na) s_diff[tid * MAXA + a] = v[child_of<EXPLICIT>(kid, e0 + a)] - vh;
+                if (a < na) s_diff[tid * MAXA + a] = cv[a] - vh;
         }
         __syncthreads();
         if (has_set) {
-            const int32_t lo = max(m0, cbeg), hi = min(m1, cend);
-            for (int32_t k = lo - cbeg; k < hi - cbeg; k++) {
+            const int32_t lo = max(m0, cb), hi = min(m1, ce);
+            for (int32_t k = lo - cb; k < hi - cb; k++) {
                 const T po = s_po[k];
 #pragma unroll
                 for (int a = 0; a < MAXA; a++)
@@ -192,7 +161,7 @@ __global__ void __launch_bounds__(BLOCK) k_update_grouped(
 #pragma unroll
     for (int a = 0; a < MAXA; a++) {
         if (a < nA) {
-            int32_t q = s0 + a;
+            const int32_t q = s0 + a;
             sbar[q] += w * pown * (double)sigma[q];
             T x = fma_t(sign, r[a], R[q]);
             if (plus) x = max_t(x, T(0));
@@ -332,62 +301,44 @@ __global__ void __launch_bounds__(BLOCK) k_br_backward(int32_t lo, int32_t hi, c
 template <typename T>
 static hipError_t forward_t(const DevGame &g, int32_t lo, int32_t hi, int32_t *tick, hipStream_t s) {
     T *r = (T *)g.reach;
-    hipLaunchKernelGGL(k_forward<T>, dim3(grid_for(hi - lo)), dim3(BLOCK), 0, s, lo, hi, g.up, (const T *)g.sigma, r,
+    const unsigned blocks = hi > lo ? grid_for(hi - lo) : 1u;   // one block still runs the counter bump
+    hipLaunchKernelGGL(k_forward<T>, dim3(blocks), dim3(BLOCK), 0, s, lo, hi, g.up, (const T *)g.sigma, r,
                        r + g.N, tick);
     return hipGetLastError();
 }
 
 hipError_t launch_forward(const DevGame &g, int32_t lo, int32_t hi, int32_t *tick, hipStream_t s) {
-    if (hi <= lo) return hipSuccess;
+    if (hi <= lo && !tick) return hipSuccess;
     return g.fp64 ? forward_t<double>(g, lo, hi, tick, s) : forward_t<float>(g, lo, hi, tick, s);
 }
 
-template <typename T, bool EX>
-static hipError_t backward_t(const DevGame &g, int32_t lo, int32_t hi, hipStream_t s) {
-    hipLaunchKernelGGL((k_backward<T, EX>), dim3(grid_for(hi - lo)), dim3(BLOCK), 0, s, lo, hi, g.kid_off, g.kid,
-                       g.node_slot, (const T *)g.sigma, (T *)g.v);
-    return hipGetLastError();
-}
-
-hipError_t launch_backward(const DevGame &g, int32_t lo, int32_t hi, hipStream_t s) {
-    if (hi <= lo) return hipSuccess;
-    if (g.explicit_kids) return g.fp64 ? backward_t<double, true>(g, lo, hi, s) : backward_t<float, true>(g, lo, hi, s);
-    return g.fp64 ? backward_t<double, false>(g, lo, hi, s) : backward_t<float, false>(g, lo, hi, s);
-}
-
 template <typename T, int MAXA, bool EX>
-static hipError_t update_t(const DevGame &g, IterFlags f, hipStream_t s) {
+static hipError_t level_t(const DevGame &g, int d, IterFlags f, hipStream_t s) {
+    const int32_t gbeg = g.grp_depth_off[d], ng = g.grp_depth_off[d + 1] - gbeg;
+    const int32_t cbeg = g.chance_off[d], nc = g.chance_off[d + 1] - cbeg;
+    const unsigned blocks = (unsigned)ng + grid_for(nc);
+    if (blocks == 0) return hipSuccess;
     const T *r = (const T *)g.reach;
-    hipLaunchKernelGGL((k_update<T, MAXA, EX>), dim3(grid_for(g.I)), dim3(BLOCK), 0, s, g.I, g.slot_off, g.mem_off,
-                       g.mem_node, g.iset_player, g.kid_off, g.kid, (const T *)g.v, r, r + g.N, (T *)g.R, g.sbar,
-                       (T *)g.sigma, g.t, f.plus, f.linear);
-    return hipGetLastError();
-}
-
-template <typename T, int MAXA, bool EX>
-static hipError_t update_grouped_t(const DevGame &g, IterFlags f, hipStream_t s) {
-    const T *r = (const T *)g.reach;
-    hipLaunchKernelGGL((k_update_grouped<T, MAXA, EX>), dim3(g.G), dim3(BLOCK), 0, s, g.grp_iset_off, g.slot_off,
-                       g.mem_off, g.mem_node, g.iset_player, g.kid_off, g.kid, (const T *)g.v, r, r + g.N, (T *)g.R,
-                       g.sbar, (T *)g.sigma, g.t, f.plus, f.linear);
+    hipLaunchKernelGGL((k_level<T, MAXA, EX>), dim3(blocks), dim3(BLOCK), 0, s, gbeg, ng, g.chance_node, cbeg, nc,
+                       g.grp_iset_off, g.slot_off, g.mem_off, g.mem_node, g.iset_player, g.kid_off, g.kid, (T *)g.v, r,
+                       r + g.N, (T *)g.R, g.sbar, (T *)g.sigma, g.t, f.plus, f.linear);
     return hipGetLastError();
 }
 
 template <typename T, bool EX>
-static hipError_t update_dispatch_ex(const DevGame &g, IterFlags f, hipStream_t s) {
-    if (g.max_actions <= 4) return update_grouped_t<T, 4, EX>(g, f, s);
-    if (g.max_actions <= 16) return update_grouped_t<T, 16, EX>(g, f, s);
-    return update_t<T, 64, EX>(g, f, s);
+static hipError_t level_dispatch_ex(const DevGame &g, int d, IterFlags f, hipStream_t s) {
+    if (g.max_actions <= 4) return level_t<T, 4, EX>(g, d, f, s);
+    if (g.max_actions <= 16) return level_t<T, 16, EX>(g, d, f, s);
+    return level_t<T, 64, EX>(g, d, f, s);
 }
 
 template <typename T>
-static hipError_t update_dispatch(const DevGame &g, IterFlags f, hipStream_t s) {
-    return g.explicit_kids ? update_dispatch_ex<T, true>(g, f, s) : update_dispatch_ex<T, false>(g, f, s);
+static hipError_t level_dispatch(const DevGame &g, int d, IterFlags f, hipStream_t s) {
+    return g.explicit_kids ? level_dispatch_ex<T, true>(g, d, f, s) : level_dispatch_ex<T, false>(g, d, f, s);
 }
 
-hipError_t launch_update(const DevGame &g, IterFlags f, hipStream_t s) {
-    if (g.I == 0) return hipSuccess;
-    return g.fp64 ? update_dispatch<double>(g, f, s) : update_dispatch<float>(g, f, s);
+hipError_t launch_level(const DevGame &g, int d, IterFlags f, hipStream_t s) {
+    return g.fp64 ? level_dispatch<double>(g, d, f, s) : level_dispatch<float>(g, d, f, s);
 }
 
 hipError_t launch_regret_matching(const DevGame &g, hipStream_t s) {

@@ -42,7 +42,9 @@ struct cfr_handle {
     cfr_options opt{};
     DevGame g{};
     // host copies of the schedule
-    std::vector<int32_t> depth_off, int_end, iset_depth_off;
+    std::vector<int32_t> depth_off, int_end, iset_depth_off, grp_depth_off, chance_off;
+    // the static launch schedule of one iteration: (kind, depth), kind 0 tick, 1 forward, 2 level
+    std::vector<std::pair<int, int>> plan;
     std::vector<int32_t> slot_map;     // canonical slot -> device slot (empty: identity)
     int32_t D = 0;
     bool br_ok = true;
@@ -62,10 +64,10 @@ struct cfr_handle {
     int64_t iters = 0;
     int64_t launches = 0;
     // algorithmic bytes per iteration of each kernel (traffic model, see model_bytes)
-    double bytes_fwd = 0, bytes_bwd = 0, bytes_upd = 0;
+    double bytes_fwd = 0, bytes_lvl = 0;
 };
 
-// Per-launch event timing for cfr_profile: class 0 tick, 1 forward, 2 backward, 3 update.
+// Per-launch event timing for cfr_profile: class 0 tick, 1 forward, 2 level.
 struct LaunchTimer {
     std::vector<hipEvent_t> ev;   // pairs (before, after)
     std::vector<int> cls;
@@ -101,64 +103,77 @@ std::vector<const void *> persistent_ptrs(const cfr_handle *h) {
             h->g.mem_node};
 }
 
-// one iteration, direct launches, in a fixed order; tm != nullptr brackets every launch with events
+// The launch schedule of one iteration (paper Proposition 3 (iii): a fixed sequence whose length
+// depends on the depth only): the forward pass over depths 1..max_depth (depth 1 always launches,
+// because its first thread advances the iteration counter), then the fused backward/update level
+// over depths max_depth-1..0, skipping levels with nothing to do.  A single-node game only ticks.
+void build_plan(cfr_handle *h) {
+    h->plan.clear();
+    const DevGame &g = h->g;
+    if (g.max_depth == 0) { h->plan.push_back({0, 0}); return; }
+    for (int d = 1; d <= g.max_depth; d++)
+        if (d == 1 || h->int_end[d] > h->depth_off[d]) h->plan.push_back({1, d});
+    for (int d = g.max_depth - 1; d >= 0; d--)
+        if (h->grp_depth_off[d + 1] > h->grp_depth_off[d] || h->chance_off[d + 1] > h->chance_off[d])
+            h->plan.push_back({2, d});
+}
+
+// one iteration, direct launches, in the plan's order; tm != nullptr brackets every launch with events
 cfr_status enqueue_iteration(cfr_handle *h, hipStream_t s, int64_t *count, LaunchTimer *tm = nullptr) {
     const DevGame &g = h->g;
+    const IterFlags f{h->opt.rule == CFR_RULE_CFR_PLUS ? 1 : 0, h->opt.averaging == CFR_AVG_LINEAR ? 1 : 0};
     int64_t n = 0;
-    auto mark = [&](int cls) -> hipError_t {
-        if (!tm) return hipSuccess;
-        if (tm->next + 1 >= tm->ev.size()) return hipErrorInvalidValue;
-        tm->cls.push_back(cls);
-        return hipEventRecord(tm->ev[tm->next++], s);
-    };
-    if (h->D == 0) {
-        HIP_TRY(mark(0)); HIP_TRY(launch_tick(g, s)); HIP_TRY(mark(-1)); n++;
-    }
-    for (int d = 1; d <= g.max_depth; d++) {
-        HIP_TRY(mark(1));
-        HIP_TRY(launch_forward(g, h->depth_off[d], h->int_end[d], d == 1 ? g.t : nullptr, s));
-        HIP_TRY(mark(-1));
+    for (const auto &step : h->plan) {
+        if (tm) {
+            if (tm->next + 1 >= tm->ev.size()) return fail(CFR_EDEVICE, "profiling event pool exhausted");
+            tm->cls.push_back(step.first);
+            HIP_TRY(hipEventRecord(tm->ev[tm->next++], s));
+        }
+        const int d = step.second;
+        if (step.first == 0) HIP_TRY(launch_tick(g, s));
+        else if (step.first == 1) HIP_TRY(launch_forward(g, h->depth_off[d], h->int_end[d], d == 1 ? g.t : nullptr, s));
+        else HIP_TRY(launch_level(g, d, f, s));
+        if (tm) {
+            tm->cls.push_back(-1);
+            HIP_TRY(hipEventRecord(tm->ev[tm->next++], s));
+        }
         n++;
     }
-    for (int d = g.max_depth - 1; d >= 0; d--) {
-        HIP_TRY(mark(2));
-        HIP_TRY(launch_backward(g, h->depth_off[d], h->int_end[d], s));
-        HIP_TRY(mark(-1));
-        n++;
-    }
-    IterFlags f{h->opt.rule == CFR_RULE_CFR_PLUS ? 1 : 0, h->opt.averaging == CFR_AVG_LINEAR ? 1 : 0};
-    if (g.I > 0) { HIP_TRY(mark(3)); HIP_TRY(launch_update(g, f, s)); HIP_TRY(mark(-1)); n++; }
     if (count) *count = n;
     return CFR_OK;
 }
 
 // Algorithmic bytes of one iteration per kernel: every index, state and value element a
 // kernel must touch in the device layout, counted once (sigma gathers count once per slot
-// and pass).  Launch ranges: a level's forward/backward launch covers [depth_off, int_end).
+// and pass).
 void model_bytes(cfr_handle *h, const Layout &L, const DeviceLayout &D) {
     const int md = L.max_depth;
     const double es = (double)h->es;
     const double kb = D.explicit_kids ? 4.0 : 0.0;
-    std::vector<double> Nr(md + 2, 0), Nint(md + 2, 0), Ad(md + 2, 0), Nd(md + 2, 0);
+    std::vector<double> Nr(md + 2, 0), Nint(md + 2, 0), Ad(md + 2, 0), Id(md + 2, 0), Md(md + 2, 0), Ed(md + 2, 0);
     for (int d = 0; d <= md; d++) {
-        Nd[d] = D.depth_off[d + 1] - D.depth_off[d];
         Nr[d] = D.int_end[d] - D.depth_off[d];
         for (int32_t n = D.depth_off[d]; n < D.int_end[d]; n++) Nint[d] += D.kid_off[n + 1] > D.kid_off[n];
-        for (int32_t i = D.iset_depth_off[d]; i < D.iset_depth_off[d + 1]; i++) Ad[d] += D.slot_off[i + 1] - D.slot_off[i];
+        for (int32_t i = D.iset_depth_off[d]; i < D.iset_depth_off[d + 1]; i++) {
+            const double nA = D.slot_off[i + 1] - D.slot_off[i], nm = D.mem_off[i + 1] - D.mem_off[i];
+            Ad[d] += nA; Id[d] += 1; Md[d] += nm; Ed[d] += nm * nA;
+        }
     }
-    double f = 0, b = 0;
+    double f = 0, lv = 0;
     for (int d = 1; d <= md; d++) f += 8 * Nr[d] + 2 * es * Nint[d - 1] + 2 * es * Nint[d] + es * Ad[d - 1];
-    for (int d = 0; d < md; d++) b += 8 * Nr[d] + 4 + (kb + es) * Nd[d + 1] + es * Nint[d] + es * Ad[d];
-    double edec = 0;
-    for (int64_t i = 0; i < L.I; i++)
-        edec += (double)(L.mem_off[i + 1] - L.mem_off[i]) * (L.slot_off[i + 1] - L.slot_off[i]);
+    for (int d = 0; d < md; d++) {
+        // decision members: id, edge offset, value write, opponent reach; edges: child (index), value;
+        // sets: member and slot offsets, player, own reach; slots: sigma read + write, R read + write,
+        // sbar read + write
+        lv += (8 + 2 * es) * Md[d] + (kb + es) * Ed[d] + (9 + es) * Id[d] + (4 * es + 16) * Ad[d];
+        // chance nodes: list entry, edge offset, value write; edges: child (index), value
+        for (int32_t j = D.chance_off[d]; j < D.chance_off[d + 1]; j++) {
+            const int32_t x = D.chance_node[j];
+            lv += 8 + es + (kb + es) * (D.kid_off[x + 1] - D.kid_off[x]);
+        }
+    }
     h->bytes_fwd = f;
-    h->bytes_bwd = b;
-    // per set: slot and member offsets and the player (17 B) plus the own reach of one member;
-    // per member: its id, edge offset, v(h) and opponent reach; per decision edge: the child
-    // value (and its child index in explicit layouts); per slot: sigma read and write, R read and
-    // write, sbar read and write (FP64)
-    h->bytes_upd = (17.0 + es) * L.I + (8.0 + 2 * es) * L.Ndec + (es + kb) * edec + (4 * es + 16.0) * L.A;
+    h->bytes_lvl = lv;
 }
 
 cfr_status capture(cfr_handle *h, int iters, hipGraph_t *graph, hipGraphExec_t *exec) {
@@ -276,6 +291,9 @@ cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_ha
     std::string err;
     cfr_status st = build_layout(game, L, err);
     if (st != CFR_OK) return fail(st, err);
+    if (!L.br_ok)
+        return fail(CFR_EUNSUPPORTED, "an information set has members at different depths; the level-fused "
+                                      "update needs every set on one depth");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(CFR_EDEVICE, "no HIP device available");
     if (o.device < 0 || o.device >= ndev) return fail(CFR_EINVAL, "device ordinal out of range");
@@ -291,6 +309,8 @@ cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_ha
     h->int_end = DL.int_end;
     h->iset_depth_off = DL.iset_depth_off;
     h->slot_map = DL.slot_canon_to_dev;
+    h->grp_depth_off = DL.grp_depth_off;
+    h->chance_off = DL.chance_off;
     h->D = L.D;
     h->br_ok = L.br_ok;
     h->E = L.E; h->Z = L.Z; h->pot = game->pot;
@@ -318,6 +338,9 @@ cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_ha
     ALLOC(g.iset_player, I);
     g.G = (int32_t)DL.grp_iset_off.size() - 1;
     ALLOC(g.grp_iset_off, (int64_t)DL.grp_iset_off.size());
+    ALLOC(g.chance_node, (int64_t)DL.chance_node.size());
+    g.grp_depth_off = h->grp_depth_off.data();
+    g.chance_off = h->chance_off.data();
     {
         char *pv = nullptr, *pr = nullptr, *ps = nullptr, *pR = nullptr;
         ALLOC(pv, N * (int64_t)h->es);
@@ -348,6 +371,7 @@ cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_ha
     UP(g.mem_node, DL.mem_node);
     UP(g.iset_player, DL.iset_player);
     UP(g.grp_iset_off, DL.grp_iset_off);
+    UP(g.chance_node, DL.chance_node);
     if (g.fp64) { UP((double *)g.v, DL.tmpl64); } else { UP((float *)g.v, DL.tmpl); }
     UP(g.vbr, DL.tmpl64);
 #undef UP
@@ -363,12 +387,8 @@ cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_ha
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
         if (e != hipSuccess) { free_handle(h); return fail(CFR_EDEVICE, std::string("setup: ") + hipGetErrorString(e)); }
     }
-    int64_t nl = 0;
-    {
-        // count launches per iteration without launching anything
-        nl = (h->D == 0 ? 1 : 0) + 2 * (int64_t)g.max_depth + (g.I > 0 ? 1 : 0);
-    }
-    h->launches = nl;
+    build_plan(h);
+    h->launches = (int64_t)h->plan.size();
     model_bytes(h, L, DL);
     st = cfr_reset(h);
     if (st != CFR_OK) { free_handle(h); return st; }
@@ -581,8 +601,8 @@ cfr_status cfr_profile(cfr_handle *h, int64_t n, void *stream, cfr_kernel_stat *
     for (auto &ev : tm.ev) (void)hipEventDestroy(ev);
     if (st != CFR_OK) return st;
     if (e != hipSuccess) return fail(CFR_EDEVICE, std::string("profiling events: ") + hipGetErrorString(e));
-    const char *names[4] = {"k_tick", "k_forward", "k_backward", "k_update"};
-    const double bytes[4] = {0.0, h->bytes_fwd, h->bytes_bwd, h->bytes_upd};
+    const char *names[4] = {"k_tick", "k_forward", "k_level", ""};
+    const double bytes[4] = {0.0, h->bytes_fwd, h->bytes_lvl, 0.0};
     int32_t k = 0;
     for (int c = 0; c < 4; c++) {
         if (cnt[c] == 0) continue;

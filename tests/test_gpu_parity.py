@@ -236,12 +236,13 @@ def test_capture_failure_falls_back(capfd):
 
 
 def test_launch_count_gate():
-    """Proposition 3 (iii): launches per iteration are c1 + c2 D with c2 = 2 (one forward and one backward
-    kernel per level) and c1 = 1 (the fused update), far under the paper's 40 + 10 D gate."""
-    for game in (gg.kuhn(), gg.leduc(3, 2), gg.leduc(13, 2)):
+    """Proposition 3 (iii): launches per iteration are at most c2 D with c2 = 2 (one forward kernel and one
+    fused backward/update kernel per level; the regret, average and regret-matching steps live inside the
+    level kernels), far under the paper's 40 + 10 D gate."""
+    for game in (gg.kuhn(), gg.leduc(3, 2), gg.leduc(13, 2), gg.example11()):
         s = cfr.Solver(game)
         c = s.counts
-        assert c["kernels_per_iteration"] == 2 * c["blocks"] + 1
+        assert c["blocks"] <= c["kernels_per_iteration"] <= 2 * c["blocks"]
         assert c["kernels_per_iteration"] <= 40 + 10 * c["blocks"]
 
 
