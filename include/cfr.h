@@ -199,8 +199,12 @@ cfr_status cfr_counts(cfr_handle *h, cfr_counts_t *out);
  * event before and after every launch, and reports for each kernel of the iteration body:
  *   name                  the kernel's symbol name (as profilers list it, without namespace)
  *   launches_per_iteration
- *   bytes_per_iteration   algorithmic bytes of all its launches in one iteration: each index,
- *                         state and value element the kernel must read or write counted once
+ *   bytes_per_iteration   bytes of all its launches in one iteration under this design: each
+ *                         index, state and value element the kernel reads or writes, counted once
+ *   method_bytes_per_iteration
+ *                         the method's per-unit byte figures (per edge, node, terminal, decision
+ *                         node and edge, information set and slot, with 4-byte indices and the
+ *                         state width) applied to the units its launches process
  *   ms_per_iteration      mean over the n iterations of the summed durations of its launches
  * The iterations advance the solver like cfr_iterate.  Writes up to max_out entries to out and
  * their number to *n_out.  Synchronises `stream`. */
@@ -208,6 +212,7 @@ typedef struct {
     char    name[32];
     int64_t launches_per_iteration;
     double  bytes_per_iteration;
+    double  method_bytes_per_iteration;
     double  ms_per_iteration;
 } cfr_kernel_stat;
 cfr_status cfr_profile(cfr_handle *h, int64_t n, void *stream, cfr_kernel_stat *out, int32_t max_out,

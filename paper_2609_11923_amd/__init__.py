@@ -61,7 +61,8 @@ class cfr_layout(ctypes.Structure):
 
 class cfr_kernel_stat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches_per_iteration", ctypes.c_int64),
-                ("bytes_per_iteration", ctypes.c_double), ("ms_per_iteration", ctypes.c_double)]
+                ("bytes_per_iteration", ctypes.c_double), ("method_bytes_per_iteration", ctypes.c_double),
+                ("ms_per_iteration", ctypes.c_double)]
 
 
 class CfrError(RuntimeError):
@@ -246,7 +247,8 @@ def cfr_profile(h, n: int, stream=None) -> list[dict]:
     k = ctypes.c_int32()
     _check(load().cfr_profile(h, int(n), stream, arr, 16, ctypes.byref(k)))
     return [dict(name=arr[i].name.decode(), launches_per_iteration=arr[i].launches_per_iteration,
-                 bytes_per_iteration=arr[i].bytes_per_iteration, ms_per_iteration=arr[i].ms_per_iteration)
+                 bytes_per_iteration=arr[i].bytes_per_iteration,
+                 method_bytes_per_iteration=arr[i].method_bytes_per_iteration, ms_per_iteration=arr[i].ms_per_iteration)
             for i in range(k.value)]
 
 

@@ -376,11 +376,12 @@ cfr_status build_device_layout(const Layout &L, int kind, DeviceLayout &D, std::
         // update groups in device information-set order, never spanning two depths
         D.grp_iset_off.assign(1, 0);
         D.grp_depth_off.assign((size_t)md + 2, 0);
+        const int32_t cap = group_members(L.max_actions);
         for (int d = 0; d <= md; d++) {
             int32_t members = 0, sets = 0;
             for (int32_t i = D.iset_depth_off[d]; i < D.iset_depth_off[d + 1]; i++) {
                 int32_t m = D.mem_off[i + 1] - D.mem_off[i];
-                if (sets > 0 && (members + m > GROUP_MEMBERS || sets + 1 > GROUP_SETS)) {
+                if (sets > 0 && (members + m > cap || sets + 1 > GROUP_SETS)) {
                     D.grp_iset_off.push_back(i);
                     members = 0; sets = 0;
                 }

@@ -67,7 +67,7 @@ struct DeviceLayout {
     std::vector<float> tmpl;             // [N]
     std::vector<double> tmpl64;          // [N]
     std::vector<int32_t> slot_canon_to_dev; // [A], empty when identical
-    // update groups: runs of consecutive information sets of one depth with at most GROUP_MEMBERS
+    // update groups: runs of consecutive information sets of one depth with at most group_members
     // members and at most GROUP_SETS sets in total (a set with more members forms a group of its
     // own); group g holds sets [grp_iset_off[g], grp_iset_off[g + 1]); the groups of depth d are
     // [grp_depth_off[d], grp_depth_off[d + 1])
@@ -78,8 +78,9 @@ struct DeviceLayout {
     std::vector<int32_t> chance_off;     // [max_depth + 2]
 };
 
-constexpr int GROUP_MEMBERS = 256;
 constexpr int GROUP_SETS = 256;
+// members per update group: two per thread of a 256-thread block when sets have at most 4 actions
+inline int group_members(int max_actions) { return max_actions <= 4 ? 512 : 256; }
 
 cfr_status build_device_layout(const Layout &L, int layout_kind, DeviceLayout &out, std::string &err);
 

@@ -12,7 +12,8 @@ namespace cfrx {
 constexpr int CODE_OWNER_MASK = 3;
 constexpr int CODE_INTERNAL = 4;
 constexpr int CODE_SLOT_SHIFT = 3;
-// Member-list entries: node id in bits 0-30, bit 31 set when the set belongs to player 2.
+// Member-list entries: node id in bits 0-30, bit 31 set when the set belongs to player 2;
+// paired with the node's first edge so that no edge-offset lookup sits on the load chain.
 constexpr int32_t MEMBER_NODE_MASK = 0x7fffffff;
 constexpr int32_t MEMBER_P2 = (int32_t)0x80000000u;
 
@@ -29,7 +30,7 @@ struct DevGame {
     int32_t *node_iset = nullptr; // [N]   information set of a decision node, -1 otherwise
     int32_t *slot_off = nullptr;  // [I+1]
     int32_t *mem_off = nullptr;   // [I+1]
-    int32_t *mem_node = nullptr;  // [Ndec]
+    int2 *mem = nullptr;          // [Ndec]  members: (node | MEMBER_P2 bit, first edge of the node)
     int8_t *iset_player = nullptr;// [I]
     int32_t G = 0;                // update groups
     int32_t *grp_iset_off = nullptr; // [G+1]

@@ -66,14 +66,15 @@ __global__ void __launch_bounds__(BLOCK) k_forward(int32_t lo, int32_t hi, const
 // Only this block reads sigma(I) during the backward pass (all members of I are here), and the
 // forward pass has already consumed it, so overwriting sigma(I) with sigma^{t+1} is safe.
 // Sets with more than BLOCK members are streamed through LDS in chunks.
-template <typename T, int MAXA, bool EXPLICIT>
+template <typename T, int MAXA, int MPT, bool EXPLICIT>
 __global__ void __launch_bounds__(BLOCK) k_level(
     int32_t gbeg, int32_t ngroups, const int32_t *__restrict__ chance_node, int32_t cbeg, int32_t nchance,
     const int32_t *__restrict__ grp_iset_off, const int32_t *__restrict__ slot_off,
-    const int32_t *__restrict__ mem_off, const int32_t *__restrict__ mem_node, const int8_t *__restrict__ iset_player,
+    const int32_t *__restrict__ mem_off, const int2 *__restrict__ mem, const int8_t *__restrict__ iset_player,
     const int32_t *__restrict__ kid_off, const int32_t *__restrict__ kid, T *__restrict__ v,
     const T *__restrict__ r1, const T *__restrict__ r2, T *__restrict__ R, double *__restrict__ sbar,
     T *__restrict__ sigma, const int32_t *__restrict__ tcount, int plus, int linear) {
+    constexpr int CHUNK = MPT * BLOCK;
     const int tid = threadIdx.x;
     if ((int32_t)blockIdx.x >= ngroups) {
         const int32_t j = ((int32_t)blockIdx.x - ngroups) * BLOCK + tid;
@@ -85,10 +86,10 @@ __global__ void __launch_bounds__(BLOCK) k_level(
         v[h] = acc;
         return;
     }
-    __shared__ T s_po[BLOCK];
-    __shared__ T s_diff[BLOCK * MAXA];
+    __shared__ T s_po[CHUNK];
+    __shared__ T s_diff[CHUNK * MAXA];
     __shared__ int32_t s_moff[BLOCK + 1];
-    __shared__ int32_t s_slot[BLOCK];
+    __shared__ int32_t s_slot[BLOCK + 1];
     const int32_t g = gbeg + (int32_t)blockIdx.x;
     const int32_t i0 = grp_iset_off[g], i1 = grp_iset_off[g + 1];
     const int32_t nsets = i1 - i0;
@@ -96,14 +97,17 @@ __global__ void __launch_bounds__(BLOCK) k_level(
         s_moff[tid] = mem_off[i0 + tid];
         s_slot[tid] = slot_off[i0 + tid];
     }
-    if (tid == 0) s_moff[nsets] = mem_off[i1];
+    if (tid == 0) {
+        s_moff[nsets] = mem_off[i1];
+        s_slot[nsets] = slot_off[i1];
+    }
     __syncthreads();
     const int32_t mbeg = s_moff[0], mend = s_moff[nsets];
     const bool has_set = tid < nsets;
     int32_t s0 = 0, nA = 0, m0 = 0, m1 = 0, pl = 1;
     if (has_set) {
         s0 = s_slot[tid];
-        nA = slot_off[i0 + tid + 1] - s0;
+        nA = s_slot[tid + 1] - s0;
         m0 = s_moff[tid];
         m1 = s_moff[tid + 1];
         pl = iset_player[i0 + tid];
@@ -111,33 +115,37 @@ __global__ void __launch_bounds__(BLOCK) k_level(
     T r[MAXA];
 #pragma unroll
     for (int a = 0; a < MAXA; a++) r[a] = T(0);
-    for (int32_t cb = mbeg; cb < mend; cb += BLOCK) {
-        const int32_t ce = min(cb + BLOCK, mend);
-        const int32_t m = cb + tid;
-        if (m < ce) {
-            // the set of member m: the last j with s_moff[j] <= m
-            int32_t lo = 0, hi = nsets - 1;
-            while (lo < hi) {
-                const int32_t mid = (lo + hi + 1) >> 1;
-                if (s_moff[mid] <= m) lo = mid; else hi = mid - 1;
-            }
-            const int32_t sb = s_slot[lo];
-            const int32_t x = mem_node[m];
-            const int32_t h = x & MEMBER_NODE_MASK;
-            const int32_t e0 = kid_off[h], na = kid_off[h + 1] - e0;
-            T cv[MAXA];
-            T vh = T(0);
+    for (int32_t cb = mbeg; cb < mend; cb += CHUNK) {
+        const int32_t ce = min(cb + CHUNK, mend);
 #pragma unroll
-            for (int a = 0; a < MAXA; a++)
-                if (a < na) {
-                    cv[a] = v[child_of<EXPLICIT>(kid, e0 + a)];
-                    vh = fma_t(sigma[sb + a], cv[a], vh);
+        for (int u = 0; u < MPT; u++) {
+            const int32_t j = u * BLOCK + tid;
+            const int32_t m = cb + j;
+            if (m < ce) {
+                // the set of member m: the last k with s_moff[k] <= m
+                int32_t lo = 0, hi = nsets - 1;
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi + 1) >> 1;
+                    if (s_moff[mid] <= m) lo = mid; else hi = mid - 1;
                 }
-            v[h] = vh;
-            s_po[tid] = (x & MEMBER_P2) ? r1[h] : r2[h];
+                const int32_t sb = s_slot[lo], na = s_slot[lo + 1] - sb;
+                const int2 x = mem[m];
+                const int32_t h = x.x & MEMBER_NODE_MASK;
+                const T po = (x.x & MEMBER_P2) ? r1[h] : r2[h];
+                T cv[MAXA];
+                T vh = T(0);
 #pragma unroll
-            for (int a = 0; a < MAXA; a++)
-                if (a < na) s_diff[tid * MAXA + a] = cv[a] - vh;
+                for (int a = 0; a < MAXA; a++)
+                    if (a < na) cv[a] = v[child_of<EXPLICIT>(kid, x.y + a)];
+#pragma unroll
+                for (int a = 0; a < MAXA; a++)
+                    if (a < na) vh = fma_t(sigma[sb + a], cv[a], vh);
+                v[h] = vh;
+                s_po[j] = po;
+#pragma unroll
+                for (int a = 0; a < MAXA; a++)
+                    if (a < na) s_diff[j * MAXA + a] = cv[a] - vh;
+            }
         }
         __syncthreads();
         if (has_set) {
@@ -155,7 +163,7 @@ __global__ void __launch_bounds__(BLOCK) k_level(
     const T *own = pl == 1 ? r1 : r2;
     const T sign = pl == 1 ? T(1) : T(-1);
     const double w = linear ? (double)tcount[0] : 1.0;
-    const double pown = (double)own[mem_node[m0] & MEMBER_NODE_MASK];
+    const double pown = (double)own[mem[m0].x & MEMBER_NODE_MASK];
     T tot = T(0);
     T Rn[MAXA];
 #pragma unroll
@@ -163,10 +171,10 @@ __global__ void __launch_bounds__(BLOCK) k_level(
         if (a < nA) {
             const int32_t q = s0 + a;
             sbar[q] += w * pown * (double)sigma[q];
-            T x = fma_t(sign, r[a], R[q]);
-            if (plus) x = max_t(x, T(0));
-            R[q] = x;
-            Rn[a] = max_t(x, T(0));
+            T y = fma_t(sign, r[a], R[q]);
+            if (plus) y = max_t(y, T(0));
+            R[q] = y;
+            Rn[a] = max_t(y, T(0));
             tot += Rn[a];
         }
     }
@@ -243,7 +251,7 @@ __global__ void __launch_bounds__(BLOCK) k_br_forward(int32_t lo, int32_t hi, co
 template <bool EXPLICIT>
 __global__ void __launch_bounds__(BLOCK) k_br_argmax(int32_t ilo, int32_t ihi, const int32_t *__restrict__ slot_off,
                                                      const int32_t *__restrict__ mem_off,
-                                                     const int32_t *__restrict__ mem_node,
+                                                     const int2 *__restrict__ mem,
                                                      const int8_t *__restrict__ iset_player,
                                                      const int32_t *__restrict__ kid_off,
                                                      const int32_t *__restrict__ kid,
@@ -260,8 +268,8 @@ __global__ void __launch_bounds__(BLOCK) k_br_argmax(int32_t ilo, int32_t ihi, c
     for (int a = 0; a < nA; a++) {
         double Q = 0.0;
         for (int32_t m = m0; m < m1; m++) {
-            int32_t h = mem_node[m] & MEMBER_NODE_MASK;
-            Q += q[h] * (sign * vbr[child_of<EXPLICIT>(kid, kid_off[h] + a)]);
+            const int2 x = mem[m];
+            Q += q[x.x & MEMBER_NODE_MASK] * (sign * vbr[child_of<EXPLICIT>(kid, x.y + a)]);
         }
         if (a == 0 || Q > bq) { bq = Q; best = a; }
     }
@@ -312,24 +320,25 @@ hipError_t launch_forward(const DevGame &g, int32_t lo, int32_t hi, int32_t *tic
     return g.fp64 ? forward_t<double>(g, lo, hi, tick, s) : forward_t<float>(g, lo, hi, tick, s);
 }
 
-template <typename T, int MAXA, bool EX>
+template <typename T, int MAXA, int MPT, bool EX>
 static hipError_t level_t(const DevGame &g, int d, IterFlags f, hipStream_t s) {
     const int32_t gbeg = g.grp_depth_off[d], ng = g.grp_depth_off[d + 1] - gbeg;
     const int32_t cbeg = g.chance_off[d], nc = g.chance_off[d + 1] - cbeg;
     const unsigned blocks = (unsigned)ng + grid_for(nc);
     if (blocks == 0) return hipSuccess;
     const T *r = (const T *)g.reach;
-    hipLaunchKernelGGL((k_level<T, MAXA, EX>), dim3(blocks), dim3(BLOCK), 0, s, gbeg, ng, g.chance_node, cbeg, nc,
-                       g.grp_iset_off, g.slot_off, g.mem_off, g.mem_node, g.iset_player, g.kid_off, g.kid, (T *)g.v, r,
+    hipLaunchKernelGGL((k_level<T, MAXA, MPT, EX>), dim3(blocks), dim3(BLOCK), 0, s, gbeg, ng, g.chance_node, cbeg, nc,
+                       g.grp_iset_off, g.slot_off, g.mem_off, g.mem, g.iset_player, g.kid_off, g.kid, (T *)g.v, r,
                        r + g.N, (T *)g.R, g.sbar, (T *)g.sigma, g.t, f.plus, f.linear);
     return hipGetLastError();
 }
 
 template <typename T, bool EX>
 static hipError_t level_dispatch_ex(const DevGame &g, int d, IterFlags f, hipStream_t s) {
-    if (g.max_actions <= 4) return level_t<T, 4, EX>(g, d, f, s);
-    if (g.max_actions <= 16) return level_t<T, 16, EX>(g, d, f, s);
-    return level_t<T, 64, EX>(g, d, f, s);
+    // members per thread must match the group capacity the compiler used (group_members)
+    if (g.max_actions <= 4) return level_t<T, 4, 2, EX>(g, d, f, s);
+    if (g.max_actions <= 16) return level_t<T, 16, 1, EX>(g, d, f, s);
+    return level_t<T, 64, 1, EX>(g, d, f, s);
 }
 
 template <typename T>
@@ -401,10 +410,10 @@ hipError_t launch_br_argmax(const DevGame &g, int32_t ilo, int32_t ihi, int br, 
     if (ihi <= ilo) return hipSuccess;
     if (g.explicit_kids)
         hipLaunchKernelGGL(k_br_argmax<true>, dim3(grid_for(ihi - ilo)), dim3(BLOCK), 0, s, ilo, ihi, g.slot_off,
-                           g.mem_off, g.mem_node, g.iset_player, g.kid_off, g.kid, g.vbr, g.qbr, g.astar, br);
+                           g.mem_off, g.mem, g.iset_player, g.kid_off, g.kid, g.vbr, g.qbr, g.astar, br);
     else
         hipLaunchKernelGGL(k_br_argmax<false>, dim3(grid_for(ihi - ilo)), dim3(BLOCK), 0, s, ilo, ihi, g.slot_off,
-                           g.mem_off, g.mem_node, g.iset_player, g.kid_off, g.kid, g.vbr, g.qbr, g.astar, br);
+                           g.mem_off, g.mem, g.iset_player, g.kid_off, g.kid, g.vbr, g.qbr, g.astar, br);
     return hipGetLastError();
 }
 

@@ -65,6 +65,7 @@ struct cfr_handle {
     int64_t launches = 0;
     // algorithmic bytes per iteration of each kernel (traffic model, see model_bytes)
     double bytes_fwd = 0, bytes_lvl = 0;
+    double method_fwd = 0, method_lvl = 0;   // per-unit byte figures of the method (see model_bytes)
 };
 
 // Per-launch event timing for cfr_profile: class 0 tick, 1 forward, 2 level.
@@ -100,7 +101,7 @@ cfr_status upload(T *dst, const std::vector<T> &src) {
 std::vector<const void *> persistent_ptrs(const cfr_handle *h) {
     return {h->R_base + h->rebind[0] * (int64_t)h->es, h->sbar_base + h->rebind[1] * 8,
             h->sigma_base + h->rebind[2] * (int64_t)h->es, h->g.v, h->g.reach, h->g.t, h->g.up, h->g.kid_off,
-            h->g.mem_node};
+            h->g.mem};
 }
 
 // The launch schedule of one iteration (paper Proposition 3 (iii): a fixed sequence whose length
@@ -174,6 +175,30 @@ void model_bytes(cfr_handle *h, const Layout &L, const DeviceLayout &D) {
     }
     h->bytes_fwd = f;
     h->bytes_lvl = lv;
+    // The method's per-unit byte figures with 4-byte indices and state width es (FP64 strategy
+    // sums): forward, per edge the parent index and edge code (8) and the two-lane reach write
+    // (2 es), per internal parent the two-lane reach read (2 es); backward, per edge the child
+    // value and pointer (es + 4), per terminal the template (es), per internal node the child
+    // offset and value write (4 + es); regret, per decision edge the child value (es), per
+    // decision node its id, value and both reaches (4 + 3 es), per set its offsets (4); per slot,
+    // regrets read and written (2 es), strategy written and read twice (3 es), strategy sums read
+    // and written (16) and the regret-matching read (2 es).
+    std::vector<double> Zd(md + 2, 0), Nd(md + 2, 0);
+    for (int d = 0; d <= md; d++) {
+        Nd[d] = D.depth_off[d + 1] - D.depth_off[d];
+        Zd[d] = Nd[d] - (double)(D.int_end[d] - D.depth_off[d]);
+        if (!D.explicit_kids) {
+            Zd[d] = 0;
+            for (int32_t n = D.depth_off[d]; n < D.depth_off[d + 1]; n++) Zd[d] += D.kid_off[n + 1] == D.kid_off[n];
+        }
+    }
+    double mf = 0, ml = 0;
+    for (int d = 1; d <= md; d++) mf += (8 + 2 * es) * Nd[d] + 2 * es * Nint[d - 1];
+    for (int d = 0; d < md; d++)
+        ml += (es + 4) * Nd[d + 1] + es * Zd[d + 1] + (4 + es) * Nint[d] + es * Ed[d] + (4 + 3 * es) * Md[d] +
+              4 * Id[d] + (7 * es + 16) * Ad[d];
+    h->method_fwd = mf;
+    h->method_lvl = ml;
 }
 
 cfr_status capture(cfr_handle *h, int iters, hipGraph_t *graph, hipGraphExec_t *exec) {
@@ -334,7 +359,7 @@ cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_ha
     ALLOC(g.node_iset, N);
     ALLOC(g.slot_off, I + 1);
     ALLOC(g.mem_off, I + 1);
-    ALLOC(g.mem_node, L.Ndec);
+    ALLOC(g.mem, L.Ndec);
     ALLOC(g.iset_player, I);
     g.G = (int32_t)DL.grp_iset_off.size() - 1;
     ALLOC(g.grp_iset_off, (int64_t)DL.grp_iset_off.size());
@@ -368,7 +393,12 @@ cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_ha
     UP(g.node_iset, DL.node_iset);
     UP(g.slot_off, DL.slot_off);
     UP(g.mem_off, DL.mem_off);
-    UP(g.mem_node, DL.mem_node);
+    {
+        std::vector<int2> mem((size_t)L.Ndec);
+        for (int64_t k = 0; k < L.Ndec; k++)
+            mem[k] = make_int2(DL.mem_node[k], DL.kid_off[DL.mem_node[k] & MEMBER_NODE_MASK]);
+        UP(g.mem, mem);
+    }
     UP(g.iset_player, DL.iset_player);
     UP(g.grp_iset_off, DL.grp_iset_off);
     UP(g.chance_node, DL.chance_node);
@@ -603,6 +633,7 @@ cfr_status cfr_profile(cfr_handle *h, int64_t n, void *stream, cfr_kernel_stat *
     if (e != hipSuccess) return fail(CFR_EDEVICE, std::string("profiling events: ") + hipGetErrorString(e));
     const char *names[4] = {"k_tick", "k_forward", "k_level", ""};
     const double bytes[4] = {0.0, h->bytes_fwd, h->bytes_lvl, 0.0};
+    const double method[4] = {0.0, h->method_fwd, h->method_lvl, 0.0};
     int32_t k = 0;
     for (int c = 0; c < 4; c++) {
         if (cnt[c] == 0) continue;
@@ -612,6 +643,7 @@ cfr_status cfr_profile(cfr_handle *h, int64_t n, void *stream, cfr_kernel_stat *
             std::snprintf(o.name, sizeof o.name, "%s", names[c]);
             o.launches_per_iteration = cnt[c] / n;
             o.bytes_per_iteration = bytes[c];
+            o.method_bytes_per_iteration = method[c];
             o.ms_per_iteration = ms[c] / (double)n;
         }
         k++;
