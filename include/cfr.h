@@ -154,6 +154,23 @@ void cfr_layout_free(cfr_layout *layout);
  * On success *out receives a new handle. */
 cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_handle **out);
 
+/* Batched form: compile n independent games (e.g. subgames of one game with their own root
+ * ranges) into one handle.  They are laid out as a depth-major forest -- the depth-d nodes,
+ * information sets and slots of game 0, then of game 1, ... -- so one launch per level (or one
+ * persistent launch, see cfr_options.persistent) advances every game.  Per-slot arrays at the ABI
+ * hold game 0's canonical slots, then game 1's (offsets from cfr_batch_size).  Games are
+ * validated one by one; the message of a failure names the game.  n == 1 equals cfr_compile. */
+cfr_status cfr_compile_batch(const cfr_game_desc *games, int32_t n, const cfr_options *opt, cfr_handle **out);
+
+/* Number of games in the handle and (if slot_base != NULL) the n + 1 offsets of each game's
+ * canonical slots in the per-slot arrays. */
+cfr_status cfr_batch_size(cfr_handle *h, int32_t *n_games, int64_t *slot_base);
+
+/* Per-game exploitability of the average profile: arrays of n entries (any may be NULL), as
+ * cfr_exploitability computes for one game.  Synchronises `stream`. */
+cfr_status cfr_batch_exploitability(cfr_handle *h, void *stream, double *expl, double *br1, double *br2,
+                                    double *value_avg, int32_t n);
+
 /* Run n CFR iterations on `stream` (asynchronous).  The first call captures the iteration
  * body into a hipGraph (after one direct iteration that counts toward n) and later calls
  * replay it.  n == 0 is a no-op.  Returns CFR_ESTATE if a persistent buffer recorded at
@@ -173,8 +190,8 @@ cfr_status cfr_strategy(cfr_handle *h, int which, float *dst, int64_t len, int d
 /* Exploitability of the average profile (eq. exploitability): expl = (BR_1 + BR_2)/2 in payoff
  * units, with br1/br2 the best-response values and value_avg player 1's value of the average
  * profile, all computed in FP64 on the device by a level-synchronous best response over the
- * compiled arrays.  Synchronises `stream`.  Any output pointer may be NULL.
- * CFR_EUNSUPPORTED if an information set spans several depths. */
+ * compiled arrays.  Synchronises `stream`.  Any output pointer may be NULL.  CFR_EINVAL on a
+ * handle holding several games (use cfr_batch_exploitability). */
 cfr_status cfr_exploitability(cfr_handle *h, void *stream, double *expl, double *br1, double *br2,
                               double *value_avg);
 

@@ -74,7 +74,8 @@ class CfrError(RuntimeError):
 _lib = None
 
 # exported symbols of include/cfr.h (the ABI tests check the library exports each one)
-EXPORTS = ["cfr_default_options", "cfr_layout_host", "cfr_layout_free", "cfr_compile", "cfr_iterate",
+EXPORTS = ["cfr_default_options", "cfr_layout_host", "cfr_layout_free", "cfr_compile", "cfr_compile_batch",
+           "cfr_batch_size", "cfr_batch_exploitability", "cfr_iterate",
            "cfr_iterations", "cfr_strategy", "cfr_exploitability", "cfr_reset", "cfr_get_state", "cfr_set_regrets",
            "cfr_counts", "cfr_profile", "cfr_debug_rebind", "cfr_destroy", "cfr_last_error"]
 
@@ -100,6 +101,10 @@ def load():
         "cfr_layout_host": (S, [ctypes.POINTER(cfr_game_desc), ctypes.POINTER(cfr_layout)]),
         "cfr_layout_free": (None, [ctypes.POINTER(cfr_layout)]),
         "cfr_compile": (S, [ctypes.POINTER(cfr_game_desc), ctypes.POINTER(cfr_options), ctypes.POINTER(_P)]),
+        "cfr_compile_batch": (S, [ctypes.POINTER(cfr_game_desc), ctypes.c_int32, ctypes.POINTER(cfr_options),
+                                  ctypes.POINTER(_P)]),
+        "cfr_batch_size": (S, [_P, ctypes.POINTER(ctypes.c_int32), _P]),
+        "cfr_batch_exploitability": (S, [_P, _P, _P, _P, _P, _P, ctypes.c_int32]),
         "cfr_iterate": (S, [_P, ctypes.c_int64, _P]),
         "cfr_iterations": (S, [_P, ctypes.POINTER(ctypes.c_int64)]),
         "cfr_strategy": (S, [_P, ctypes.c_int, _P, ctypes.c_int64, ctypes.c_int, _P]),
@@ -200,6 +205,29 @@ def cfr_compile(game, options: cfr_options | None = None):
     return h
 
 
+def cfr_compile_batch(games, options: cfr_options | None = None):
+    gds = [g if isinstance(g, GameDesc) else GameDesc(g) for g in games]
+    arr = (cfr_game_desc * len(gds))(*[gd.desc for gd in gds])
+    h = _P()
+    _check(load().cfr_compile_batch(arr, len(gds), ctypes.byref(options) if options is not None else None,
+                                    ctypes.byref(h)))
+    return h
+
+
+def cfr_batch_size(h):
+    n = ctypes.c_int32()
+    _check(load().cfr_batch_size(h, ctypes.byref(n), None))
+    base = np.zeros(n.value + 1, np.int64)
+    _check(load().cfr_batch_size(h, ctypes.byref(n), _ptr(base)))
+    return n.value, base
+
+
+def cfr_batch_exploitability(h, n: int, stream=None):
+    out = [np.zeros(n) for _ in range(4)]
+    _check(load().cfr_batch_exploitability(h, stream, *[_ptr(a) for a in out], n))
+    return tuple(out)
+
+
 def cfr_iterate(h, n: int, stream=None):
     _check(load().cfr_iterate(h, int(n), stream))
 
@@ -273,9 +301,13 @@ class Solver:
         o.device, o.test_fail_capture = device, int(test_fail_capture)
         o.precision = precision
         self.options = o
-        self.h = cfr_compile(game, o)
+        if isinstance(game, (list, tuple)):
+            self.h = cfr_compile_batch(game, o)
+        else:
+            self.h = cfr_compile(game, o)
         self.counts = cfr_counts(self.h)
         self.A = int(self.counts["slots"])
+        self.n_games, self.slot_base = cfr_batch_size(self.h)
 
     @staticmethod
     def _stream(stream):
@@ -318,6 +350,10 @@ class Solver:
 
     def exploitability(self, stream=None):
         return cfr_exploitability(self.h, self._stream(stream))
+
+    def batch_exploitability(self, stream=None):
+        """(expl, br1, br2, value) arrays with one entry per game."""
+        return cfr_batch_exploitability(self.h, self.n_games, self._stream(stream))
 
     def reset(self):
         cfr_reset(self.h)

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <new>
 
 namespace cfrx {
@@ -238,7 +239,7 @@ inline int32_t edge_code(int owner, bool internal, int32_t slot) {
 }
 }  // namespace
 
-cfr_status build_device_layout(const Layout &L, int kind, DeviceLayout &D, std::string &err) {
+cfr_status build_device_layout(const Layout &L, int kind, int group_actions, DeviceLayout &D, std::string &err) {
     try {
         const int64_t N = L.N, I = L.I, A = L.A;
         const int md = L.max_depth;
@@ -376,7 +377,7 @@ cfr_status build_device_layout(const Layout &L, int kind, DeviceLayout &D, std::
         // update groups in device information-set order, never spanning two depths
         D.grp_iset_off.assign(1, 0);
         D.grp_depth_off.assign((size_t)md + 2, 0);
-        const int32_t cap = group_members(L.max_actions);
+        const int32_t cap = group_members(group_actions > L.max_actions ? group_actions : L.max_actions);
         for (int d = 0; d <= md; d++) {
             int32_t members = 0, sets = 0;
             for (int32_t i = D.iset_depth_off[d]; i < D.iset_depth_off[d + 1]; i++) {
@@ -398,9 +399,209 @@ cfr_status build_device_layout(const Layout &L, int kind, DeviceLayout &D, std::
                 if (L.node_type[inv[x]] == CFR_NODE_CHANCE && D.kid_off[x + 1] > D.kid_off[x]) D.chance_node.push_back(x);
             D.chance_off[d + 1] = (int32_t)D.chance_node.size();
         }
+        // single-game forest metadata
+        D.n_games = 1;
+        D.game_root.assign(1, 0);
+        D.game_slot_base = {0, (int64_t)A};
+        D.game_depth.assign(1, md);
+        D.game_range.assign((size_t)(md + 1) * GR_FIELDS, 0);
+        for (int d = 0; d <= md; d++) {
+            int32_t *r = &D.game_range[(size_t)d * GR_FIELDS];
+            r[0] = D.depth_off[d]; r[1] = D.depth_off[d + 1];
+            r[2] = D.grp_depth_off[d]; r[3] = D.grp_depth_off[d + 1];
+            r[4] = D.chance_off[d]; r[5] = D.chance_off[d + 1];
+        }
         return CFR_OK;
     } catch (const std::bad_alloc &) {
         err = "host allocation failed while building the device layout";
+        return CFR_ENOMEM;
+    }
+}
+
+cfr_status build_forest(std::vector<Layout> &Ls, std::vector<DeviceLayout> &Ds, DeviceLayout &F, std::string &err) {
+    try {
+        const int n = (int)Ds.size();
+        if (n == 1) {
+            F = std::move(Ds[0]);
+            Ds.clear();
+            return CFR_OK;
+        }
+        int MD = 0;
+        for (int s = 0; s < n; s++) MD = std::max(MD, (int)Ds[s].depth_off.size() - 2);
+        auto md_of = [&](int s) { return (int)Ds[s].depth_off.size() - 2; };
+        auto cnt = [&](const std::vector<int32_t> &off, int s, int d) -> int32_t {
+            return d <= md_of(s) ? off[d + 1] - off[d] : 0;
+        };
+        // node, set, group and chance bases per (depth, game)
+        std::vector<int64_t> nb((size_t)(MD + 1) * n), ib((size_t)(MD + 1) * n), gb((size_t)(MD + 1) * n),
+            cb((size_t)(MD + 1) * n);
+        F.depth_off.assign((size_t)MD + 2, 0);
+        F.iset_depth_off.assign((size_t)MD + 2, 0);
+        F.grp_depth_off.assign((size_t)MD + 2, 0);
+        F.chance_off.assign((size_t)MD + 2, 0);
+        int64_t N = 0, I = 0, G = 0, C = 0;
+        for (int d = 0; d <= MD; d++) {
+            F.depth_off[d] = (int32_t)N; F.iset_depth_off[d] = (int32_t)I;
+            F.grp_depth_off[d] = (int32_t)G; F.chance_off[d] = (int32_t)C;
+            for (int s = 0; s < n; s++) {
+                const DeviceLayout &D = Ds[s];
+                nb[(size_t)d * n + s] = N; ib[(size_t)d * n + s] = I;
+                gb[(size_t)d * n + s] = G; cb[(size_t)d * n + s] = C;
+                N += cnt(D.depth_off, s, d); I += cnt(D.iset_depth_off, s, d);
+                G += cnt(D.grp_depth_off, s, d); C += cnt(D.chance_off, s, d);
+            }
+        }
+        F.depth_off[MD + 1] = (int32_t)N; F.iset_depth_off[MD + 1] = (int32_t)I;
+        F.grp_depth_off[MD + 1] = (int32_t)G; F.chance_off[MD + 1] = (int32_t)C;
+        if (N > 0x7fffffffLL) { err = "batch too large"; return CFR_EINVAL; }
+        // per game: depth of each node and of each set, to remap ids
+        std::vector<std::vector<int8_t>> ndep(n), idep(n);
+        std::vector<std::vector<int32_t>> slot_set(n);
+        for (int s = 0; s < n; s++) {
+            const DeviceLayout &D = Ds[s];
+            ndep[s].resize(D.depth_off.back());
+            for (int d = 0; d <= md_of(s); d++)
+                for (int32_t x = D.depth_off[d]; x < D.depth_off[d + 1]; x++) ndep[s][x] = (int8_t)d;
+            const int32_t Is = D.iset_depth_off.back();
+            idep[s].resize(Is);
+            for (int d = 0; d <= md_of(s); d++)
+                for (int32_t i = D.iset_depth_off[d]; i < D.iset_depth_off[d + 1]; i++) idep[s][i] = (int8_t)d;
+            slot_set[s].resize(D.slot_off.empty() ? 0 : D.slot_off.back());
+            for (int32_t i = 0; i < Is; i++)
+                for (int32_t q = D.slot_off[i]; q < D.slot_off[i + 1]; q++) slot_set[s][q] = i;
+        }
+        auto node = [&](int s, int32_t x) -> int32_t {
+            const int d = ndep[s][x];
+            return (int32_t)(nb[(size_t)d * n + s] + (x - Ds[s].depth_off[d]));
+        };
+        auto iset = [&](int s, int32_t i) -> int32_t {
+            const int d = idep[s][i];
+            return (int32_t)(ib[(size_t)d * n + s] + (i - Ds[s].iset_depth_off[d]));
+        };
+        // sets and slots in forest order
+        F.slot_off.assign((size_t)I + 1, 0);
+        F.iset_player.assign((size_t)I, 0);
+        F.mem_off.assign((size_t)I + 1, 0);
+        for (int s = 0; s < n; s++) {
+            const DeviceLayout &D = Ds[s];
+            for (int32_t i = 0; i + 1 < (int32_t)D.slot_off.size(); i++) {
+                const int32_t fi = iset(s, i);
+                F.slot_off[fi + 1] = D.slot_off[i + 1] - D.slot_off[i];
+                F.mem_off[fi + 1] = D.mem_off[i + 1] - D.mem_off[i];
+                F.iset_player[fi] = D.iset_player[i];
+            }
+        }
+        for (int64_t i = 0; i < I; i++) { F.slot_off[i + 1] += F.slot_off[i]; F.mem_off[i + 1] += F.mem_off[i]; }
+        auto slot = [&](int s, int32_t q) -> int32_t {
+            const int32_t i = slot_set[s][q];
+            return F.slot_off[iset(s, i)] + (q - Ds[s].slot_off[i]);
+        };
+        // node arrays
+        int64_t E = 0;
+        for (int s = 0; s < n; s++) E += Ds[s].kid_off.back() - Ds[s].kid_off.front();
+        F.explicit_kids = true;
+        F.up_parent.assign((size_t)N, -1);
+        F.up_code.assign((size_t)N, 0);
+        F.node_slot.assign((size_t)N, -1);
+        F.node_iset.assign((size_t)N, -1);
+        F.tmpl.assign((size_t)N, 0.0f);
+        F.tmpl64.assign((size_t)N, 0.0);
+        F.kid_off.assign((size_t)N + 1, 0);
+        F.kid.assign((size_t)E, 0);
+        std::vector<int32_t> nkids((size_t)N, 0);
+        for (int s = 0; s < n; s++) {
+            const DeviceLayout &D = Ds[s];
+            const int32_t Ns = D.depth_off.back();
+            for (int32_t x = 0; x < Ns; x++) {
+                const int32_t fx = node(s, x);
+                F.up_parent[fx] = D.up_parent[x] >= 0 ? node(s, D.up_parent[x]) : -1;
+                int32_t code = D.up_code[x];
+                const int owner = code & 3;
+                if (owner) code = (int32_t)(((uint32_t)slot(s, (int32_t)((uint32_t)code >> 3)) << 3) | (uint32_t)(code & 7));
+                F.up_code[fx] = code;
+                if (D.node_iset[x] >= 0) {
+                    F.node_iset[fx] = iset(s, D.node_iset[x]);
+                    F.node_slot[fx] = F.slot_off[F.node_iset[fx]];
+                }
+                F.tmpl[fx] = D.tmpl[x];
+                F.tmpl64[fx] = D.tmpl64[x];
+                nkids[fx] = D.kid_off[x + 1] - D.kid_off[x];
+            }
+        }
+        for (int64_t x = 0; x < N; x++) F.kid_off[x + 1] = F.kid_off[x] + nkids[x];
+        for (int s = 0; s < n; s++) {
+            const DeviceLayout &D = Ds[s];
+            const int32_t Ns = D.depth_off.back();
+            for (int32_t x = 0; x < Ns; x++) {
+                const int32_t fx = node(s, x);
+                int32_t e = F.kid_off[fx];
+                for (int32_t k = D.kid_off[x]; k < D.kid_off[x + 1]; k++)
+                    F.kid[e++] = node(s, D.explicit_kids ? D.kid[k] : k);
+            }
+        }
+        // members (player tag kept), groups, chance nodes
+        F.mem_node.assign((size_t)F.mem_off[I], 0);
+        for (int s = 0; s < n; s++) {
+            const DeviceLayout &D = Ds[s];
+            for (int32_t i = 0; i + 1 < (int32_t)D.mem_off.size(); i++) {
+                int32_t w = F.mem_off[iset(s, i)];
+                for (int32_t k = D.mem_off[i]; k < D.mem_off[i + 1]; k++) {
+                    const uint32_t tag = (uint32_t)D.mem_node[k] & 0x80000000u;
+                    F.mem_node[w++] = (int32_t)((uint32_t)node(s, D.mem_node[k] & 0x7fffffff) | tag);
+                }
+            }
+        }
+        F.grp_iset_off.assign((size_t)G + 1, 0);
+        F.chance_node.assign((size_t)C, 0);
+        for (int d = 0; d <= MD; d++)
+            for (int s = 0; s < n; s++) {
+                const DeviceLayout &D = Ds[s];
+                if (d > md_of(s)) continue;
+                int64_t g = gb[(size_t)d * n + s];
+                for (int32_t k = D.grp_depth_off[d]; k < D.grp_depth_off[d + 1]; k++, g++) {
+                    F.grp_iset_off[g] = iset(s, D.grp_iset_off[k]);
+                    // a group ends where the next starts; the last set of the game's depth ends it
+                    const int32_t last = D.grp_iset_off[k + 1] - 1;
+                    F.grp_iset_off[g + 1] = iset(s, last) + 1;
+                }
+                int64_t c = cb[(size_t)d * n + s];
+                for (int32_t k = D.chance_off[d]; k < D.chance_off[d + 1]; k++) F.chance_node[c++] = node(s, D.chance_node[k]);
+            }
+        F.int_end.assign((size_t)MD + 1, 0);
+        for (int d = 0; d <= MD; d++) F.int_end[d] = F.depth_off[d + 1];  // terminals interleave across games
+        // canonical slots at the ABI: game s's canonical slots follow game s-1's
+        F.n_games = n;
+        F.game_root.resize(n);
+        F.game_depth.resize(n);
+        F.game_slot_base.assign((size_t)n + 1, 0);
+        for (int s = 0; s < n; s++) {
+            F.game_root[s] = node(s, 0);
+            F.game_depth[s] = md_of(s);
+            F.game_slot_base[s + 1] = F.game_slot_base[s] + (int64_t)slot_set[s].size();
+        }
+        F.slot_canon_to_dev.assign((size_t)F.game_slot_base[n], 0);
+        for (int s = 0; s < n; s++) {
+            const DeviceLayout &D = Ds[s];
+            const int64_t As = (int64_t)slot_set[s].size();
+            for (int64_t c = 0; c < As; c++) {
+                const int32_t q = D.slot_canon_to_dev.empty() ? (int32_t)c : D.slot_canon_to_dev[c];
+                F.slot_canon_to_dev[F.game_slot_base[s] + c] = slot(s, q);
+            }
+        }
+        F.game_range.assign((size_t)n * (MD + 1) * GR_FIELDS, 0);
+        for (int s = 0; s < n; s++)
+            for (int d = 0; d <= MD; d++) {
+                int32_t *r = &F.game_range[((size_t)s * (MD + 1) + d) * GR_FIELDS];
+                const size_t k = (size_t)d * n + s;
+                r[0] = (int32_t)nb[k]; r[1] = (int32_t)(nb[k] + cnt(Ds[s].depth_off, s, d));
+                r[2] = (int32_t)gb[k]; r[3] = (int32_t)(gb[k] + cnt(Ds[s].grp_depth_off, s, d));
+                r[4] = (int32_t)cb[k]; r[5] = (int32_t)(cb[k] + cnt(Ds[s].chance_off, s, d));
+            }
+        Ds.clear();
+        Ls.clear();
+        return CFR_OK;
+    } catch (const std::bad_alloc &) {
+        err = "host allocation failed while merging the batch";
         return CFR_ENOMEM;
     }
 }

@@ -76,12 +76,28 @@ struct DeviceLayout {
     // internal chance nodes by depth: chance_node[chance_off[d] .. chance_off[d + 1])
     std::vector<int32_t> chance_node;
     std::vector<int32_t> chance_off;     // [max_depth + 2]
+    // forests (batches of independent games, depth-major: the depth-d nodes of game 0, then of
+    // game 1, ...; likewise information sets, slots, groups and chance nodes)
+    int32_t n_games = 1;
+    std::vector<int32_t> game_root;      // [n] forest id of each game's root (= its index)
+    std::vector<int64_t> game_slot_base; // [n + 1] offsets of each game's canonical slots at the ABI
+    std::vector<int32_t> game_depth;     // [n] max depth of each game
+    // per game and depth d (stride GR_FIELDS): node range, group range, chance-node range, slot count
+    std::vector<int32_t> game_range;     // [n * (max_depth + 1) * GR_FIELDS]
 };
+
+constexpr int GR_FIELDS = 6;  // node lo, node hi, group lo, group hi, chance lo, chance hi
 
 constexpr int GROUP_SETS = 256;
 // members per update group: two per thread of a 256-thread block when sets have at most 4 actions
 inline int group_members(int max_actions) { return max_actions <= 4 ? 512 : 256; }
 
-cfr_status build_device_layout(const Layout &L, int layout_kind, DeviceLayout &out, std::string &err);
+// group_actions: the action bound the update groups are sized for (>= L.max_actions)
+cfr_status build_device_layout(const Layout &L, int layout_kind, int group_actions, DeviceLayout &out,
+                               std::string &err);
+
+// Merge the device layouts of independent games into one depth-major forest (see DeviceLayout).
+// Ls and Ds are consumed (moved or cleared).  A single game is moved through unchanged.
+cfr_status build_forest(std::vector<Layout> &Ls, std::vector<DeviceLayout> &Ds, DeviceLayout &F, std::string &err);
 
 }  // namespace cfrx

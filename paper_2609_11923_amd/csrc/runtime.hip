@@ -46,6 +46,11 @@ struct cfr_handle {
     // the static launch schedule of one iteration: (kind, depth), kind 0 tick, 1 forward, 2 level
     std::vector<std::pair<int, int>> plan;
     std::vector<int32_t> slot_map;     // canonical slot -> device slot (empty: identity)
+    // batches: number of games, canonical slot offsets, per-game depth and ranges, pots
+    int32_t n_games = 1;
+    std::vector<int64_t> game_slot_base;
+    std::vector<int32_t> game_depth, game_range;
+    std::vector<double> game_pot;
     int32_t D = 0;
     bool br_ok = true;
     int64_t E = 0, Z = 0;
@@ -147,8 +152,8 @@ cfr_status enqueue_iteration(cfr_handle *h, hipStream_t s, int64_t *count, Launc
 // Algorithmic bytes of one iteration per kernel: every index, state and value element a
 // kernel must touch in the device layout, counted once (sigma gathers count once per slot
 // and pass).
-void model_bytes(cfr_handle *h, const Layout &L, const DeviceLayout &D) {
-    const int md = L.max_depth;
+void model_bytes(cfr_handle *h, const DeviceLayout &D) {
+    const int md = (int)D.depth_off.size() - 2;
     const double es = (double)h->es;
     const double kb = D.explicit_kids ? 4.0 : 0.0;
     std::vector<double> Nr(md + 2, 0), Nint(md + 2, 0), Ad(md + 2, 0), Id(md + 2, 0), Md(md + 2, 0), Ed(md + 2, 0);
@@ -300,9 +305,11 @@ void cfr_layout_free(cfr_layout *l) {
     std::memset(l, 0, sizeof *l);
 }
 
-cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_handle **out) {
+// Compile one game or a batch of independent games (a depth-major forest, see build_forest).
+static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_options *opt, cfr_handle **out) {
     if (!out) return fail(CFR_EINVAL, "out is NULL");
     *out = nullptr;
+    if (!games || n <= 0) return fail(CFR_EINVAL, "no games");
     cfr_options o;
     cfr_default_options(&o);
     if (opt) o = *opt;
@@ -312,54 +319,79 @@ cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_ha
     if (o.layout != CFR_LAYOUT_BFS && o.layout != CFR_LAYOUT_PUBLIC) return fail(CFR_EINVAL, "unknown layout");
     if (o.iters_per_graph < 1 || o.iters_per_graph > 1000) return fail(CFR_EINVAL, "iters_per_graph must be in [1, 1000]");
     if (o.precision != CFR_PRECISION_FP32 && o.precision != CFR_PRECISION_FP64) return fail(CFR_EINVAL, "unknown precision");
-    Layout L;
     std::string err;
-    cfr_status st = build_layout(game, L, err);
-    if (st != CFR_OK) return fail(st, err);
-    if (!L.br_ok)
-        return fail(CFR_EUNSUPPORTED, "an information set has members at different depths; the level-fused "
-                                      "update needs every set on one depth");
+    cfr_status st = CFR_OK;
+    // canonical layouts first: the update groups of every game are sized for the batch's action bound
+    std::vector<Layout> Ls((size_t)n);
+    int64_t N = 0, E = 0, Z = 0, Ndec = 0, I = 0, A = 0;
+    int max_actions = 0, max_depth = 0, blocks = 0;
+    for (int s = 0; s < n; s++) {
+        st = build_layout(&games[s], Ls[s], err);
+        if (st != CFR_OK) return fail(st, n > 1 ? "game " + std::to_string(s) + ": " + err : err);
+        if (!Ls[s].br_ok)
+            return fail(CFR_EUNSUPPORTED, "an information set has members at different depths; the level-fused "
+                                          "update needs every set on one depth");
+        N += Ls[s].N; E += Ls[s].E; Z += Ls[s].Z; Ndec += Ls[s].Ndec; I += Ls[s].I; A += Ls[s].A;
+        max_actions = std::max(max_actions, Ls[s].max_actions);
+        max_depth = std::max(max_depth, Ls[s].max_depth);
+        blocks = std::max(blocks, Ls[s].D);
+    }
+    if (N > 0x7fffffffLL || A > (1LL << 28)) return fail(CFR_EINVAL, "batch too large");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(CFR_EDEVICE, "no HIP device available");
     if (o.device < 0 || o.device >= ndev) return fail(CFR_EINVAL, "device ordinal out of range");
     HIP_TRY(hipSetDevice(o.device));
 
+    DeviceLayout DL;
+    {
+        std::vector<DeviceLayout> Ds((size_t)n);
+        for (int s = 0; s < n; s++) {
+            st = build_device_layout(Ls[s], o.layout, max_actions, Ds[s], err);
+            if (st != CFR_OK) return fail(st, err);
+            if (n > 1) Ls[s] = Layout();  // free the canonical arrays early
+        }
+        st = build_forest(Ls, Ds, DL, err);
+        if (st != CFR_OK) return fail(st, err);
+    }
     cfr_handle *h = new cfr_handle();
     h->opt = o;
     h->use_graph = o.use_graph != 0;
-    DeviceLayout DL;
-    st = build_device_layout(L, o.layout, DL, err);
-    if (st != CFR_OK) { delete h; return fail(st, err); }
     h->depth_off = DL.depth_off;
     h->int_end = DL.int_end;
     h->iset_depth_off = DL.iset_depth_off;
     h->slot_map = DL.slot_canon_to_dev;
     h->grp_depth_off = DL.grp_depth_off;
     h->chance_off = DL.chance_off;
-    h->D = L.D;
-    h->br_ok = L.br_ok;
-    h->E = L.E; h->Z = L.Z; h->pot = game->pot;
+    h->n_games = DL.n_games;
+    h->game_slot_base = DL.game_slot_base;
+    h->game_depth = DL.game_depth;
+    h->game_range = DL.game_range;
+    for (int s = 0; s < n; s++) h->game_pot.push_back(games[s].pot);
+    h->D = blocks;
+    h->br_ok = true;
+    h->E = E; h->Z = Z; h->pot = games[0].pot;
     DevGame &g = h->g;
-    g.N = (int32_t)L.N; g.I = (int32_t)L.I; g.A = (int32_t)L.A; g.Ndec = (int32_t)L.Ndec;
-    g.max_depth = L.max_depth; g.max_actions = L.max_actions;
+    g.N = (int32_t)N; g.I = (int32_t)I; g.A = (int32_t)A; g.Ndec = (int32_t)Ndec;
+    g.max_depth = max_depth; g.max_actions = max_actions;
     g.fp64 = o.precision == CFR_PRECISION_FP64 ? 1 : 0;
     g.explicit_kids = DL.explicit_kids ? 1 : 0;
     h->es = g.fp64 ? 8 : 4;
-    const int64_t N = L.N, I = L.I, A = L.A;
 
     std::vector<int2> up((size_t)N);
-    for (int64_t n = 0; n < N; n++) up[n] = make_int2(DL.up_parent[n], DL.up_code[n]);
+    for (int64_t k = 0; k < N; k++) up[k] = make_int2(DL.up_parent[k], DL.up_code[k]);
+    DL.up_parent = std::vector<int32_t>();
+    DL.up_code = std::vector<int32_t>();
 
-#define ALLOC(ptr, n) do { st = dev_alloc(h, &(ptr), (n)); if (st != CFR_OK) { free_handle(h); return st; } } while (0)
+#define ALLOC(ptr, cnt) do { st = dev_alloc(h, &(ptr), (cnt)); if (st != CFR_OK) { free_handle(h); return st; } } while (0)
     ALLOC(g.up, N);
     ALLOC(g.kid_off, N + 1);
-    if (g.explicit_kids) ALLOC(g.kid, L.E);
+    if (g.explicit_kids) ALLOC(g.kid, E);
     if (!h->slot_map.empty()) ALLOC(g.slot_map, A);
     ALLOC(g.node_slot, N);
     ALLOC(g.node_iset, N);
     ALLOC(g.slot_off, I + 1);
     ALLOC(g.mem_off, I + 1);
-    ALLOC(g.mem, L.Ndec);
+    ALLOC(g.mem, Ndec);
     ALLOC(g.iset_player, I);
     g.G = (int32_t)DL.grp_iset_off.size() - 1;
     ALLOC(g.grp_iset_off, (int64_t)DL.grp_iset_off.size());
@@ -394,8 +426,8 @@ cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_ha
     UP(g.slot_off, DL.slot_off);
     UP(g.mem_off, DL.mem_off);
     {
-        std::vector<int2> mem((size_t)L.Ndec);
-        for (int64_t k = 0; k < L.Ndec; k++)
+        std::vector<int2> mem((size_t)Ndec);
+        for (int64_t k = 0; k < Ndec; k++)
             mem[k] = make_int2(DL.mem_node[k], DL.kid_off[DL.mem_node[k] & MEMBER_NODE_MASK]);
         UP(g.mem, mem);
     }
@@ -404,25 +436,43 @@ cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_ha
     UP(g.chance_node, DL.chance_node);
     if (g.fp64) { UP((double *)g.v, DL.tmpl64); } else { UP((float *)g.v, DL.tmpl); }
     UP(g.vbr, DL.tmpl64);
-#undef UP
     {
-        // root reach = 1 in both lanes and in the best-response lane; written once, never overwritten
-        float one = 1.0f;
-        double oned = 1.0;
-        const void *src = g.fp64 ? (const void *)&oned : (const void *)&one;
+        // roots (the first n nodes) have reach 1 in both lanes and in the best-response lane;
+        // written once, never overwritten
+        std::vector<float> onef((size_t)n, 1.0f);
+        std::vector<double> oned((size_t)n, 1.0);
         char *r = (char *)g.reach;
-        hipError_t e = hipMemcpy(r, src, h->es, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(r + N * (int64_t)h->es, src, h->es, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(g.qbr, &oned, sizeof oned, hipMemcpyHostToDevice);
+        const void *src = g.fp64 ? (const void *)oned.data() : (const void *)onef.data();
+        hipError_t e = hipMemcpy(r, src, h->es * n, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(r + N * (int64_t)h->es, src, h->es * n, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(g.qbr, oned.data(), sizeof(double) * n, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
         if (e != hipSuccess) { free_handle(h); return fail(CFR_EDEVICE, std::string("setup: ") + hipGetErrorString(e)); }
     }
+#undef UP
     build_plan(h);
     h->launches = (int64_t)h->plan.size();
-    model_bytes(h, L, DL);
+    model_bytes(h, DL);
     st = cfr_reset(h);
     if (st != CFR_OK) { free_handle(h); return st; }
     *out = h;
+    return CFR_OK;
+}
+
+cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_handle **out) {
+    if (!game) return fail(CFR_EINVAL, "game description is NULL");
+    return compile_games(game, 1, opt, out);
+}
+
+cfr_status cfr_compile_batch(const cfr_game_desc *games, int32_t n, const cfr_options *opt, cfr_handle **out) {
+    return compile_games(games, n, opt, out);
+}
+
+cfr_status cfr_batch_size(cfr_handle *h, int32_t *n_games, int64_t *slot_base) {
+    if (!h) return fail(CFR_EINVAL, "handle is NULL");
+    if (n_games) *n_games = h->n_games;
+    if (slot_base)
+        for (int s = 0; s <= h->n_games; s++) slot_base[s] = h->game_slot_base[(size_t)s];
     return CFR_OK;
 }
 
@@ -562,14 +612,13 @@ cfr_status cfr_set_regrets(cfr_handle *h, const float *r0, int64_t len, int src_
     return CFR_OK;
 }
 
-cfr_status cfr_exploitability(cfr_handle *h, void *stream, double *expl, double *br1, double *br2,
-                              double *value_avg) {
-    if (!h) return fail(CFR_EINVAL, "handle is NULL");
+// Best responses of every game of the handle: vals[k][s] for k = best responder 1, 2 and the
+// average-profile value (k = 0), read at each game's root.
+static cfr_status best_responses(cfr_handle *h, hipStream_t s, std::vector<double> vals[3]) {
     if (!h->br_ok) return fail(CFR_EUNSUPPORTED, "an information set spans several depths; the level-synchronous best response needs one depth per set");
     HIP_TRY(hipSetDevice(h->opt.device));
-    hipStream_t s = (hipStream_t)stream;
     const DevGame &g = h->g;
-    double vals[3] = {0, 0, 0};
+    const int n = h->n_games;
     HIP_TRY(launch_average(g, s));
     const int order[3] = {1, 2, 0};
     for (int k = 0; k < 3; k++) {
@@ -580,16 +629,42 @@ cfr_status cfr_exploitability(cfr_handle *h, void *stream, double *expl, double 
             if (br != 0) HIP_TRY(launch_br_argmax(g, h->iset_depth_off[d], h->iset_depth_off[d + 1], br, s));
             HIP_TRY(launch_br_backward(g, h->depth_off[d], h->int_end[d], br, s));
         }
-        double root = 0.0;
-        HIP_TRY(hipMemcpyAsync(&root, g.vbr, sizeof(double), hipMemcpyDeviceToHost, s));
+        vals[br].assign((size_t)n, 0.0);
+        HIP_TRY(hipMemcpyAsync(vals[br].data(), g.vbr, sizeof(double) * n, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        vals[br] = root;
     }
-    double b1 = vals[1], b2 = -vals[2];
+    return CFR_OK;
+}
+
+cfr_status cfr_exploitability(cfr_handle *h, void *stream, double *expl, double *br1, double *br2,
+                              double *value_avg) {
+    if (!h) return fail(CFR_EINVAL, "handle is NULL");
+    if (h->n_games != 1) return fail(CFR_EINVAL, "handle holds a batch; use cfr_batch_exploitability");
+    std::vector<double> vals[3];
+    cfr_status st = best_responses(h, (hipStream_t)stream, vals);
+    if (st != CFR_OK) return st;
+    double b1 = vals[1][0], b2 = -vals[2][0];
     if (br1) *br1 = b1;
     if (br2) *br2 = b2;
-    if (value_avg) *value_avg = vals[0];
+    if (value_avg) *value_avg = vals[0][0];
     if (expl) *expl = 0.5 * (b1 + b2);
+    return CFR_OK;
+}
+
+cfr_status cfr_batch_exploitability(cfr_handle *h, void *stream, double *expl, double *br1, double *br2,
+                                    double *value_avg, int32_t n) {
+    if (!h) return fail(CFR_EINVAL, "handle is NULL");
+    if (n != h->n_games) return fail(CFR_EINVAL, "n must equal the number of games " + std::to_string(h->n_games));
+    std::vector<double> vals[3];
+    cfr_status st = best_responses(h, (hipStream_t)stream, vals);
+    if (st != CFR_OK) return st;
+    for (int s = 0; s < n; s++) {
+        const double b1 = vals[1][(size_t)s], b2 = -vals[2][(size_t)s];
+        if (br1) br1[s] = b1;
+        if (br2) br2[s] = b2;
+        if (value_avg) value_avg[s] = vals[0][(size_t)s];
+        if (expl) expl[s] = 0.5 * (b1 + b2);
+    }
     return CFR_OK;
 }
 
