@@ -105,6 +105,9 @@ typedef struct {
     int test_fail_capture; /* test hook: treat graph capture as failed (warns once, launches directly) */
     int precision;         /* CFR_PRECISION_*: type of reach, values, regrets and strategy (default FP32);
                               strategy sums are FP64 in both */
+    int persistent;        /* 1: each cfr_iterate call is one persistent launch running all n iterations
+                              of every game, with per-game barriers (default 0: one launch per level) */
+    int wg_nodes;          /* persistent form: target nodes per workgroup (0 = 16384); cfr_autotune picks it */
 } cfr_options;
 
 /* Sizes of a compiled game.  blocks = number of depth levels that hold edges (D of eq. blocks). */
@@ -162,6 +165,26 @@ cfr_status cfr_compile(const cfr_game_desc *game, const cfr_options *opt, cfr_ha
  * validated one by one; the message of a failure names the game.  n == 1 equals cfr_compile. */
 cfr_status cfr_compile_batch(const cfr_game_desc *games, int32_t n, const cfr_options *opt, cfr_handle **out);
 
+/* Schedule chosen by cfr_autotune. */
+typedef struct {
+    int32_t persistent;        /* 1 persistent launch, 0 one launch per level (graph replay) */
+    int32_t wg_nodes;          /* persistent form: target nodes per workgroup */
+    int32_t blocks;            /* persistent form: workgroups of the launch */
+    int32_t candidates;        /* schedules measured (0 when read from the cache) */
+    double  ms_per_iteration;  /* measured time of the chosen schedule */
+} cfr_tune_result;
+
+/* Autotuner: time `iters` iterations under each candidate schedule -- one launch per level, and
+ * the persistent launch at several workgroup sizes -- keep the fastest, and reset the solver
+ * state (the measurement iterations are discarded).  With cache_path != NULL the choice is read
+ * from / appended to that text file, keyed by device name, precision and the handle's sizes.
+ * Synchronous. */
+cfr_status cfr_autotune(cfr_handle *h, int64_t iters, void *stream, const char *cache_path, cfr_tune_result *out);
+
+/* Select a schedule explicitly (as cfr_autotune would): persistent 0/1 and, for the persistent
+ * form, the target nodes per workgroup (0 = 16384). */
+cfr_status cfr_set_schedule(cfr_handle *h, int32_t persistent, int32_t wg_nodes);
+
 /* Number of games in the handle and (if slot_base != NULL) the n + 1 offsets of each game's
  * canonical slots in the per-slot arrays. */
 cfr_status cfr_batch_size(cfr_handle *h, int32_t *n_games, int64_t *slot_base);
@@ -174,7 +197,9 @@ cfr_status cfr_batch_exploitability(cfr_handle *h, void *stream, double *expl, d
 /* Run n CFR iterations on `stream` (asynchronous).  The first call captures the iteration
  * body into a hipGraph (after one direct iteration that counts toward n) and later calls
  * replay it.  n == 0 is a no-op.  Returns CFR_ESTATE if a persistent buffer recorded at
- * capture time has changed. */
+ * capture time has changed.  Under the persistent schedule the call is one launch that runs all
+ * n iterations and synchronises `stream`, so that a per-game barrier time-out (CFR_EDEVICE) is
+ * reported by the call that hit it. */
 cfr_status cfr_iterate(cfr_handle *h, int64_t n, void *stream);
 
 /* Iterations completed so far (host count). */

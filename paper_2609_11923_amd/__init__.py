@@ -42,7 +42,13 @@ class cfr_game_desc(ctypes.Structure):
 class cfr_options(ctypes.Structure):
     _fields_ = [("rule", ctypes.c_int), ("averaging", ctypes.c_int), ("order", ctypes.c_int),
                 ("iters_per_graph", ctypes.c_int), ("layout", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("device", ctypes.c_int), ("test_fail_capture", ctypes.c_int), ("precision", ctypes.c_int)]
+                ("device", ctypes.c_int), ("test_fail_capture", ctypes.c_int), ("precision", ctypes.c_int),
+                ("persistent", ctypes.c_int), ("wg_nodes", ctypes.c_int)]
+
+
+class cfr_tune_result(ctypes.Structure):
+    _fields_ = [("persistent", ctypes.c_int32), ("wg_nodes", ctypes.c_int32), ("blocks", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("ms_per_iteration", ctypes.c_double)]
 
 
 class cfr_counts_t(ctypes.Structure):
@@ -75,7 +81,7 @@ _lib = None
 
 # exported symbols of include/cfr.h (the ABI tests check the library exports each one)
 EXPORTS = ["cfr_default_options", "cfr_layout_host", "cfr_layout_free", "cfr_compile", "cfr_compile_batch",
-           "cfr_batch_size", "cfr_batch_exploitability", "cfr_iterate",
+           "cfr_batch_size", "cfr_batch_exploitability", "cfr_autotune", "cfr_set_schedule", "cfr_iterate",
            "cfr_iterations", "cfr_strategy", "cfr_exploitability", "cfr_reset", "cfr_get_state", "cfr_set_regrets",
            "cfr_counts", "cfr_profile", "cfr_debug_rebind", "cfr_destroy", "cfr_last_error"]
 
@@ -105,6 +111,8 @@ def load():
                                   ctypes.POINTER(_P)]),
         "cfr_batch_size": (S, [_P, ctypes.POINTER(ctypes.c_int32), _P]),
         "cfr_batch_exploitability": (S, [_P, _P, _P, _P, _P, _P, ctypes.c_int32]),
+        "cfr_autotune": (S, [_P, ctypes.c_int64, _P, ctypes.c_char_p, ctypes.POINTER(cfr_tune_result)]),
+        "cfr_set_schedule": (S, [_P, ctypes.c_int32, ctypes.c_int32]),
         "cfr_iterate": (S, [_P, ctypes.c_int64, _P]),
         "cfr_iterations": (S, [_P, ctypes.POINTER(ctypes.c_int64)]),
         "cfr_strategy": (S, [_P, ctypes.c_int, _P, ctypes.c_int64, ctypes.c_int, _P]),
@@ -228,6 +236,16 @@ def cfr_batch_exploitability(h, n: int, stream=None):
     return tuple(out)
 
 
+def cfr_autotune(h, iters: int, stream=None, cache_path: str | None = None) -> dict:
+    r = cfr_tune_result()
+    _check(load().cfr_autotune(h, int(iters), stream, cache_path.encode() if cache_path else None, ctypes.byref(r)))
+    return {f: getattr(r, f) for f, _ in cfr_tune_result._fields_}
+
+
+def cfr_set_schedule(h, persistent: bool, wg_nodes: int = 0):
+    _check(load().cfr_set_schedule(h, int(persistent), int(wg_nodes)))
+
+
 def cfr_iterate(h, n: int, stream=None):
     _check(load().cfr_iterate(h, int(n), stream))
 
@@ -294,12 +312,13 @@ class Solver:
 
     def __init__(self, game, rule=CFR_RULE_CFR_PLUS, averaging=CFR_AVG_LINEAR, order=CFR_ORDER_SIMULTANEOUS,
                  iters_per_graph=1, layout=CFR_LAYOUT_PUBLIC, use_graph=True, device=0, test_fail_capture=False,
-                 precision=CFR_PRECISION_FP32):
+                 precision=CFR_PRECISION_FP32, persistent=False, wg_nodes=0):
         o = cfr_default_options()
         o.rule, o.averaging, o.order = rule, averaging, order
         o.iters_per_graph, o.layout, o.use_graph = iters_per_graph, layout, int(use_graph)
         o.device, o.test_fail_capture = device, int(test_fail_capture)
         o.precision = precision
+        o.persistent, o.wg_nodes = int(persistent), int(wg_nodes)
         self.options = o
         if isinstance(game, (list, tuple)):
             self.h = cfr_compile_batch(game, o)
@@ -350,6 +369,12 @@ class Solver:
 
     def exploitability(self, stream=None):
         return cfr_exploitability(self.h, self._stream(stream))
+
+    def autotune(self, iters: int, stream=None, cache_path=None) -> dict:
+        return cfr_autotune(self.h, iters, self._stream(stream), cache_path)
+
+    def set_schedule(self, persistent: bool, wg_nodes: int = 0):
+        cfr_set_schedule(self.h, persistent, wg_nodes)
 
     def batch_exploitability(self, stream=None):
         """(expl, br1, br2, value) arrays with one entry per game."""

@@ -16,6 +16,10 @@ constexpr int CODE_SLOT_SHIFT = 3;
 // paired with the node's first edge so that no edge-offset lookup sits on the load chain.
 constexpr int32_t MEMBER_NODE_MASK = 0x7fffffff;
 constexpr int32_t MEMBER_P2 = (int32_t)0x80000000u;
+// fields per (game, depth) in game_range: node lo/hi, group lo/hi, chance lo/hi
+constexpr int GR_FIELDS_DEV = 6;
+// bound on one barrier wait (spins of ~100 ns): a stuck wait raises the error flag instead of hanging
+constexpr int64_t BARRIER_SPIN_LIMIT = 20000000;
 
 struct DevGame {
     int32_t N = 0, I = 0, A = 0, Ndec = 0, max_depth = 0, max_actions = 0;
@@ -66,6 +70,17 @@ hipError_t launch_forward(const DevGame &g, int32_t lo, int32_t hi, int32_t *tic
 hipError_t launch_level(const DevGame &g, int d, IterFlags f, hipStream_t s);
 // sigma <- regret matching of R (all information sets)
 hipError_t launch_regret_matching(const DevGame &g, hipStream_t s);
+// The persistent batched launch: work table (one int4 per block: game, rank, blocks of the game),
+// per-game level ranges and depths, barrier counters and the time-out flag (all device memory).
+struct PersistentPlan {
+    int32_t blocks = 0, n_games = 0, max_depth = 0;
+    int4 *wg_table = nullptr;
+    int32_t *game_range = nullptr, *game_depth = nullptr, *barrier = nullptr, *err = nullptr;
+};
+// zero the barriers, run T iterations of every game in one launch, advance the counter by T
+hipError_t launch_persistent(const DevGame &g, const PersistentPlan &p, int32_t T, IterFlags f, hipStream_t s);
+// resident blocks per compute unit of the persistent kernel for this game's configuration
+hipError_t persistent_occupancy(const DevGame &g, int *blocks_per_cu);
 // counter bump for games without edges
 hipError_t launch_tick(const DevGame &g, hipStream_t s);
 // out2[q] <- normalised average strategy (float, device order), sigbar[q] <- same in double

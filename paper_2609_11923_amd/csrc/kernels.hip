@@ -36,85 +36,100 @@ __device__ __forceinline__ int32_t child_of(const int32_t *__restrict__ kid, int
     else return edge;
 }
 
+// Forward reach of one node c (eqs. reach, lanes): both lanes copy the parent's reach; the lane of
+// the parent's owner multiplies by sigma(slot).  Terminals carry no reach.
+template <typename T>
+__device__ __forceinline__ void forward_node(int32_t c, const int2 *__restrict__ up, const T *__restrict__ sigma,
+                                             T *__restrict__ r1, T *__restrict__ r2) {
+    const int2 u = up[c];
+    if (!(u.y & CODE_INTERNAL)) return;
+    const int owner = u.y & CODE_OWNER_MASK;
+    const T s = owner ? sigma[u.y >> CODE_SLOT_SHIFT] : T(1);
+    const T a = r1[u.x], b = r2[u.x];
+    r1[c] = owner == 1 ? a * s : a;
+    r2[c] = owner == 2 ? b * s : b;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_forward(int32_t lo, int32_t hi, const int2 *__restrict__ up,
                                                    const T *__restrict__ sigma, T *__restrict__ r1,
                                                    T *__restrict__ r2, int32_t *tick) {
     if (tick && blockIdx.x == 0 && threadIdx.x == 0) tick[0] += 1;
-    int32_t c = lo + (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
-    if (c >= hi) return;
-    int2 u = up[c];
-    if (!(u.y & CODE_INTERNAL)) return;
-    int owner = u.y & CODE_OWNER_MASK;
-    T s = owner ? sigma[u.y >> CODE_SLOT_SHIFT] : T(1);
-    T a = r1[u.x], b = r2[u.x];
-    r1[c] = owner == 1 ? a * s : a;
-    r2[c] = owner == 2 ? b * s : b;
+    const int32_t c = lo + (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
+    if (c < hi) forward_node<T>(c, up, sigma, r1, r2);
 }
 
-// One backward level fused with the regret / average / regret-matching update of the
-// information sets on that level.  Launched once per depth d (deepest first) with
-//   blocks [0, ngroups)            one update group each: consecutive information sets of depth d
-//                                  with at most BLOCK members and BLOCK sets in total
-//   blocks [ngroups, ...)          one thread per internal chance node of depth d
-// Group blocks, phase 1 (one thread per member h, coalesced over the member list):
-//   v(h) = sum_a sigma^t(I, a) v(h.a)   -- written to v, the backward value pass at h
+// Arrays read and written by the backward/update level.
+template <typename T>
+struct LevelArgs {
+    const int32_t *grp_iset_off, *slot_off, *mem_off;
+    const int2 *mem;
+    const int8_t *iset_player;
+    const int32_t *kid_off, *kid, *chance_node;
+    T *v;
+    T *r1, *r2;   // reach lanes (the level only reads them; the persistent form's forward levels write)
+    T *R;
+    double *sbar;
+    T *sigma;
+};
+
+// Value of an internal chance node: the sum of its children (chance folded into the template).
+template <typename T, bool EXPLICIT>
+__device__ __forceinline__ void chance_value(int32_t h, const LevelArgs<T> &a) {
+    const int32_t b = a.kid_off[h], e = a.kid_off[h + 1];
+    T acc = T(0);
+    for (int32_t c = b; c < e; c++) acc += a.v[child_of<EXPLICIT>(a.kid, c)];
+    a.v[h] = acc;
+}
+
+// LDS staging of one update group (members of a chunk, the group's set offsets)
+template <typename T, int MAXA, int MPT>
+struct GroupLds {
+    T po[MPT * BLOCK];
+    T diff[MPT * BLOCK * MAXA];
+    int32_t moff[BLOCK + 1];
+    int32_t slot[BLOCK + 1];
+};
+
+// One update group: consecutive information sets of one depth with at most MPT * BLOCK members
+// and BLOCK sets.  Phase 1 (one thread per member h, coalesced over the member list):
+//   v(h) = sum_a sigma^t(I, a) v(h.a)   -- written to v: the backward value pass at h
 //   stage pi_{-i}(h) and v(h.a) - v(h) in LDS.
 // Phase 2 (one thread per set I): reduce the set's members from LDS in ascending member order,
 //   r(I,a) = sum_h s_i pi_{-i}(h) (v(h.a) - v(h)), then R <- R + r (CFR+: max(R, 0)),
 //   sbar += w_t pi_i(I) sigma^t (FP64), sigma^{t+1} = regret matching of R.
-// Only this block reads sigma(I) during the backward pass (all members of I are here), and the
+// Only this group reads sigma(I) during the backward pass (all members of I are here), and the
 // forward pass has already consumed it, so overwriting sigma(I) with sigma^{t+1} is safe.
-// Sets with more than BLOCK members are streamed through LDS in chunks.
+// Sets with more members than a chunk are streamed through LDS chunk by chunk.  Must be called by
+// every thread of the block (it synchronises the block).
 template <typename T, int MAXA, int MPT, bool EXPLICIT>
-__global__ void __launch_bounds__(BLOCK) k_level(
-    int32_t gbeg, int32_t ngroups, const int32_t *__restrict__ chance_node, int32_t cbeg, int32_t nchance,
-    const int32_t *__restrict__ grp_iset_off, const int32_t *__restrict__ slot_off,
-    const int32_t *__restrict__ mem_off, const int2 *__restrict__ mem, const int8_t *__restrict__ iset_player,
-    const int32_t *__restrict__ kid_off, const int32_t *__restrict__ kid, T *__restrict__ v,
-    const T *__restrict__ r1, const T *__restrict__ r2, T *__restrict__ R, double *__restrict__ sbar,
-    T *__restrict__ sigma, const int32_t *__restrict__ tcount, int plus, int linear) {
+__device__ void group_update(int32_t g, double w, int plus, const LevelArgs<T> &a, GroupLds<T, MAXA, MPT> &L) {
     constexpr int CHUNK = MPT * BLOCK;
     const int tid = threadIdx.x;
-    if ((int32_t)blockIdx.x >= ngroups) {
-        const int32_t j = ((int32_t)blockIdx.x - ngroups) * BLOCK + tid;
-        if (j >= nchance) return;
-        const int32_t h = chance_node[cbeg + j];
-        const int32_t b = kid_off[h], e = kid_off[h + 1];
-        T acc = T(0);
-        for (int32_t c = b; c < e; c++) acc += v[child_of<EXPLICIT>(kid, c)];
-        v[h] = acc;
-        return;
-    }
-    __shared__ T s_po[CHUNK];
-    __shared__ T s_diff[CHUNK * MAXA];
-    __shared__ int32_t s_moff[BLOCK + 1];
-    __shared__ int32_t s_slot[BLOCK + 1];
-    const int32_t g = gbeg + (int32_t)blockIdx.x;
-    const int32_t i0 = grp_iset_off[g], i1 = grp_iset_off[g + 1];
+    const int32_t i0 = a.grp_iset_off[g], i1 = a.grp_iset_off[g + 1];
     const int32_t nsets = i1 - i0;
     if (tid < nsets) {
-        s_moff[tid] = mem_off[i0 + tid];
-        s_slot[tid] = slot_off[i0 + tid];
+        L.moff[tid] = a.mem_off[i0 + tid];
+        L.slot[tid] = a.slot_off[i0 + tid];
     }
     if (tid == 0) {
-        s_moff[nsets] = mem_off[i1];
-        s_slot[nsets] = slot_off[i1];
+        L.moff[nsets] = a.mem_off[i1];
+        L.slot[nsets] = a.slot_off[i1];
     }
     __syncthreads();
-    const int32_t mbeg = s_moff[0], mend = s_moff[nsets];
+    const int32_t mbeg = L.moff[0], mend = L.moff[nsets];
     const bool has_set = tid < nsets;
     int32_t s0 = 0, nA = 0, m0 = 0, m1 = 0, pl = 1;
     if (has_set) {
-        s0 = s_slot[tid];
-        nA = s_slot[tid + 1] - s0;
-        m0 = s_moff[tid];
-        m1 = s_moff[tid + 1];
-        pl = iset_player[i0 + tid];
+        s0 = L.slot[tid];
+        nA = L.slot[tid + 1] - s0;
+        m0 = L.moff[tid];
+        m1 = L.moff[tid + 1];
+        pl = a.iset_player[i0 + tid];
     }
     T r[MAXA];
 #pragma unroll
-    for (int a = 0; a < MAXA; a++) r[a] = T(0);
+    for (int k = 0; k < MAXA; k++) r[k] = T(0);
     for (int32_t cb = mbeg; cb < mend; cb += CHUNK) {
         const int32_t ce = min(cb + CHUNK, mend);
 #pragma unroll
@@ -122,67 +137,165 @@ __global__ void __launch_bounds__(BLOCK) k_level(
             const int32_t j = u * BLOCK + tid;
             const int32_t m = cb + j;
             if (m < ce) {
-                // the set of member m: the last k with s_moff[k] <= m
+                // the set of member m: the last k with moff[k] <= m
                 int32_t lo = 0, hi = nsets - 1;
                 while (lo < hi) {
                     const int32_t mid = (lo + hi + 1) >> 1;
-                    if (s_moff[mid] <= m) lo = mid; else hi = mid - 1;
+                    if (L.moff[mid] <= m) lo = mid; else hi = mid - 1;
                 }
-                const int32_t sb = s_slot[lo], na = s_slot[lo + 1] - sb;
-                const int2 x = mem[m];
+                const int32_t sb = L.slot[lo], na = L.slot[lo + 1] - sb;
+                const int2 x = a.mem[m];
                 const int32_t h = x.x & MEMBER_NODE_MASK;
-                const T po = (x.x & MEMBER_P2) ? r1[h] : r2[h];
+                const T po = (x.x & MEMBER_P2) ? a.r1[h] : a.r2[h];
                 T cv[MAXA];
                 T vh = T(0);
 #pragma unroll
-                for (int a = 0; a < MAXA; a++)
-                    if (a < na) cv[a] = v[child_of<EXPLICIT>(kid, x.y + a)];
+                for (int k = 0; k < MAXA; k++)
+                    if (k < na) cv[k] = a.v[child_of<EXPLICIT>(a.kid, x.y + k)];
 #pragma unroll
-                for (int a = 0; a < MAXA; a++)
-                    if (a < na) vh = fma_t(sigma[sb + a], cv[a], vh);
-                v[h] = vh;
-                s_po[j] = po;
+                for (int k = 0; k < MAXA; k++)
+                    if (k < na) vh = fma_t(a.sigma[sb + k], cv[k], vh);
+                a.v[h] = vh;
+                L.po[j] = po;
 #pragma unroll
-                for (int a = 0; a < MAXA; a++)
-                    if (a < na) s_diff[j * MAXA + a] = cv[a] - vh;
+                for (int k = 0; k < MAXA; k++)
+                    if (k < na) L.diff[j * MAXA + k] = cv[k] - vh;
             }
         }
         __syncthreads();
         if (has_set) {
             const int32_t lo = max(m0, cb), hi = min(m1, ce);
             for (int32_t k = lo - cb; k < hi - cb; k++) {
-                const T po = s_po[k];
+                const T po = L.po[k];
 #pragma unroll
-                for (int a = 0; a < MAXA; a++)
-                    if (a < nA) r[a] = fma_t(po, s_diff[k * MAXA + a], r[a]);
+                for (int q = 0; q < MAXA; q++)
+                    if (q < nA) r[q] = fma_t(po, L.diff[k * MAXA + q], r[q]);
             }
         }
         __syncthreads();
     }
     if (!has_set) return;
-    const T *own = pl == 1 ? r1 : r2;
+    const T *own = pl == 1 ? a.r1 : a.r2;
     const T sign = pl == 1 ? T(1) : T(-1);
-    const double w = linear ? (double)tcount[0] : 1.0;
-    const double pown = (double)own[mem[m0].x & MEMBER_NODE_MASK];
+    const double pown = (double)own[a.mem[m0].x & MEMBER_NODE_MASK];
     T tot = T(0);
     T Rn[MAXA];
 #pragma unroll
-    for (int a = 0; a < MAXA; a++) {
-        if (a < nA) {
-            const int32_t q = s0 + a;
-            sbar[q] += w * pown * (double)sigma[q];
-            T y = fma_t(sign, r[a], R[q]);
+    for (int k = 0; k < MAXA; k++) {
+        if (k < nA) {
+            const int32_t q = s0 + k;
+            a.sbar[q] += w * pown * (double)a.sigma[q];
+            T y = fma_t(sign, r[k], a.R[q]);
             if (plus) y = max_t(y, T(0));
-            R[q] = y;
-            Rn[a] = max_t(y, T(0));
-            tot += Rn[a];
+            a.R[q] = y;
+            Rn[k] = max_t(y, T(0));
+            tot += Rn[k];
         }
     }
     const T inv = tot > T(0) ? T(1) / tot : T(0);
     const T uni = T(1) / (T)nA;
 #pragma unroll
-    for (int a = 0; a < MAXA; a++)
-        if (a < nA) sigma[s0 + a] = tot > T(0) ? Rn[a] * inv : uni;
+    for (int k = 0; k < MAXA; k++)
+        if (k < nA) a.sigma[s0 + k] = tot > T(0) ? Rn[k] * inv : uni;
+}
+
+// One backward level fused with the update of its information sets, launched once per depth d
+// (deepest first): blocks [0, ngroups) take one update group each, the remaining blocks one thread
+// per internal chance node of the level.
+template <typename T, int MAXA, int MPT, bool EXPLICIT>
+__global__ void __launch_bounds__(BLOCK) k_level(int32_t gbeg, int32_t ngroups, int32_t cbeg, int32_t nchance,
+                                                 LevelArgs<T> a, const int32_t *__restrict__ tcount, int plus,
+                                                 int linear) {
+    if ((int32_t)blockIdx.x >= ngroups) {
+        const int32_t j = ((int32_t)blockIdx.x - ngroups) * BLOCK + (int32_t)threadIdx.x;
+        if (j < nchance) chance_value<T, EXPLICIT>(a.chance_node[cbeg + j], a);
+        return;
+    }
+    __shared__ GroupLds<T, MAXA, MPT> L;
+    const double w = linear ? (double)tcount[0] : 1.0;
+    group_update<T, MAXA, MPT, EXPLICIT>(gbeg + (int32_t)blockIdx.x, w, plus, a, L);
+}
+
+// Per-game barrier among the W blocks of one game.  Thread 0 publishes the block's writes
+// (device-scope release), arrives on the game's counter and waits, with a bounded spin, until all
+// W blocks of this epoch arrived; on time-out it raises the error flag and stops waiting, so every
+// wave still exits.  Returns false once the error flag is up.
+__device__ __forceinline__ bool game_barrier(int32_t *ctr, int32_t W, int32_t &epoch, int32_t *err) {
+    __shared__ int32_t s_ok;
+    if (W == 1) {
+        __syncthreads();
+        return true;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        epoch += 1;
+        __threadfence();
+        atomicAdd(ctr, 1);
+        const int32_t target = epoch * W;
+        int64_t spins = 0;
+        int32_t ok = 1;
+        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                ++spins > BARRIER_SPIN_LIMIT) {
+                atomicExch(err, 1);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// The batched persistent form: one launch runs T whole iterations for every game of a forest.
+// Block b works on game wg_table[b].x as rank wg_table[b].y of wg_table[b].z blocks (game -1:
+// an idle padding block).  A game's blocks stride over each forward level's nodes and each
+// backward level's update groups and chance nodes, meeting at a per-game barrier between levels;
+// games never wait for each other.  Iteration t0 + k (k = 1..T) uses the same arithmetic, in the
+// same order per set, as the level-synchronous kernels.  n_iter is the number of iterations.
+template <typename T, int MAXA, int MPT, bool EXPLICIT>
+__global__ void __launch_bounds__(BLOCK) k_persistent(const int4 *__restrict__ wg_table,
+                                                      const int32_t *__restrict__ game_range,
+                                                      const int32_t *__restrict__ game_depth, int32_t MD, int32_t n_iter,
+                                                      const int2 *__restrict__ up, LevelArgs<T> a,
+                                                      const int32_t *__restrict__ tcount, int32_t *barrier,
+                                                      int32_t *err, int plus, int linear) {
+    __shared__ GroupLds<T, MAXA, MPT> L;
+    const int4 wt = wg_table[blockIdx.x];
+    const int32_t gm = wt.x, rank = wt.y, W = wt.z;
+    if (gm < 0) return;
+    const int32_t *gr = game_range + (size_t)gm * (MD + 1) * GR_FIELDS_DEV;
+    const int32_t Ds = game_depth[gm];
+    const int32_t t0 = tcount[0];
+    const int tid = threadIdx.x;
+    int32_t epoch = 0;
+    for (int32_t it = 1; it <= n_iter; it++) {
+        const double w = linear ? (double)(t0 + it) : 1.0;
+        for (int32_t d = 1; d <= Ds; d++) {
+            const int32_t lo = gr[d * GR_FIELDS_DEV], hi = gr[d * GR_FIELDS_DEV + 1];
+            for (int32_t c = lo + rank * BLOCK + tid; c < hi; c += W * BLOCK)
+                forward_node<T>(c, up, a.sigma, a.r1, a.r2);
+            if (!game_barrier(barrier + gm, W, epoch, err)) return;
+        }
+        for (int32_t d = Ds - 1; d >= 0; d--) {
+            const int32_t *r = gr + d * GR_FIELDS_DEV;
+            for (int32_t g = r[2] + rank; g < r[3]; g += W) group_update<T, MAXA, MPT, EXPLICIT>(g, w, plus, a, L);
+            for (int32_t j = r[4] + rank * BLOCK + tid; j < r[5]; j += W * BLOCK) chance_value<T, EXPLICIT>(a.chance_node[j], a);
+            if (!game_barrier(barrier + gm, W, epoch, err)) return;
+        }
+    }
+}
+
+__global__ void k_fill_int(int32_t n, int32_t *p, int32_t value) {
+    const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) p[i] = value;
+}
+
+__global__ void k_add_counter(int32_t *t, int32_t n) {
+    if (threadIdx.x == 0) t[0] += n;
 }
 
 template <typename T>
@@ -320,16 +433,26 @@ hipError_t launch_forward(const DevGame &g, int32_t lo, int32_t hi, int32_t *tic
     return g.fp64 ? forward_t<double>(g, lo, hi, tick, s) : forward_t<float>(g, lo, hi, tick, s);
 }
 
+template <typename T>
+static LevelArgs<T> level_args(const DevGame &g) {
+    LevelArgs<T> a;
+    a.grp_iset_off = g.grp_iset_off; a.slot_off = g.slot_off; a.mem_off = g.mem_off; a.mem = g.mem;
+    a.iset_player = g.iset_player; a.kid_off = g.kid_off; a.kid = g.kid; a.chance_node = g.chance_node;
+    a.v = (T *)g.v;
+    a.r1 = (T *)g.reach;
+    a.r2 = (T *)g.reach + g.N;
+    a.R = (T *)g.R; a.sbar = g.sbar; a.sigma = (T *)g.sigma;
+    return a;
+}
+
 template <typename T, int MAXA, int MPT, bool EX>
 static hipError_t level_t(const DevGame &g, int d, IterFlags f, hipStream_t s) {
     const int32_t gbeg = g.grp_depth_off[d], ng = g.grp_depth_off[d + 1] - gbeg;
     const int32_t cbeg = g.chance_off[d], nc = g.chance_off[d + 1] - cbeg;
     const unsigned blocks = (unsigned)ng + grid_for(nc);
     if (blocks == 0) return hipSuccess;
-    const T *r = (const T *)g.reach;
-    hipLaunchKernelGGL((k_level<T, MAXA, MPT, EX>), dim3(blocks), dim3(BLOCK), 0, s, gbeg, ng, g.chance_node, cbeg, nc,
-                       g.grp_iset_off, g.slot_off, g.mem_off, g.mem, g.iset_player, g.kid_off, g.kid, (T *)g.v, r,
-                       r + g.N, (T *)g.R, g.sbar, (T *)g.sigma, g.t, f.plus, f.linear);
+    hipLaunchKernelGGL((k_level<T, MAXA, MPT, EX>), dim3(blocks), dim3(BLOCK), 0, s, gbeg, ng, cbeg, nc,
+                       level_args<T>(g), g.t, f.plus, f.linear);
     return hipGetLastError();
 }
 
@@ -348,6 +471,54 @@ static hipError_t level_dispatch(const DevGame &g, int d, IterFlags f, hipStream
 
 hipError_t launch_level(const DevGame &g, int d, IterFlags f, hipStream_t s) {
     return g.fp64 ? level_dispatch<double>(g, d, f, s) : level_dispatch<float>(g, d, f, s);
+}
+
+template <typename T, int MAXA, int MPT, bool EX>
+static const void *persistent_fn() {
+    return reinterpret_cast<const void *>(&k_persistent<T, MAXA, MPT, EX>);
+}
+
+template <typename T, int MAXA, int MPT, bool EX>
+static hipError_t persistent_t(const DevGame &g, const PersistentPlan &p, int32_t T_, IterFlags f, hipStream_t s) {
+    hipLaunchKernelGGL((k_persistent<T, MAXA, MPT, EX>), dim3(p.blocks), dim3(BLOCK), 0, s, p.wg_table,
+                       p.game_range, p.game_depth, p.max_depth, T_, g.up, level_args<T>(g), g.t, p.barrier, p.err,
+                       f.plus, f.linear);
+    return hipGetLastError();
+}
+
+template <typename T, bool EX>
+static hipError_t persistent_dispatch_ex(const DevGame &g, const PersistentPlan &p, int32_t T_, IterFlags f,
+                                         hipStream_t s) {
+    if (g.max_actions <= 4) return persistent_t<T, 4, 2, EX>(g, p, T_, f, s);
+    if (g.max_actions <= 16) return persistent_t<T, 16, 1, EX>(g, p, T_, f, s);
+    return persistent_t<T, 64, 1, EX>(g, p, T_, f, s);
+}
+
+hipError_t launch_persistent(const DevGame &g, const PersistentPlan &p, int32_t T_, IterFlags f, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_int, dim3((p.n_games + 255) / 256), dim3(256), 0, s, p.n_games, p.barrier, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (g.fp64) e = g.explicit_kids ? persistent_dispatch_ex<double, true>(g, p, T_, f, s)
+                                    : persistent_dispatch_ex<double, false>(g, p, T_, f, s);
+    else e = g.explicit_kids ? persistent_dispatch_ex<float, true>(g, p, T_, f, s)
+                             : persistent_dispatch_ex<float, false>(g, p, T_, f, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_add_counter, dim3(1), dim3(64), 0, s, g.t, T_);
+    return hipGetLastError();
+}
+
+hipError_t persistent_occupancy(const DevGame &g, int *blocks_per_cu) {
+    const void *fn = nullptr;
+    if (g.fp64) {
+        if (g.max_actions <= 4) fn = g.explicit_kids ? persistent_fn<double, 4, 2, true>() : persistent_fn<double, 4, 2, false>();
+        else if (g.max_actions <= 16) fn = g.explicit_kids ? persistent_fn<double, 16, 1, true>() : persistent_fn<double, 16, 1, false>();
+        else fn = g.explicit_kids ? persistent_fn<double, 64, 1, true>() : persistent_fn<double, 64, 1, false>();
+    } else {
+        if (g.max_actions <= 4) fn = g.explicit_kids ? persistent_fn<float, 4, 2, true>() : persistent_fn<float, 4, 2, false>();
+        else if (g.max_actions <= 16) fn = g.explicit_kids ? persistent_fn<float, 16, 1, true>() : persistent_fn<float, 16, 1, false>();
+        else fn = g.explicit_kids ? persistent_fn<float, 64, 1, true>() : persistent_fn<float, 64, 1, false>();
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, BLOCK, 0);
 }
 
 hipError_t launch_regret_matching(const DevGame &g, hipStream_t s) {

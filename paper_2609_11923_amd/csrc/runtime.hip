@@ -51,6 +51,15 @@ struct cfr_handle {
     std::vector<int64_t> game_slot_base;
     std::vector<int32_t> game_depth, game_range;
     std::vector<double> game_pot;
+    // persistent schedule
+    bool persistent = false;
+    int32_t wg_nodes = 16384;
+    PersistentPlan pp{};
+    std::vector<void *> pp_allocs;
+    hipGraph_t pgraph = nullptr;
+    hipGraphExec_t pexec = nullptr;
+    int64_t pgraph_n = -1;
+    std::string device_name;
     int32_t D = 0;
     bool br_ok = true;
     int64_t E = 0, Z = 0;
@@ -229,7 +238,10 @@ void free_handle(cfr_handle *h) {
     if (h->execk) (void)hipGraphExecDestroy(h->execk);
     if (h->graph1) (void)hipGraphDestroy(h->graph1);
     if (h->graphk) (void)hipGraphDestroy(h->graphk);
+    if (h->pexec) (void)hipGraphExecDestroy(h->pexec);
+    if (h->pgraph) (void)hipGraphDestroy(h->pgraph);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    for (void *p : h->pp_allocs) (void)hipFree(p);
     for (void *p : h->allocs) (void)hipFree(p);
     delete h;
 }
@@ -264,6 +276,8 @@ void cfr_default_options(cfr_options *o) {
     o->device = 0;
     o->test_fail_capture = 0;
     o->precision = CFR_PRECISION_FP32;
+    o->persistent = 0;
+    o->wg_nodes = 0;
 }
 
 const char *cfr_last_error(void) { return g_err.c_str(); }
@@ -303,6 +317,133 @@ void cfr_layout_free(cfr_layout *l) {
     std::free(l->node_infoset); std::free(l->node_type); std::free(l->tmpl); std::free(l->slot_off);
     std::free(l->mem_off); std::free(l->mem_node); std::free(l->iset_player); std::free(l->iset_key);
     std::memset(l, 0, sizeof *l);
+}
+
+// XCD-aware work table of the persistent launch.  Each game gets W = ceil(nodes / wg_nodes)
+// workgroups (at least 1), all on one XCD (the hardware dispatches block b to XCD b % 8), so its
+// working set stays in that XCD's L2.  Games are assigned to XCDs largest first onto the least
+// loaded XCD; each XCD's blocks take consecutive slots b = x + 8k and short XCDs are padded with
+// idle blocks.  The grid never exceeds the resident capacity, so the blocks of a game are
+// co-resident and its barrier can complete; if it would, wg_nodes is doubled.
+static cfr_status build_persistent_plan(cfr_handle *h, int32_t wg_nodes) {
+    constexpr int XCD = 8;
+    const DevGame &g = h->g;
+    const int n = h->n_games;
+    const int MD = g.max_depth;
+    int per_cu = 0, cus = 0;
+    HIP_TRY(persistent_occupancy(g, &per_cu));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, h->opt.device));
+    cus = prop.multiProcessorCount;
+    const int64_t capacity = (int64_t)per_cu * cus;
+    if (capacity < XCD) return fail(CFR_EDEVICE, "persistent kernel cannot be resident");
+    std::vector<int64_t> nodes((size_t)n, 0);
+    for (int s = 0; s < n; s++)
+        for (int d = 0; d <= MD; d++) {
+            const int32_t *r = &h->game_range[((size_t)s * (MD + 1) + d) * GR_FIELDS];
+            nodes[s] += r[1] - r[0];
+        }
+    std::vector<int> order((size_t)n);
+    for (int s = 0; s < n; s++) order[s] = s;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return nodes[a] > nodes[b]; });
+    if (wg_nodes <= 0) wg_nodes = 16384;
+    std::vector<std::vector<int>> xg(XCD);
+    std::vector<int64_t> W((size_t)n);
+    for (;;) {
+        for (auto &v : xg) v.clear();
+        std::vector<int64_t> load(XCD, 0), blocks(XCD, 0);
+        for (int s : order) {
+            W[s] = std::max<int64_t>(1, (nodes[s] + wg_nodes - 1) / wg_nodes);
+            int best = 0;
+            for (int x = 1; x < XCD; x++) if (load[x] < load[best]) best = x;
+            xg[best].push_back(s);
+            load[best] += nodes[s];
+            blocks[best] += W[s];
+        }
+        const int64_t maxb = *std::max_element(blocks.begin(), blocks.end());
+        if (maxb * XCD <= capacity) break;
+        if (wg_nodes >= (1 << 30)) return fail(CFR_EUNSUPPORTED, "too many games for one resident launch");
+        wg_nodes *= 2;
+    }
+    int64_t maxb = 0;
+    for (int x = 0; x < XCD; x++) {
+        int64_t b = 0;
+        for (int s : xg[x]) b += W[s];
+        maxb = std::max(maxb, b);
+    }
+    const int64_t total = maxb * XCD;
+    std::vector<int4> table((size_t)total, make_int4(-1, 0, 0, 0));
+    for (int x = 0; x < XCD; x++) {
+        int64_t k = 0;
+        for (int s : xg[x])
+            for (int64_t r = 0; r < W[s]; r++, k++) table[(size_t)(x + XCD * k)] = make_int4(s, (int)r, (int)W[s], 0);
+    }
+    // device copies (replacing any previous plan)
+    for (void *p : h->pp_allocs) (void)hipFree(p);
+    h->pp_allocs.clear();
+    auto alloc = [&](void **p, size_t bytes) -> cfr_status {
+        hipError_t e = hipMalloc(p, bytes ? bytes : 4);
+        if (e != hipSuccess) return fail(CFR_ENOMEM, "hipMalloc for the persistent plan failed");
+        h->pp_allocs.push_back(*p);
+        return CFR_OK;
+    };
+    PersistentPlan &pp = h->pp;
+    cfr_status st;
+    if ((st = alloc((void **)&pp.wg_table, table.size() * sizeof(int4))) != CFR_OK) return st;
+    if ((st = alloc((void **)&pp.game_range, h->game_range.size() * sizeof(int32_t))) != CFR_OK) return st;
+    if ((st = alloc((void **)&pp.game_depth, (size_t)n * sizeof(int32_t))) != CFR_OK) return st;
+    if ((st = alloc((void **)&pp.barrier, (size_t)n * sizeof(int32_t))) != CFR_OK) return st;
+    if ((st = alloc((void **)&pp.err, sizeof(int32_t))) != CFR_OK) return st;
+    HIP_TRY(hipMemcpy(pp.wg_table, table.data(), table.size() * sizeof(int4), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(pp.game_range, h->game_range.data(), h->game_range.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(pp.game_depth, h->game_depth.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(pp.err, 0, sizeof(int32_t)));
+    pp.blocks = (int32_t)total;
+    pp.n_games = n;
+    pp.max_depth = MD;
+    h->wg_nodes = wg_nodes;
+    if (h->pexec) { (void)hipGraphExecDestroy(h->pexec); h->pexec = nullptr; }
+    if (h->pgraph) { (void)hipGraphDestroy(h->pgraph); h->pgraph = nullptr; }
+    h->pgraph_n = -1;
+    return CFR_OK;
+}
+
+static cfr_status persistent_iterate(cfr_handle *h, int64_t n, hipStream_t s) {
+    if (n > 0x7fffffffLL) return fail(CFR_EINVAL, "n too large for one persistent launch");
+    const IterFlags f{h->opt.rule == CFR_RULE_CFR_PLUS ? 1 : 0, h->opt.averaging == CFR_AVG_LINEAR ? 1 : 0};
+    if (h->use_graph && h->pgraph_n != n) {
+        if (h->pexec) { (void)hipGraphExecDestroy(h->pexec); h->pexec = nullptr; }
+        if (h->pgraph) { (void)hipGraphDestroy(h->pgraph); h->pgraph = nullptr; }
+        h->pgraph_n = -1;
+        hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = launch_persistent(h->g, h->pp, (int32_t)n, f, h->cap_stream);
+            hipGraph_t gr = nullptr;
+            e = hipStreamEndCapture(h->cap_stream, &gr);
+            if (le == hipSuccess && e == hipSuccess && gr) {
+                hipGraphExec_t ex = nullptr;
+                if (hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) == hipSuccess) {
+                    h->pgraph = gr; h->pexec = ex; h->pgraph_n = n;
+                } else {
+                    (void)hipGraphDestroy(gr);
+                }
+            } else if (gr) {
+                (void)hipGraphDestroy(gr);
+            }
+        }
+    }
+    if (h->pexec && h->pgraph_n == n) {
+        hipError_t e = hipGraphLaunch(h->pexec, s);
+        if (e != hipSuccess) return fail(CFR_EGRAPH, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    } else {
+        HIP_TRY(launch_persistent(h->g, h->pp, (int32_t)n, f, s));
+    }
+    int32_t err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, h->pp.err, sizeof err, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (err) return fail(CFR_EDEVICE, "a per-game barrier of the persistent launch timed out");
+    h->iters += n;
+    return CFR_OK;
 }
 
 // Compile one game or a batch of independent games (a depth-major forest, see build_forest).
@@ -453,6 +594,15 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     build_plan(h);
     h->launches = (int64_t)h->plan.size();
     model_bytes(h, DL);
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, o.device) == hipSuccess) h->device_name = prop.gcnArchName;
+    }
+    if (o.persistent) {
+        st = build_persistent_plan(h, o.wg_nodes);
+        if (st != CFR_OK) { free_handle(h); return st; }
+        h->persistent = true;
+    }
     st = cfr_reset(h);
     if (st != CFR_OK) { free_handle(h); return st; }
     *out = h;
@@ -498,6 +648,7 @@ cfr_status cfr_iterate(cfr_handle *h, int64_t n, void *stream) {
     if (n == 0) return CFR_OK;
     HIP_TRY(hipSetDevice(h->opt.device));
     hipStream_t s = (hipStream_t)stream;
+    if (h->persistent) return persistent_iterate(h, n, s);
     if (h->captured && h->pinned != persistent_ptrs(h))
         return fail(CFR_ESTATE, "a persistent buffer changed since graph capture; refusing to replay");
     if (!h->use_graph) {
@@ -724,6 +875,92 @@ cfr_status cfr_profile(cfr_handle *h, int64_t n, void *stream, cfr_kernel_stat *
         k++;
     }
     *n_out = k < max_out ? k : max_out;
+    return CFR_OK;
+}
+
+cfr_status cfr_set_schedule(cfr_handle *h, int32_t persistent, int32_t wg_nodes) {
+    if (!h) return fail(CFR_EINVAL, "handle is NULL");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    HIP_TRY(hipDeviceSynchronize());
+    if (persistent) {
+        cfr_status st = build_persistent_plan(h, wg_nodes);
+        if (st != CFR_OK) return st;
+    }
+    h->persistent = persistent != 0;
+    return CFR_OK;
+}
+
+static std::string tune_key(const cfr_handle *h) {
+    return h->device_name + " fp" + (h->g.fp64 ? "64" : "32") + " games=" + std::to_string(h->n_games) +
+           " nodes=" + std::to_string(h->g.N) + " slots=" + std::to_string(h->g.A) +
+           " depth=" + std::to_string(h->g.max_depth);
+}
+
+cfr_status cfr_autotune(cfr_handle *h, int64_t iters, void *stream, const char *cache_path, cfr_tune_result *out) {
+    if (!h || iters <= 0) return fail(CFR_EINVAL, "bad argument");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    hipStream_t s = (hipStream_t)stream;
+    const std::string key = tune_key(h);
+    cfr_tune_result best{};
+    best.ms_per_iteration = -1.0;
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "r")) {
+            char line[512];
+            while (std::fgets(line, sizeof line, f)) {
+                int pers = 0, wg = 0;
+                double ms = 0;
+                char k[400];
+                if (std::sscanf(line, "%d %d %lf %399[^\n]", &pers, &wg, &ms, k) == 4 && key == k) {
+                    best.persistent = pers; best.wg_nodes = wg; best.ms_per_iteration = ms;
+                }
+            }
+            std::fclose(f);
+        }
+    }
+    int candidates = 0;
+    if (best.ms_per_iteration < 0) {
+        std::vector<std::pair<int, int>> cand = {{0, 0}};
+        for (int wg : {1024, 4096, 16384, 65536, 262144}) cand.push_back({1, wg});
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        int32_t last_blocks = -1;
+        for (auto c : cand) {
+            cfr_status st = cfr_set_schedule(h, c.first, c.second);
+            if (st != CFR_OK) continue;
+            if (c.first && h->pp.blocks == last_blocks) continue;  // same launch shape as the previous size
+            if (c.first) last_blocks = h->pp.blocks;
+            st = cfr_iterate(h, iters, stream);            // warm-up (capture)
+            if (st == CFR_OK) HIP_TRY(hipEventRecord(e0, s));
+            if (st == CFR_OK) st = cfr_iterate(h, iters, stream);
+            if (st != CFR_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return st; }
+            HIP_TRY(hipEventRecord(e1, s));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            const double per = ms / (double)iters;
+            candidates++;
+            if (best.ms_per_iteration < 0 || per < best.ms_per_iteration) {
+                best.persistent = c.first; best.wg_nodes = c.first ? h->wg_nodes : 0; best.ms_per_iteration = per;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (best.ms_per_iteration < 0) return fail(CFR_EDEVICE, "no schedule could run");
+        if (cache_path) {
+            if (FILE *f = std::fopen(cache_path, "a")) {
+                std::fprintf(f, "%d %d %.6f %s\n", best.persistent, best.wg_nodes, best.ms_per_iteration, key.c_str());
+                std::fclose(f);
+            }
+        }
+    }
+    cfr_status st = cfr_set_schedule(h, best.persistent, best.wg_nodes);
+    if (st != CFR_OK) return st;
+    st = cfr_reset(h);
+    if (st != CFR_OK) return st;
+    best.blocks = h->persistent ? h->pp.blocks : 0;
+    best.candidates = candidates;
+    if (out) *out = best;
     return CFR_OK;
 }
 

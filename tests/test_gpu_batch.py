@@ -109,3 +109,51 @@ def test_batch_rejects_invalid_game_with_index():
     with pytest.raises(cfr.CfrError) as e:
         cfr.Solver(games)
     assert e.value.status == cfr.CFR_EINVAL and "game 1" in str(e.value)
+
+
+@pytest.mark.parametrize("wg_nodes", [1024, 4096, 1 << 20])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_persistent_equals_level_synchronous(wg_nodes, precision):
+    """One persistent launch per call (per-game barriers between levels; small wg_nodes gives each game
+    several workgroups) reproduces the level-synchronous launches bitwise."""
+    games = subgames(12, seed=7, lo=1e3, hi=3e4) + [gg.leduc(3, 2)]
+    p = cfr.CFR_PRECISION_FP32 if precision == "fp32" else cfr.CFR_PRECISION_FP64
+    note(f"[persistent] {len(games)} games, {sum(g.n_nodes for g in games)} nodes, wg_nodes={wg_nodes}")
+    a = cfr.Solver(games, precision=p, persistent=True, wg_nodes=wg_nodes)
+    b = cfr.Solver(games, precision=p)
+    for n in (7, 25):
+        a.iterate(n)
+        b.iterate(n)
+    assert a.iterations == b.iterations == 32
+    Ra, Sa = a.state()
+    Rb, Sb = b.state()
+    assert np.array_equal(Ra, Rb) and np.array_equal(Sa, Sb)
+    assert np.array_equal(a.strategy(), b.strategy())
+    assert np.array_equal(a.batch_exploitability()[0], b.batch_exploitability()[0])
+
+
+def test_persistent_single_game():
+    g = gg.leduc(13, 2)
+    a = cfr.Solver(g, persistent=True, wg_nodes=65536)
+    b = cfr.Solver(g)
+    a.iterate(20)
+    b.iterate(20)
+    assert np.array_equal(a.state()[0], b.state()[0])
+
+
+def test_autotune_picks_a_schedule_and_resets(tmp_path):
+    games = subgames(16, seed=9, lo=1e3, hi=2e4)
+    s = cfr.Solver(games, precision=cfr.CFR_PRECISION_FP64)
+    cache = str(tmp_path / "tune.txt")
+    r = s.autotune(10, cache_path=cache)
+    note(f"[autotune] {r}")
+    assert r["candidates"] >= 2 and r["ms_per_iteration"] > 0
+    assert s.iterations == 0
+    s.iterate(30)
+    ref = cfr.Solver(games, precision=cfr.CFR_PRECISION_FP64)
+    ref.iterate(30)
+    assert np.array_equal(s.state()[0], ref.state()[0])
+    # second call reads the cache
+    t = cfr.Solver(games, precision=cfr.CFR_PRECISION_FP64)
+    r2 = t.autotune(10, cache_path=cache)
+    assert r2["candidates"] == 0 and r2["persistent"] == r["persistent"]
