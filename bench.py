@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -69,6 +71,84 @@ def stored_traffic(kernel, workload, precision, launches):
     return (rec["fetch_bytes_per_iteration"] + rec["write_bytes_per_iteration"]) / launches
 
 
+def crossing_iterations(checkpoints, expl, thr):
+    """Per game, the iteration at which exploitability first reaches thr, log-log interpolated
+    between the bracketing checkpoints (paper Sec. 6 methodology); inf if never."""
+    checkpoints = np.asarray(checkpoints, float)
+    expl = np.asarray(expl, float)          # [checkpoints, games]
+    out = np.full(expl.shape[1], np.inf)
+    for g in range(expl.shape[1]):
+        e = expl[:, g]
+        hit = np.nonzero(e <= thr)[0]
+        if hit.size == 0:
+            continue
+        k = hit[0]
+        if k == 0 or e[k - 1] <= 0 or e[k] <= 0:
+            out[g] = checkpoints[k]
+            continue
+        x0, x1 = np.log(checkpoints[k - 1]), np.log(checkpoints[k])
+        y0, y1 = np.log(e[k - 1]), np.log(e[k])
+        f = (np.log(thr) - y0) / (y1 - y0) if y1 != y0 else 1.0
+        out[g] = float(np.exp(x0 + f * (x1 - x0)))
+    return out
+
+
+def batch_games(n, seed):
+    import gamegen as gg
+    specs = gg.random_subgames(n, seed, lo=1e3, hi=1e6, game_seed=0)
+    return [gg.subgame(**{k: v for k, v in sp.items() if k != "target"}) for sp in specs], specs
+
+
+def run_batch(cfr, torch, games, iters, precision, log, tune_iters=20, warm=None):
+    """Solve a batch of subgames: autotuned schedule, `iters` iterations timed in one call, then a
+    fresh solve with exploitability checkpoints (not timed) for time to 1e-3 pot.  warm: optional
+    initial regrets (canonical slot order) for the warm-started form."""
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    s = cfr.Solver(games, precision=precision)
+    t_compile = time.perf_counter() - t0
+    tune = s.autotune(tune_iters, stream=stream)
+    log(f"[bench] batch autotune: {tune}")
+    if warm is not None:
+        s.set_regrets(warm, stream=stream)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    s.iterate(iters, stream=stream)
+    ev1.record(stream)
+    ev1.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    e_final = s.batch_exploitability(stream=stream)[0]
+    # checkpointed solve for time to threshold
+    s.reset()
+    if warm is not None:
+        s.set_regrets(warm, stream=stream)
+    checkpoints, expl = [], []
+    done = 0
+    k = 1
+    while done < iters:
+        nxt = min(iters, k)
+        s.iterate(nxt - done, stream=stream)
+        done = nxt
+        checkpoints.append(done)
+        expl.append(s.batch_exploitability(stream=stream)[0])
+        k *= 2
+    pots = np.array([g.pot for g in games])
+    cross = crossing_iterations(checkpoints, expl, 1e-3 * pots.min())
+    ms_it = ms / iters
+    return dict(
+        compile_s=t_compile, schedule=tune, iterations=iters, ms_total=ms, ms_per_iteration=ms_it,
+        edges=int(sum(g.n_edges for g in games)),
+        edge_iterations_per_s=sum(g.n_edges for g in games) * iters / (ms * 1e-3),
+        expl_final_median=float(np.median(e_final)), expl_final_max=float(np.max(e_final)),
+        reached_1e3pot=int(np.isfinite(cross).sum()),
+        iterations_to_1e3pot_median=float(np.median(cross)),
+        time_to_1e3pot_all_ms=float(np.max(cross) * ms_it) if np.isfinite(cross).all() else None,
+        time_to_1e3pot_median_ms=float(np.median(cross) * ms_it),
+    ), cross
+
+
 def cpu_baseline(sample_fn, n_full, seconds):
     import oracle
     g = sample_fn()
@@ -102,6 +182,8 @@ def main():
     ap.add_argument("--iters-per-graph", type=int, default=1)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--direct", action="store_true", help="launch kernels directly instead of replaying a graph")
+    ap.add_argument("--batch-games", type=int, default=256)
+    ap.add_argument("--batch-iters", type=int, default=500)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration for profilers)")
     args = ap.parse_args()
@@ -115,6 +197,14 @@ def main():
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
+
+    if args.workload == "batch":
+        games, _ = batch_games(args.batch_games, args.seed)
+        log(f"[bench] batch of {len(games)} subgames, {sum(g.n_edges for g in games)} edges")
+        prec = cfr.CFR_PRECISION_FP64 if args.precision == "fp64" else cfr.CFR_PRECISION_FP32
+        res, _ = run_batch(cfr, torch, games, args.batch_iters, prec, log)
+        print(json.dumps({"workload": "batch", "n_games": len(games), "precision": args.precision, **res}), flush=True)
+        return
 
     t0 = time.perf_counter()
     game, desc, sample_fn, sample_desc = make_workload(args.workload, args.K, args.seed)

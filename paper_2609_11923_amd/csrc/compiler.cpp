@@ -393,11 +393,18 @@ cfr_status build_device_layout(const Layout &L, int kind, int group_actions, Dev
         }
         // internal chance nodes by depth
         D.chance_off.assign((size_t)md + 2, 0);
+        D.bigc_off.assign((size_t)md + 2, 0);
         D.chance_node.clear();
+        D.bigc_node.clear();
         for (int d = 0; d <= md; d++) {
-            for (int32_t x = D.depth_off[d]; x < D.int_end[d]; x++)
-                if (L.node_type[inv[x]] == CFR_NODE_CHANCE && D.kid_off[x + 1] > D.kid_off[x]) D.chance_node.push_back(x);
+            for (int32_t x = D.depth_off[d]; x < D.int_end[d]; x++) {
+                if (L.node_type[inv[x]] != CFR_NODE_CHANCE) continue;
+                const int32_t k = D.kid_off[x + 1] - D.kid_off[x];
+                if (k > BIG_FANOUT) D.bigc_node.push_back(x);
+                else if (k > 0) D.chance_node.push_back(x);
+            }
             D.chance_off[d + 1] = (int32_t)D.chance_node.size();
+            D.bigc_off[d + 1] = (int32_t)D.bigc_node.size();
         }
         // single-game forest metadata
         D.n_games = 1;
@@ -410,6 +417,7 @@ cfr_status build_device_layout(const Layout &L, int kind, int group_actions, Dev
             r[0] = D.depth_off[d]; r[1] = D.depth_off[d + 1];
             r[2] = D.grp_depth_off[d]; r[3] = D.grp_depth_off[d + 1];
             r[4] = D.chance_off[d]; r[5] = D.chance_off[d + 1];
+            r[6] = D.bigc_off[d]; r[7] = D.bigc_off[d + 1];
         }
         return CFR_OK;
     } catch (const std::bad_alloc &) {
@@ -434,25 +442,26 @@ cfr_status build_forest(std::vector<Layout> &Ls, std::vector<DeviceLayout> &Ds, 
         };
         // node, set, group and chance bases per (depth, game)
         std::vector<int64_t> nb((size_t)(MD + 1) * n), ib((size_t)(MD + 1) * n), gb((size_t)(MD + 1) * n),
-            cb((size_t)(MD + 1) * n);
+            cb((size_t)(MD + 1) * n), bb((size_t)(MD + 1) * n);
         F.depth_off.assign((size_t)MD + 2, 0);
         F.iset_depth_off.assign((size_t)MD + 2, 0);
         F.grp_depth_off.assign((size_t)MD + 2, 0);
         F.chance_off.assign((size_t)MD + 2, 0);
-        int64_t N = 0, I = 0, G = 0, C = 0;
+        F.bigc_off.assign((size_t)MD + 2, 0);
+        int64_t N = 0, I = 0, G = 0, C = 0, B = 0;
         for (int d = 0; d <= MD; d++) {
             F.depth_off[d] = (int32_t)N; F.iset_depth_off[d] = (int32_t)I;
-            F.grp_depth_off[d] = (int32_t)G; F.chance_off[d] = (int32_t)C;
+            F.grp_depth_off[d] = (int32_t)G; F.chance_off[d] = (int32_t)C; F.bigc_off[d] = (int32_t)B;
             for (int s = 0; s < n; s++) {
                 const DeviceLayout &D = Ds[s];
                 nb[(size_t)d * n + s] = N; ib[(size_t)d * n + s] = I;
-                gb[(size_t)d * n + s] = G; cb[(size_t)d * n + s] = C;
+                gb[(size_t)d * n + s] = G; cb[(size_t)d * n + s] = C; bb[(size_t)d * n + s] = B;
                 N += cnt(D.depth_off, s, d); I += cnt(D.iset_depth_off, s, d);
-                G += cnt(D.grp_depth_off, s, d); C += cnt(D.chance_off, s, d);
+                G += cnt(D.grp_depth_off, s, d); C += cnt(D.chance_off, s, d); B += cnt(D.bigc_off, s, d);
             }
         }
         F.depth_off[MD + 1] = (int32_t)N; F.iset_depth_off[MD + 1] = (int32_t)I;
-        F.grp_depth_off[MD + 1] = (int32_t)G; F.chance_off[MD + 1] = (int32_t)C;
+        F.grp_depth_off[MD + 1] = (int32_t)G; F.chance_off[MD + 1] = (int32_t)C; F.bigc_off[MD + 1] = (int32_t)B;
         if (N > 0x7fffffffLL) { err = "batch too large"; return CFR_EINVAL; }
         // per game: depth of each node and of each set, to remap ids
         std::vector<std::vector<int8_t>> ndep(n), idep(n);
@@ -553,6 +562,7 @@ cfr_status build_forest(std::vector<Layout> &Ls, std::vector<DeviceLayout> &Ds, 
         }
         F.grp_iset_off.assign((size_t)G + 1, 0);
         F.chance_node.assign((size_t)C, 0);
+        F.bigc_node.assign((size_t)B, 0);
         for (int d = 0; d <= MD; d++)
             for (int s = 0; s < n; s++) {
                 const DeviceLayout &D = Ds[s];
@@ -566,6 +576,8 @@ cfr_status build_forest(std::vector<Layout> &Ls, std::vector<DeviceLayout> &Ds, 
                 }
                 int64_t c = cb[(size_t)d * n + s];
                 for (int32_t k = D.chance_off[d]; k < D.chance_off[d + 1]; k++) F.chance_node[c++] = node(s, D.chance_node[k]);
+                int64_t b = bb[(size_t)d * n + s];
+                for (int32_t k = D.bigc_off[d]; k < D.bigc_off[d + 1]; k++) F.bigc_node[b++] = node(s, D.bigc_node[k]);
             }
         F.int_end.assign((size_t)MD + 1, 0);
         for (int d = 0; d <= MD; d++) F.int_end[d] = F.depth_off[d + 1];  // terminals interleave across games
@@ -596,6 +608,7 @@ cfr_status build_forest(std::vector<Layout> &Ls, std::vector<DeviceLayout> &Ds, 
                 r[0] = (int32_t)nb[k]; r[1] = (int32_t)(nb[k] + cnt(Ds[s].depth_off, s, d));
                 r[2] = (int32_t)gb[k]; r[3] = (int32_t)(gb[k] + cnt(Ds[s].grp_depth_off, s, d));
                 r[4] = (int32_t)cb[k]; r[5] = (int32_t)(cb[k] + cnt(Ds[s].chance_off, s, d));
+                r[6] = (int32_t)bb[k]; r[7] = (int32_t)(bb[k] + cnt(Ds[s].bigc_off, s, d));
             }
         Ds.clear();
         Ls.clear();

@@ -73,20 +73,25 @@ struct DeviceLayout {
     // [grp_depth_off[d], grp_depth_off[d + 1])
     std::vector<int32_t> grp_iset_off;
     std::vector<int32_t> grp_depth_off;  // [max_depth + 2]
-    // internal chance nodes by depth: chance_node[chance_off[d] .. chance_off[d + 1])
+    // internal chance nodes by depth: chance_node[chance_off[d] .. chance_off[d + 1]) for fan-out
+    // <= BIG_FANOUT (one thread each), bigc_node[bigc_off[d] .. bigc_off[d + 1]) above it (one
+    // workgroup each)
     std::vector<int32_t> chance_node;
     std::vector<int32_t> chance_off;     // [max_depth + 2]
+    std::vector<int32_t> bigc_node;
+    std::vector<int32_t> bigc_off;       // [max_depth + 2]
     // forests (batches of independent games, depth-major: the depth-d nodes of game 0, then of
     // game 1, ...; likewise information sets, slots, groups and chance nodes)
     int32_t n_games = 1;
     std::vector<int32_t> game_root;      // [n] forest id of each game's root (= its index)
     std::vector<int64_t> game_slot_base; // [n + 1] offsets of each game's canonical slots at the ABI
     std::vector<int32_t> game_depth;     // [n] max depth of each game
-    // per game and depth d (stride GR_FIELDS): node range, group range, chance-node range, slot count
+    // per game and depth d (stride GR_FIELDS): node, group, chance-node and big-chance-node ranges
     std::vector<int32_t> game_range;     // [n * (max_depth + 1) * GR_FIELDS]
 };
 
-constexpr int GR_FIELDS = 6;  // node lo, node hi, group lo, group hi, chance lo, chance hi
+constexpr int GR_FIELDS = 8;  // node lo/hi, group lo/hi, chance lo/hi, big chance lo/hi
+constexpr int BIG_FANOUT = 64;
 
 constexpr int GROUP_SETS = 256;
 // members per update group: two per thread of a 256-thread block when sets have at most 4 actions

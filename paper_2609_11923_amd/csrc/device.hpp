@@ -16,8 +16,8 @@ constexpr int CODE_SLOT_SHIFT = 3;
 // paired with the node's first edge so that no edge-offset lookup sits on the load chain.
 constexpr int32_t MEMBER_NODE_MASK = 0x7fffffff;
 constexpr int32_t MEMBER_P2 = (int32_t)0x80000000u;
-// fields per (game, depth) in game_range: node lo/hi, group lo/hi, chance lo/hi
-constexpr int GR_FIELDS_DEV = 6;
+// fields per (game, depth) in game_range: node lo/hi, group lo/hi, chance lo/hi, big chance lo/hi
+constexpr int GR_FIELDS_DEV = 8;
 // bound on one barrier wait (spins of ~100 ns): a stuck wait raises the error flag instead of hanging
 constexpr int64_t BARRIER_SPIN_LIMIT = 20000000;
 
@@ -41,7 +41,9 @@ struct DevGame {
     // host copies of per-depth ranges (launch parameters)
     const int32_t *grp_depth_off = nullptr;  // [max_depth+2] groups of depth d
     const int32_t *chance_off = nullptr;     // [max_depth+2] chance nodes of depth d
-    int32_t *chance_node = nullptr;          // device: internal chance nodes by depth
+    int32_t *chance_node = nullptr;          // device: internal chance nodes by depth (small fan-out)
+    const int32_t *bigc_off = nullptr;       // [max_depth+2] big-fan-out chance nodes of depth d
+    int32_t *bigc_node = nullptr;            // device: chance nodes with fan-out above BIG_FANOUT
     // iteration state, element type float or double (fp64)
     void *v = nullptr;            // [N]   player-1 chance-weighted values; terminals hold the template
     void *reach = nullptr;        // [2N]  lane 0: player 1 reach, lane 1: player 2 reach

@@ -65,7 +65,7 @@ struct LevelArgs {
     const int32_t *grp_iset_off, *slot_off, *mem_off;
     const int2 *mem;
     const int8_t *iset_player;
-    const int32_t *kid_off, *kid, *chance_node;
+    const int32_t *kid_off, *kid, *chance_node, *bigc_node;
     T *v;
     T *r1, *r2;   // reach lanes (the level only reads them; the persistent form's forward levels write)
     T *R;
@@ -80,6 +80,25 @@ __device__ __forceinline__ void chance_value(int32_t h, const LevelArgs<T> &a) {
     T acc = T(0);
     for (int32_t c = b; c < e; c++) acc += a.v[child_of<EXPLICIT>(a.kid, c)];
     a.v[h] = acc;
+}
+
+// Value of a chance node with large fan-out, by a whole block: each thread sums a strided slice
+// of the children in order, then a fixed-shape tree reduction over the block (deterministic).
+// Must be called by every thread of the block.
+template <typename T, bool EXPLICIT>
+__device__ void big_chance_value(int32_t h, const LevelArgs<T> &a, T *red) {
+    const int tid = threadIdx.x;
+    const int32_t b = a.kid_off[h], e = a.kid_off[h + 1];
+    T acc = T(0);
+    for (int32_t c = b + tid; c < e; c += BLOCK) acc += a.v[child_of<EXPLICIT>(a.kid, c)];
+    red[tid] = acc;
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) a.v[h] = red[0];
+    __syncthreads();
 }
 
 // LDS staging of one update group (members of a chunk, the group's set offsets)
@@ -203,15 +222,20 @@ __device__ void group_update(int32_t g, double w, int plus, const LevelArgs<T> &
 // (deepest first): blocks [0, ngroups) take one update group each, the remaining blocks one thread
 // per internal chance node of the level.
 template <typename T, int MAXA, int MPT, bool EXPLICIT>
-__global__ void __launch_bounds__(BLOCK) k_level(int32_t gbeg, int32_t ngroups, int32_t cbeg, int32_t nchance,
-                                                 LevelArgs<T> a, const int32_t *__restrict__ tcount, int plus,
-                                                 int linear) {
-    if ((int32_t)blockIdx.x >= ngroups) {
-        const int32_t j = ((int32_t)blockIdx.x - ngroups) * BLOCK + (int32_t)threadIdx.x;
+__global__ void __launch_bounds__(BLOCK) k_level(int32_t gbeg, int32_t ngroups, int32_t bbeg, int32_t nbig,
+                                                 int32_t cbeg, int32_t nchance, LevelArgs<T> a,
+                                                 const int32_t *__restrict__ tcount, int plus, int linear) {
+    __shared__ GroupLds<T, MAXA, MPT> L;
+    const int32_t blk = (int32_t)blockIdx.x;
+    if (blk >= ngroups + nbig) {
+        const int32_t j = (blk - ngroups - nbig) * BLOCK + (int32_t)threadIdx.x;
         if (j < nchance) chance_value<T, EXPLICIT>(a.chance_node[cbeg + j], a);
         return;
     }
-    __shared__ GroupLds<T, MAXA, MPT> L;
+    if (blk >= ngroups) {
+        big_chance_value<T, EXPLICIT>(a.bigc_node[bbeg + blk - ngroups], a, L.po);
+        return;
+    }
     const double w = linear ? (double)tcount[0] : 1.0;
     group_update<T, MAXA, MPT, EXPLICIT>(gbeg + (int32_t)blockIdx.x, w, plus, a, L);
 }
@@ -283,6 +307,7 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(const int4 *__restrict__ w
         for (int32_t d = Ds - 1; d >= 0; d--) {
             const int32_t *r = gr + d * GR_FIELDS_DEV;
             for (int32_t g = r[2] + rank; g < r[3]; g += W) group_update<T, MAXA, MPT, EXPLICIT>(g, w, plus, a, L);
+            for (int32_t b = r[6] + rank; b < r[7]; b += W) big_chance_value<T, EXPLICIT>(a.bigc_node[b], a, L.po);
             for (int32_t j = r[4] + rank * BLOCK + tid; j < r[5]; j += W * BLOCK) chance_value<T, EXPLICIT>(a.chance_node[j], a);
             if (!game_barrier(barrier + gm, W, epoch, err)) return;
         }
@@ -438,6 +463,7 @@ static LevelArgs<T> level_args(const DevGame &g) {
     LevelArgs<T> a;
     a.grp_iset_off = g.grp_iset_off; a.slot_off = g.slot_off; a.mem_off = g.mem_off; a.mem = g.mem;
     a.iset_player = g.iset_player; a.kid_off = g.kid_off; a.kid = g.kid; a.chance_node = g.chance_node;
+    a.bigc_node = g.bigc_node;
     a.v = (T *)g.v;
     a.r1 = (T *)g.reach;
     a.r2 = (T *)g.reach + g.N;
@@ -449,9 +475,10 @@ template <typename T, int MAXA, int MPT, bool EX>
 static hipError_t level_t(const DevGame &g, int d, IterFlags f, hipStream_t s) {
     const int32_t gbeg = g.grp_depth_off[d], ng = g.grp_depth_off[d + 1] - gbeg;
     const int32_t cbeg = g.chance_off[d], nc = g.chance_off[d + 1] - cbeg;
-    const unsigned blocks = (unsigned)ng + grid_for(nc);
+    const int32_t bbeg = g.bigc_off[d], nb = g.bigc_off[d + 1] - bbeg;
+    const unsigned blocks = (unsigned)ng + (unsigned)nb + grid_for(nc);
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_level<T, MAXA, MPT, EX>), dim3(blocks), dim3(BLOCK), 0, s, gbeg, ng, cbeg, nc,
+    hipLaunchKernelGGL((k_level<T, MAXA, MPT, EX>), dim3(blocks), dim3(BLOCK), 0, s, gbeg, ng, bbeg, nb, cbeg, nc,
                        level_args<T>(g), g.t, f.plus, f.linear);
     return hipGetLastError();
 }

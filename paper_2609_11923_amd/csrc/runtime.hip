@@ -42,7 +42,7 @@ struct cfr_handle {
     cfr_options opt{};
     DevGame g{};
     // host copies of the schedule
-    std::vector<int32_t> depth_off, int_end, iset_depth_off, grp_depth_off, chance_off;
+    std::vector<int32_t> depth_off, int_end, iset_depth_off, grp_depth_off, chance_off, bigc_off;
     // the static launch schedule of one iteration: (kind, depth), kind 0 tick, 1 forward, 2 level
     std::vector<std::pair<int, int>> plan;
     std::vector<int32_t> slot_map;     // canonical slot -> device slot (empty: identity)
@@ -129,7 +129,8 @@ void build_plan(cfr_handle *h) {
     for (int d = 1; d <= g.max_depth; d++)
         if (d == 1 || h->int_end[d] > h->depth_off[d]) h->plan.push_back({1, d});
     for (int d = g.max_depth - 1; d >= 0; d--)
-        if (h->grp_depth_off[d + 1] > h->grp_depth_off[d] || h->chance_off[d + 1] > h->chance_off[d])
+        if (h->grp_depth_off[d + 1] > h->grp_depth_off[d] || h->chance_off[d + 1] > h->chance_off[d] ||
+            h->bigc_off[d + 1] > h->bigc_off[d])
             h->plan.push_back({2, d});
 }
 
@@ -184,6 +185,10 @@ void model_bytes(cfr_handle *h, const DeviceLayout &D) {
         // chance nodes: list entry, edge offset, value write; edges: child (index), value
         for (int32_t j = D.chance_off[d]; j < D.chance_off[d + 1]; j++) {
             const int32_t x = D.chance_node[j];
+            lv += 8 + es + (kb + es) * (D.kid_off[x + 1] - D.kid_off[x]);
+        }
+        for (int32_t j = D.bigc_off[d]; j < D.bigc_off[d + 1]; j++) {
+            const int32_t x = D.bigc_node[j];
             lv += 8 + es + (kb + es) * (D.kid_off[x + 1] - D.kid_off[x]);
         }
     }
@@ -503,6 +508,7 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     h->slot_map = DL.slot_canon_to_dev;
     h->grp_depth_off = DL.grp_depth_off;
     h->chance_off = DL.chance_off;
+    h->bigc_off = DL.bigc_off;
     h->n_games = DL.n_games;
     h->game_slot_base = DL.game_slot_base;
     h->game_depth = DL.game_depth;
@@ -537,8 +543,10 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     g.G = (int32_t)DL.grp_iset_off.size() - 1;
     ALLOC(g.grp_iset_off, (int64_t)DL.grp_iset_off.size());
     ALLOC(g.chance_node, (int64_t)DL.chance_node.size());
+    ALLOC(g.bigc_node, (int64_t)DL.bigc_node.size());
     g.grp_depth_off = h->grp_depth_off.data();
     g.chance_off = h->chance_off.data();
+    g.bigc_off = h->bigc_off.data();
     {
         char *pv = nullptr, *pr = nullptr, *ps = nullptr, *pR = nullptr;
         ALLOC(pv, N * (int64_t)h->es);
@@ -575,6 +583,7 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     UP(g.iset_player, DL.iset_player);
     UP(g.grp_iset_off, DL.grp_iset_off);
     UP(g.chance_node, DL.chance_node);
+    UP(g.bigc_node, DL.bigc_node);
     if (g.fp64) { UP((double *)g.v, DL.tmpl64); } else { UP((float *)g.v, DL.tmpl); }
     UP(g.vbr, DL.tmpl64);
     {
