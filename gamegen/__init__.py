@@ -406,3 +406,83 @@ def degenerate(kind: str) -> Game:
         return from_arrays([GG_P1, GG_P2, T], [[1], [2], []], [None, None, None], [5, 6, -1], [0, 0, 1.5],
                            name=kind)
     raise ValueError(kind)
+
+
+# --- inputs of the learned warm start ----------------------------------------------------------
+
+def mlp_init(sizes, seed: int) -> np.ndarray:
+    """Seeded initial parameters of a ReLU network, flat float32 in layer order (W_l row-major
+    [fan_in, fan_out], then b_l): He-uniform hidden weights, a smaller uniform output layer, zero
+    biases.  sizes: [(fan_in, fan_out), ...]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for k, (fi, fo) in enumerate(sizes):
+        lim = np.sqrt(6.0 / fi) if k + 1 < len(sizes) else np.sqrt(1.0 / fi)
+        parts.append(rng.uniform(-lim, lim, size=fi * fo))
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def _norm_entropy(r):
+    r = np.asarray(r, np.float64)
+    r = r / r.sum()
+    k = len(r)
+    if k <= 1:
+        return 1.0
+    nz = r[r > 0]
+    return float(-(nz * np.log(nz)).sum() / np.log(k))
+
+
+def warm_descriptors(game: Game, mem_off, mem_node, iset_player):
+    """Per-information-set inputs of the feature rows for a card game from this module (canonical
+    set order, given by the compiled member lists; generator node ids are canonical ids):
+      bucket   int16  canonical two-card hand index of the acting player's hand, mod 64
+      history  int16  rank of the set's public betting state among the decision states of the
+                      public tree (same tree shape for every subgame of a round), -1 if >= 32
+      scalars  float32 [I, 8]: 0 pot odds to_call / (pot + to_call); 1 own hand's range weight
+                      times the own hand count (1 = uniform); 2 opponent range entropy / log K;
+                      3-5 the opponent's three largest range masses; 6 log K_opp / log 630;
+                      7 own range entropy / log K."""
+    m = game.meta
+    mem_off = np.asarray(mem_off, np.int64)
+    first = np.asarray(mem_node, np.int64)[mem_off[:-1]]
+    I = len(first)
+    player = np.asarray(iset_player)
+    pt = np.asarray(m["pub_type"])
+    dec = np.flatnonzero((pt == GG_P1) | (pt == GG_P2))
+    code = np.full(len(pt), -1, np.int64)
+    code[dec] = np.arange(len(dec))
+    pub = np.asarray(game.pub, np.int64)[first]
+    history = np.where(pub >= 0, code[np.maximum(pub, 0)], -1)
+    history = np.where(history < 32, history, -1).astype(np.int16)
+    pair = np.asarray(m["node_pair"], np.int64)[first]
+    p1 = player == 1
+    hidx = np.where(p1, np.asarray(m["pair_h1"])[pair], np.asarray(m["pair_h2"])[pair])
+    hands = (m["hands1"], m["hands2"])
+    gids = [np.array([two_card_gid(*h) for h in hs], np.int64) for hs in hands]
+    bucket = (np.where(p1, gids[0][np.minimum(hidx, len(gids[0]) - 1)],
+                       gids[1][np.minimum(hidx, len(gids[1]) - 1)]) % 64).astype(np.int16)
+    ranges = []
+    for k, hs in enumerate(hands):
+        r = np.asarray(m.get(f"r{k + 1}", np.ones(len(hs))), np.float64)
+        ranges.append(r / r.sum())
+    K = [len(r) for r in ranges]
+    ent = [_norm_entropy(r) for r in ranges]
+    top = []
+    for r in ranges:
+        t = np.sort(r)[::-1][:3]
+        top.append(np.concatenate([t, np.zeros(3 - len(t))]))
+    c1 = np.asarray(m["pub_c1"])[np.maximum(pub, 0)]
+    c2 = np.asarray(m["pub_c2"])[np.maximum(pub, 0)]
+    to_call = np.abs(c1 - c2)
+    sc = np.zeros((I, 8), np.float64)
+    sc[:, 0] = to_call / (c1 + c2 + to_call)
+    own = np.where(p1, 0, 1)
+    opp = 1 - own
+    sc[:, 1] = np.where(p1, ranges[0][np.minimum(hidx, K[0] - 1)] * K[0],
+                        ranges[1][np.minimum(hidx, K[1] - 1)] * K[1])
+    sc[:, 2] = np.array(ent)[opp]
+    sc[:, 3:6] = np.stack(top)[opp]
+    sc[:, 6] = np.log(np.array(K, np.float64))[opp] / np.log(630.0)
+    sc[:, 7] = np.array(ent)[own]
+    return bucket, history, sc.astype(np.float32)
