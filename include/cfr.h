@@ -271,6 +271,92 @@ void cfr_destroy(cfr_handle *h);
 /* Message of the last failed call on this thread ("" if none). */
 const char *cfr_last_error(void);
 
+/* ---- Learned warm start --------------------------------------------------------------------
+ * Not part of the paper: a small network proposes initial regrets per information set, CFR+ runs
+ * from them, and exact exploitability judges the result.  Zero initial regrets (the uniform
+ * strategy, cfr_reset) remain the fallback, and sets with more than CFR_MLP_OUT actions always
+ * start uniform.
+ *
+ * Network: x (in_dim bf16) -> n_hidden ReLU layers of `hidden` units -> CFR_MLP_OUT logits z.
+ * Parameters form one flat float32 vector, layer by layer: W_l row-major [fan_in][fan_out], then
+ * b_l [fan_out].  Hidden products run on the BF16 matrix cores with FP32 accumulation; bf16 are
+ * stored: the rows, the weight copies, hidden activations and hidden pre-activation gradients.
+ * Loss of a row with n legal actions (the first n outputs), target distribution t and weight w:
+ *   p_a = softplus(z_a), q = p / sum_a p_a, CE = -sum_a t_a log q_a,  L = sum w CE / sum w.
+ * Optimiser: Adam with bias correction on the FP32 master parameters.
+ * Every reduction runs in a fixed order, so calls are bitwise reproducible. */
+#define CFR_FEATURES 128
+#define CFR_MLP_OUT 4
+enum { CFR_MLP_PARAMS = 0, CFR_MLP_GRADS = 1, CFR_MLP_ADAM_M = 2, CFR_MLP_ADAM_V = 3 };
+
+typedef struct cfr_mlp cfr_mlp;
+typedef struct {
+    int32_t in_dim;    /* 64, 128 or 256 (CFR_FEATURES for rows made by cfr_features) */
+    int32_t hidden;    /* 64, 128 or 256 */
+    int32_t n_hidden;  /* 1..4 */
+    int32_t max_rows;  /* rows per training call and per inference chunk, 1..2^20 */
+    int32_t device;
+    float   beta1, beta2, eps;  /* Adam */
+} cfr_mlp_desc;
+
+/* 128 -> 3 x 256 -> 4, max_rows 4096, device 0, Adam 0.9 / 0.999 / 1e-8. */
+void cfr_mlp_default_desc(cfr_mlp_desc *d);
+/* Allocate a network (all device memory is owned by it); parameters start at zero. */
+cfr_status cfr_mlp_create(const cfr_mlp_desc *d, cfr_mlp **out);
+cfr_status cfr_mlp_num_params(cfr_mlp *n, int64_t *count);
+/* Load the flat parameter vector from host memory; clears the Adam moments and step count.
+ * Synchronous. */
+cfr_status cfr_mlp_set_params(cfr_mlp *n, const float *params, int64_t len);
+/* Copy a flat host vector out: CFR_MLP_PARAMS, CFR_MLP_GRADS (of the last backward call),
+ * CFR_MLP_ADAM_M or CFR_MLP_ADAM_V.  Synchronous. */
+cfr_status cfr_mlp_get(cfr_mlp *n, int which, float *dst, int64_t len);
+/* Logits z[rows][4] (device, float32) of device rows x[rows][in_dim] (bf16), on `stream`. */
+cfr_status cfr_mlp_forward(cfr_mlp *n, const void *x, int64_t rows, float *z, void *stream);
+/* Loss and parameter gradients of one minibatch of rows <= max_rows, on `stream`.  Device
+ * arrays: x [.][in_dim] bf16, target [.][4] float32 (entries past a row's legal actions are
+ * ignored), weight [.] float32 or NULL (all 1), nact [.] legal actions per row (1..4; other values
+ * are clamped).  With idx (device int32 [rows]) the minibatch is rows idx[r] of arrays holding
+ * n_data rows (indices are clamped into range); without it, the first `rows` rows.  If loss is
+ * not NULL the call synchronises `stream` and writes L there. */
+cfr_status cfr_mlp_backward(cfr_mlp *n, const void *x, const float *target, const float *weight,
+                            const uint8_t *nact, const int32_t *idx, int64_t n_data, int64_t rows, double *loss,
+                            void *stream);
+/* One Adam step with learning rate lr on the gradients of the last backward call. */
+cfr_status cfr_mlp_adam(cfr_mlp *n, float lr, void *stream);
+/* cfr_mlp_backward followed by cfr_mlp_adam. */
+cfr_status cfr_mlp_train_step(cfr_mlp *n, const void *x, const float *target, const float *weight,
+                              const uint8_t *nact, const int32_t *idx, int64_t n_data, int64_t rows, float lr,
+                              double *loss, void *stream);
+/* Release the network after the device has finished queued work; NULL is ignored. */
+void cfr_mlp_destroy(cfr_mlp *n);
+
+/* Number of information sets of the handle (rows of cfr_features: every game's sets in canonical
+ * order, games in order). */
+cfr_status cfr_num_infosets(cfr_handle *h, int64_t *count);
+/* Feature rows of every information set into x[rows][CFR_FEATURES] (device, bf16), on `stream`:
+ *   0-63    one-hot bucket[i] (device int16; values outside 0..63: none)
+ *   64-95   one-hot history[i] (device int16; values outside 0..31: none)
+ *   96-103  scalars[i][0..7] (device float32)
+ *   104-107 legal-action mask (first min(n, 4) actions)
+ *   108-111 the instantaneous regrets of the uniform strategy (eq. instregret at sigma uniform)
+ *           of the first four actions over the sum of their magnitudes (0 for sets of > 4 actions)
+ *   112-115 regret matching (plus) of those regrets
+ *   116     acting player (0 for player 1, 1 for player 2); 117-127 zero.
+ * The regrets come from one plain (unclamped, uniformly weighted) iteration from zero regrets, so
+ * the call resets the handle: on completion of the queued work its regrets, strategy sums and
+ * counter are zero as after cfr_reset.  It also records m(I), the sum of the magnitudes of those
+ * (up to four) regrets, for cfr_warm_start.  rows must equal cfr_num_infosets. */
+cfr_status cfr_features(cfr_handle *h, const int16_t *bucket, const int16_t *history, const float *scalars,
+                        void *x, int64_t rows, void *stream);
+/* Warm start: run the network on rows x (as made by cfr_features) and set the cumulative regrets
+ * to scale * m(I) * softplus(z) for the legal actions of every set with at most 4 actions, 0 for
+ * larger sets, then recompute the current strategy (as cfr_set_regrets does).  m(I) is the sum of
+ * the magnitudes of the set's instantaneous regrets under the uniform strategy, recorded by the
+ * last cfr_features call (CFR_ESTATE if there was none), so scale counts iterations' worth of
+ * regret.  Strategy sums and the counter are left as they are.  scale = 0 gives the uniform start. */
+cfr_status cfr_warm_start(cfr_handle *h, cfr_mlp *n, const void *x, int64_t rows, float scale, void *stream);
+
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,8 +11,9 @@ Loss of one row with n legal actions (the first n of the outputs), target distri
 row weight w:
     p_a = softplus(z_a),  q_a = p_a / sum_b p_b,  CE = -sum_a t_a log q_a,
     L = sum_r w_r CE_r / sum_r w_r.
-Warm-start regrets: R0(I, a) = c * softplus(z_a) for the legal actions of a set with at most
-4 actions, and 0 (the uniform strategy) for larger sets.
+Warm-start regrets: R0(I, a) = c * m(I) * softplus(z_a) for the legal actions of a set with at
+most 4 actions, and 0 (the uniform strategy) for larger sets; m(I) is the sum of the magnitudes
+of the set's instantaneous regrets under the uniform strategy (the regret unit of the set).
 Adam: Kingma and Ba (2015), Algorithm 1, with the bias corrections.
 
 quant=True rounds to bfloat16 (round to nearest, ties to even, from the FP32 value) exactly
@@ -142,14 +143,27 @@ def adam(theta, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return theta - lr * mhat / (np.sqrt(vhat) + eps), m, v
 
 
-def warm_regrets(z, slot_off, scale):
-    """Initial regrets in slot order from per-set logits z [I, 4]."""
+def regret_unit(slot_off, R1):
+    """m(I): the sum of |R1| over the first four actions of each set with at most four actions
+    (0 for larger sets), R1 being the instantaneous regrets of the uniform strategy."""
+    slot_off = np.asarray(slot_off)
+    m = np.zeros(len(slot_off) - 1)
+    for i in range(len(m)):
+        n = slot_off[i + 1] - slot_off[i]
+        if n <= OUT:
+            m[i] = np.abs(np.asarray(R1[slot_off[i]:slot_off[i + 1]], np.float64)).sum()
+    return m
+
+
+def warm_regrets(z, slot_off, scale, unit):
+    """Initial regrets in slot order from per-set logits z [I, 4]: scale * m(I) * softplus(z) on
+    the legal actions of sets with at most four actions, zero (uniform) elsewhere."""
     slot_off = np.asarray(slot_off)
     R0 = np.zeros(int(slot_off[-1]))
     for i in range(len(slot_off) - 1):
         n = slot_off[i + 1] - slot_off[i]
         if n <= OUT:
-            R0[slot_off[i]:slot_off[i + 1]] = scale * softplus(np.asarray(z[i][:n], np.float64))
+            R0[slot_off[i]:slot_off[i + 1]] = scale * unit[i] * softplus(np.asarray(z[i][:n], np.float64))
     return R0
 
 

@@ -26,6 +26,8 @@ CFR_ORDER_SIMULTANEOUS, CFR_ORDER_ALTERNATING = 0, 1
 CFR_LAYOUT_BFS, CFR_LAYOUT_PUBLIC = 0, 1
 CFR_STRATEGY_CURRENT, CFR_STRATEGY_AVERAGE = 0, 1
 CFR_PRECISION_FP32, CFR_PRECISION_FP64 = 0, 1
+CFR_FEATURES, CFR_MLP_OUT = 128, 4
+CFR_MLP_PARAMS, CFR_MLP_GRADS, CFR_MLP_ADAM_M, CFR_MLP_ADAM_V = 0, 1, 2, 3
 
 _STATUS = {0: "CFR_OK", 1: "CFR_EINVAL", 2: "CFR_ENOMEM", 3: "CFR_EDEVICE", 4: "CFR_EGRAPH", 5: "CFR_ESTATE",
            6: "CFR_EUNSUPPORTED"}
@@ -71,6 +73,12 @@ class cfr_kernel_stat(ctypes.Structure):
                 ("ms_per_iteration", ctypes.c_double)]
 
 
+class cfr_mlp_desc(ctypes.Structure):
+    _fields_ = [("in_dim", ctypes.c_int32), ("hidden", ctypes.c_int32), ("n_hidden", ctypes.c_int32),
+                ("max_rows", ctypes.c_int32), ("device", ctypes.c_int32), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
 class CfrError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{_STATUS.get(status, status)}: {msg}")
@@ -83,7 +91,10 @@ _lib = None
 EXPORTS = ["cfr_default_options", "cfr_layout_host", "cfr_layout_free", "cfr_compile", "cfr_compile_batch",
            "cfr_batch_size", "cfr_batch_exploitability", "cfr_autotune", "cfr_set_schedule", "cfr_iterate",
            "cfr_iterations", "cfr_strategy", "cfr_exploitability", "cfr_reset", "cfr_get_state", "cfr_set_regrets",
-           "cfr_counts", "cfr_profile", "cfr_debug_rebind", "cfr_destroy", "cfr_last_error"]
+           "cfr_counts", "cfr_profile", "cfr_debug_rebind", "cfr_destroy", "cfr_last_error",
+           "cfr_mlp_default_desc", "cfr_mlp_create", "cfr_mlp_num_params", "cfr_mlp_set_params", "cfr_mlp_get",
+           "cfr_mlp_forward", "cfr_mlp_backward", "cfr_mlp_adam", "cfr_mlp_train_step", "cfr_mlp_destroy",
+           "cfr_num_infosets", "cfr_features", "cfr_warm_start"]
 
 
 def load():
@@ -127,6 +138,21 @@ def load():
         "cfr_debug_rebind": (S, [_P, ctypes.c_int, ctypes.c_int64]),
         "cfr_destroy": (None, [_P]),
         "cfr_last_error": (ctypes.c_char_p, []),
+        "cfr_mlp_default_desc": (None, [ctypes.POINTER(cfr_mlp_desc)]),
+        "cfr_mlp_create": (S, [ctypes.POINTER(cfr_mlp_desc), ctypes.POINTER(_P)]),
+        "cfr_mlp_num_params": (S, [_P, ctypes.POINTER(ctypes.c_int64)]),
+        "cfr_mlp_set_params": (S, [_P, _P, ctypes.c_int64]),
+        "cfr_mlp_get": (S, [_P, ctypes.c_int, _P, ctypes.c_int64]),
+        "cfr_mlp_forward": (S, [_P, _P, ctypes.c_int64, _P, _P]),
+        "cfr_mlp_backward": (S, [_P, _P, _P, _P, _P, _P, ctypes.c_int64, ctypes.c_int64,
+                                 ctypes.POINTER(ctypes.c_double), _P]),
+        "cfr_mlp_adam": (S, [_P, ctypes.c_float, _P]),
+        "cfr_mlp_train_step": (S, [_P, _P, _P, _P, _P, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_float,
+                                   ctypes.POINTER(ctypes.c_double), _P]),
+        "cfr_mlp_destroy": (None, [_P]),
+        "cfr_num_infosets": (S, [_P, ctypes.POINTER(ctypes.c_int64)]),
+        "cfr_features": (S, [_P, _P, _P, _P, _P, ctypes.c_int64, _P]),
+        "cfr_warm_start": (S, [_P, _P, _P, ctypes.c_int64, ctypes.c_float, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -307,6 +333,101 @@ def cfr_destroy(h):
         load().cfr_destroy(h)
 
 
+def _dptr(t):
+    """Device pointer of a torch tensor (or an int address); None stays NULL."""
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return ctypes.c_void_p(t.data_ptr())
+    return ctypes.c_void_p(int(t))
+
+
+def _stream_arg(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def cfr_mlp_default_desc() -> cfr_mlp_desc:
+    d = cfr_mlp_desc()
+    load().cfr_mlp_default_desc(ctypes.byref(d))
+    return d
+
+
+def cfr_num_infosets(h) -> int:
+    n = ctypes.c_int64()
+    _check(load().cfr_num_infosets(h, ctypes.byref(n)))
+    return n.value
+
+
+def cfr_features(h, bucket, history, scalars, x, rows: int, stream=None):
+    _check(load().cfr_features(h, _dptr(bucket), _dptr(history), _dptr(scalars), _dptr(x), int(rows),
+                               _stream_arg(stream)))
+
+
+def cfr_warm_start(h, mlp, x, rows: int, scale: float, stream=None):
+    _check(load().cfr_warm_start(h, mlp, _dptr(x), int(rows), float(scale), _stream_arg(stream)))
+
+
+class Mlp:
+    """The warm-start network (cfr_mlp).  Device arrays are torch tensors (or raw addresses)."""
+
+    def __init__(self, in_dim=CFR_FEATURES, hidden=256, n_hidden=3, max_rows=4096, device=0, beta1=0.9,
+                 beta2=0.999, eps=1e-8):
+        d = cfr_mlp_default_desc()
+        d.in_dim, d.hidden, d.n_hidden, d.max_rows, d.device = in_dim, hidden, n_hidden, max_rows, device
+        d.beta1, d.beta2, d.eps = beta1, beta2, eps
+        self.desc = d
+        self.h = _P()
+        _check(load().cfr_mlp_create(ctypes.byref(d), ctypes.byref(self.h)))
+        n = ctypes.c_int64()
+        _check(load().cfr_mlp_num_params(self.h, ctypes.byref(n)))
+        self.P = n.value
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, np.float32)
+        _check(load().cfr_mlp_set_params(self.h, _ptr(a), a.size))
+
+    def get(self, which=CFR_MLP_PARAMS) -> np.ndarray:
+        out = np.zeros(self.P, np.float32)
+        _check(load().cfr_mlp_get(self.h, int(which), _ptr(out), self.P))
+        return out
+
+    def forward(self, x, rows: int, z, stream=None):
+        _check(load().cfr_mlp_forward(self.h, _dptr(x), int(rows), _dptr(z), _stream_arg(stream)))
+
+    def backward(self, x, target, weight, nact, rows: int, idx=None, n_data: int = 0, want_loss=True, stream=None):
+        loss = ctypes.c_double()
+        _check(load().cfr_mlp_backward(self.h, _dptr(x), _dptr(target), _dptr(weight), _dptr(nact), _dptr(idx),
+                                       int(n_data), int(rows), ctypes.byref(loss) if want_loss else None,
+                                       _stream_arg(stream)))
+        return loss.value if want_loss else None
+
+    def adam(self, lr: float, stream=None):
+        _check(load().cfr_mlp_adam(self.h, float(lr), _stream_arg(stream)))
+
+    def train_step(self, x, target, weight, nact, rows: int, lr: float, idx=None, n_data: int = 0, want_loss=False,
+                   stream=None):
+        loss = ctypes.c_double()
+        _check(load().cfr_mlp_train_step(self.h, _dptr(x), _dptr(target), _dptr(weight), _dptr(nact), _dptr(idx),
+                                         int(n_data), int(rows), float(lr),
+                                         ctypes.byref(loss) if want_loss else None, _stream_arg(stream)))
+        return loss.value if want_loss else None
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().cfr_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Solver:
     """Owns one compiled game.  ``stream`` may be a torch.cuda.Stream, a raw hipStream_t int, or None."""
 
@@ -382,6 +503,17 @@ class Solver:
 
     def reset(self):
         cfr_reset(self.h)
+
+    @property
+    def n_infosets(self) -> int:
+        return cfr_num_infosets(self.h)
+
+    def features(self, bucket, history, scalars, x, stream=None):
+        """Feature rows of every information set into the device tensor x (bf16 [I, 128]); resets."""
+        cfr_features(self.h, bucket, history, scalars, x, self.n_infosets, self._stream(stream))
+
+    def warm_start(self, mlp: "Mlp", x, scale: float, stream=None):
+        cfr_warm_start(self.h, mlp.h, x, self.n_infosets, scale, self._stream(stream))
 
     def close(self):
         if getattr(self, "h", None):

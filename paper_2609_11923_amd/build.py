@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libcfr.so")
-SOURCES = ["compiler.cpp", "kernels.hip", "runtime.hip"]
+SOURCES = ["compiler.cpp", "kernels.hip", "runtime.hip", "mlp.hip"]
 ARCH = "gfx950"
 
 

@@ -11,6 +11,7 @@
 // and the handle keeps launching the same kernels directly.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -20,6 +21,7 @@
 #include "../../include/cfr.h"
 #include "compiler.hpp"
 #include "device.hpp"
+#include "mlp.hpp"
 
 using namespace cfrx;
 
@@ -30,6 +32,12 @@ cfr_status fail(cfr_status s, const std::string &m) {
     g_err = m;
     return s;
 }
+
+}  // namespace
+
+void cfrx::set_last_error(const std::string &m) { g_err = m; }
+
+namespace {
 
 #define HIP_TRY(expr)                                                                                   \
     do {                                                                                                \
@@ -80,6 +88,13 @@ struct cfr_handle {
     // algorithmic bytes per iteration of each kernel (traffic model, see model_bytes)
     double bytes_fwd = 0, bytes_lvl = 0;
     double method_fwd = 0, method_lvl = 0;   // per-unit byte figures of the method (see model_bytes)
+    // canonical information sets of all games (rows of the warm-start network)
+    int64_t I_canon = 0;
+    int32_t *canon_off = nullptr;      // [I + 1] canonical slot offsets, global over the batch
+    int8_t *canon_player = nullptr;    // [I]
+    float *warm_z = nullptr;           // [I * 4] logits, allocated on first warm start
+    float *warm_mag = nullptr;         // [I] regret unit of each set, written by cfr_features
+    bool have_mag = false;
 };
 
 // Per-launch event timing for cfr_profile: class 0 tick, 1 forward, 2 level.
@@ -135,9 +150,11 @@ void build_plan(cfr_handle *h) {
 }
 
 // one iteration, direct launches, in the plan's order; tm != nullptr brackets every launch with events
-cfr_status enqueue_iteration(cfr_handle *h, hipStream_t s, int64_t *count, LaunchTimer *tm = nullptr) {
+cfr_status enqueue_iteration(cfr_handle *h, hipStream_t s, int64_t *count, LaunchTimer *tm = nullptr,
+                             const IterFlags *flags = nullptr) {
     const DevGame &g = h->g;
-    const IterFlags f{h->opt.rule == CFR_RULE_CFR_PLUS ? 1 : 0, h->opt.averaging == CFR_AVG_LINEAR ? 1 : 0};
+    const IterFlags f = flags ? *flags
+                              : IterFlags{h->opt.rule == CFR_RULE_CFR_PLUS ? 1 : 0, h->opt.averaging == CFR_AVG_LINEAR ? 1 : 0};
     int64_t n = 0;
     for (const auto &step : h->plan) {
         if (tm) {
@@ -471,18 +488,25 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     std::vector<Layout> Ls((size_t)n);
     int64_t N = 0, E = 0, Z = 0, Ndec = 0, I = 0, A = 0;
     int max_actions = 0, max_depth = 0, blocks = 0;
+    std::vector<int32_t> canon_off;
+    std::vector<int8_t> canon_player;
     for (int s = 0; s < n; s++) {
         st = build_layout(&games[s], Ls[s], err);
         if (st != CFR_OK) return fail(st, n > 1 ? "game " + std::to_string(s) + ": " + err : err);
         if (!Ls[s].br_ok)
             return fail(CFR_EUNSUPPORTED, "an information set has members at different depths; the level-fused "
                                           "update needs every set on one depth");
+        for (int64_t i = 0; i < Ls[s].I; i++) {
+            canon_off.push_back((int32_t)(A + Ls[s].slot_off[(size_t)i]));
+            canon_player.push_back(Ls[s].iset_player[(size_t)i]);
+        }
         N += Ls[s].N; E += Ls[s].E; Z += Ls[s].Z; Ndec += Ls[s].Ndec; I += Ls[s].I; A += Ls[s].A;
         max_actions = std::max(max_actions, Ls[s].max_actions);
         max_depth = std::max(max_depth, Ls[s].max_depth);
         blocks = std::max(blocks, Ls[s].D);
     }
     if (N > 0x7fffffffLL || A > (1LL << 28)) return fail(CFR_EINVAL, "batch too large");
+    canon_off.push_back((int32_t)A);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(CFR_EDEVICE, "no HIP device available");
     if (o.device < 0 || o.device >= ndev) return fail(CFR_EINVAL, "device ordinal out of range");
@@ -563,7 +587,11 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     ALLOC(g.astar, I);
     ALLOC(g.out, A);
     ALLOC(g.out2, A);
+    ALLOC(h->canon_off, I + 1);
+    ALLOC(h->canon_player, I);
+    ALLOC(h->warm_mag, I);
 #undef ALLOC
+    h->I_canon = I;
     h->R_base = (char *)g.R; h->sbar_base = (char *)g.sbar; h->sigma_base = (char *)g.sigma;
 #define UP(dst, src) do { st = upload(dst, src); if (st != CFR_OK) { free_handle(h); return st; } } while (0)
     UP(g.up, up);
@@ -584,6 +612,8 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     UP(g.grp_iset_off, DL.grp_iset_off);
     UP(g.chance_node, DL.chance_node);
     UP(g.bigc_node, DL.bigc_node);
+    UP(h->canon_off, canon_off);
+    UP(h->canon_player, canon_player);
     if (g.fp64) { UP((double *)g.v, DL.tmpl64); } else { UP((float *)g.v, DL.tmpl); }
     UP(g.vbr, DL.tmpl64);
     {
@@ -976,6 +1006,68 @@ cfr_status cfr_autotune(cfr_handle *h, int64_t iters, void *stream, const char *
 cfr_status cfr_debug_rebind(cfr_handle *h, int which, int64_t delta) {
     if (!h || which < 0 || which > 2) return fail(CFR_EINVAL, "bad argument");
     h->rebind[which] = delta;
+    return CFR_OK;
+}
+
+cfr_status cfr_num_infosets(cfr_handle *h, int64_t *count) {
+    if (!h || !count) return fail(CFR_EINVAL, "NULL argument");
+    *count = h->I_canon;
+    return CFR_OK;
+}
+
+cfr_status cfr_features(cfr_handle *h, const int16_t *bucket, const int16_t *history, const float *scalars, void *x,
+                        int64_t rows, void *stream) {
+    if (!h) return fail(CFR_EINVAL, "handle is NULL");
+    if (rows != h->I_canon) return fail(CFR_EINVAL, "rows must equal the information-set count " + std::to_string(h->I_canon));
+    if (rows > 0 && (!bucket || !history || !scalars || !x)) return fail(CFR_EINVAL, "NULL argument");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    hipStream_t s = (hipStream_t)stream;
+    const DevGame &g = h->g;
+    auto clear = [&]() -> cfr_status {
+        HIP_TRY(hipMemsetAsync(g.R, 0, (size_t)(g.A > 0 ? g.A : 1) * h->es, s));
+        HIP_TRY(hipMemsetAsync(g.sbar, 0, (size_t)(g.A > 0 ? g.A : 1) * sizeof(double), s));
+        HIP_TRY(hipMemsetAsync(g.t, 0, sizeof(int32_t), s));
+        HIP_TRY(launch_regret_matching(g, s));
+        return CFR_OK;
+    };
+    cfr_status st = clear();
+    if (st != CFR_OK) return st;
+    // one plain iteration from zero regrets: R becomes the instantaneous regrets of the uniform strategy
+    const IterFlags plain{0, 0};
+    st = enqueue_iteration(h, s, nullptr, nullptr, &plain);
+    if (st != CFR_OK) return st;
+    FeatureArgs f{};
+    f.canon_off = h->canon_off; f.player = h->canon_player; f.slot_map = g.slot_map;
+    f.bucket = bucket; f.history = history; f.scalars = scalars; f.I = rows; f.X = (uint16_t *)x;
+    f.mag = h->warm_mag;
+    HIP_TRY(launch_features(f, g.R, g.fp64 != 0, s));
+    st = clear();
+    if (st != CFR_OK) return st;
+    h->iters = 0;
+    h->have_mag = true;
+    return CFR_OK;
+}
+
+cfr_status cfr_warm_start(cfr_handle *h, cfr_mlp *n, const void *x, int64_t rows, float scale, void *stream) {
+    if (!h || !n) return fail(CFR_EINVAL, "NULL argument");
+    if (rows != h->I_canon) return fail(CFR_EINVAL, "rows must equal the information-set count " + std::to_string(h->I_canon));
+    if (mlp_in_dim(n) != CFR_FEATURES) return fail(CFR_EINVAL, "the network's in_dim must be CFR_FEATURES");
+    if (mlp_device(n) != h->opt.device) return fail(CFR_EINVAL, "network and handle live on different devices");
+    if (!(scale >= 0.f) || !std::isfinite(scale)) return fail(CFR_EINVAL, "scale must be finite and >= 0");
+    if (rows > 0 && !x) return fail(CFR_EINVAL, "NULL argument");
+    if (!h->have_mag) return fail(CFR_ESTATE, "call cfr_features first: it records the regret unit of every set");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    hipStream_t s = (hipStream_t)stream;
+    if (rows == 0) return CFR_OK;
+    if (!h->warm_z) {
+        cfr_status st = dev_alloc(h, &h->warm_z, rows * 4);
+        if (st != CFR_OK) return st;
+    }
+    cfr_status st = mlp_forward_internal(n, x, rows, h->warm_z, s);
+    if (st != CFR_OK) return st;
+    HIP_TRY(launch_warm_regrets(h->canon_off, rows, h->warm_z, h->warm_mag, scale, h->g.out, s));
+    HIP_TRY(launch_regrets_from_float(h->g, h->g.out, s));
+    HIP_TRY(launch_regret_matching(h->g, s));
     return CFR_OK;
 }
 

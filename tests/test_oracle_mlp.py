@@ -121,9 +121,12 @@ def test_quantised_forward_is_exact_on_representable_values():
 def test_warm_regrets_and_fallback():
     slot_off = np.array([0, 2, 7, 10])      # 2 actions, 5 actions (fallback), 3 actions
     z = np.array([[0.0, 1.0, 9, 9], [1, 1, 1, 1], [-1.0, 0.0, 2.0, 9]])
-    R0 = om.warm_regrets(z, slot_off, 2.0)
-    assert R0[0] == pytest.approx(2 * np.log(2.0))
-    assert R0[1] == pytest.approx(2 * np.log1p(np.e))
+    R1 = np.array([1.0, -2.0, 1, 1, 1, 1, 1, 0.5, 0.25, -0.25])
+    unit = om.regret_unit(slot_off, R1)
+    assert np.array_equal(unit, [3.0, 0.0, 1.0])
+    R0 = om.warm_regrets(z, slot_off, 2.0, unit)
+    assert R0[0] == pytest.approx(6 * np.log(2.0))
+    assert R0[1] == pytest.approx(6 * np.log1p(np.e))
     assert np.all(R0[2:7] == 0.0)
     assert R0[9] == pytest.approx(2 * np.log1p(np.exp(2.0)))
 
