@@ -71,35 +71,13 @@ def stored_traffic(kernel, workload, precision, launches):
     return (rec["fetch_bytes_per_iteration"] + rec["write_bytes_per_iteration"]) / launches
 
 
-def crossing_iterations(checkpoints, expl, thr):
-    """Per game, the iteration at which exploitability first reaches thr, log-log interpolated
-    between the bracketing checkpoints (paper Sec. 6 methodology); inf if never."""
-    checkpoints = np.asarray(checkpoints, float)
-    expl = np.asarray(expl, float)          # [checkpoints, games]
-    out = np.full(expl.shape[1], np.inf)
-    for g in range(expl.shape[1]):
-        e = expl[:, g]
-        hit = np.nonzero(e <= thr)[0]
-        if hit.size == 0:
-            continue
-        k = hit[0]
-        if k == 0 or e[k - 1] <= 0 or e[k] <= 0:
-            out[g] = checkpoints[k]
-            continue
-        x0, x1 = np.log(checkpoints[k - 1]), np.log(checkpoints[k])
-        y0, y1 = np.log(e[k - 1]), np.log(e[k])
-        f = (np.log(thr) - y0) / (y1 - y0) if y1 != y0 else 1.0
-        out[g] = float(np.exp(x0 + f * (x1 - x0)))
-    return out
-
-
 def batch_games(n, seed):
     import gamegen as gg
     specs = gg.random_subgames(n, seed, lo=1e3, hi=1e6, game_seed=0)
     return [gg.subgame(**{k: v for k, v in sp.items() if k != "target"}) for sp in specs], specs
 
 
-def run_batch(cfr, torch, games, iters, precision, log, tune_iters=20, warm=None):
+def run_batch(cfr, torch, games, iters, precision, log, tune_iters=20, warm=None, max_iters=4000):
     """Solve a batch of subgames: autotuned schedule, `iters` iterations timed in one call, then a
     fresh solve with exploitability checkpoints (not timed) for time to 1e-3 pot.  warm: optional
     initial regrets (canonical slot order) for the warm-started form."""
@@ -124,19 +102,22 @@ def run_batch(cfr, torch, games, iters, precision, log, tune_iters=20, warm=None
     s.reset()
     if warm is not None:
         s.set_regrets(warm, stream=stream)
-    checkpoints, expl = [], []
+    from paper_2609_11923_amd.warm import crossing_iterations, geometric_checkpoints, alone_ms_per_iteration
+    checkpoints, expl = geometric_checkpoints(max_iters), []
     done = 0
-    k = 1
-    while done < iters:
-        nxt = min(iters, k)
-        s.iterate(nxt - done, stream=stream)
-        done = nxt
-        checkpoints.append(done)
+    for c in checkpoints:
+        s.iterate(c - done, stream=stream)
+        done = c
         expl.append(s.batch_exploitability(stream=stream)[0])
-        k *= 2
+        log(f"[bench] batch iteration {done}: median expl {np.median(expl[-1]):.3e}")
     pots = np.array([g.pot for g in games])
     cross = crossing_iterations(checkpoints, expl, 1e-3 * pots.min())
     ms_it = ms / iters
+    s.close()
+    alone = alone_ms_per_iteration(games, torch, log=log)
+    fin = np.isfinite(cross)
+    seq_ms = float(np.sum(cross[fin] * alone[fin]))
+    bat_ms = float(np.max(cross[fin]) * ms_it) if fin.any() else None
     return dict(
         compile_s=t_compile, schedule=tune, iterations=iters, ms_total=ms, ms_per_iteration=ms_it,
         edges=int(sum(g.n_edges for g in games)),
@@ -146,7 +127,100 @@ def run_batch(cfr, torch, games, iters, precision, log, tune_iters=20, warm=None
         iterations_to_1e3pot_median=float(np.median(cross)),
         time_to_1e3pot_all_ms=float(np.max(cross) * ms_it) if np.isfinite(cross).all() else None,
         time_to_1e3pot_median_ms=float(np.median(cross) * ms_it),
+        checkpoint_iterations=int(max_iters),
+        one_at_a_time={
+            "what": "each game alone on its own handle (hipGraph replay), run to its own crossing iteration; "
+                    "the batch reproduces each game's iterates bitwise, so crossing iterations are shared",
+            "ms_per_iteration_median": float(np.median(alone)), "ms_per_iteration_sum": float(np.sum(alone)),
+            "games_counted": int(fin.sum()),
+            "time_to_1e3pot_all_ms": seq_ms,
+            "batched_time_to_1e3pot_same_games_ms": bat_ms,
+            "wall_time_reduction": (1.0 - bat_ms / seq_ms) if bat_ms and seq_ms > 0 else None,
+        },
     ), cross
+
+
+def run_warm(cfr, torch, args, log):
+    """Learned warm start: train the network on average strategies of solved subgames (their own
+    payoff seeds, so nothing about the test payoffs can be memorised), pick the regret scale on a
+    validation batch, then solve the held-out test batch cold, warm and with the untrained
+    network."""
+    import gamegen as gg
+    from paper_2609_11923_amd import warm
+    t0 = time.perf_counter()
+    tr_specs = gg.random_subgames(args.warm_train_games, seed=1, lo=1e3, hi=args.warm_train_hi, game_seed=1)
+    X, T, W, N, dstats = warm.make_training_set(tr_specs, args.warm_target_iters, torch, probe=args.warm_probe,
+                                                log=log)
+    va_specs = gg.random_subgames(args.warm_val_games, seed=2, lo=1e3, hi=1e6, game_seed=2)
+    Xv, Tv, Wv, Nv, vstats = warm.make_training_set(va_specs, args.warm_target_iters, torch, probe=args.warm_probe,
+                                                    log=log)
+    t_data = time.perf_counter() - t0
+    sizes = [(cfr.CFR_FEATURES, 256), (256, 256), (256, 256), (256, cfr.CFR_MLP_OUT)]
+    theta0 = gg.mlp_init(sizes, seed=0)
+    mlp = cfr.Mlp()
+    mlp.set_params(theta0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    log(f"[warm] weighted target entropy (the loss floor): train {dstats['target_entropy']:.4f}, "
+        f"validation {vstats['target_entropy']:.4f}")
+    hist = warm.train(mlp, X, T, W, N, torch, epochs=args.warm_epochs, lr=args.warm_lr, val=(Xv, Tv, Wv, Nv), log=log)
+    t_train = time.perf_counter() - t1
+    steps = hist[-1]["steps"] if hist else 0
+    del X, T, W, N
+    log("[warm] choosing the regret scale on the validation batch")
+    val_games = warm.subgames(va_specs)
+    scale, table = warm.choose_scale(val_games, torch, mlp, args.warm_scales, args.warm_val_iters,
+                                     probe=args.warm_probe, log=log)
+    control = cfr.Mlp()
+    control.set_params(theta0)
+    log("[warm] evaluating on the held-out test batch")
+    test_games, _ = batch_games(args.batch_games, args.seed)
+    ev = warm.evaluate(test_games, torch, mlp, scale, args.warm_max_iters, control=control, probe=args.warm_probe,
+                       log=log)
+    cold, wst = ev["cold"]["_cross"], ev["warm"]["_cross"]
+    both = np.isfinite(cold) & np.isfinite(wst)
+    # throughput of the network on the matrix cores: one forward over every test set's row
+    log("[warm] timing inference")
+    rows = warm.Rows(test_games, torch)
+    s = cfr.Solver(test_games)
+    rows.features(s, probe=args.warm_probe)
+    z = torch.empty(rows.I, 4, dtype=torch.float32, device="cuda")
+    mlp.forward(rows.x, rows.I, z)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        mlp.forward(rows.x, rows.I, z)
+    e1.record()
+    e1.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / 5
+    hidden_flops = 2.0 * rows.I * sum(fi * fo for fi, fo in sizes[:-1])
+    s.close()
+    out = {
+        "threshold": "exploitability <= 1e-3 pot (device best response, FP64)",
+        "test": f"{len(test_games)} held-out subgames (the batched workload), up to {args.warm_max_iters} iterations",
+        "network": "128 -> 3 x 256 ReLU -> 4, BF16 MFMA, FP32 accumulation, Adam on FP32 master weights",
+        "probe_iterations": args.warm_probe,
+        "train": {"subgames": dstats["subgames"], "edges": dstats["edges"], "rows": dstats["rows"],
+                  "target_entropy": dstats["target_entropy"], "val_target_entropy": vstats["target_entropy"],
+                  "lr": args.warm_lr, "weights": "regret unit m(I), normalised per subgame",
+                  "target_iterations": args.warm_target_iters, "epochs": args.warm_epochs, "steps": steps,
+                  "batch": 4096, "data_s": t_data, "train_s": t_train, "history": hist,
+                  "train_tflops": 3 * 2.0 * steps * 4096 * sum(fi * fo for fi, fo in sizes) / max(t_train, 1e-9) / 1e12},
+        "scale": scale, "scale_search": table,
+        "cold": {k: v for k, v in ev["cold"].items() if not k.startswith("_")},
+        "warm": {k: v for k, v in ev["warm"].items() if not k.startswith("_")},
+        "control_untrained_net": {k: v for k, v in ev["control_untrained_net"].items() if not k.startswith("_")},
+        "schedule": ev["schedule"],
+        "paired": {"games_both_reached": int(both.sum()),
+                   "iteration_ratio_median": float(np.median(wst[both] / cold[both])) if both.any() else None,
+                   "warm_faster_fraction": float(np.mean(wst[both] < cold[both])) if both.any() else None},
+        "inference": {"rows": rows.I, "ms": fwd_ms, "hidden_tflops": hidden_flops / (fwd_ms * 1e-3) / 1e12,
+                      "peak_tflops_bf16": 2500.0},
+    }
+    c_t, w_t = out["cold"]["time_ms_median"], out["warm"]["time_ms_median"]
+    out["wall_time_reduction_median"] = (1.0 - w_t / c_t) if np.isfinite(c_t) and np.isfinite(w_t) else None
+    return out
 
 
 def cpu_baseline(sample_fn, n_full, seconds):
@@ -184,6 +258,18 @@ def main():
     ap.add_argument("--direct", action="store_true", help="launch kernels directly instead of replaying a graph")
     ap.add_argument("--batch-games", type=int, default=256)
     ap.add_argument("--batch-iters", type=int, default=500)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-subgame measurement")
+    ap.add_argument("--no-warm", action="store_true", help="skip the learned warm-start measurement")
+    ap.add_argument("--warm-train-games", type=int, default=2000)
+    ap.add_argument("--warm-train-hi", type=float, default=1e6, help="largest training subgame (edges)")
+    ap.add_argument("--warm-target-iters", type=int, default=500)
+    ap.add_argument("--warm-val-games", type=int, default=64)
+    ap.add_argument("--warm-val-iters", type=int, default=1000)
+    ap.add_argument("--warm-epochs", type=int, default=8)
+    ap.add_argument("--warm-lr", type=float, default=2e-3)
+    ap.add_argument("--warm-probe", type=int, default=16, help="probe iterations whose strategies feed the network")
+    ap.add_argument("--warm-max-iters", type=int, default=2000)
+    ap.add_argument("--warm-scales", type=float, nargs="+", default=[1.0, 3.0, 10.0, 30.0, 100.0])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration for profilers)")
     args = ap.parse_args()
@@ -198,6 +284,10 @@ def main():
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
+    if args.workload == "warm":
+        res = run_warm(cfr, torch, args, log)
+        print(json.dumps({"workload": "warm", **res}), flush=True)
+        return
     if args.workload == "batch":
         games, _ = batch_games(args.batch_games, args.seed)
         log(f"[bench] batch of {len(games)} subgames, {sum(g.n_edges for g in games)} edges")
@@ -301,6 +391,18 @@ def main():
         "exploitability_after": {"iterations": solver.iterations, "expl": e, "pot": float(c["pot"])},
         "device_bytes": int(c["device_bytes"]),
     }
+    solver.close()
+    del solver
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        games, _ = batch_games(args.batch_games, args.seed)
+        log(f"[bench] batch of {len(games)} subgames, {sum(g.n_edges for g in games)} edges")
+        res, _ = run_batch(cfr, torch, games, args.batch_iters, cfr.CFR_PRECISION_FP32, log)
+        out["batch"] = {"workload": f"{len(games)} subgames cut at round-B public states, 1e3-1e6 edges "
+                                    f"log-uniform, Dirichlet(1) ranges", "precision": "fp32", **res}
+        del games
+    if not args.no_warm:
+        out["warm_start"] = run_warm(cfr, torch, args, log)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(sample_fn, n_nodes, args.cpu_seconds)

@@ -433,9 +433,22 @@ def _norm_entropy(r):
     return float(-(nz * np.log(nz)).sum() / np.log(k))
 
 
-def warm_descriptors(game: Game, mem_off, mem_node, iset_player):
-    """Per-information-set inputs of the feature rows for a card game from this module (canonical
-    set order, given by the compiled member lists; generator node ids are canonical ids):
+def first_members(game: Game):
+    """(first member node, acting player) of every information set, sets in order of first
+    occurrence among decision nodes in node-id order.  Generator node ids are breadth-first with
+    children in action order, so this is the canonical set order of the compiled game."""
+    ty = np.asarray(game.type)
+    dec = np.flatnonzero((ty == GG_P1) | (ty == GG_P2))
+    keys = np.asarray(game.key)[dec]
+    # sets are keyed by (player, key)
+    _, first_idx = np.unique(np.stack([ty[dec].astype(np.int64), keys]), axis=1, return_index=True)
+    first = np.sort(dec[first_idx])
+    return first, ty[first].astype(np.int8)
+
+
+def warm_descriptors(game: Game, mem_off=None, mem_node=None, iset_player=None):
+    """Per-information-set inputs of the feature rows for a card game from this module, in
+    canonical set order (from the compiled member lists when given, else first_members):
       bucket   int16  canonical two-card hand index of the acting player's hand, mod 64
       history  int16  rank of the set's public betting state among the decision states of the
                       public tree (same tree shape for every subgame of a round), -1 if >= 32
@@ -444,10 +457,12 @@ def warm_descriptors(game: Game, mem_off, mem_node, iset_player):
                       3-5 the opponent's three largest range masses; 6 log K_opp / log 630;
                       7 own range entropy / log K."""
     m = game.meta
-    mem_off = np.asarray(mem_off, np.int64)
-    first = np.asarray(mem_node, np.int64)[mem_off[:-1]]
+    if mem_off is None:
+        first, player = first_members(game)
+    else:
+        first = np.asarray(mem_node, np.int64)[np.asarray(mem_off, np.int64)[:-1]]
+        player = np.asarray(iset_player)
     I = len(first)
-    player = np.asarray(iset_player)
     pt = np.asarray(m["pub_type"])
     dec = np.flatnonzero((pt == GG_P1) | (pt == GG_P2))
     code = np.full(len(pt), -1, np.int64)

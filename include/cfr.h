@@ -172,6 +172,7 @@ typedef struct {
     int32_t blocks;            /* persistent form: workgroups of the launch */
     int32_t candidates;        /* schedules measured (0 when read from the cache) */
     double  ms_per_iteration;  /* measured time of the chosen schedule */
+    int32_t failed;            /* persistent candidates dropped because a per-game barrier timed out */
 } cfr_tune_result;
 
 /* Autotuner: time `iters` iterations under each candidate schedule -- one launch per level, and
@@ -341,13 +342,21 @@ cfr_status cfr_num_infosets(cfr_handle *h, int64_t *count);
  *   108-111 the instantaneous regrets of the uniform strategy (eq. instregret at sigma uniform)
  *           of the first four actions over the sum of their magnitudes (0 for sets of > 4 actions)
  *   112-115 regret matching (plus) of those regrets
- *   116     acting player (0 for player 1, 1 for player 2); 117-127 zero.
- * The regrets come from one plain (unclamped, uniformly weighted) iteration from zero regrets, so
- * the call resets the handle: on completion of the queued work its regrets, strategy sums and
- * counter are zero as after cfr_reset.  It also records m(I), the sum of the magnitudes of those
- * (up to four) regrets, for cfr_warm_start.  rows must equal cfr_num_infosets. */
+ *   116     acting player (0 for player 1, 1 for player 2); 117-119 zero
+ *   120-123 the current strategy after the probe (first four actions; uniform without a probe)
+ *   124-127 the normalised average strategy after the probe (uniform without a probe or sum 0)
+ *   (120-127 are zero for sets of more than four actions.)
+ * The regrets of 108-115 come from one plain (unclamped, uniformly weighted) iteration from zero
+ * regrets, after which the handle is reset (regrets, strategy sums and counter zero, as after
+ * cfr_reset).  It also records m(I), the sum of the magnitudes of those (up to four) regrets, for
+ * cfr_warm_start.  Then, if probe_iters > 0, it runs the first probe_iters iterations of the solve
+ * (as cfr_iterate) and leaves the handle there: a warm start then continues from iteration
+ * probe_iters with the strategy sums of the probe.  rows must equal cfr_num_infosets. */
 cfr_status cfr_features(cfr_handle *h, const int16_t *bucket, const int16_t *history, const float *scalars,
-                        void *x, int64_t rows, void *stream);
+                        int32_t probe_iters, void *x, int64_t rows, void *stream);
+/* m(I) of every information set (rows floats, device), as recorded by the last cfr_features call
+ * (CFR_ESTATE if there was none), on `stream`. */
+cfr_status cfr_regret_unit(cfr_handle *h, float *unit, int64_t rows, void *stream);
 /* Warm start: run the network on rows x (as made by cfr_features) and set the cumulative regrets
  * to scale * m(I) * softplus(z) for the legal actions of every set with at most 4 actions, 0 for
  * larger sets, then recompute the current strategy (as cfr_set_regrets does).  m(I) is the sum of

@@ -167,14 +167,16 @@ def warm_regrets(z, slot_off, scale, unit):
     return R0
 
 
-def features(slot_off, player, R1, bucket, history, scalars):
+def features(slot_off, player, R1, bucket, history, scalars, cur=None, avg=None):
     """Feature rows [I, 128] (bfloat16 values held in FP64) of every information set.
 
     R1: the regrets after one plain CFR iteration from zero regrets (the instantaneous regrets
     of the uniform strategy), in slot order.  Columns: 0-63 one-hot hand bucket; 64-95 one-hot
     public-history code; 96-103 the caller's scalars; 104-107 legal-action mask; 108-111 the
     first four regrets over the sum of their magnitudes; 112-115 regret matching (plus) of those
-    regrets; 116 the acting player (0 or 1); 117-127 zero."""
+    regrets; 116 the acting player (0 or 1); 117-119 zero; 120-123 the current strategy and
+    124-127 the normalised average strategy after a probe run (slot order arrays cur and avg;
+    uniform when not given); 120-127 are zero for sets of more than four actions."""
     slot_off = np.asarray(slot_off)
     I = len(slot_off) - 1
     X = np.zeros((I, FEAT))
@@ -195,4 +197,8 @@ def features(slot_off, player, R1, bucket, history, scalars):
             pos = np.maximum(r, 0.0)
             X[i, 112:112 + k] = pos / pos.sum() if pos.sum() > 0 else 1.0 / k
         X[i, 116] = float(player[i] == 2)
+        if n <= OUT:
+            sl = slice(slot_off[i], slot_off[i + 1])
+            X[i, 120:120 + n] = 1.0 / n if cur is None else np.asarray(cur[sl], np.float64)
+            X[i, 124:124 + n] = 1.0 / n if avg is None else np.asarray(avg[sl], np.float64)
     return bf16(X)

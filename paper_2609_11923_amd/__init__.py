@@ -50,7 +50,7 @@ class cfr_options(ctypes.Structure):
 
 class cfr_tune_result(ctypes.Structure):
     _fields_ = [("persistent", ctypes.c_int32), ("wg_nodes", ctypes.c_int32), ("blocks", ctypes.c_int32),
-                ("candidates", ctypes.c_int32), ("ms_per_iteration", ctypes.c_double)]
+                ("candidates", ctypes.c_int32), ("ms_per_iteration", ctypes.c_double), ("failed", ctypes.c_int32)]
 
 
 class cfr_counts_t(ctypes.Structure):
@@ -94,7 +94,7 @@ EXPORTS = ["cfr_default_options", "cfr_layout_host", "cfr_layout_free", "cfr_com
            "cfr_counts", "cfr_profile", "cfr_debug_rebind", "cfr_destroy", "cfr_last_error",
            "cfr_mlp_default_desc", "cfr_mlp_create", "cfr_mlp_num_params", "cfr_mlp_set_params", "cfr_mlp_get",
            "cfr_mlp_forward", "cfr_mlp_backward", "cfr_mlp_adam", "cfr_mlp_train_step", "cfr_mlp_destroy",
-           "cfr_num_infosets", "cfr_features", "cfr_warm_start"]
+           "cfr_num_infosets", "cfr_features", "cfr_regret_unit", "cfr_warm_start"]
 
 
 def load():
@@ -151,7 +151,8 @@ def load():
                                    ctypes.POINTER(ctypes.c_double), _P]),
         "cfr_mlp_destroy": (None, [_P]),
         "cfr_num_infosets": (S, [_P, ctypes.POINTER(ctypes.c_int64)]),
-        "cfr_features": (S, [_P, _P, _P, _P, _P, ctypes.c_int64, _P]),
+        "cfr_features": (S, [_P, _P, _P, _P, ctypes.c_int32, _P, ctypes.c_int64, _P]),
+        "cfr_regret_unit": (S, [_P, _P, ctypes.c_int64, _P]),
         "cfr_warm_start": (S, [_P, _P, _P, ctypes.c_int64, ctypes.c_float, _P]),
     }
     for name, (res, args) in sig.items():
@@ -345,6 +346,8 @@ def _dptr(t):
 def _stream_arg(stream):
     if stream is None:
         return None
+    if isinstance(stream, ctypes.c_void_p):
+        return stream
     if hasattr(stream, "cuda_stream"):
         return ctypes.c_void_p(stream.cuda_stream)
     return ctypes.c_void_p(int(stream))
@@ -362,9 +365,13 @@ def cfr_num_infosets(h) -> int:
     return n.value
 
 
-def cfr_features(h, bucket, history, scalars, x, rows: int, stream=None):
-    _check(load().cfr_features(h, _dptr(bucket), _dptr(history), _dptr(scalars), _dptr(x), int(rows),
-                               _stream_arg(stream)))
+def cfr_features(h, bucket, history, scalars, x, rows: int, probe_iters: int = 0, stream=None):
+    _check(load().cfr_features(h, _dptr(bucket), _dptr(history), _dptr(scalars), int(probe_iters), _dptr(x),
+                               int(rows), _stream_arg(stream)))
+
+
+def cfr_regret_unit(h, unit, rows: int, stream=None):
+    _check(load().cfr_regret_unit(h, _dptr(unit), int(rows), _stream_arg(stream)))
 
 
 def cfr_warm_start(h, mlp, x, rows: int, scale: float, stream=None):
@@ -508,9 +515,14 @@ class Solver:
     def n_infosets(self) -> int:
         return cfr_num_infosets(self.h)
 
-    def features(self, bucket, history, scalars, x, stream=None):
-        """Feature rows of every information set into the device tensor x (bf16 [I, 128]); resets."""
-        cfr_features(self.h, bucket, history, scalars, x, self.n_infosets, self._stream(stream))
+    def features(self, bucket, history, scalars, x, probe_iters: int = 0, stream=None):
+        """Feature rows of every information set into the device tensor x (bf16 [I, 128]); resets,
+        then runs probe_iters iterations (their strategies fill columns 120-127)."""
+        cfr_features(self.h, bucket, history, scalars, x, self.n_infosets, probe_iters, self._stream(stream))
+
+    def regret_unit(self, unit, stream=None):
+        """m(I) of every set into the device float32 tensor unit [I] (after features())."""
+        cfr_regret_unit(self.h, unit, self.n_infosets, self._stream(stream))
 
     def warm_start(self, mlp: "Mlp", x, scale: float, stream=None):
         cfr_warm_start(self.h, mlp.h, x, self.n_infosets, scale, self._stream(stream))

@@ -18,8 +18,10 @@ constexpr int32_t MEMBER_NODE_MASK = 0x7fffffff;
 constexpr int32_t MEMBER_P2 = (int32_t)0x80000000u;
 // fields per (game, depth) in game_range: node lo/hi, group lo/hi, chance lo/hi, big chance lo/hi
 constexpr int GR_FIELDS_DEV = 8;
-// bound on one barrier wait (spins of ~100 ns): a stuck wait raises the error flag instead of hanging
-constexpr int64_t BARRIER_SPIN_LIMIT = 20000000;
+// bound on one barrier wait, in seconds of the device's constant-rate clock: a stuck wait raises
+// the error flag (the launch then reports CFR_EDEVICE) instead of hanging.  A count of polls is no
+// time bound: under contention one acquire poll can take microseconds.
+constexpr double BARRIER_TIMEOUT_S = 2.0;
 
 struct DevGame {
     int32_t N = 0, I = 0, A = 0, Ndec = 0, max_depth = 0, max_actions = 0;
@@ -78,6 +80,7 @@ struct PersistentPlan {
     int32_t blocks = 0, n_games = 0, max_depth = 0;
     int4 *wg_table = nullptr;
     int32_t *game_range = nullptr, *game_depth = nullptr, *barrier = nullptr, *err = nullptr;
+    int64_t timeout_ticks = 0;   // BARRIER_TIMEOUT_S in ticks of wall_clock64()
 };
 // zero the barriers, run T iterations of every game in one launch, advance the counter by T
 hipError_t launch_persistent(const DevGame &g, const PersistentPlan &p, int32_t T, IterFlags f, hipStream_t s);

@@ -244,7 +244,8 @@ __global__ void __launch_bounds__(BLOCK) k_level(int32_t gbeg, int32_t ngroups, 
 // (device-scope release), arrives on the game's counter and waits, with a bounded spin, until all
 // W blocks of this epoch arrived; on time-out it raises the error flag and stops waiting, so every
 // wave still exits.  Returns false once the error flag is up.
-__device__ __forceinline__ bool game_barrier(int32_t *ctr, int32_t W, int32_t &epoch, int32_t *err) {
+__device__ __forceinline__ bool game_barrier(int32_t *ctr, int32_t W, int32_t &epoch, int32_t *err,
+                                             int64_t timeout_ticks) {
     __shared__ int32_t s_ok;
     if (W == 1) {
         __syncthreads();
@@ -256,11 +257,11 @@ __device__ __forceinline__ bool game_barrier(int32_t *ctr, int32_t W, int32_t &e
         __threadfence();
         atomicAdd(ctr, 1);
         const int32_t target = epoch * W;
-        int64_t spins = 0;
+        const int64_t t_start = (int64_t)wall_clock64();
         int32_t ok = 1;
         while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-                ++spins > BARRIER_SPIN_LIMIT) {
+                (int64_t)wall_clock64() - t_start > timeout_ticks) {
                 atomicExch(err, 1);
                 ok = 0;
                 break;
@@ -286,7 +287,7 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(const int4 *__restrict__ w
                                                       const int32_t *__restrict__ game_depth, int32_t MD, int32_t n_iter,
                                                       const int2 *__restrict__ up, LevelArgs<T> a,
                                                       const int32_t *__restrict__ tcount, int32_t *barrier,
-                                                      int32_t *err, int plus, int linear) {
+                                                      int32_t *err, int64_t timeout_ticks, int plus, int linear) {
     __shared__ GroupLds<T, MAXA, MPT> L;
     const int4 wt = wg_table[blockIdx.x];
     const int32_t gm = wt.x, rank = wt.y, W = wt.z;
@@ -302,14 +303,14 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(const int4 *__restrict__ w
             const int32_t lo = gr[d * GR_FIELDS_DEV], hi = gr[d * GR_FIELDS_DEV + 1];
             for (int32_t c = lo + rank * BLOCK + tid; c < hi; c += W * BLOCK)
                 forward_node<T>(c, up, a.sigma, a.r1, a.r2);
-            if (!game_barrier(barrier + gm, W, epoch, err)) return;
+            if (!game_barrier(barrier + gm, W, epoch, err, timeout_ticks)) return;
         }
         for (int32_t d = Ds - 1; d >= 0; d--) {
             const int32_t *r = gr + d * GR_FIELDS_DEV;
             for (int32_t g = r[2] + rank; g < r[3]; g += W) group_update<T, MAXA, MPT, EXPLICIT>(g, w, plus, a, L);
             for (int32_t b = r[6] + rank; b < r[7]; b += W) big_chance_value<T, EXPLICIT>(a.bigc_node[b], a, L.po);
             for (int32_t j = r[4] + rank * BLOCK + tid; j < r[5]; j += W * BLOCK) chance_value<T, EXPLICIT>(a.chance_node[j], a);
-            if (!game_barrier(barrier + gm, W, epoch, err)) return;
+            if (!game_barrier(barrier + gm, W, epoch, err, timeout_ticks)) return;
         }
     }
 }
@@ -509,7 +510,7 @@ template <typename T, int MAXA, int MPT, bool EX>
 static hipError_t persistent_t(const DevGame &g, const PersistentPlan &p, int32_t T_, IterFlags f, hipStream_t s) {
     hipLaunchKernelGGL((k_persistent<T, MAXA, MPT, EX>), dim3(p.blocks), dim3(BLOCK), 0, s, p.wg_table,
                        p.game_range, p.game_depth, p.max_depth, T_, g.up, level_args<T>(g), g.t, p.barrier, p.err,
-                       f.plus, f.linear);
+                       p.timeout_ticks, f.plus, f.linear);
     return hipGetLastError();
 }
 

@@ -316,12 +316,40 @@ __global__ void k_gather_rows(const uint16_t *X, const float *T, const float *w,
 }
 
 // ---- compiled game <-> network rows --------------------------------------------------------
+// Columns 120-127 after a probe run: the current strategy (regret matching of the latest regrets)
+// and the normalised average strategy over the first four actions (uniform where the sum is 0;
+// zero for sets of more than four actions).  One thread per set writes the 16-byte chunk.
+template <typename T>
+__global__ __launch_bounds__(256) void k_features_probe(FeatureArgs f, const T *sigma, const double *sbar) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= f.I) return;
+    const int off = f.canon_off[i], n = f.canon_off[i + 1] - off;
+    float col[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) col[j] = 0.f;
+    if (n <= 4) {
+        double sb[4] = {0, 0, 0, 0}, tot = 0.0;
+        for (int a = 0; a < n; a++) {
+            const int q = f.slot_map ? f.slot_map[off + a] : off + a;
+            col[a] = (float)sigma[q];
+            sb[a] = sbar[q];
+            tot += sb[a];
+        }
+        for (int a = 0; a < n; a++) col[4 + a] = tot > 0.0 ? (float)(sb[a] / tot) : (float)(1.0 / n);
+    }
+    uint16_t o[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) o[j] = to_bf16(col[j]);
+    *(uint4 *)(f.X + i * 128 + 120) = *(const uint4 *)o;
+}
+
 // Feature row of information set i (16 threads per row, 8 columns each), and mag[i], the sum of
 // the magnitudes of those regrets (the unit of the warm-start regrets):
 //   0-63 one-hot hand bucket, 64-95 one-hot public-history code, 96-103 caller scalars,
 //   104-107 legal-action mask, 108-111 the first four instantaneous regrets of the uniform
 //   strategy over the sum of their magnitudes, 112-115 regret matching (plus) of those regrets,
-//   116 acting player (0 / 1), 117-127 zero.
+//   116 acting player (0 / 1), 117-119 zero, 120-127 the strategies of a probe run (uniform here;
+//   k_features_probe overwrites them after one).
 template <typename T>
 __global__ __launch_bounds__(256) void k_features(FeatureArgs f, const T *R) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -362,6 +390,10 @@ __global__ __launch_bounds__(256) void k_features(FeatureArgs f, const T *R) {
                 for (int a = 0; a < k; a++) col[a] = sp > 0.0 ? (float)((r[a] > 0.0 ? r[a] : 0.0) / sp) : (float)(1.0 / k);
             col[4] = f.player[i] == 2 ? 1.f : 0.f;
         }
+    } else if (c0 == 120) {
+        const int n = f.canon_off[i + 1] - f.canon_off[i];
+        if (n <= 4)
+            for (int a = 0; a < n; a++) col[a] = col[4 + a] = (float)(1.0 / n);
     }
     uint16_t o[8];
 #pragma unroll
@@ -388,6 +420,15 @@ hipError_t launch_features(const FeatureArgs &f, const void *R, bool fp64, hipSt
     const unsigned blocks = (unsigned)((threads + 255) / 256);
     if (fp64) k_features<double><<<blocks, 256, 0, s>>>(f, (const double *)R);
     else k_features<float><<<blocks, 256, 0, s>>>(f, (const float *)R);
+    return hipGetLastError();
+}
+
+hipError_t launch_features_probe(const FeatureArgs &f, const void *sigma, const double *sbar, bool fp64,
+                                 hipStream_t s) {
+    if (f.I == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((f.I + 255) / 256);
+    if (fp64) k_features_probe<double><<<blocks, 256, 0, s>>>(f, (const double *)sigma, sbar);
+    else k_features_probe<float><<<blocks, 256, 0, s>>>(f, (const float *)sigma, sbar);
     return hipGetLastError();
 }
 

@@ -24,6 +24,9 @@ struct FeatureArgs {
 
 // R: device-order regrets after one plain iteration from zero (float or double per fp64)
 hipError_t launch_features(const FeatureArgs &f, const void *R, bool fp64, hipStream_t s);
+// columns 120-127 from the current strategy and the strategy sums (device order)
+hipError_t launch_features_probe(const FeatureArgs &f, const void *sigma, const double *sbar, bool fp64,
+                                 hipStream_t s);
 hipError_t launch_warm_regrets(const int32_t *canon_off, int64_t I, const float *z, const float *mag, float scale,
                                float *R0, hipStream_t s);
 cfr_status mlp_forward_internal(cfr_mlp *n, const void *x, int64_t rows, float *z, hipStream_t s);

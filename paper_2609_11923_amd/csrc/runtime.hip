@@ -420,6 +420,12 @@ static cfr_status build_persistent_plan(cfr_handle *h, int32_t wg_nodes) {
     HIP_TRY(hipMemcpy(pp.game_range, h->game_range.data(), h->game_range.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(pp.game_depth, h->game_depth.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(pp.err, 0, sizeof(int32_t)));
+    {
+        int khz = 0;  // rate of the constant clock wall_clock64() reads
+        HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->opt.device));
+        if (khz <= 0) return fail(CFR_EDEVICE, "device reports no wall-clock rate");
+        pp.timeout_ticks = (int64_t)(BARRIER_TIMEOUT_S * 1000.0 * khz);
+    }
     pp.blocks = (int32_t)total;
     pp.n_games = n;
     pp.max_depth = MD;
@@ -956,7 +962,7 @@ cfr_status cfr_autotune(cfr_handle *h, int64_t iters, void *stream, const char *
             std::fclose(f);
         }
     }
-    int candidates = 0;
+    int candidates = 0, failed = 0;
     if (best.ms_per_iteration < 0) {
         std::vector<std::pair<int, int>> cand = {{0, 0}};
         for (int wg : {1024, 4096, 16384, 65536, 262144}) cand.push_back({1, wg});
@@ -972,6 +978,14 @@ cfr_status cfr_autotune(cfr_handle *h, int64_t iters, void *stream, const char *
             st = cfr_iterate(h, iters, stream);            // warm-up (capture)
             if (st == CFR_OK) HIP_TRY(hipEventRecord(e0, s));
             if (st == CFR_OK) st = cfr_iterate(h, iters, stream);
+            if (st == CFR_EDEVICE && c.first) {
+                // a per-game barrier of this launch shape timed out (its blocks were not all
+                // resident): drop the candidate; the next plan build clears the error flag
+                std::fprintf(stderr, "cfr: autotune dropped persistent schedule wg_nodes=%d (%s)\n", h->wg_nodes,
+                             g_err.c_str());
+                failed++;
+                continue;
+            }
             if (st != CFR_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return st; }
             HIP_TRY(hipEventRecord(e1, s));
             HIP_TRY(hipEventSynchronize(e1));
@@ -999,6 +1013,7 @@ cfr_status cfr_autotune(cfr_handle *h, int64_t iters, void *stream, const char *
     if (st != CFR_OK) return st;
     best.blocks = h->persistent ? h->pp.blocks : 0;
     best.candidates = candidates;
+    best.failed = failed;
     if (out) *out = best;
     return CFR_OK;
 }
@@ -1015,9 +1030,10 @@ cfr_status cfr_num_infosets(cfr_handle *h, int64_t *count) {
     return CFR_OK;
 }
 
-cfr_status cfr_features(cfr_handle *h, const int16_t *bucket, const int16_t *history, const float *scalars, void *x,
-                        int64_t rows, void *stream) {
+cfr_status cfr_features(cfr_handle *h, const int16_t *bucket, const int16_t *history, const float *scalars,
+                        int32_t probe_iters, void *x, int64_t rows, void *stream) {
     if (!h) return fail(CFR_EINVAL, "handle is NULL");
+    if (probe_iters < 0) return fail(CFR_EINVAL, "probe_iters must be >= 0");
     if (rows != h->I_canon) return fail(CFR_EINVAL, "rows must equal the information-set count " + std::to_string(h->I_canon));
     if (rows > 0 && (!bucket || !history || !scalars || !x)) return fail(CFR_EINVAL, "NULL argument");
     HIP_TRY(hipSetDevice(h->opt.device));
@@ -1045,6 +1061,24 @@ cfr_status cfr_features(cfr_handle *h, const int16_t *bucket, const int16_t *his
     if (st != CFR_OK) return st;
     h->iters = 0;
     h->have_mag = true;
+    if (probe_iters > 0) {
+        // the first probe_iters iterations of the solve itself; their strategies become columns 120-127
+        st = cfr_iterate(h, probe_iters, stream);
+        if (st != CFR_OK) return st;
+        HIP_TRY(launch_features_probe(f, g.sigma, g.sbar, g.fp64 != 0, s));
+    }
+    return CFR_OK;
+}
+
+cfr_status cfr_regret_unit(cfr_handle *h, float *unit, int64_t rows, void *stream) {
+    if (!h) return fail(CFR_EINVAL, "handle is NULL");
+    if (rows != h->I_canon) return fail(CFR_EINVAL, "rows must equal the information-set count " + std::to_string(h->I_canon));
+    if (!h->have_mag) return fail(CFR_ESTATE, "call cfr_features first: it records the regret unit of every set");
+    if (rows == 0) return CFR_OK;
+    if (!unit) return fail(CFR_EINVAL, "NULL argument");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    HIP_TRY(hipMemcpyAsync(unit, h->warm_mag, (size_t)rows * sizeof(float), hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
     return CFR_OK;
 }
 

@@ -1,0 +1,324 @@
+"""Learned warm start for batches of subgames (host-side driver of the library's kernels).
+
+The paper has no learned part.  This module trains the warm-start network (cfr_mlp) on average
+strategies the solver itself produced, and measures what it buys: iterations and wall time to
+exploitability <= 1e-3 pot for the warm-started batch against plain cold-start CFR+ on the same
+GPU, with an untrained network as a control.  Exact exploitability (the device best response)
+is the judge; scale 0 (the cold start) is the fallback.
+
+Everything numeric runs in libcfr.so: the solver, the feature rows, the network's forward,
+backward and Adam steps, the warm-start injection.  torch holds device memory and streams;
+numpy shuffles indices and assembles targets on the host.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import (CFR_FEATURES, CFR_PRECISION_FP32, Mlp, Solver)
+
+THRESHOLD = 1e-3  # of the pot
+
+
+def crossing_iterations(checkpoints, expl, thr):
+    """Per game, the iteration at which exploitability first reaches thr, log-log interpolated
+    between the bracketing checkpoints (the paper's time-to-target methodology); inf if never."""
+    checkpoints = np.asarray(checkpoints, float)
+    expl = np.asarray(expl, float)          # [checkpoints, games]
+    out = np.full(expl.shape[1], np.inf)
+    for g in range(expl.shape[1]):
+        e = expl[:, g]
+        hit = np.nonzero(e <= thr)[0]
+        if hit.size == 0:
+            continue
+        k = hit[0]
+        if k == 0 or e[k - 1] <= 0 or e[k] <= 0:
+            out[g] = checkpoints[k]
+            continue
+        x0, x1 = np.log(checkpoints[k - 1]), np.log(checkpoints[k])
+        y0, y1 = np.log(e[k - 1]), np.log(e[k])
+        f = (np.log(thr) - y0) / (y1 - y0) if y1 != y0 else 1.0
+        out[g] = float(np.exp(x0 + f * (x1 - x0)))
+    return out
+
+
+def subgames(specs):
+    import gamegen as gg
+    return [gg.subgame(**{k: v for k, v in sp.items() if k != "target"}) for sp in specs]
+
+
+class Rows:
+    """Device inputs of cfr_features for a list of games (canonical set order, games in order)."""
+
+    def __init__(self, games, torch, device="cuda:0"):
+        import gamegen as gg
+        bs, hs, ss, na = [], [], [], []
+        self.game_off = [0]
+        for g in games:
+            first, _ = gg.first_members(g)
+            b, h, s = gg.warm_descriptors(g)
+            bs.append(b); hs.append(h); ss.append(s)
+            na.append(np.asarray(g.n_children)[first])
+            self.game_off.append(self.game_off[-1] + len(first))
+        self.nact = np.concatenate(na).astype(np.int64)
+        self.I = len(self.nact)
+        self.bucket = torch.tensor(np.concatenate(bs), device=device)
+        self.history = torch.tensor(np.concatenate(hs), device=device)
+        self.scalars = torch.tensor(np.concatenate(ss), device=device)
+        self.x = torch.empty(self.I, CFR_FEATURES, dtype=torch.bfloat16, device=device)
+
+    def features(self, solver, probe=0, stream=None):
+        assert solver.n_infosets == self.I
+        solver.features(self.bucket, self.history, self.scalars, self.x, probe_iters=probe, stream=stream)
+
+
+def make_training_set(specs, iters, torch, probe=0, chunk=256, precision=CFR_PRECISION_FP32, log=print):
+    """Solve the subgames of `specs` in batches of `chunk` for `iters` CFR+ iterations and keep,
+    per information set with at most 4 actions, its feature row and the solver's average
+    strategy as the target.  Row weights are the sets' regret units m(I) (which grow with the
+    opponent's and chance's reach of the set), normalised to sum to 1 over each subgame.
+    Returns device tensors X [n, 128] bf16, T [n, 4] f32, W [n] f32, nact [n] u8, and stats."""
+    Xs, Ts, Ws, Ns = [], [], [], []
+    ent = 0.0
+    t0 = time.perf_counter()
+    stats = dict(subgames=0, edges=0, rows=0, gen_s=0.0, compile_s=0.0, solve_s=0.0)
+    for c0 in range(0, len(specs), chunk):
+        ta = time.perf_counter()
+        games = subgames(specs[c0:c0 + chunk])
+        tb = time.perf_counter()
+        s = Solver(games, precision=precision)
+        rows = Rows(games, torch)
+        tc = time.perf_counter()
+        rows.features(s, probe=probe)       # the probe is the first `probe` iterations of this solve
+        unit = torch.empty(rows.I, dtype=torch.float32, device=rows.x.device)
+        s.regret_unit(unit)
+        s.iterate(iters - probe)
+        avg = s.strategy(average=True)        # host copy, synchronises
+        td = time.perf_counter()
+        off = np.concatenate([[0], np.cumsum(rows.nact)])
+        keep = np.flatnonzero(rows.nact <= 4)
+        T = np.zeros((len(keep), 4), np.float32)
+        for a in range(4):
+            has = rows.nact[keep] > a
+            T[has, a] = avg[off[keep[has]] + a]
+        u = unit.cpu().numpy().astype(np.float64)
+        W = np.zeros(rows.I)
+        for k, (lo, hi) in enumerate(zip(rows.game_off[:-1], rows.game_off[1:])):
+            tot = u[lo:hi].sum()
+            W[lo:hi] = u[lo:hi] / tot if tot > 0 else 1.0 / max(hi - lo, 1)
+        Wk = W[keep]
+        Tp = np.where(T > 0, T, 1.0)
+        ent += float((Wk * -(T * np.log(Tp)).sum(axis=1)).sum())
+        Xs.append(rows.x[torch.tensor(keep, device=rows.x.device)])
+        Ts.append(torch.tensor(T, device=rows.x.device))
+        Ws.append(torch.tensor(Wk.astype(np.float32), device=rows.x.device))
+        Ns.append(torch.tensor(rows.nact[keep].astype(np.uint8), device=rows.x.device))
+        stats["subgames"] += len(games)
+        stats["edges"] += int(sum(g.n_edges for g in games))
+        stats["rows"] += len(keep)
+        stats["gen_s"] += tb - ta
+        stats["compile_s"] += tc - tb
+        stats["solve_s"] += td - tc
+        s.close()
+        del games
+        log(f"[warm] data {stats['subgames']}/{len(specs)} subgames, {stats['rows']} rows, "
+            f"{time.perf_counter() - t0:.1f} s")
+    X = torch.cat(Xs)
+    T = torch.cat(Ts)
+    W = torch.cat(Ws)
+    N = torch.cat(Ns)
+    # the weighted target entropy: the loss a perfect predictor would reach
+    stats["target_entropy"] = ent / max(float(W.sum().item()), 1e-30)
+    return X, T, W, N, stats
+
+
+def train(mlp: Mlp, X, T, W, N, torch, epochs=4, batch=4096, lr=1e-3, lr_min=1e-4, seed=0, val=None, log=print):
+    """Adam on shuffled minibatches of weighted rows, cosine learning-rate decay.  val: an optional
+    (X, T, W, N) whose loss is reported after every epoch."""
+    n = X.shape[0]
+    rng = np.random.default_rng(seed)
+    steps = epochs * max(1, n // batch)
+    step = 0
+    hist = []
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        perm = torch.tensor(rng.permutation(n).astype(np.int32), device=X.device)
+        for k in range(0, n - batch + 1 if n >= batch else 1, batch):
+            idx = perm[k:k + batch]
+            rows = int(idx.shape[0])
+            lr_t = lr_min + 0.5 * (lr - lr_min) * (1 + np.cos(np.pi * step / max(1, steps)))
+            mlp.train_step(X, T, W, N, rows, lr_t, idx=idx, n_data=n, stream=stream)
+            step += 1
+        torch.cuda.synchronize()
+        rec = dict(epoch=ep + 1, steps=step, s=time.perf_counter() - t0)
+        if val is not None:
+            rec["val_loss"] = loss_of(mlp, *val, torch=torch)
+        m = min(n, 65536)
+        rec["train_loss_sample"] = loss_of(mlp, X[:m], T[:m], W[:m], N[:m], torch=torch)
+        hist.append(rec)
+        log(f"[warm] epoch {rec}")
+    return hist
+
+
+def loss_of(mlp: Mlp, X, T, W, N, torch):
+    """Weighted mean cross entropy over rows (chunks of max_rows); the gradient buffer is
+    overwritten, the parameters are not."""
+    n = X.shape[0]
+    cap = mlp.desc.max_rows
+    tot, wt = 0.0, 0.0
+    for k in range(0, n, cap):
+        r = min(cap, n - k)
+        wk = float(W[k:k + r].sum().item())
+        tot += wk * mlp.backward(X[k:k + r], T[k:k + r], W[k:k + r], N[k:k + r], r)
+        wt += wk
+    return tot / max(wt, 1e-30)
+
+
+def solve_curves(s: Solver, rows: Rows, torch, checkpoints, mlp=None, scale=0.0, probe=0, log=None):
+    """One batch solve from scratch on solver s, with exploitability checkpoints at absolute
+    iteration counts (a warm start's probe iterations count).  Timed on the stream with events:
+    the warm start (feature pass, probe iterations, network, injection) and the iterations; the
+    best-response evaluations at the checkpoints are not timed.  Returns (expl [checkpoints,
+    games], warm_ms, iter_ms, the checkpoints used)."""
+    stream = torch.cuda.Stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    warm_ms = 0.0
+    s.reset()
+    torch.cuda.synchronize()
+    if mlp is not None:
+        ev[0].record(stream)
+        rows.features(s, probe=probe, stream=stream)
+        s.warm_start(mlp, rows.x, scale, stream=stream)
+        ev[1].record(stream)
+        ev[1].synchronize()
+        warm_ms = ev[0].elapsed_time(ev[1])
+    done = probe if mlp is not None else 0
+    checkpoints = [int(c) for c in checkpoints if c > done]
+    expl, iter_ms = [], 0.0
+    for c in checkpoints:
+        ev[0].record(stream)
+        s.iterate(int(c) - done, stream=stream)
+        ev[1].record(stream)
+        ev[1].synchronize()
+        iter_ms += ev[0].elapsed_time(ev[1])
+        done = int(c)
+        expl.append(s.batch_exploitability(stream=stream)[0])
+        if log is not None:
+            log(f"[warm]   iteration {done}: median expl {np.median(expl[-1]):.3e}")
+    return np.array(expl), warm_ms, iter_ms, checkpoints
+
+
+LEVEL_SYNC = {"persistent": 0, "wg_nodes": 0}
+
+
+def batch_solver(games, torch, schedule=LEVEL_SYNC, precision=CFR_PRECISION_FP32, tune_iters=20, log=print):
+    """A compiled batch on the given schedule (None: autotuned).  Warm and cold arms share the
+    handle, so they always run the same schedule."""
+    log(f"[warm] compiling {len(games)} games")
+    s = Solver(games, precision=precision)
+    if schedule is None:
+        schedule = s.autotune(tune_iters, stream=torch.cuda.Stream())
+        log(f"[warm] autotune: {schedule}")
+    else:
+        s.set_schedule(bool(schedule["persistent"]), int(schedule.get("wg_nodes", 0)))
+    return s, schedule
+
+
+def summarize(cross, ms_per_iter, warm_ms, skip=0):
+    """Iterations to the threshold count from the start; wall time is the warm start (which holds
+    the first `skip` iterations) plus the remaining iterations at the measured rate."""
+    fin = np.isfinite(cross)
+    t = lambda it: float(warm_ms + max(it - skip, 0.0) * ms_per_iter)  # noqa: E731
+    q = lambda a, p: float(np.percentile(a, p)) if a.size else None  # noqa: E731
+    return dict(
+        reached=int(fin.sum()), games=int(cross.size),
+        iterations_median=float(np.median(cross)),
+        iterations_iqr=[float(np.percentile(cross, 25)), float(np.percentile(cross, 75))],
+        time_ms_median=t(np.median(cross)),
+        time_ms_iqr=[t(np.percentile(cross, 25)), t(np.percentile(cross, 75))],
+        time_ms_all=t(np.max(cross)) if fin.all() else None,
+        probe_iterations=int(skip),
+        reached_iterations_median=q(cross[fin], 50),
+        warm_ms=float(warm_ms), ms_per_iteration=float(ms_per_iter),
+    )
+
+
+def geometric_checkpoints(t_max):
+    c, k = [], 8
+    while k < t_max:
+        c.append(k)
+        k = int(np.ceil(k * 1.5))
+    return c + [t_max]
+
+
+def choose_scale(games, torch, mlp, scales, t_max, probe=0, schedule=LEVEL_SYNC, log=print):
+    """The scale whose warm start reaches the threshold in the fewest iterations (median over the
+    validation games; ties and unreached games broken by the geometric mean of the final
+    exploitability)."""
+    cps = geometric_checkpoints(t_max)
+    pots = np.array([g.pot for g in games])
+    s, _ = batch_solver(games, torch, schedule=schedule, log=log)
+    rows = Rows(games, torch)
+    best = None
+    table = []
+    for c in scales:
+        log(f"[warm] validation solve at scale {c}")
+        e, _, _, used = solve_curves(s, rows, torch, cps, mlp=mlp, scale=c, probe=probe, log=log)
+        cross = crossing_iterations(used, e, THRESHOLD * pots.min())
+        score = (float(np.median(cross)), float(np.exp(np.mean(np.log(np.maximum(e[-1], 1e-12))))))
+        table.append(dict(scale=c, median_iterations=score[0], final_expl_geomean=score[1]))
+        log(f"[warm] scale {c}: median iterations {score[0]:.1f}, final expl geomean {score[1]:.3e}")
+        if best is None or score < best[0]:
+            best = (score, c)
+    s.close()
+    return best[1], table
+
+
+def evaluate(games, torch, mlp, scale, t_max, control=None, probe=0, schedule=LEVEL_SYNC, log=print):
+    """Cold, warm and (optional) control-network solves of the same batch with the same compiled
+    handle and schedule; per-game iterations and wall time to exploitability <= 1e-3 pot."""
+    s, schedule = batch_solver(games, torch, schedule=schedule, log=log)
+    rows = Rows(games, torch)
+    cps = geometric_checkpoints(t_max)
+    pots = np.array([g.pot for g in games])
+    thr = THRESHOLD * pots.min()
+    out = {"schedule": schedule}
+    arms = [("cold", None, 0.0), ("warm", mlp, scale)]
+    if control is not None:
+        arms.append(("control_untrained_net", control, scale))
+    for name, net, c in arms:
+        log(f"[warm] test solve: {name}")
+        e, warm_ms, iter_ms, used = solve_curves(s, rows, torch, cps, mlp=net, scale=c, probe=probe, log=log)
+        cross = crossing_iterations(used, e, thr)
+        # iterations count from the start (probe included); the probe's time is inside warm_ms
+        skip = probe if net is not None else 0
+        out[name] = summarize(cross, iter_ms / (used[-1] - skip), warm_ms, skip)
+        out[name]["expl_final_median"] = float(np.median(e[-1]))
+        out[name]["_cross"] = cross
+        log(f"[warm] {name}: {({k: v for k, v in out[name].items() if not k.startswith('_')})}")
+    s.close()
+    return out
+
+
+def alone_ms_per_iteration(games, torch, iters=50, log=print):
+    """Milliseconds per iteration of each game solved on its own (one handle, hipGraph replay):
+    the per-game cost of plain one-at-a-time solving.  A batch reproduces each game's iterates
+    bitwise, so its crossing iterations carry over unchanged."""
+    out = np.zeros(len(games))
+    stream = torch.cuda.Stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for k, g in enumerate(games):
+        s = Solver(g)
+        s.iterate(3, stream=stream)       # direct iteration + capture
+        ev[0].record(stream)
+        s.iterate(iters, stream=stream)
+        ev[1].record(stream)
+        ev[1].synchronize()
+        out[k] = ev[0].elapsed_time(ev[1]) / iters
+        s.close()
+        if (k + 1) % 64 == 0:
+            log(f"[warm] timed {k + 1}/{len(games)} games alone")
+    return out
+

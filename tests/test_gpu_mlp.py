@@ -3,9 +3,10 @@
 reference feature rows built from the oracle's own CFR, and the warm-start injection against the
 oracle's CFR from the same initial regrets.
 
-Tolerances: forward, loss and gradients <= 1e-3 normwise relative (the bar for BF16 kernels
-against FP64; the rounding points are emulated, so what remains is FP32 accumulation order and
-the rare bfloat16 rounding flip of an activation sitting on a rounding boundary); Adam from the
+Tolerances: loss and gradients <= 1e-3 normwise relative (the bar for BF16 kernels against FP64;
+the rounding points are emulated, so what remains is FP32 accumulation order and the rare
+bfloat16 rounding flip of an activation sitting on a rounding boundary); logits <= 1e-4 in the
+Frobenius norm and <= 4e-3 in the max norm, which a few isolated flips can reach; Adam from the
 same gradients to FP32 rounding; feature rows bit-exact except the regret blocks, which may
 differ by one bfloat16 step where the FP64 and FP32 normalisations round apart."""
 import sys
@@ -86,9 +87,15 @@ def test_forward_matches_oracle(shape, rows):
     torch.cuda.synchronize()
     _, zq = om.forward(theta, sizes, X, quant=True)
     _, z64 = om.forward(theta, sizes, X, quant=False)
-    e = rel(z.cpu().numpy(), zq)
-    note(f"  rel vs emulated {e:.2e}, vs unrounded FP64 {rel(z.cpu().numpy(), z64):.2e}")
-    assert e <= 1e-3
+    zg = z.cpu().numpy().astype(np.float64)
+    e = rel(zg, zq)
+    fro = float(np.linalg.norm(zg - zq) / max(np.linalg.norm(zq), 1e-30))
+    note(f"  rel vs emulated: max {e:.2e}, frobenius {fro:.2e}; vs unrounded FP64 {rel(zg, z64):.2e}")
+    # typical rows agree to FP32 accumulation order; an activation whose FP32 and FP64 values round
+    # to neighbouring bfloat16 numbers moves its row by about one bfloat16 step (2^-8) of that
+    # contribution, so the max-norm bound allows a few such flips
+    assert fro <= 1e-4
+    assert e <= 4e-3
 
 
 @pytest.mark.parametrize("shape", [(128, 256, 3), (64, 64, 1)])
@@ -241,7 +248,7 @@ def test_features_match_oracle_and_reset(precision):
     torch.cuda.synchronize()
     got = x.float().cpu().numpy().astype(np.float64)
     ref = oracle_features(games, b, h, sc)
-    exact = np.r_[0:108, 116:128]
+    exact = np.r_[0:108, 116:128]   # 120-127: uniform without a probe, computed identically
     assert np.array_equal(got[:, exact], ref[:, exact])
     d = np.abs(got[:, 108:116] - ref[:, 108:116])
     note(f"  regret block: {(d > 0).mean():.2e} of entries differ, max {d.max():.2e}")
@@ -260,6 +267,42 @@ def test_features_match_oracle_and_reset(precision):
     t = cfr.Solver(games, precision=p)
     t.iterate(7)
     assert np.array_equal(s.state()[0], t.state()[0])
+
+
+@pytest.mark.parametrize("probe", [1, 8])
+def test_probe_columns_match_oracle_and_the_solve_continues(probe):
+    games = warm_games()
+    b, h, sc = descriptors(games)
+    s = cfr.Solver(games, precision=cfr.CFR_PRECISION_FP64)
+    I = s.n_infosets
+    x = torch.zeros(I, 128, dtype=torch.bfloat16, device=DEV)
+    s.features(torch.tensor(b, device=DEV), torch.tensor(h, device=DEV), torch.tensor(sc, device=DEV), x,
+               probe_iters=probe)
+    torch.cuda.synchronize()
+    assert s.iterations == probe
+    got = x.float().cpu().numpy().astype(np.float64)
+    rows, o = [], 0
+    for g in games:
+        orc = oracle.Oracle(g, plus=False, linear=False)
+        orc.iterate(1)
+        L = orc.layout()
+        I_k = len(L["slot_off"]) - 1
+        op = oracle.Oracle(g)
+        op.iterate(probe)
+        _, _, cur, avg = op.state()
+        rows.append(om.features(L["slot_off"], L["iset_player"], orc.state()[0], b[o:o + I_k], h[o:o + I_k],
+                                sc[o:o + I_k], cur, avg))
+        o += I_k
+    ref = np.concatenate(rows)
+    assert np.array_equal(got[:, :108], ref[:, :108]) and np.array_equal(got[:, 116:120], ref[:, 116:120])
+    d = np.abs(got[:, 108:] - ref[:, 108:])
+    note(f"[probe {probe}] strategy columns: {(d[:, 12:] > 0).mean():.2e} differ, max {d.max():.2e}")
+    assert np.all(d <= 2.0 ** -8 * np.abs(ref[:, 108:]) + 1e-12)
+    # the probe iterations are the first iterations of the solve
+    s.iterate(20)
+    t = cfr.Solver(games, precision=cfr.CFR_PRECISION_FP64)
+    t.iterate(probe + 20)
+    assert np.array_equal(s.state()[0], t.state()[0]) and np.array_equal(s.state()[1], t.state()[1])
 
 
 def test_warm_start_matches_oracle_cfr_from_the_same_regrets():

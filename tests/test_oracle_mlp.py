@@ -151,7 +151,15 @@ def test_feature_rows_by_hand():
     assert np.array_equal(X[2, 104:108], [1, 1, 1, 1]) and np.all(X[2, 108:116] == 0)
     assert list(X[:, 116]) == [0, 1, 0]
     assert np.array_equal(X[:, 96:104], om.bf16(sc))
-    assert np.all(X[:, 117:] == 0)
+    assert np.all(X[:, 117:120] == 0)
+    # no probe: uniform strategies; none for the five-action set
+    assert np.array_equal(X[0, 120:128], om.bf16([1 / 3, 1 / 3, 1 / 3, 0, 1 / 3, 1 / 3, 1 / 3, 0]))
+    assert np.array_equal(X[1, 120:128], [0.5, 0.5, 0, 0, 0.5, 0.5, 0, 0]) and np.all(X[2, 120:] == 0)
+    cur = np.array([0.25, 0.75, 0, 1, 0, 0.2, 0.2, 0.2, 0.2, 0.2])
+    avg = np.array([0.5, 0.5, 0, 0.125, 0.875, 0.2, 0.2, 0.2, 0.2, 0.2])
+    X = om.features(slot_off, player, R1, bucket, history, sc, cur, avg)
+    assert np.array_equal(X[0, 120:128], [0.25, 0.75, 0, 0, 0.5, 0.5, 0, 0])
+    assert np.array_equal(X[1, 120:128], [1, 0, 0, 0, 0.125, 0.875, 0, 0]) and np.all(X[2, 120:] == 0)
 
 
 def test_instantaneous_regret_feature_source_is_brute_force_regret():
@@ -186,3 +194,22 @@ def test_descriptors_of_a_subgame():
     first = L["mem_node"][L["mem_off"][:-1]]
     assert np.all(np.asarray(g.type)[first] == L["iset_player"])
     assert np.all((sc[:, 0] >= 0) & (sc[:, 0] < 0.5))
+
+
+@pytest.mark.parametrize("which", ["kuhn", "leduc", "subgame", "random"])
+def test_first_members_follow_the_canonical_set_order(which):
+    import oracle
+    if which == "kuhn":
+        g = gg.kuhn()
+    elif which == "leduc":
+        g = gg.leduc(3, 2)
+    elif which == "subgame":
+        spec = gg.random_subgames(1, 5, lo=2e3, hi=5e3)[0]
+        spec.pop("target")
+        g = gg.subgame(**spec)
+    else:
+        g = gg.random_game(11, 5, 5, 7, max_actions=5)
+    L = oracle.Oracle(g).layout()
+    first, player = gg.first_members(g)
+    assert np.array_equal(first, L["mem_node"][L["mem_off"][:-1]])
+    assert np.array_equal(player, L["iset_player"])
