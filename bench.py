@@ -140,6 +140,75 @@ def run_batch(cfr, torch, games, iters, precision, log, tune_iters=20, warm=None
     ), cross
 
 
+def measure_game(cfr, torch, game, args, precision, log):
+    """Compile one game, replay `warmup` then time `steps` iterations (hip events on the stream the
+    graph is launched on), then per-kernel durations and bytes (cfr_profile) and the roofline of
+    the dominant kernel; the handle is released before returning."""
+    t0 = time.perf_counter()
+    prec = cfr.CFR_PRECISION_FP64 if precision == "fp64" else cfr.CFR_PRECISION_FP32
+    solver = cfr.Solver(game, iters_per_graph=args.iters_per_graph, precision=prec, use_graph=not args.direct)
+    t_compile = time.perf_counter() - t0
+    c = solver.counts
+    log(f"[bench] {precision}: compiled in {t_compile:.1f} s: {c}")
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    solver.iterate(max(args.warmup, 1), stream=stream)   # the first call also captures the graph
+    stream.synchronize()
+    t_warm = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    solver.iterate(args.steps, stream=stream)
+    ev1.record(stream)
+    ev1.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    ms_step = ms / args.steps
+    log(f"[bench] {precision}: {args.steps} iterations in {ms:.2f} ms ({ms_step:.4f} ms/iteration)")
+    kernels = solver.profile(args.profile_iters, stream=stream)
+    bytes_iter = sum(k["bytes_per_iteration"] for k in kernels)
+    method_iter = sum(k["method_bytes_per_iteration"] for k in kernels)
+    dom = max(kernels, key=lambda k: k["ms_per_iteration"])
+    nl = dom["launches_per_iteration"]
+    per_launch_ms = dom["ms_per_iteration"] / nl
+    per_launch_method = dom["method_bytes_per_iteration"] / nl
+    per_launch_design = dom["bytes_per_iteration"] / nl
+    achieved = per_launch_method / (per_launch_ms * 1e-3) / 1e9
+    traffic = stored_traffic(dom["name"], args.workload, precision, nl)
+    log(f"[bench] {precision}: kernels {kernels}")
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calibrate_copy} MiB done")
+        del src, dst
+    e, b1, b2, v = solver.exploitability(stream=stream)
+    res = dict(
+        counts=c, compile_s=t_compile, warmup_s=t_warm, ms_per_iteration=ms_step,
+        iterations_per_s=args.steps / (ms * 1e-3),
+        hbm_gbps_method_bytes=method_iter / (ms_step * 1e-3) / 1e9, method_bytes_per_iteration=method_iter,
+        hbm_gbps_design_bytes=bytes_iter / (ms_step * 1e-3) / 1e9, design_bytes_per_iteration=bytes_iter,
+        roofline={
+            "bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+            "launches_per_iteration": nl, "ms_per_launch": per_launch_ms,
+            "method_bytes_per_launch": per_launch_method,
+            "design_bytes_per_launch": per_launch_design,
+            "achieved_design_bytes": per_launch_design / (per_launch_ms * 1e-3) / 1e9,
+            "achieved_traffic": None if traffic is None else traffic / (per_launch_ms * 1e-3) / 1e9,
+        },
+        kernels=kernels,
+        exploitability_after={"iterations": solver.iterations, "expl": e, "pot": float(c["pot"])},
+    )
+    solver.close()
+    del solver
+    torch.cuda.empty_cache()
+    return res
+
+
 def run_warm(cfr, torch, args, log):
     """Learned warm start: train the network on average strategies of solved subgames (their own
     payoff seeds, so nothing about the test payoffs can be memorised), pick the regret scale on a
@@ -254,7 +323,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--iters-per-graph", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-state run of the same game")
     ap.add_argument("--direct", action="store_true", help="launch kernels directly instead of replaying a graph")
     ap.add_argument("--batch-games", type=int, default=256)
     ap.add_argument("--batch-iters", type=int, default=500)
@@ -268,8 +338,8 @@ def main():
     ap.add_argument("--warm-epochs", type=int, default=8)
     ap.add_argument("--warm-lr", type=float, default=2e-3)
     ap.add_argument("--warm-probe", type=int, default=16, help="probe iterations whose strategies feed the network")
-    ap.add_argument("--warm-max-iters", type=int, default=2000)
-    ap.add_argument("--warm-scales", type=float, nargs="+", default=[1.0, 3.0, 10.0, 30.0, 100.0])
+    ap.add_argument("--warm-max-iters", type=int, default=4000)
+    ap.add_argument("--warm-scales", type=float, nargs="+", default=[0.25, 0.5, 1.0, 2.0, 4.0])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration for profilers)")
     args = ap.parse_args()
@@ -300,68 +370,18 @@ def main():
     game, desc, sample_fn, sample_desc = make_workload(args.workload, args.K, args.seed)
     t_gen = time.perf_counter() - t0
     log(f"[bench] generated {args.workload}: {game.n_nodes} nodes in {t_gen:.1f} s")
-    t0 = time.perf_counter()
-    prec = cfr.CFR_PRECISION_FP64 if args.precision == "fp64" else cfr.CFR_PRECISION_FP32
-    solver = cfr.Solver(game, iters_per_graph=args.iters_per_graph, precision=prec, use_graph=not args.direct)
-    t_compile = time.perf_counter() - t0
-    c = solver.counts
-    log(f"[bench] compiled in {t_compile:.1f} s: {c}")
     n_nodes = game.n_nodes
-    del game
-
     torch.cuda.set_device(0)
-    stream = torch.cuda.Stream()
-    t0 = time.perf_counter()
-    solver.iterate(max(args.warmup, 1), stream=stream)   # the first call also captures the graph
-    stream.synchronize()
-    t_warm = time.perf_counter() - t0
-    log(f"[bench] warmup {args.warmup} iterations (incl. capture) {t_warm:.2f} s")
-
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    ev0.record(stream)
-    solver.iterate(args.steps, stream=stream)
-    ev1.record(stream)
-    ev1.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = ev0.elapsed_time(ev1)
-    ms_step = ms / args.steps
-    log(f"[bench] {args.steps} iterations in {ms:.2f} ms ({ms_step:.4f} ms/iteration, wall {wall:.3f} s)")
-
-    kernels = solver.profile(args.profile_iters, stream=stream)
-    bytes_iter = sum(k["bytes_per_iteration"] for k in kernels)
-    method_iter = sum(k["method_bytes_per_iteration"] for k in kernels)
-    dom = max(kernels, key=lambda k: k["ms_per_iteration"])
-    nl = dom["launches_per_iteration"]
-    per_launch_ms = dom["ms_per_iteration"] / nl
-    per_launch_method = dom["method_bytes_per_iteration"] / nl
-    per_launch_design = dom["bytes_per_iteration"] / nl
-    achieved = per_launch_method / (per_launch_ms * 1e-3) / 1e9
-    traffic = stored_traffic(dom["name"], args.workload, args.precision, nl)
-    log(f"[bench] kernels: {kernels}")
-
-    if args.calibrate_copy > 0:
-        n = args.calibrate_copy * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy of {args.calibrate_copy} MiB done")
-        del src, dst
-
-    e, b1, b2, v = solver.exploitability(stream=stream)
+    m = measure_game(cfr, torch, game, args, args.precision, log)
+    c = m["counts"]
     out = {
         "metric": METRIC,
-        "value": args.steps / (ms * 1e-3),
+        "value": m["iterations_per_s"],
         "unit": "iterations/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": m["ms_per_iteration"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -370,29 +390,26 @@ def main():
         "config": {
             "workload": desc, "nodes": int(c["nodes"]), "edges": int(c["edges"]), "infosets": int(c["infosets"]),
             "slots": int(c["slots"]), "blocks": int(c["blocks"]), "rule": "CFR+, simultaneous, linear averaging",
-            "state": ("FP64" if args.precision == "fp64" else "FP32") + " reach/values/regrets/strategy, FP64 strategy sums", "graph": f"{args.iters_per_graph} iteration(s) per hipGraph",
+            "state": ("FP64" if args.precision == "fp64" else "FP32") + " reach/values/regrets/strategy, FP64 strategy sums",
+            "graph": f"{args.iters_per_graph} iteration(s) per hipGraph",
         },
         # whole iteration: the method's per-unit byte figures, and the bytes this design's kernels touch
-        "hbm_gbps_method_bytes": method_iter / (ms_step * 1e-3) / 1e9,
-        "method_bytes_per_iteration": method_iter,
-        "hbm_gbps_design_bytes": bytes_iter / (ms_step * 1e-3) / 1e9,
-        "design_bytes_per_iteration": bytes_iter,
-        "roofline": {
-            "bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-            "launches_per_iteration": nl, "ms_per_launch": per_launch_ms,
-            "method_bytes_per_launch": per_launch_method,
-            "design_bytes_per_launch": per_launch_design,
-            "achieved_design_bytes": per_launch_design / (per_launch_ms * 1e-3) / 1e9,
-            "achieved_traffic": None if traffic is None else traffic / (per_launch_ms * 1e-3) / 1e9,
-        },
-        "kernels": kernels,
-        "setup_s": {"generate": t_gen, "compile": t_compile, "warmup_and_capture": t_warm},
-        "exploitability_after": {"iterations": solver.iterations, "expl": e, "pot": float(c["pot"])},
+        "hbm_gbps_method_bytes": m["hbm_gbps_method_bytes"],
+        "method_bytes_per_iteration": m["method_bytes_per_iteration"],
+        "hbm_gbps_design_bytes": m["hbm_gbps_design_bytes"],
+        "design_bytes_per_iteration": m["design_bytes_per_iteration"],
+        "roofline": m["roofline"],
+        "kernels": m["kernels"],
+        "setup_s": {"generate": t_gen, "compile": m["compile_s"], "warmup_and_capture": m["warmup_s"]},
+        "exploitability_after": m["exploitability_after"],
         "device_bytes": int(c["device_bytes"]),
     }
-    solver.close()
-    del solver
+    if args.precision == "fp32" and not args.no_fp64:
+        # the same game with FP64 state (the configuration held to the full parity bar)
+        f64 = measure_game(cfr, torch, game, args, "fp64", log)
+        out["fp64_state"] = {k: f64[k] for k in ("iterations_per_s", "ms_per_iteration", "hbm_gbps_method_bytes",
+                                                  "hbm_gbps_design_bytes", "roofline", "exploitability_after")}
+    del game
     torch.cuda.empty_cache()
     if not args.no_batch:
         games, _ = batch_games(args.batch_games, args.seed)
