@@ -106,12 +106,17 @@ def regret_match(R, isets):
     return sig
 
 
-def cfr(P, isets, nslots, T, plus=True, linear=True):
-    """Simultaneous CFR / CFR+ by terminal sums; returns (R, sbar)."""
+def cfr(P, isets, nslots, T, plus=True, linear=True, rule=None):
+    """Simultaneous CFR / CFR+ / DCFR / PCFR+ by terminal sums; returns (R, sbar).  rule (None:
+    CFR+ if plus else CFR) follows the published definitions: DCFR discounts positive regrets
+    by t^1.5/(t^1.5+1), negative ones by 1/2 and the strategy sums by (t/(t+1))^2 after adding;
+    PCFR+ plays regret matching of R + (last instantaneous regret) and averages with weight t^2."""
+    rule = rule or ("cfr+" if plus else "cfr")
     R = np.zeros(nslots)
     S = np.zeros(nslots)
+    pred = np.zeros(nslots)
     for t in range(1, T + 1):
-        sig = regret_match(R, isets)
+        sig = regret_match(R + pred if rule == "pcfr+" else R, isets)
         cfv = np.zeros(nslots)
         own_reach = {}
         for pic, u, decs in P:
@@ -131,11 +136,18 @@ def cfr(P, isets, nslots, T, plus=True, linear=True):
                 own_reach[i] = mine_before
         for i, (pl, nA, s) in enumerate(isets):
             v = float(np.dot(sig[s:s + nA], cfv[s:s + nA]))
-            R[s:s + nA] += cfv[s:s + nA] - v
-            if plus:
+            r = cfv[s:s + nA] - v
+            R[s:s + nA] += r
+            if rule in ("cfr+", "pcfr+"):
                 R[s:s + nA] = np.maximum(R[s:s + nA], 0.0)
-            w = float(t) if linear else 1.0
+            if rule == "dcfr":
+                R[s:s + nA] *= np.where(R[s:s + nA] > 0, t ** 1.5 / (t ** 1.5 + 1), 0.5)
+            if rule == "pcfr+":
+                pred[s:s + nA] = r
+            w = {"dcfr": 1.0, "pcfr+": float(t) * t}.get(rule, float(t) if linear else 1.0)
             # an information set every terminal path avoids has no recorded reach; its
             # average contribution is then zero (its own reach is zero under sigma)
             S[s:s + nA] += w * own_reach.get(i, 0.0) * sig[s:s + nA]
+            if rule == "dcfr":
+                S[s:s + nA] *= (t / (t + 1.0)) ** 2
     return R, S

@@ -83,15 +83,28 @@ typedef struct {
     int64_t hcap;
     int64_t *hkey, *hval;
     /* solver state (per slot) */
-    st_t *R, *sigma, *rinst;
+    st_t *R, *sigma, *rinst, *pred;
     double *sbar;
     int64_t *avg_stamp;           /* per infoset: last (iteration, player) stamp the average was added */
-    int plus, linear, alternating;
+    int rule, linear, alternating; /* rule: RULE_CFR, RULE_CFR_PLUS, RULE_DCFR, RULE_PCFR_PLUS */
     int64_t t;                    /* iterations done */
     /* scratch for BR */
     double *memo, *q;
     int *astar;
 } oracle;
+
+/* Update rules (paper Sec. 6 "Update rule and update order"; constants the paper leaves out are
+ * those of the published methods):
+ *   CFR    R += r;                                     average weight w_t (t or 1)
+ *   CFR+   R = max(R + r, 0);                          average weight w_t
+ *   DCFR   R = R + r, then times t^a/(t^a+1) where positive and t^b/(t^b+1) where not
+ *          (a = 3/2, b = 0); S = (S + pi sigma) (t/(t+1))^g (g = 2)   (Brown and Sandholm 2019)
+ *   PCFR+  R = max(R + r, 0); sigma^{t+1} = regret matching of R + m with the prediction
+ *          m = r (the latest instantaneous regret); average weight t^2  (Farina et al. 2021) */
+enum { RULE_CFR = 0, RULE_CFR_PLUS = 1, RULE_DCFR = 2, RULE_PCFR_PLUS = 3 };
+#define DCFR_ALPHA 1.5
+#define DCFR_BETA 0.0
+#define DCFR_GAMMA 2.0
 
 static uint64_t mix64(uint64_t x) {
     x ^= x >> 33; x *= 0xff51afd7ed558ccdull; x ^= x >> 33; x *= 0xc4ceb9fe1a85ec53ull; x ^= x >> 33;
@@ -117,7 +130,7 @@ void or_destroy(oracle *o) {
     if (!o) return;
     free(o->type); free(o->kb); free(o->nk); free(o->kids); free(o->prob); free(o->key); free(o->payoff);
     free(o->canon); free(o->order); free(o->depth); free(o->iset); free(o->info); free(o->mem_off); free(o->mem);
-    free(o->hkey); free(o->hval); free(o->R); free(o->sbar); free(o->sigma); free(o->rinst); free(o->avg_stamp);
+    free(o->hkey); free(o->hval); free(o->R); free(o->sbar); free(o->sigma); free(o->rinst); free(o->pred); free(o->avg_stamp);
     free(o->memo); free(o->q); free(o->astar);
     free(o);
 }
@@ -249,12 +262,13 @@ oracle *or_create(int64_t n, int64_t root, const int8_t *type, const int64_t *ch
     o->sbar = (double *)calloc((size_t)A, 8);
     o->sigma = (st_t *)calloc((size_t)A, sizeof(st_t));
     o->rinst = (st_t *)calloc((size_t)A, sizeof(st_t));
+    o->pred = (st_t *)calloc((size_t)A, sizeof(st_t));
     o->avg_stamp = (int64_t *)malloc((size_t)(o->ni ? o->ni : 1) * 8);
     for (int64_t i = 0; i < o->ni; i++) o->avg_stamp[i] = -1;
     o->memo = (double *)malloc((size_t)n * 8);
     o->q = (double *)malloc((size_t)n * 8);
     o->astar = (int *)malloc((size_t)(o->ni ? o->ni : 1) * sizeof(int));
-    o->plus = 1; o->linear = 1; o->alternating = 0; o->t = 0;
+    o->rule = RULE_CFR_PLUS; o->linear = 1; o->alternating = 0; o->t = 0;
     return o;
 }
 
@@ -307,13 +321,17 @@ void or_layout(const oracle *o, int32_t *depth_off, int32_t *parent, int32_t *ch
 }
 
 void or_set_options(oracle *o, int plus, int linear, int alternating) {
-    o->plus = plus; o->linear = linear; o->alternating = alternating;
+    o->rule = plus ? RULE_CFR_PLUS : RULE_CFR; o->linear = linear; o->alternating = alternating;
 }
+
+/* rule: RULE_CFR .. RULE_PCFR_PLUS (linear applies to CFR and CFR+ only) */
+void or_set_rule(oracle *o, int rule) { o->rule = rule; }
 
 void or_reset(oracle *o) {
     int64_t A = o->na;
     memset(o->R, 0, (size_t)(A ? A : 1) * sizeof(st_t));
     memset(o->sbar, 0, (size_t)(A ? A : 1) * 8);
+    memset(o->pred, 0, (size_t)(A ? A : 1) * sizeof(st_t));
     for (int64_t i = 0; i < o->ni; i++) o->avg_stamp[i] = -1;
     o->t = 0;
 }
@@ -325,11 +343,19 @@ static void regret_match(const st_t *R, st_t *sig, int nA) {
     for (int a = 0; a < nA; a++) sig[a] = tot > 0 ? (R[a] > 0 ? R[a] : (st_t)0) / tot : (st_t)1 / (st_t)nA;
 }
 
+/* the strategy the next traversal plays: regret matching of R, or of R + prediction (PCFR+) */
+static void current_strategy(const oracle *o, const oinfo *I, st_t *sig) {
+    if (o->rule != RULE_PCFR_PLUS) { regret_match(o->R + I->slot, sig, I->nA); return; }
+    st_t tmp[64];
+    for (int32_t a = 0; a < I->nA; a++) tmp[a] = o->R[I->slot + a] + o->pred[I->slot + a];
+    regret_match(tmp, sig, I->nA);
+}
+
 static void regret_match_player(oracle *o, int player) {
     for (int64_t i = 0; i < o->ni; i++) {
         oinfo *I = &o->info[i];
         if (player && I->player != player) continue;
-        regret_match(o->R + I->slot, o->sigma + I->slot, I->nA);
+        current_strategy(o, I, o->sigma + I->slot);
     }
 }
 
@@ -372,15 +398,26 @@ static st_t walk(oracle *o, int64_t h, st_t pi1, st_t pi2, st_t pic, int upd, do
     return v;
 }
 
-static void apply_regrets(oracle *o, int player) {
+/* Regret update of iteration t for the sets of `player` (0: both); DCFR also discounts their
+ * strategy sums, whose iteration-t contribution the traversal has just added. */
+static void apply_regrets(oracle *o, int player, int64_t t) {
+    const double ta = pow((double)t, DCFR_ALPHA), tb = pow((double)t, DCFR_BETA);
+    const st_t pos = (st_t)(ta / (ta + 1.0)), neg = (st_t)(tb / (tb + 1.0));
+    const double sdisc = pow((double)t / (double)(t + 1), DCFR_GAMMA);
     for (int64_t i = 0; i < o->ni; i++) {
         oinfo *I = &o->info[i];
         if (player && I->player != player) continue;
         for (int a = 0; a < I->nA; a++) {
             int64_t q = I->slot + a;
             o->R[q] += o->rinst[q];
+            if (o->rule == RULE_CFR_PLUS || o->rule == RULE_PCFR_PLUS) {
+                if (o->R[q] < 0) o->R[q] = 0;
+            } else if (o->rule == RULE_DCFR) {
+                o->R[q] *= o->R[q] > 0 ? pos : neg;
+                o->sbar[q] *= sdisc;
+            }
+            if (o->rule == RULE_PCFR_PLUS) o->pred[q] = o->rinst[q];
             o->rinst[q] = 0;
-            if (o->plus && o->R[q] < 0) o->R[q] = 0;
         }
     }
 }
@@ -390,18 +427,19 @@ double or_iterate(oracle *o, int64_t T) {
     st_t v = 0;
     for (int64_t it = 0; it < T; it++) {
         int64_t t = o->t + 1;
-        double w = o->linear ? (double)t : 1.0;
+        double w = o->rule == RULE_DCFR ? 1.0 : o->rule == RULE_PCFR_PLUS ? (double)t * (double)t
+                 : o->linear ? (double)t : 1.0;
         if (!o->alternating) {
             regret_match_player(o, 0);
             v = walk(o, o->root, 1.0, 1.0, 1.0, 3, w, 2 * t);
-            apply_regrets(o, 0);
+            apply_regrets(o, 0, t);
         } else {
             regret_match_player(o, 0);
             v = walk(o, o->root, 1.0, 1.0, 1.0, 1, w, 2 * t);
-            apply_regrets(o, 1);
+            apply_regrets(o, 1, t);
             regret_match_player(o, 1);
             walk(o, o->root, 1.0, 1.0, 1.0, 2, w, 2 * t + 1);
-            apply_regrets(o, 2);
+            apply_regrets(o, 2, t);
         }
         o->t = t;
     }
@@ -418,7 +456,7 @@ void or_get(const oracle *o, double *R, double *sbar, double *sigma_cur, double 
         if (R) for (int a = 0; a < I->nA; a++) R[I->slot + a] = (double)o->R[I->slot + a];
         if (sbar) for (int a = 0; a < I->nA; a++) sbar[I->slot + a] = o->sbar[I->slot + a];
         if (sigma_cur) {
-            regret_match(o->R + I->slot, tmp, I->nA);
+            current_strategy(o, I, tmp);
             for (int a = 0; a < I->nA; a++) sigma_cur[I->slot + a] = (double)tmp[a];
         }
         if (sigma_avg) {
@@ -432,6 +470,7 @@ void or_get(const oracle *o, double *R, double *sbar, double *sigma_cur, double 
 void or_set_state(oracle *o, const double *R, const double *sbar, int64_t t) {
     if (R) for (int64_t q = 0; q < o->na; q++) o->R[q] = (st_t)R[q];
     if (sbar) memcpy(o->sbar, sbar, (size_t)o->na * 8);
+    memset(o->pred, 0, (size_t)(o->na ? o->na : 1) * sizeof(st_t));   /* no prediction yet */
     o->t = t;
 }
 
