@@ -83,8 +83,18 @@ typedef struct {
     double         pot;
 } cfr_game_desc;
 
-enum { CFR_RULE_CFR_PLUS = 0, CFR_RULE_CFR = 1 };        /* CFR+ clamps regrets at 0 after the add */
-enum { CFR_AVG_LINEAR = 0, CFR_AVG_UNIFORM = 1 };       /* w_t = t or 1 */
+/* Update rules (paper Sec. 6, "Update rule and update order"); the constants the paper leaves out
+ * are those of the published methods:
+ *   CFR+   R = max(R + r, 0); average weight w_t (CFR_AVG_*)
+ *   CFR    R = R + r;         average weight w_t
+ *   DCFR   R = R + r, then multiplied by t^1.5/(t^1.5+1) where positive and by 1/2 where not;
+ *          strategy sums S = (S + pi_i sigma) (t/(t+1))^2 (averaging option ignored)
+ *   PCFR+  R = max(R + r, 0); the next strategy is regret matching of R + r (the latest
+ *          instantaneous regret as the prediction); average weight t^2 (averaging option ignored)
+ * Alternating order: each iteration runs player 1's half (its regrets, sums and strategy) and then
+ * player 2's half against player 1's updated strategy, both with the weights of iteration t. */
+enum { CFR_RULE_CFR_PLUS = 0, CFR_RULE_CFR = 1, CFR_RULE_DCFR = 2, CFR_RULE_PCFR_PLUS = 3 };
+enum { CFR_AVG_LINEAR = 0, CFR_AVG_UNIFORM = 1 };       /* w_t = t or 1 (CFR and CFR+) */
 enum { CFR_ORDER_SIMULTANEOUS = 0, CFR_ORDER_ALTERNATING = 1 };
 /* Device node order within a depth level.  BFS: the canonical order.  PUBLIC: internal nodes
  * first, then terminals, each grouped by public state (first occurrence), canonical order

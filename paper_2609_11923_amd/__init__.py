@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcfr.so")
 
 CFR_OK, CFR_EINVAL, CFR_ENOMEM, CFR_EDEVICE, CFR_EGRAPH, CFR_ESTATE, CFR_EUNSUPPORTED = range(7)
-CFR_RULE_CFR_PLUS, CFR_RULE_CFR = 0, 1
+CFR_RULE_CFR_PLUS, CFR_RULE_CFR, CFR_RULE_DCFR, CFR_RULE_PCFR_PLUS = 0, 1, 2, 3
 CFR_AVG_LINEAR, CFR_AVG_UNIFORM = 0, 1
 CFR_ORDER_SIMULTANEOUS, CFR_ORDER_ALTERNATING = 0, 1
 CFR_LAYOUT_BFS, CFR_LAYOUT_PUBLIC = 0, 1

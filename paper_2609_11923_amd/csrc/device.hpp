@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "../../include/cfr.h"
+
 namespace cfrx {
 
 // Edge code stored with every node for the edge into it:
@@ -22,10 +24,13 @@ constexpr int GR_FIELDS_DEV = 8;
 // the error flag (the launch then reports CFR_EDEVICE) instead of hanging.  A count of polls is no
 // time bound: under contention one acquire poll can take microseconds.
 constexpr double BARRIER_TIMEOUT_S = 2.0;
+// DCFR's published constants (the paper names the rule but not its constants)
+constexpr double DCFR_ALPHA = 1.5, DCFR_BETA = 0.0, DCFR_GAMMA = 2.0;
 
 struct DevGame {
     int32_t N = 0, I = 0, A = 0, Ndec = 0, max_depth = 0, max_actions = 0;
     int fp64 = 0;                 // state type: 0 float (paper's configured dtype), 1 double
+    int rule = 0;                 // CFR_RULE_* (selects the update's instantiation)
     // structure (read-only after compile)
     int explicit_kids = 0;        // 1: child a of n is kid[kid_off[n] + a]; 0: it is kid_off[n] + a
     int2 *up = nullptr;           // [N]   (parent, edge code)
@@ -51,6 +56,7 @@ struct DevGame {
     void *reach = nullptr;        // [2N]  lane 0: player 1 reach, lane 1: player 2 reach
     void *sigma = nullptr;        // [A]   current strategy
     void *R = nullptr;            // [A]   cumulative regrets
+    void *pred = nullptr;         // [A]   PCFR+ prediction (the latest instantaneous regret), else nullptr
     double *sbar = nullptr;       // [A]   strategy sums (FP64)
     int32_t *t = nullptr;         // [1]   iterations started (device counter)
     // evaluation scratch (best response, FP64)
@@ -63,8 +69,9 @@ struct DevGame {
 };
 
 struct IterFlags {
-    int plus;     // CFR+ clamp
-    int linear;   // w_t = t
+    int rule;     // CFR_RULE_*
+    int linear;   // w_t = t (CFR and CFR+)
+    int upd;      // players whose sets a level updates: bit 0 player 1, bit 1 player 2
 };
 
 // one level of the forward reach pass: nodes [lo, hi) of one depth; tick != nullptr bumps the counter
@@ -82,8 +89,10 @@ struct PersistentPlan {
     int32_t *game_range = nullptr, *game_depth = nullptr, *barrier = nullptr, *err = nullptr;
     int64_t timeout_ticks = 0;   // BARRIER_TIMEOUT_S in ticks of wall_clock64()
 };
-// zero the barriers, run T iterations of every game in one launch, advance the counter by T
-hipError_t launch_persistent(const DevGame &g, const PersistentPlan &p, int32_t T, IterFlags f, hipStream_t s);
+// zero the barriers, run T iterations of every game in one launch (both halves of each iteration
+// when alternating), advance the counter by T
+hipError_t launch_persistent(const DevGame &g, const PersistentPlan &p, int32_t T, IterFlags f, int alternating,
+                             hipStream_t s);
 // resident blocks per compute unit of the persistent kernel for this game's configuration
 hipError_t persistent_occupancy(const DevGame &g, int *blocks_per_cu);
 // counter bump for games without edges

@@ -71,7 +71,33 @@ struct LevelArgs {
     T *R;
     double *sbar;
     T *sigma;
+    T *pred;      // PCFR+ prediction buffer, nullptr for the other rules
 };
+
+// What the update of iteration t does (paper Sec. 6, update rules; see cfr.h).
+struct RuleArgs {
+    int rule;          // CFR_RULE_*
+    int upd;           // players whose sets are updated: bit 0 player 1, bit 1 player 2
+    double w;          // average weight (t or 1 for CFR and CFR+, t^2 for PCFR+, 1 for DCFR)
+    double pos, neg;   // DCFR: discounts of positive and of other regrets
+    double sdisc;      // DCFR: strategy-sum discount
+};
+
+__device__ __forceinline__ RuleArgs rule_args(int rule, int linear, int upd, int32_t t) {
+    RuleArgs r;
+    r.rule = rule;
+    r.upd = upd;
+    const double td = (double)t;
+    r.w = rule == CFR_RULE_DCFR ? 1.0 : rule == CFR_RULE_PCFR_PLUS ? td * td : linear ? td : 1.0;
+    r.pos = r.neg = r.sdisc = 1.0;
+    if (rule == CFR_RULE_DCFR) {
+        const double ta = pow(td, DCFR_ALPHA), tb = pow(td, DCFR_BETA);
+        r.pos = ta / (ta + 1.0);
+        r.neg = tb / (tb + 1.0);
+        r.sdisc = pow(td / (td + 1.0), DCFR_GAMMA);
+    }
+    return r;
+}
 
 // Value of an internal chance node: the sum of its children (chance folded into the template).
 template <typename T, bool EXPLICIT>
@@ -121,8 +147,9 @@ struct GroupLds {
 // forward pass has already consumed it, so overwriting sigma(I) with sigma^{t+1} is safe.
 // Sets with more members than a chunk are streamed through LDS chunk by chunk.  Must be called by
 // every thread of the block (it synchronises the block).
-template <typename T, int MAXA, int MPT, bool EXPLICIT>
-__device__ void group_update(int32_t g, double w, int plus, const LevelArgs<T> &a, GroupLds<T, MAXA, MPT> &L) {
+template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT>
+__device__ void group_update(int32_t g, const RuleArgs &ru, const LevelArgs<T> &a, GroupLds<T, MAXA, MPT> &L) {
+    // EXT: the discounted and predictive rules (DCFR, PCFR+); otherwise CFR or CFR+ (lean tail)
     constexpr int CHUNK = MPT * BLOCK;
     const int tid = threadIdx.x;
     const int32_t i0 = a.grp_iset_off[g], i1 = a.grp_iset_off[g + 1];
@@ -194,22 +221,81 @@ __device__ void group_update(int32_t g, double w, int plus, const LevelArgs<T> &
         __syncthreads();
     }
     if (!has_set) return;
+    // alternating order: the other player's half leaves this set's state alone (values only)
+    if (!((ru.upd >> (pl - 1)) & 1)) return;
     const T *own = pl == 1 ? a.r1 : a.r2;
     const T sign = pl == 1 ? T(1) : T(-1);
     const double pown = (double)own[a.mem[m0].x & MEMBER_NODE_MASK];
     T tot = T(0);
     T Rn[MAXA];
+    if constexpr (!EXT) {
+        const bool clamp = ru.rule != CFR_RULE_CFR;
 #pragma unroll
-    for (int k = 0; k < MAXA; k++) {
-        if (k < nA) {
-            const int32_t q = s0 + k;
-            a.sbar[q] += w * pown * (double)a.sigma[q];
-            T y = fma_t(sign, r[k], a.R[q]);
-            if (plus) y = max_t(y, T(0));
-            a.R[q] = y;
-            Rn[k] = max_t(y, T(0));
-            tot += Rn[k];
+        for (int k = 0; k < MAXA; k++) {
+            if (k < nA) {
+                const int32_t q = s0 + k;
+                a.sbar[q] += ru.w * pown * (double)a.sigma[q];
+                T y = fma_t(sign, r[k], a.R[q]);
+                if (clamp) y = max_t(y, T(0));
+                a.R[q] = y;
+                Rn[k] = max_t(y, T(0));
+                tot += Rn[k];
+            }
         }
+    } else {
+        // all loads of the set first, one branch on the rule, then the stores
+        T Rk[MAXA], sk[MAXA];
+        double sb[MAXA];
+#pragma unroll
+        for (int k = 0; k < MAXA; k++)
+            if (k < nA) {
+                Rk[k] = a.R[s0 + k];
+                sk[k] = a.sigma[s0 + k];
+                sb[k] = a.sbar[s0 + k];
+            }
+        if (ru.rule == CFR_RULE_DCFR) {
+            const T pos = (T)ru.pos, neg = (T)ru.neg;
+#pragma unroll
+            for (int k = 0; k < MAXA; k++)
+                if (k < nA) {
+                    sb[k] = (sb[k] + pown * (double)sk[k]) * ru.sdisc;
+                    T y = fma_t(sign, r[k], Rk[k]);
+                    y = y > T(0) ? y * pos : y * neg;
+                    Rk[k] = y;
+                    Rn[k] = max_t(y, T(0));
+                    tot += Rn[k];
+                }
+        } else if (ru.rule == CFR_RULE_PCFR_PLUS) {
+#pragma unroll
+            for (int k = 0; k < MAXA; k++)
+                if (k < nA) {
+                    sb[k] += ru.w * pown * (double)sk[k];
+                    const T y = max_t(fma_t(sign, r[k], Rk[k]), T(0));
+                    const T m = sign * r[k];
+                    Rk[k] = y;
+                    a.pred[s0 + k] = m;
+                    Rn[k] = max_t(y + m, T(0));
+                    tot += Rn[k];
+                }
+        } else {
+            const bool clamp = ru.rule != CFR_RULE_CFR;
+#pragma unroll
+            for (int k = 0; k < MAXA; k++)
+                if (k < nA) {
+                    sb[k] += ru.w * pown * (double)sk[k];
+                    T y = fma_t(sign, r[k], Rk[k]);
+                    if (clamp) y = max_t(y, T(0));
+                    Rk[k] = y;
+                    Rn[k] = max_t(y, T(0));
+                    tot += Rn[k];
+                }
+        }
+#pragma unroll
+        for (int k = 0; k < MAXA; k++)
+            if (k < nA) {
+                a.R[s0 + k] = Rk[k];
+                a.sbar[s0 + k] = sb[k];
+            }
     }
     const T inv = tot > T(0) ? T(1) / tot : T(0);
     const T uni = T(1) / (T)nA;
@@ -221,10 +307,10 @@ __device__ void group_update(int32_t g, double w, int plus, const LevelArgs<T> &
 // One backward level fused with the update of its information sets, launched once per depth d
 // (deepest first): blocks [0, ngroups) take one update group each, the remaining blocks one thread
 // per internal chance node of the level.
-template <typename T, int MAXA, int MPT, bool EXPLICIT>
+template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT>
 __global__ void __launch_bounds__(BLOCK) k_level(int32_t gbeg, int32_t ngroups, int32_t bbeg, int32_t nbig,
                                                  int32_t cbeg, int32_t nchance, LevelArgs<T> a,
-                                                 const int32_t *__restrict__ tcount, int plus, int linear) {
+                                                 const int32_t *__restrict__ tcount, int rule, int linear, int upd) {
     __shared__ GroupLds<T, MAXA, MPT> L;
     const int32_t blk = (int32_t)blockIdx.x;
     if (blk >= ngroups + nbig) {
@@ -236,8 +322,8 @@ __global__ void __launch_bounds__(BLOCK) k_level(int32_t gbeg, int32_t ngroups, 
         big_chance_value<T, EXPLICIT>(a.bigc_node[bbeg + blk - ngroups], a, L.po);
         return;
     }
-    const double w = linear ? (double)tcount[0] : 1.0;
-    group_update<T, MAXA, MPT, EXPLICIT>(gbeg + (int32_t)blockIdx.x, w, plus, a, L);
+    const RuleArgs ru = rule_args(rule, linear, upd, tcount[0]);
+    group_update<T, MAXA, MPT, EXPLICIT, EXT>(gbeg + (int32_t)blockIdx.x, ru, a, L);
 }
 
 // Per-game barrier among the W blocks of one game.  Thread 0 publishes the block's writes
@@ -281,13 +367,14 @@ __device__ __forceinline__ bool game_barrier(int32_t *ctr, int32_t W, int32_t &e
 // backward level's update groups and chance nodes, meeting at a per-game barrier between levels;
 // games never wait for each other.  Iteration t0 + k (k = 1..T) uses the same arithmetic, in the
 // same order per set, as the level-synchronous kernels.  n_iter is the number of iterations.
-template <typename T, int MAXA, int MPT, bool EXPLICIT>
+template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT>
 __global__ void __launch_bounds__(BLOCK) k_persistent(const int4 *__restrict__ wg_table,
                                                       const int32_t *__restrict__ game_range,
                                                       const int32_t *__restrict__ game_depth, int32_t MD, int32_t n_iter,
                                                       const int2 *__restrict__ up, LevelArgs<T> a,
                                                       const int32_t *__restrict__ tcount, int32_t *barrier,
-                                                      int32_t *err, int64_t timeout_ticks, int plus, int linear) {
+                                                      int32_t *err, int64_t timeout_ticks, int rule, int linear,
+                                                      int alternating) {
     __shared__ GroupLds<T, MAXA, MPT> L;
     const int4 wt = wg_table[blockIdx.x];
     const int32_t gm = wt.x, rank = wt.y, W = wt.z;
@@ -297,20 +384,23 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(const int4 *__restrict__ w
     const int32_t t0 = tcount[0];
     const int tid = threadIdx.x;
     int32_t epoch = 0;
+    const int halves = alternating ? 2 : 1;
     for (int32_t it = 1; it <= n_iter; it++) {
-        const double w = linear ? (double)(t0 + it) : 1.0;
-        for (int32_t d = 1; d <= Ds; d++) {
-            const int32_t lo = gr[d * GR_FIELDS_DEV], hi = gr[d * GR_FIELDS_DEV + 1];
-            for (int32_t c = lo + rank * BLOCK + tid; c < hi; c += W * BLOCK)
-                forward_node<T>(c, up, a.sigma, a.r1, a.r2);
-            if (!game_barrier(barrier + gm, W, epoch, err, timeout_ticks)) return;
-        }
-        for (int32_t d = Ds - 1; d >= 0; d--) {
-            const int32_t *r = gr + d * GR_FIELDS_DEV;
-            for (int32_t g = r[2] + rank; g < r[3]; g += W) group_update<T, MAXA, MPT, EXPLICIT>(g, w, plus, a, L);
-            for (int32_t b = r[6] + rank; b < r[7]; b += W) big_chance_value<T, EXPLICIT>(a.bigc_node[b], a, L.po);
-            for (int32_t j = r[4] + rank * BLOCK + tid; j < r[5]; j += W * BLOCK) chance_value<T, EXPLICIT>(a.chance_node[j], a);
-            if (!game_barrier(barrier + gm, W, epoch, err, timeout_ticks)) return;
+        for (int half = 0; half < halves; half++) {
+            const RuleArgs ru = rule_args(rule, linear, alternating ? 1 << half : 3, t0 + it);
+            for (int32_t d = 1; d <= Ds; d++) {
+                const int32_t lo = gr[d * GR_FIELDS_DEV], hi = gr[d * GR_FIELDS_DEV + 1];
+                for (int32_t c = lo + rank * BLOCK + tid; c < hi; c += W * BLOCK)
+                    forward_node<T>(c, up, a.sigma, a.r1, a.r2);
+                if (!game_barrier(barrier + gm, W, epoch, err, timeout_ticks)) return;
+            }
+            for (int32_t d = Ds - 1; d >= 0; d--) {
+                const int32_t *r = gr + d * GR_FIELDS_DEV;
+                for (int32_t g = r[2] + rank; g < r[3]; g += W) group_update<T, MAXA, MPT, EXPLICIT, EXT>(g, ru, a, L);
+                for (int32_t b = r[6] + rank; b < r[7]; b += W) big_chance_value<T, EXPLICIT>(a.bigc_node[b], a, L.po);
+                for (int32_t j = r[4] + rank * BLOCK + tid; j < r[5]; j += W * BLOCK) chance_value<T, EXPLICIT>(a.chance_node[j], a);
+                if (!game_barrier(barrier + gm, W, epoch, err, timeout_ticks)) return;
+            }
         }
     }
 }
@@ -326,15 +416,18 @@ __global__ void k_add_counter(int32_t *t, int32_t n) {
 
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_regret_matching(int32_t I, const int32_t *__restrict__ slot_off,
-                                                           const T *__restrict__ R, T *__restrict__ sigma) {
+                                                           const T *__restrict__ R, const T *__restrict__ pred,
+                                                           T *__restrict__ sigma) {
     int32_t i = (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
     if (i >= I) return;
     int32_t s0 = slot_off[i], s1 = slot_off[i + 1];
+    // PCFR+: regret matching of R + prediction
+    auto x = [&](int32_t q) { return pred ? R[q] + pred[q] : R[q]; };
     T tot = T(0);
-    for (int32_t q = s0; q < s1; q++) tot += max_t(R[q], T(0));
+    for (int32_t q = s0; q < s1; q++) tot += max_t(x(q), T(0));
     const T inv = tot > T(0) ? T(1) / tot : T(0);
     const T uni = T(1) / (T)(s1 - s0);
-    for (int32_t q = s0; q < s1; q++) sigma[q] = tot > T(0) ? max_t(R[q], T(0)) * inv : uni;
+    for (int32_t q = s0; q < s1; q++) sigma[q] = tot > T(0) ? max_t(x(q), T(0)) * inv : uni;
 }
 
 __global__ void k_tick(int32_t *t) {
@@ -469,27 +562,36 @@ static LevelArgs<T> level_args(const DevGame &g) {
     a.r1 = (T *)g.reach;
     a.r2 = (T *)g.reach + g.N;
     a.R = (T *)g.R; a.sbar = g.sbar; a.sigma = (T *)g.sigma;
+    a.pred = (T *)g.pred;
     return a;
 }
 
-template <typename T, int MAXA, int MPT, bool EX>
+template <typename T, int MAXA, int MPT, bool EX, bool XT>
 static hipError_t level_t(const DevGame &g, int d, IterFlags f, hipStream_t s) {
     const int32_t gbeg = g.grp_depth_off[d], ng = g.grp_depth_off[d + 1] - gbeg;
     const int32_t cbeg = g.chance_off[d], nc = g.chance_off[d + 1] - cbeg;
     const int32_t bbeg = g.bigc_off[d], nb = g.bigc_off[d + 1] - bbeg;
     const unsigned blocks = (unsigned)ng + (unsigned)nb + grid_for(nc);
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_level<T, MAXA, MPT, EX>), dim3(blocks), dim3(BLOCK), 0, s, gbeg, ng, bbeg, nb, cbeg, nc,
-                       level_args<T>(g), g.t, f.plus, f.linear);
+    hipLaunchKernelGGL((k_level<T, MAXA, MPT, EX, XT>), dim3(blocks), dim3(BLOCK), 0, s, gbeg, ng, bbeg, nb, cbeg, nc,
+                       level_args<T>(g), g.t, f.rule, f.linear, f.upd);
     return hipGetLastError();
+}
+
+// the discounted and predictive rules get their own instantiation, so CFR and CFR+ keep a lean update
+inline bool ext_rule(int rule) { return rule == CFR_RULE_DCFR || rule == CFR_RULE_PCFR_PLUS; }
+
+template <typename T, bool EX, bool XT>
+static hipError_t level_dispatch_xt(const DevGame &g, int d, IterFlags f, hipStream_t s) {
+    // members per thread must match the group capacity the compiler used (group_members)
+    if (g.max_actions <= 4) return level_t<T, 4, 2, EX, XT>(g, d, f, s);
+    if (g.max_actions <= 16) return level_t<T, 16, 1, EX, XT>(g, d, f, s);
+    return level_t<T, 64, 1, EX, XT>(g, d, f, s);
 }
 
 template <typename T, bool EX>
 static hipError_t level_dispatch_ex(const DevGame &g, int d, IterFlags f, hipStream_t s) {
-    // members per thread must match the group capacity the compiler used (group_members)
-    if (g.max_actions <= 4) return level_t<T, 4, 2, EX>(g, d, f, s);
-    if (g.max_actions <= 16) return level_t<T, 16, 1, EX>(g, d, f, s);
-    return level_t<T, 64, 1, EX>(g, d, f, s);
+    return ext_rule(f.rule) ? level_dispatch_xt<T, EX, true>(g, d, f, s) : level_dispatch_xt<T, EX, false>(g, d, f, s);
 }
 
 template <typename T>
@@ -501,51 +603,66 @@ hipError_t launch_level(const DevGame &g, int d, IterFlags f, hipStream_t s) {
     return g.fp64 ? level_dispatch<double>(g, d, f, s) : level_dispatch<float>(g, d, f, s);
 }
 
-template <typename T, int MAXA, int MPT, bool EX>
+template <typename T, int MAXA, int MPT, bool EX, bool XT>
 static const void *persistent_fn() {
-    return reinterpret_cast<const void *>(&k_persistent<T, MAXA, MPT, EX>);
+    return reinterpret_cast<const void *>(&k_persistent<T, MAXA, MPT, EX, XT>);
 }
 
-template <typename T, int MAXA, int MPT, bool EX>
-static hipError_t persistent_t(const DevGame &g, const PersistentPlan &p, int32_t T_, IterFlags f, hipStream_t s) {
-    hipLaunchKernelGGL((k_persistent<T, MAXA, MPT, EX>), dim3(p.blocks), dim3(BLOCK), 0, s, p.wg_table,
+template <typename T, int MAXA, int MPT, bool EX, bool XT>
+static hipError_t persistent_t(const DevGame &g, const PersistentPlan &p, int32_t T_, IterFlags f, int alt,
+                               hipStream_t s) {
+    hipLaunchKernelGGL((k_persistent<T, MAXA, MPT, EX, XT>), dim3(p.blocks), dim3(BLOCK), 0, s, p.wg_table,
                        p.game_range, p.game_depth, p.max_depth, T_, g.up, level_args<T>(g), g.t, p.barrier, p.err,
-                       p.timeout_ticks, f.plus, f.linear);
+                       p.timeout_ticks, f.rule, f.linear, alt);
     return hipGetLastError();
+}
+
+template <typename T, bool EX, bool XT>
+static hipError_t persistent_dispatch_xt(const DevGame &g, const PersistentPlan &p, int32_t T_, IterFlags f,
+                                         int alt, hipStream_t s) {
+    if (g.max_actions <= 4) return persistent_t<T, 4, 2, EX, XT>(g, p, T_, f, alt, s);
+    if (g.max_actions <= 16) return persistent_t<T, 16, 1, EX, XT>(g, p, T_, f, alt, s);
+    return persistent_t<T, 64, 1, EX, XT>(g, p, T_, f, alt, s);
 }
 
 template <typename T, bool EX>
 static hipError_t persistent_dispatch_ex(const DevGame &g, const PersistentPlan &p, int32_t T_, IterFlags f,
-                                         hipStream_t s) {
-    if (g.max_actions <= 4) return persistent_t<T, 4, 2, EX>(g, p, T_, f, s);
-    if (g.max_actions <= 16) return persistent_t<T, 16, 1, EX>(g, p, T_, f, s);
-    return persistent_t<T, 64, 1, EX>(g, p, T_, f, s);
+                                         int alt, hipStream_t s) {
+    return ext_rule(f.rule) ? persistent_dispatch_xt<T, EX, true>(g, p, T_, f, alt, s)
+                            : persistent_dispatch_xt<T, EX, false>(g, p, T_, f, alt, s);
 }
 
-hipError_t launch_persistent(const DevGame &g, const PersistentPlan &p, int32_t T_, IterFlags f, hipStream_t s) {
+hipError_t launch_persistent(const DevGame &g, const PersistentPlan &p, int32_t T_, IterFlags f, int alt,
+                             hipStream_t s) {
     hipLaunchKernelGGL(k_fill_int, dim3((p.n_games + 255) / 256), dim3(256), 0, s, p.n_games, p.barrier, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (g.fp64) e = g.explicit_kids ? persistent_dispatch_ex<double, true>(g, p, T_, f, s)
-                                    : persistent_dispatch_ex<double, false>(g, p, T_, f, s);
-    else e = g.explicit_kids ? persistent_dispatch_ex<float, true>(g, p, T_, f, s)
-                             : persistent_dispatch_ex<float, false>(g, p, T_, f, s);
+    if (g.fp64) e = g.explicit_kids ? persistent_dispatch_ex<double, true>(g, p, T_, f, alt, s)
+                                    : persistent_dispatch_ex<double, false>(g, p, T_, f, alt, s);
+    else e = g.explicit_kids ? persistent_dispatch_ex<float, true>(g, p, T_, f, alt, s)
+                             : persistent_dispatch_ex<float, false>(g, p, T_, f, alt, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_add_counter, dim3(1), dim3(64), 0, s, g.t, T_);
     return hipGetLastError();
 }
 
+template <typename T, bool EX, bool XT>
+static const void *persistent_fn_for(const DevGame &g) {
+    if (g.max_actions <= 4) return persistent_fn<T, 4, 2, EX, XT>();
+    if (g.max_actions <= 16) return persistent_fn<T, 16, 1, EX, XT>();
+    return persistent_fn<T, 64, 1, EX, XT>();
+}
+
+template <typename T>
+static const void *persistent_fn_t(const DevGame &g) {
+    const bool x = ext_rule(g.rule);
+    if (g.explicit_kids) return x ? persistent_fn_for<T, true, true>(g) : persistent_fn_for<T, true, false>(g);
+    return x ? persistent_fn_for<T, false, true>(g) : persistent_fn_for<T, false, false>(g);
+}
+
+// the instantiation launch_persistent uses for this game
 hipError_t persistent_occupancy(const DevGame &g, int *blocks_per_cu) {
-    const void *fn = nullptr;
-    if (g.fp64) {
-        if (g.max_actions <= 4) fn = g.explicit_kids ? persistent_fn<double, 4, 2, true>() : persistent_fn<double, 4, 2, false>();
-        else if (g.max_actions <= 16) fn = g.explicit_kids ? persistent_fn<double, 16, 1, true>() : persistent_fn<double, 16, 1, false>();
-        else fn = g.explicit_kids ? persistent_fn<double, 64, 1, true>() : persistent_fn<double, 64, 1, false>();
-    } else {
-        if (g.max_actions <= 4) fn = g.explicit_kids ? persistent_fn<float, 4, 2, true>() : persistent_fn<float, 4, 2, false>();
-        else if (g.max_actions <= 16) fn = g.explicit_kids ? persistent_fn<float, 16, 1, true>() : persistent_fn<float, 16, 1, false>();
-        else fn = g.explicit_kids ? persistent_fn<float, 64, 1, true>() : persistent_fn<float, 64, 1, false>();
-    }
+    const void *fn = g.fp64 ? persistent_fn_t<double>(g) : persistent_fn_t<float>(g);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, BLOCK, 0);
 }
 
@@ -553,10 +670,10 @@ hipError_t launch_regret_matching(const DevGame &g, hipStream_t s) {
     if (g.I == 0) return hipSuccess;
     if (g.fp64)
         hipLaunchKernelGGL(k_regret_matching<double>, dim3(grid_for(g.I)), dim3(BLOCK), 0, s, g.I, g.slot_off,
-                           (const double *)g.R, (double *)g.sigma);
+                           (const double *)g.R, (const double *)g.pred, (double *)g.sigma);
     else
         hipLaunchKernelGGL(k_regret_matching<float>, dim3(grid_for(g.I)), dim3(BLOCK), 0, s, g.I, g.slot_off,
-                           (const float *)g.R, (float *)g.sigma);
+                           (const float *)g.R, (const float *)g.pred, (float *)g.sigma);
     return hipGetLastError();
 }
 

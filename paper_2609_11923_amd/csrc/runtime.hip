@@ -51,7 +51,8 @@ struct cfr_handle {
     DevGame g{};
     // host copies of the schedule
     std::vector<int32_t> depth_off, int_end, iset_depth_off, grp_depth_off, chance_off, bigc_off;
-    // the static launch schedule of one iteration: (kind, depth), kind 0 tick, 1 forward, 2 level
+    // the static launch schedule of one iteration: (kind, depth), kind 0 tick, 1 forward, 2 level,
+    // plus HALF for the second (player 2) half of an alternating iteration
     std::vector<std::pair<int, int>> plan;
     std::vector<int32_t> slot_map;     // canonical slot -> device slot (empty: identity)
     // batches: number of games, canonical slot offsets, per-game depth and ranges, pots
@@ -137,34 +138,45 @@ std::vector<const void *> persistent_ptrs(const cfr_handle *h) {
 // depends on the depth only): the forward pass over depths 1..max_depth (depth 1 always launches,
 // because its first thread advances the iteration counter), then the fused backward/update level
 // over depths max_depth-1..0, skipping levels with nothing to do.  A single-node game only ticks.
+constexpr int HALF = 10;
+
 void build_plan(cfr_handle *h) {
     h->plan.clear();
     const DevGame &g = h->g;
     if (g.max_depth == 0) { h->plan.push_back({0, 0}); return; }
-    for (int d = 1; d <= g.max_depth; d++)
-        if (d == 1 || h->int_end[d] > h->depth_off[d]) h->plan.push_back({1, d});
-    for (int d = g.max_depth - 1; d >= 0; d--)
-        if (h->grp_depth_off[d + 1] > h->grp_depth_off[d] || h->chance_off[d + 1] > h->chance_off[d] ||
-            h->bigc_off[d + 1] > h->bigc_off[d])
-            h->plan.push_back({2, d});
+    const int halves = h->opt.order == CFR_ORDER_ALTERNATING ? 2 : 1;
+    for (int half = 0; half < halves; half++) {
+        for (int d = 1; d <= g.max_depth; d++)
+            if (d == 1 || h->int_end[d] > h->depth_off[d]) h->plan.push_back({1 + HALF * half, d});
+        for (int d = g.max_depth - 1; d >= 0; d--)
+            if (h->grp_depth_off[d + 1] > h->grp_depth_off[d] || h->chance_off[d + 1] > h->chance_off[d] ||
+                h->bigc_off[d + 1] > h->bigc_off[d])
+                h->plan.push_back({2 + HALF * half, d});
+    }
 }
 
 // one iteration, direct launches, in the plan's order; tm != nullptr brackets every launch with events
+// flags (optional) replace the handle's rule for one simultaneous pass (the second half of an
+// alternating plan is then skipped)
 cfr_status enqueue_iteration(cfr_handle *h, hipStream_t s, int64_t *count, LaunchTimer *tm = nullptr,
                              const IterFlags *flags = nullptr) {
     const DevGame &g = h->g;
-    const IterFlags f = flags ? *flags
-                              : IterFlags{h->opt.rule == CFR_RULE_CFR_PLUS ? 1 : 0, h->opt.averaging == CFR_AVG_LINEAR ? 1 : 0};
+    const bool alt = h->opt.order == CFR_ORDER_ALTERNATING && !flags;
     int64_t n = 0;
     for (const auto &step : h->plan) {
+        const int kind = step.first % HALF, half = step.first / HALF;
+        if (half > 0 && !alt) continue;
         if (tm) {
             if (tm->next + 1 >= tm->ev.size()) return fail(CFR_EDEVICE, "profiling event pool exhausted");
-            tm->cls.push_back(step.first);
+            tm->cls.push_back(kind);
             HIP_TRY(hipEventRecord(tm->ev[tm->next++], s));
         }
         const int d = step.second;
-        if (step.first == 0) HIP_TRY(launch_tick(g, s));
-        else if (step.first == 1) HIP_TRY(launch_forward(g, h->depth_off[d], h->int_end[d], d == 1 ? g.t : nullptr, s));
+        IterFlags f = flags ? *flags : IterFlags{h->opt.rule, h->opt.averaging == CFR_AVG_LINEAR ? 1 : 0, 3};
+        if (alt) f.upd = 1 << half;
+        if (kind == 0) HIP_TRY(launch_tick(g, s));
+        else if (kind == 1)
+            HIP_TRY(launch_forward(g, h->depth_off[d], h->int_end[d], d == 1 && half == 0 ? g.t : nullptr, s));
         else HIP_TRY(launch_level(g, d, f, s));
         if (tm) {
             tm->cls.push_back(-1);
@@ -209,8 +221,12 @@ void model_bytes(cfr_handle *h, const DeviceLayout &D) {
             lv += 8 + es + (kb + es) * (D.kid_off[x + 1] - D.kid_off[x]);
         }
     }
-    h->bytes_fwd = f;
-    h->bytes_lvl = lv;
+    const double halves = h->opt.order == CFR_ORDER_ALTERNATING ? 2.0 : 1.0;
+    double pred_bytes = 0;   // PCFR+: the prediction written and read back by regret matching
+    if (h->opt.rule == CFR_RULE_PCFR_PLUS)
+        for (int d = 0; d < md; d++) pred_bytes += 2 * es * Ad[d];
+    h->bytes_fwd = f * halves;
+    h->bytes_lvl = (lv + pred_bytes) * halves;
     // The method's per-unit byte figures with 4-byte indices and state width es (FP64 strategy
     // sums): forward, per edge the parent index and edge code (8) and the two-lane reach write
     // (2 es), per internal parent the two-lane reach read (2 es); backward, per edge the child
@@ -233,8 +249,8 @@ void model_bytes(cfr_handle *h, const DeviceLayout &D) {
     for (int d = 0; d < md; d++)
         ml += (es + 4) * Nd[d + 1] + es * Zd[d + 1] + (4 + es) * Nint[d] + es * Ed[d] + (4 + 3 * es) * Md[d] +
               4 * Id[d] + (7 * es + 16) * Ad[d];
-    h->method_fwd = mf;
-    h->method_lvl = ml;
+    h->method_fwd = mf * halves;
+    h->method_lvl = (ml + pred_bytes) * halves;
 }
 
 cfr_status capture(cfr_handle *h, int iters, hipGraph_t *graph, hipGraphExec_t *exec) {
@@ -438,14 +454,15 @@ static cfr_status build_persistent_plan(cfr_handle *h, int32_t wg_nodes) {
 
 static cfr_status persistent_iterate(cfr_handle *h, int64_t n, hipStream_t s) {
     if (n > 0x7fffffffLL) return fail(CFR_EINVAL, "n too large for one persistent launch");
-    const IterFlags f{h->opt.rule == CFR_RULE_CFR_PLUS ? 1 : 0, h->opt.averaging == CFR_AVG_LINEAR ? 1 : 0};
+    const IterFlags f{h->opt.rule, h->opt.averaging == CFR_AVG_LINEAR ? 1 : 0, 3};
+    const int alt = h->opt.order == CFR_ORDER_ALTERNATING ? 1 : 0;
     if (h->use_graph && h->pgraph_n != n) {
         if (h->pexec) { (void)hipGraphExecDestroy(h->pexec); h->pexec = nullptr; }
         if (h->pgraph) { (void)hipGraphDestroy(h->pgraph); h->pgraph = nullptr; }
         h->pgraph_n = -1;
         hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t le = launch_persistent(h->g, h->pp, (int32_t)n, f, h->cap_stream);
+            hipError_t le = launch_persistent(h->g, h->pp, (int32_t)n, f, alt, h->cap_stream);
             hipGraph_t gr = nullptr;
             e = hipStreamEndCapture(h->cap_stream, &gr);
             if (le == hipSuccess && e == hipSuccess && gr) {
@@ -464,7 +481,7 @@ static cfr_status persistent_iterate(cfr_handle *h, int64_t n, hipStream_t s) {
         hipError_t e = hipGraphLaunch(h->pexec, s);
         if (e != hipSuccess) return fail(CFR_EGRAPH, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
     } else {
-        HIP_TRY(launch_persistent(h->g, h->pp, (int32_t)n, f, s));
+        HIP_TRY(launch_persistent(h->g, h->pp, (int32_t)n, f, alt, s));
     }
     int32_t err = 0;
     HIP_TRY(hipMemcpyAsync(&err, h->pp.err, sizeof err, hipMemcpyDeviceToHost, s));
@@ -482,9 +499,9 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     cfr_options o;
     cfr_default_options(&o);
     if (opt) o = *opt;
-    if (o.rule != CFR_RULE_CFR_PLUS && o.rule != CFR_RULE_CFR) return fail(CFR_EINVAL, "unknown rule");
+    if (o.rule < CFR_RULE_CFR_PLUS || o.rule > CFR_RULE_PCFR_PLUS) return fail(CFR_EINVAL, "unknown rule");
     if (o.averaging != CFR_AVG_LINEAR && o.averaging != CFR_AVG_UNIFORM) return fail(CFR_EINVAL, "unknown averaging");
-    if (o.order != CFR_ORDER_SIMULTANEOUS) return fail(CFR_EUNSUPPORTED, "alternating updates are not built yet");
+    if (o.order != CFR_ORDER_SIMULTANEOUS && o.order != CFR_ORDER_ALTERNATING) return fail(CFR_EINVAL, "unknown order");
     if (o.layout != CFR_LAYOUT_BFS && o.layout != CFR_LAYOUT_PUBLIC) return fail(CFR_EINVAL, "unknown layout");
     if (o.iters_per_graph < 1 || o.iters_per_graph > 1000) return fail(CFR_EINVAL, "iters_per_graph must be in [1, 1000]");
     if (o.precision != CFR_PRECISION_FP32 && o.precision != CFR_PRECISION_FP64) return fail(CFR_EINVAL, "unknown precision");
@@ -551,6 +568,7 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     g.N = (int32_t)N; g.I = (int32_t)I; g.A = (int32_t)A; g.Ndec = (int32_t)Ndec;
     g.max_depth = max_depth; g.max_actions = max_actions;
     g.fp64 = o.precision == CFR_PRECISION_FP64 ? 1 : 0;
+    g.rule = o.rule;
     g.explicit_kids = DL.explicit_kids ? 1 : 0;
     h->es = g.fp64 ? 8 : 4;
 
@@ -584,6 +602,11 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
         ALLOC(ps, (A > 0 ? A : 1) * (int64_t)h->es);
         ALLOC(pR, (A > 0 ? A : 1) * (int64_t)h->es);
         g.v = pv; g.reach = pr; g.sigma = ps; g.R = pR;
+        if (o.rule == CFR_RULE_PCFR_PLUS) {
+            char *pp = nullptr;
+            ALLOC(pp, (A > 0 ? A : 1) * (int64_t)h->es);
+            g.pred = pp;
+        }
     }
     ALLOC(g.sbar, A);
     ALLOC(g.t, 1);
@@ -679,6 +702,7 @@ cfr_status cfr_reset(cfr_handle *h) {
     const DevGame &g = h->g;
     hipStream_t s = h->cap_stream;
     HIP_TRY(hipMemsetAsync(g.R, 0, (size_t)(g.A > 0 ? g.A : 1) * h->es, s));
+    if (g.pred) HIP_TRY(hipMemsetAsync(g.pred, 0, (size_t)(g.A > 0 ? g.A : 1) * h->es, s));
     HIP_TRY(hipMemsetAsync(g.sbar, 0, (size_t)(g.A > 0 ? g.A : 1) * sizeof(double), s));
     HIP_TRY(hipMemsetAsync(g.t, 0, sizeof(int32_t), s));
     HIP_TRY(launch_regret_matching(g, s));
@@ -802,6 +826,7 @@ cfr_status cfr_set_regrets(cfr_handle *h, const float *r0, int64_t len, int src_
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipMemcpyAsync(h->g.out, r0, (size_t)len * sizeof(float),
                            src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    if (h->g.pred) HIP_TRY(hipMemsetAsync(h->g.pred, 0, (size_t)len * h->es, s));
     HIP_TRY(launch_regrets_from_float(h->g, h->g.out, s));
     HIP_TRY(launch_regret_matching(h->g, s));
     if (!src_on_device) HIP_TRY(hipStreamSynchronize(s));
@@ -1041,6 +1066,7 @@ cfr_status cfr_features(cfr_handle *h, const int16_t *bucket, const int16_t *his
     const DevGame &g = h->g;
     auto clear = [&]() -> cfr_status {
         HIP_TRY(hipMemsetAsync(g.R, 0, (size_t)(g.A > 0 ? g.A : 1) * h->es, s));
+        if (g.pred) HIP_TRY(hipMemsetAsync(g.pred, 0, (size_t)(g.A > 0 ? g.A : 1) * h->es, s));
         HIP_TRY(hipMemsetAsync(g.sbar, 0, (size_t)(g.A > 0 ? g.A : 1) * sizeof(double), s));
         HIP_TRY(hipMemsetAsync(g.t, 0, sizeof(int32_t), s));
         HIP_TRY(launch_regret_matching(g, s));
@@ -1049,7 +1075,7 @@ cfr_status cfr_features(cfr_handle *h, const int16_t *bucket, const int16_t *his
     cfr_status st = clear();
     if (st != CFR_OK) return st;
     // one plain iteration from zero regrets: R becomes the instantaneous regrets of the uniform strategy
-    const IterFlags plain{0, 0};
+    const IterFlags plain{CFR_RULE_CFR, 0, 3};
     st = enqueue_iteration(h, s, nullptr, nullptr, &plain);
     if (st != CFR_OK) return st;
     FeatureArgs f{};
@@ -1100,6 +1126,7 @@ cfr_status cfr_warm_start(cfr_handle *h, cfr_mlp *n, const void *x, int64_t rows
     cfr_status st = mlp_forward_internal(n, x, rows, h->warm_z, s);
     if (st != CFR_OK) return st;
     HIP_TRY(launch_warm_regrets(h->canon_off, rows, h->warm_z, h->warm_mag, scale, h->g.out, s));
+    if (h->g.pred) HIP_TRY(hipMemsetAsync(h->g.pred, 0, (size_t)h->g.A * h->es, s));
     HIP_TRY(launch_regrets_from_float(h->g, h->g.out, s));
     HIP_TRY(launch_regret_matching(h->g, s));
     return CFR_OK;
