@@ -140,6 +140,45 @@ def run_batch(cfr, torch, games, iters, precision, log, tune_iters=20, warm=None
     ), cross
 
 
+def run_rules(cfr, torch, games, log, max_iters=4000):
+    """Time to exploitability <= 1e-3 pot of the batch under each update rule and order (the same
+    games, compiled per rule, level-synchronous graph, FP32 state).  Iterations count full
+    iterations (an alternating one runs both players' halves); wall time uses each rule's own
+    measured time per iteration."""
+    from paper_2609_11923_amd.warm import crossing_iterations, geometric_checkpoints
+    pots = np.array([g.pot for g in games])
+    cps = geometric_checkpoints(max_iters)
+    out = {}
+    for name, rule, order in [("CFR+", cfr.CFR_RULE_CFR_PLUS, cfr.CFR_ORDER_SIMULTANEOUS),
+                              ("CFR+ alternating", cfr.CFR_RULE_CFR_PLUS, cfr.CFR_ORDER_ALTERNATING),
+                              ("DCFR", cfr.CFR_RULE_DCFR, cfr.CFR_ORDER_SIMULTANEOUS),
+                              ("DCFR alternating", cfr.CFR_RULE_DCFR, cfr.CFR_ORDER_ALTERNATING),
+                              ("PCFR+", cfr.CFR_RULE_PCFR_PLUS, cfr.CFR_ORDER_SIMULTANEOUS),
+                              ("PCFR+ alternating", cfr.CFR_RULE_PCFR_PLUS, cfr.CFR_ORDER_ALTERNATING)]:
+        s = cfr.Solver(games, rule=rule, order=order)
+        stream = torch.cuda.Stream()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        expl, done, ms = [], 0, 0.0
+        for c in cps:
+            ev0.record(stream)
+            s.iterate(c - done, stream=stream)
+            ev1.record(stream)
+            ev1.synchronize()
+            ms += ev0.elapsed_time(ev1)
+            done = c
+            expl.append(s.batch_exploitability(stream=stream)[0])
+        s.close()
+        cross = crossing_iterations(cps, expl, 1e-3 * pots.min())
+        ms_it = ms / cps[-1]
+        fin = np.isfinite(cross)
+        out[name] = dict(ms_per_iteration=ms_it, reached=int(fin.sum()), iterations_median=float(np.median(cross)),
+                         time_to_1e3pot_median_ms=float(np.median(cross) * ms_it),
+                         time_to_1e3pot_all_ms=float(np.max(cross) * ms_it) if fin.all() else None,
+                         expl_at_max_median=float(np.median(expl[-1])))
+        log(f"[bench] rule {name}: {out[name]}")
+    return out
+
+
 def measure_game(cfr, torch, game, args, precision, log):
     """Compile one game, replay `warmup` then time `steps` iterations (hip events on the stream the
     graph is launched on), then per-kernel durations and bytes (cfr_profile) and the roofline of
@@ -330,6 +369,7 @@ def main():
     ap.add_argument("--batch-iters", type=int, default=500)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-subgame measurement")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm-start measurement")
+    ap.add_argument("--no-rules", action="store_true", help="skip the update-rule comparison on the batch")
     ap.add_argument("--warm-train-games", type=int, default=2000)
     ap.add_argument("--warm-train-hi", type=float, default=1e6, help="largest training subgame (edges)")
     ap.add_argument("--warm-target-iters", type=int, default=500)
@@ -417,6 +457,8 @@ def main():
         res, _ = run_batch(cfr, torch, games, args.batch_iters, cfr.CFR_PRECISION_FP32, log)
         out["batch"] = {"workload": f"{len(games)} subgames cut at round-B public states, 1e3-1e6 edges "
                                     f"log-uniform, Dirichlet(1) ranges", "precision": "fp32", **res}
+        if not args.no_rules:
+            out["batch"]["rules"] = run_rules(cfr, torch, games, log)
         del games
     if not args.no_warm:
         out["warm_start"] = run_warm(cfr, torch, args, log)
