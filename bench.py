@@ -248,6 +248,9 @@ def measure_game(cfr, torch, game, args, precision, log):
     return res
 
 
+WARM_RULES = {}
+
+
 def run_warm(cfr, torch, args, log):
     """Learned warm start: train the network on average strategies of solved subgames (their own
     payoff seeds, so nothing about the test payoffs can be memorised), pick the regret scale on a
@@ -255,13 +258,15 @@ def run_warm(cfr, torch, args, log):
     network."""
     import gamegen as gg
     from paper_2609_11923_amd import warm
+    rule, order = WARM_RULES[args.warm_rule]
+    kw = dict(rule=rule, order=order)
     t0 = time.perf_counter()
     tr_specs = gg.random_subgames(args.warm_train_games, seed=1, lo=1e3, hi=args.warm_train_hi, game_seed=1)
     X, T, W, N, dstats = warm.make_training_set(tr_specs, args.warm_target_iters, torch, probe=args.warm_probe,
-                                                log=log)
+                                                solver_kw=kw, log=log)
     va_specs = gg.random_subgames(args.warm_val_games, seed=2, lo=1e3, hi=1e6, game_seed=2)
     Xv, Tv, Wv, Nv, vstats = warm.make_training_set(va_specs, args.warm_target_iters, torch, probe=args.warm_probe,
-                                                    log=log)
+                                                    solver_kw=kw, log=log)
     t_data = time.perf_counter() - t0
     sizes = [(cfr.CFR_FEATURES, 256), (256, 256), (256, 256), (256, cfr.CFR_MLP_OUT)]
     theta0 = gg.mlp_init(sizes, seed=0)
@@ -278,19 +283,19 @@ def run_warm(cfr, torch, args, log):
     log("[warm] choosing the regret scale on the validation batch")
     val_games = warm.subgames(va_specs)
     scale, table = warm.choose_scale(val_games, torch, mlp, args.warm_scales, args.warm_val_iters,
-                                     probe=args.warm_probe, log=log)
+                                     probe=args.warm_probe, solver_kw=kw, add=args.warm_add, log=log)
     control = cfr.Mlp()
     control.set_params(theta0)
     log("[warm] evaluating on the held-out test batch")
     test_games, _ = batch_games(args.batch_games, args.seed)
     ev = warm.evaluate(test_games, torch, mlp, scale, args.warm_max_iters, control=control, probe=args.warm_probe,
-                       log=log)
+                       solver_kw=kw, add=args.warm_add, log=log)
     cold, wst = ev["cold"]["_cross"], ev["warm"]["_cross"]
     both = np.isfinite(cold) & np.isfinite(wst)
     # throughput of the network on the matrix cores: one forward over every test set's row
     log("[warm] timing inference")
     rows = warm.Rows(test_games, torch)
-    s = cfr.Solver(test_games)
+    s = cfr.Solver(test_games, **kw)
     rows.features(s, probe=args.warm_probe)
     z = torch.empty(rows.I, 4, dtype=torch.float32, device="cuda")
     mlp.forward(rows.x, rows.I, z)
@@ -309,6 +314,8 @@ def run_warm(cfr, torch, args, log):
         "test": f"{len(test_games)} held-out subgames (the batched workload), up to {args.warm_max_iters} iterations",
         "network": "128 -> 3 x 256 ReLU -> 4, BF16 MFMA, FP32 accumulation, Adam on FP32 master weights",
         "probe_iterations": args.warm_probe,
+        "rule": args.warm_rule,
+        "injection": "added to the probe's regrets" if args.warm_add else "replaces the probe's regrets",
         "train": {"subgames": dstats["subgames"], "edges": dstats["edges"], "rows": dstats["rows"],
                   "target_entropy": dstats["target_entropy"], "val_target_entropy": vstats["target_entropy"],
                   "lr": args.warm_lr, "weights": "regret unit m(I), normalised per subgame",
@@ -378,8 +385,12 @@ def main():
     ap.add_argument("--warm-epochs", type=int, default=8)
     ap.add_argument("--warm-lr", type=float, default=2e-3)
     ap.add_argument("--warm-probe", type=int, default=16, help="probe iterations whose strategies feed the network")
+    ap.add_argument("--warm-replace", dest="warm_add", action="store_false",
+                    help="replace the probe's regrets by the network's instead of adding to them")
+    ap.add_argument("--warm-rule", default="cfr+", choices=["cfr+", "cfr+-alt", "dcfr-alt", "pcfr+"],
+                    help="update rule of the warm-start experiment (training targets, probe and solves)")
     ap.add_argument("--warm-max-iters", type=int, default=4000)
-    ap.add_argument("--warm-scales", type=float, nargs="+", default=[0.25, 0.5, 1.0, 2.0, 4.0])
+    ap.add_argument("--warm-scales", type=float, nargs="+", default=[0.25, 0.5, 1.0, 2.0, 4.0, 8.0])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration for profilers)")
     args = ap.parse_args()
@@ -390,6 +401,10 @@ def main():
 
     import torch
     import paper_2609_11923_amd as cfr
+    WARM_RULES.update({"cfr+": (cfr.CFR_RULE_CFR_PLUS, cfr.CFR_ORDER_SIMULTANEOUS),
+                       "cfr+-alt": (cfr.CFR_RULE_CFR_PLUS, cfr.CFR_ORDER_ALTERNATING),
+                       "dcfr-alt": (cfr.CFR_RULE_DCFR, cfr.CFR_ORDER_ALTERNATING),
+                       "pcfr+": (cfr.CFR_RULE_PCFR_PLUS, cfr.CFR_ORDER_SIMULTANEOUS)})
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)

@@ -369,11 +369,13 @@ cfr_status cfr_features(cfr_handle *h, const int16_t *bucket, const int16_t *his
 cfr_status cfr_regret_unit(cfr_handle *h, float *unit, int64_t rows, void *stream);
 /* Warm start: run the network on rows x (as made by cfr_features) and set the cumulative regrets
  * to scale * m(I) * softplus(z) for the legal actions of every set with at most 4 actions, 0 for
- * larger sets, then recompute the current strategy (as cfr_set_regrets does).  m(I) is the sum of
+ * larger sets (add = 0; this also clears the PCFR+ prediction), or add that to the current
+ * regrets (add = 1, keeping whatever a probe accumulated), then recompute the current strategy.  m(I) is the sum of
  * the magnitudes of the set's instantaneous regrets under the uniform strategy, recorded by the
  * last cfr_features call (CFR_ESTATE if there was none), so scale counts iterations' worth of
  * regret.  Strategy sums and the counter are left as they are.  scale = 0 gives the uniform start. */
-cfr_status cfr_warm_start(cfr_handle *h, cfr_mlp *n, const void *x, int64_t rows, float scale, void *stream);
+cfr_status cfr_warm_start(cfr_handle *h, cfr_mlp *n, const void *x, int64_t rows, float scale, int32_t add,
+                          void *stream);
 
 
 #ifdef __cplusplus

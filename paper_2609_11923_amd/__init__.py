@@ -153,7 +153,7 @@ def load():
         "cfr_num_infosets": (S, [_P, ctypes.POINTER(ctypes.c_int64)]),
         "cfr_features": (S, [_P, _P, _P, _P, ctypes.c_int32, _P, ctypes.c_int64, _P]),
         "cfr_regret_unit": (S, [_P, _P, ctypes.c_int64, _P]),
-        "cfr_warm_start": (S, [_P, _P, _P, ctypes.c_int64, ctypes.c_float, _P]),
+        "cfr_warm_start": (S, [_P, _P, _P, ctypes.c_int64, ctypes.c_float, ctypes.c_int32, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -374,8 +374,8 @@ def cfr_regret_unit(h, unit, rows: int, stream=None):
     _check(load().cfr_regret_unit(h, _dptr(unit), int(rows), _stream_arg(stream)))
 
 
-def cfr_warm_start(h, mlp, x, rows: int, scale: float, stream=None):
-    _check(load().cfr_warm_start(h, mlp, _dptr(x), int(rows), float(scale), _stream_arg(stream)))
+def cfr_warm_start(h, mlp, x, rows: int, scale: float, add: bool = False, stream=None):
+    _check(load().cfr_warm_start(h, mlp, _dptr(x), int(rows), float(scale), int(add), _stream_arg(stream)))
 
 
 class Mlp:
@@ -524,8 +524,8 @@ class Solver:
         """m(I) of every set into the device float32 tensor unit [I] (after features())."""
         cfr_regret_unit(self.h, unit, self.n_infosets, self._stream(stream))
 
-    def warm_start(self, mlp: "Mlp", x, scale: float, stream=None):
-        cfr_warm_start(self.h, mlp.h, x, self.n_infosets, scale, self._stream(stream))
+    def warm_start(self, mlp: "Mlp", x, scale: float, add: bool = False, stream=None):
+        cfr_warm_start(self.h, mlp.h, x, self.n_infosets, scale, add, self._stream(stream))
 
     def close(self):
         if getattr(self, "h", None):

@@ -104,6 +104,8 @@ hipError_t launch_average(const DevGame &g, hipStream_t s);
 hipError_t launch_sigma_to_float(const DevGame &g, float *dst, hipStream_t s);
 hipError_t launch_gather_float(const DevGame &g, const float *src, float *dst, hipStream_t s);
 hipError_t launch_regrets_from_float(const DevGame &g, const float *src, hipStream_t s);
+// R[map q] += src[q] (canonical float source)
+hipError_t launch_regrets_add_float(const DevGame &g, const float *src, hipStream_t s);
 // best response pieces (FP64); br = 1 or 2 selects the best responder, 0 evaluates the average profile
 hipError_t launch_br_forward(const DevGame &g, int32_t lo, int32_t hi, int br, hipStream_t s);
 hipError_t launch_br_argmax(const DevGame &g, int32_t ilo, int32_t ihi, int br, hipStream_t s);

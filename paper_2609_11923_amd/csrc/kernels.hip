@@ -466,6 +466,17 @@ __global__ void __launch_bounds__(BLOCK) k_scatter(int32_t n, const int32_t *__r
     if (i < n) dst[map ? map[i] : i] = (D)src[i];
 }
 
+// dst[map i] += src[i]
+template <typename S, typename D>
+__global__ void __launch_bounds__(BLOCK) k_scatter_add(int32_t n, const int32_t *__restrict__ map,
+                                                       const S *__restrict__ src, D *__restrict__ dst) {
+    int32_t i = (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
+    if (i < n) {
+        const int32_t j = map ? map[i] : i;
+        dst[j] = dst[j] + (D)src[i];
+    }
+}
+
 // ---- best response (FP64) -------------------------------------------------
 
 __global__ void __launch_bounds__(BLOCK) k_br_forward(int32_t lo, int32_t hi, const int2 *__restrict__ up,
@@ -713,6 +724,17 @@ hipError_t launch_regrets_from_float(const DevGame &g, const float *src, hipStre
     else
         hipLaunchKernelGGL((k_scatter<float, float>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, g.slot_map, src,
                            (float *)g.R);
+    return hipGetLastError();
+}
+
+hipError_t launch_regrets_add_float(const DevGame &g, const float *src, hipStream_t s) {
+    if (g.A == 0) return hipSuccess;
+    if (g.fp64)
+        hipLaunchKernelGGL((k_scatter_add<float, double>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, g.slot_map,
+                           src, (double *)g.R);
+    else
+        hipLaunchKernelGGL((k_scatter_add<float, float>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, g.slot_map,
+                           src, (float *)g.R);
     return hipGetLastError();
 }
 

@@ -1108,7 +1108,8 @@ cfr_status cfr_regret_unit(cfr_handle *h, float *unit, int64_t rows, void *strea
     return CFR_OK;
 }
 
-cfr_status cfr_warm_start(cfr_handle *h, cfr_mlp *n, const void *x, int64_t rows, float scale, void *stream) {
+cfr_status cfr_warm_start(cfr_handle *h, cfr_mlp *n, const void *x, int64_t rows, float scale, int32_t add,
+                          void *stream) {
     if (!h || !n) return fail(CFR_EINVAL, "NULL argument");
     if (rows != h->I_canon) return fail(CFR_EINVAL, "rows must equal the information-set count " + std::to_string(h->I_canon));
     if (mlp_in_dim(n) != CFR_FEATURES) return fail(CFR_EINVAL, "the network's in_dim must be CFR_FEATURES");
@@ -1126,8 +1127,12 @@ cfr_status cfr_warm_start(cfr_handle *h, cfr_mlp *n, const void *x, int64_t rows
     cfr_status st = mlp_forward_internal(n, x, rows, h->warm_z, s);
     if (st != CFR_OK) return st;
     HIP_TRY(launch_warm_regrets(h->canon_off, rows, h->warm_z, h->warm_mag, scale, h->g.out, s));
-    if (h->g.pred) HIP_TRY(hipMemsetAsync(h->g.pred, 0, (size_t)h->g.A * h->es, s));
-    HIP_TRY(launch_regrets_from_float(h->g, h->g.out, s));
+    if (add) {
+        HIP_TRY(launch_regrets_add_float(h->g, h->g.out, s));
+    } else {
+        if (h->g.pred) HIP_TRY(hipMemsetAsync(h->g.pred, 0, (size_t)h->g.A * h->es, s));
+        HIP_TRY(launch_regrets_from_float(h->g, h->g.out, s));
+    }
     HIP_TRY(launch_regret_matching(h->g, s));
     return CFR_OK;
 }

@@ -73,7 +73,8 @@ class Rows:
         solver.features(self.bucket, self.history, self.scalars, self.x, probe_iters=probe, stream=stream)
 
 
-def make_training_set(specs, iters, torch, probe=0, chunk=256, precision=CFR_PRECISION_FP32, log=print):
+def make_training_set(specs, iters, torch, probe=0, chunk=256, precision=CFR_PRECISION_FP32, solver_kw=None,
+                      log=print):
     """Solve the subgames of `specs` in batches of `chunk` for `iters` CFR+ iterations and keep,
     per information set with at most 4 actions, its feature row and the solver's average
     strategy as the target.  Row weights are the sets' regret units m(I) (which grow with the
@@ -87,7 +88,7 @@ def make_training_set(specs, iters, torch, probe=0, chunk=256, precision=CFR_PRE
         ta = time.perf_counter()
         games = subgames(specs[c0:c0 + chunk])
         tb = time.perf_counter()
-        s = Solver(games, precision=precision)
+        s = Solver(games, precision=precision, **(solver_kw or {}))
         rows = Rows(games, torch)
         tc = time.perf_counter()
         rows.features(s, probe=probe)       # the probe is the first `probe` iterations of this solve
@@ -176,7 +177,7 @@ def loss_of(mlp: Mlp, X, T, W, N, torch):
     return tot / max(wt, 1e-30)
 
 
-def solve_curves(s: Solver, rows: Rows, torch, checkpoints, mlp=None, scale=0.0, probe=0, log=None):
+def solve_curves(s: Solver, rows: Rows, torch, checkpoints, mlp=None, scale=0.0, probe=0, add=False, log=None):
     """One batch solve from scratch on solver s, with exploitability checkpoints at absolute
     iteration counts (a warm start's probe iterations count).  Timed on the stream with events:
     the warm start (feature pass, probe iterations, network, injection) and the iterations; the
@@ -190,7 +191,7 @@ def solve_curves(s: Solver, rows: Rows, torch, checkpoints, mlp=None, scale=0.0,
     if mlp is not None:
         ev[0].record(stream)
         rows.features(s, probe=probe, stream=stream)
-        s.warm_start(mlp, rows.x, scale, stream=stream)
+        s.warm_start(mlp, rows.x, scale, add=add, stream=stream)
         ev[1].record(stream)
         ev[1].synchronize()
         warm_ms = ev[0].elapsed_time(ev[1])
@@ -213,11 +214,12 @@ def solve_curves(s: Solver, rows: Rows, torch, checkpoints, mlp=None, scale=0.0,
 LEVEL_SYNC = {"persistent": 0, "wg_nodes": 0}
 
 
-def batch_solver(games, torch, schedule=LEVEL_SYNC, precision=CFR_PRECISION_FP32, tune_iters=20, log=print):
+def batch_solver(games, torch, schedule=LEVEL_SYNC, precision=CFR_PRECISION_FP32, tune_iters=20, solver_kw=None,
+                 log=print):
     """A compiled batch on the given schedule (None: autotuned).  Warm and cold arms share the
-    handle, so they always run the same schedule."""
+    handle, so they always run the same schedule and rule (solver_kw: rule, order)."""
     log(f"[warm] compiling {len(games)} games")
-    s = Solver(games, precision=precision)
+    s = Solver(games, precision=precision, **(solver_kw or {}))
     if schedule is None:
         schedule = s.autotune(tune_iters, stream=torch.cuda.Stream())
         log(f"[warm] autotune: {schedule}")
@@ -245,27 +247,28 @@ def summarize(cross, ms_per_iter, warm_ms, skip=0):
     )
 
 
-def geometric_checkpoints(t_max):
-    c, k = [], 8
+def geometric_checkpoints(t_max, first=8):
+    c, k = [], first
     while k < t_max:
         c.append(k)
         k = int(np.ceil(k * 1.5))
     return c + [t_max]
 
 
-def choose_scale(games, torch, mlp, scales, t_max, probe=0, schedule=LEVEL_SYNC, log=print):
+def choose_scale(games, torch, mlp, scales, t_max, probe=0, schedule=LEVEL_SYNC, solver_kw=None, add=False,
+                 log=print):
     """The scale whose warm start reaches the threshold in the fewest iterations (median over the
     validation games; ties and unreached games broken by the geometric mean of the final
     exploitability)."""
     cps = geometric_checkpoints(t_max)
     pots = np.array([g.pot for g in games])
-    s, _ = batch_solver(games, torch, schedule=schedule, log=log)
+    s, _ = batch_solver(games, torch, schedule=schedule, solver_kw=solver_kw, log=log)
     rows = Rows(games, torch)
     best = None
     table = []
     for c in scales:
         log(f"[warm] validation solve at scale {c}")
-        e, _, _, used = solve_curves(s, rows, torch, cps, mlp=mlp, scale=c, probe=probe, log=log)
+        e, _, _, used = solve_curves(s, rows, torch, cps, mlp=mlp, scale=c, probe=probe, add=add, log=log)
         cross = crossing_iterations(used, e, THRESHOLD * pots.min())
         score = (float(np.median(cross)), float(np.exp(np.mean(np.log(np.maximum(e[-1], 1e-12))))))
         table.append(dict(scale=c, median_iterations=score[0], final_expl_geomean=score[1]))
@@ -276,10 +279,11 @@ def choose_scale(games, torch, mlp, scales, t_max, probe=0, schedule=LEVEL_SYNC,
     return best[1], table
 
 
-def evaluate(games, torch, mlp, scale, t_max, control=None, probe=0, schedule=LEVEL_SYNC, log=print):
+def evaluate(games, torch, mlp, scale, t_max, control=None, probe=0, schedule=LEVEL_SYNC, solver_kw=None, add=False,
+             log=print):
     """Cold, warm and (optional) control-network solves of the same batch with the same compiled
     handle and schedule; per-game iterations and wall time to exploitability <= 1e-3 pot."""
-    s, schedule = batch_solver(games, torch, schedule=schedule, log=log)
+    s, schedule = batch_solver(games, torch, schedule=schedule, solver_kw=solver_kw, log=log)
     rows = Rows(games, torch)
     cps = geometric_checkpoints(t_max)
     pots = np.array([g.pot for g in games])
@@ -290,7 +294,7 @@ def evaluate(games, torch, mlp, scale, t_max, control=None, probe=0, schedule=LE
         arms.append(("control_untrained_net", control, scale))
     for name, net, c in arms:
         log(f"[warm] test solve: {name}")
-        e, warm_ms, iter_ms, used = solve_curves(s, rows, torch, cps, mlp=net, scale=c, probe=probe, log=log)
+        e, warm_ms, iter_ms, used = solve_curves(s, rows, torch, cps, mlp=net, scale=c, probe=probe, add=add, log=log)
         cross = crossing_iterations(used, e, thr)
         # iterations count from the start (probe included); the probe's time is inside warm_ms
         skip = probe if net is not None else 0

@@ -371,3 +371,31 @@ def test_warm_start_scale_zero_is_the_cold_start():
         s.warm_start(m, x, -1.0)
     with pytest.raises(cfr.CfrError):
         cfr.cfr_warm_start(s.h, m.h, x, I - 1, 1.0)
+
+
+def test_warm_start_add_mode_adds_to_the_probe_regrets():
+    games = warm_games()
+    b, h, sc = descriptors(games)
+    s = cfr.Solver(games, precision=cfr.CFR_PRECISION_FP64, rule=cfr.CFR_RULE_DCFR, order=cfr.CFR_ORDER_ALTERNATING)
+    I = s.n_infosets
+    x = torch.zeros(I, 128, dtype=torch.bfloat16, device=DEV)
+    s.features(torch.tensor(b, device=DEV), torch.tensor(h, device=DEV), torch.tensor(sc, device=DEV), x,
+               probe_iters=5)
+    R5, S5 = s.state()
+    m, _, _ = net(seed=33)
+    z = torch.zeros(I, 4, dtype=torch.float32, device=DEV)
+    m.forward(x, I, z)
+    unit = torch.zeros(I, dtype=torch.float32, device=DEV)
+    s.regret_unit(unit)
+    s.warm_start(m, x, 0.5, add=True)
+    R, S = s.state()
+    zc, uc = z.cpu().numpy(), unit.cpu().numpy().astype(np.float64)
+    base, o = s.slot_base, 0
+    for k, g in enumerate(games):
+        L = oracle.Oracle(g).layout()
+        Ik = len(L["slot_off"]) - 1
+        add = om.warm_regrets(zc[o:o + Ik], L["slot_off"], 0.5, uc[o:o + Ik])
+        o += Ik
+        sl = slice(base[k], base[k + 1])
+        assert rel(R[sl] - R5[sl], add) <= 1e-6, k
+    assert np.array_equal(S, S5) and s.iterations == 5

@@ -4,7 +4,8 @@ Train the network on the average strategies the solver produced for one set of s
 own payoff seed), then solve held-out subgames (another payoff seed) three ways on one compiled
 batch: cold (plain CFR+ from zero regrets), warm (the first `PROBE` iterations of the solve, then
 regrets from the trained network), and the same warm start with the untrained network.  Exact
-exploitability (the device best response) decides.  Every step is seeded and every reduction has
+exploitability (the device best response) decides.  The network's regrets are added to the
+probe's (scale 0.5 iterations' worth).  Every step is seeded and every reduction has
 a fixed order, so the outcome is reproducible; the gain itself is not pinned by the paper (it has
 no learned part)."""
 import sys
@@ -40,7 +41,7 @@ def test_trained_network_beats_cold_start_and_untrained_network():
     ctl = cfr.Mlp()
     ctl.set_params(theta0)
     test = warm.subgames(gg.random_subgames(64, seed=12, lo=1e3, hi=1e5, game_seed=6))
-    ev = warm.evaluate(test, torch, net, 1.0, 3000, control=ctl, probe=PROBE, log=note)
+    ev = warm.evaluate(test, torch, net, 0.5, 3000, control=ctl, probe=PROBE, add=True, log=note)
     cold, wst, unt = ev["cold"]["_cross"], ev["warm"]["_cross"], ev["control_untrained_net"]["_cross"]
     note(f"[warm test] median iterations: cold {np.median(cold):.1f}, warm {np.median(wst):.1f}, "
          f"untrained {np.median(unt):.1f}; warm faster on {np.mean(wst < cold):.2f} of games")
