@@ -179,6 +179,48 @@ def run_rules(cfr, torch, games, log, max_iters=4000):
     return out
 
 
+def run_lifecycle(cfr, torch, games, specs, log, solves=5):
+    """Reuse versus rebuild (the paper's lifecycle comparison) for new root ranges of every game
+    of the batch: rewriting the root chance in place and resetting, against compiling the changed
+    batch and running its first iteration (which captures the graph)."""
+    import gamegen as gg
+    rng = np.random.default_rng(123)
+    s = cfr.Solver(games, lifecycle=True)
+    s.iterate(2)
+    reuse, rebuild = [], []
+    for _ in range(solves):
+        probs = []
+        new_specs = []
+        for g, sp in zip(games, specs):
+            r1 = rng.dirichlet(np.ones(len(sp["hands1"])))
+            r2 = rng.dirichlet(np.ones(len(sp["hands2"])))
+            probs.append(gg.subgame_root_probs(g, r1, r2))
+            new_specs.append(dict({k: v for k, v in sp.items() if k != "target"}, r1=r1, r2=r2))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k, p in enumerate(probs):
+            s.set_root_chance(p, game=k)
+        s.reset()
+        s.iterate(1)
+        torch.cuda.synchronize()
+        reuse.append(time.perf_counter() - t0)
+        new_games = [gg.subgame(**sp) for sp in new_specs]     # input generation: not timed
+        t0 = time.perf_counter()
+        t = cfr.Solver(new_games)
+        t.iterate(1)
+        torch.cuda.synchronize()
+        rebuild.append(time.perf_counter() - t0)
+        t.close()
+    s.close()
+    out = dict(solves=solves, reuse_ms_median=1e3 * float(np.median(reuse)),
+               rebuild_ms_median=1e3 * float(np.median(rebuild)),
+               what="new root ranges for all games: in-place root chance + reset + first iteration, versus "
+                    "compile + first iteration (graph capture); game generation excluded")
+    out["speedup"] = out["rebuild_ms_median"] / out["reuse_ms_median"]
+    log(f"[bench] lifecycle: {out}")
+    return out
+
+
 def measure_game(cfr, torch, game, args, precision, log):
     """Compile one game, replay `warmup` then time `steps` iterations (hip events on the stream the
     graph is launched on), then per-kernel durations and bytes (cfr_profile) and the roofline of
@@ -467,13 +509,14 @@ def main():
     del game
     torch.cuda.empty_cache()
     if not args.no_batch:
-        games, _ = batch_games(args.batch_games, args.seed)
+        games, bspecs = batch_games(args.batch_games, args.seed)
         log(f"[bench] batch of {len(games)} subgames, {sum(g.n_edges for g in games)} edges")
         res, _ = run_batch(cfr, torch, games, args.batch_iters, cfr.CFR_PRECISION_FP32, log)
         out["batch"] = {"workload": f"{len(games)} subgames cut at round-B public states, 1e3-1e6 edges "
                                     f"log-uniform, Dirichlet(1) ranges", "precision": "fp32", **res}
         if not args.no_rules:
             out["batch"]["rules"] = run_rules(cfr, torch, games, log)
+        out["batch"]["lifecycle"] = run_lifecycle(cfr, torch, games, bspecs, log)
         del games
     if not args.no_warm:
         out["warm_start"] = run_warm(cfr, torch, args, log)

@@ -118,6 +118,8 @@ typedef struct {
     int persistent;        /* 1: each cfr_iterate call is one persistent launch running all n iterations
                               of every game, with per-game barriers (default 0: one launch per level) */
     int wg_nodes;          /* persistent form: target nodes per workgroup (0 = 16384); cfr_autotune picks it */
+    int lifecycle;         /* 1: keep per terminal its node, payoff and chance product (and each game's root
+                              chance) on the device, for cfr_set_payoffs / cfr_set_root_chance (default 0) */
 } cfr_options;
 
 /* Sizes of a compiled game.  blocks = number of depth levels that hold edges (D of eq. blocks). */
@@ -244,6 +246,21 @@ cfr_status cfr_get_state(cfr_handle *h, double *regrets, double *strategy_sum, i
  * src_on_device) and recompute the current strategy from them: a warm start.  Strategy sums and
  * the counter are left as they are (call cfr_reset first for a fresh solve). */
 cfr_status cfr_set_regrets(cfr_handle *h, const float *r0, int64_t len, int src_on_device, void *stream);
+
+/* In-place re-solve (paper Appendix H, set_payoffs and set_root_chance; Table 'tab:lifecycle'):
+ * rewrite the chance-folded template v_tmpl(z) = pi_c(z) u(z) of one game of the handle (game in
+ * [0, n_games)) without reallocating anything, so a captured graph stays valid.  The solver state
+ * (regrets, strategy sums, counter) is left alone: call cfr_reset for a fresh solve, or continue
+ * from the previous solution.  Both need the handle compiled with options.lifecycle = 1
+ * (CFR_ESTATE otherwise), wait for queued work on `stream` to read the host array and return
+ * with the rewrite queued on `stream`.
+ * cfr_set_payoffs: payoff[num_nodes] in the game description's node numbering (only terminal
+ *   entries are read; finite), num_nodes as compiled.
+ * cfr_set_root_chance: the root must be a chance node; prob[n] gives its children's probabilities
+ *   in the description's child order (finite, >= 0, summing to 1 within 1e-9).  Terminals below
+ *   child a get pi_c(z) = prob[a] * (the chance product below the root). */
+cfr_status cfr_set_payoffs(cfr_handle *h, int32_t game, const double *payoff, int64_t num_nodes, void *stream);
+cfr_status cfr_set_root_chance(cfr_handle *h, int32_t game, const double *prob, int64_t n, void *stream);
 
 /* Sizes and per-iteration launch count of a compiled game. */
 cfr_status cfr_counts(cfr_handle *h, cfr_counts_t *out);

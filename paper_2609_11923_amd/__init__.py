@@ -45,7 +45,7 @@ class cfr_options(ctypes.Structure):
     _fields_ = [("rule", ctypes.c_int), ("averaging", ctypes.c_int), ("order", ctypes.c_int),
                 ("iters_per_graph", ctypes.c_int), ("layout", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("device", ctypes.c_int), ("test_fail_capture", ctypes.c_int), ("precision", ctypes.c_int),
-                ("persistent", ctypes.c_int), ("wg_nodes", ctypes.c_int)]
+                ("persistent", ctypes.c_int), ("wg_nodes", ctypes.c_int), ("lifecycle", ctypes.c_int)]
 
 
 class cfr_tune_result(ctypes.Structure):
@@ -94,7 +94,8 @@ EXPORTS = ["cfr_default_options", "cfr_layout_host", "cfr_layout_free", "cfr_com
            "cfr_counts", "cfr_profile", "cfr_debug_rebind", "cfr_destroy", "cfr_last_error",
            "cfr_mlp_default_desc", "cfr_mlp_create", "cfr_mlp_num_params", "cfr_mlp_set_params", "cfr_mlp_get",
            "cfr_mlp_forward", "cfr_mlp_backward", "cfr_mlp_adam", "cfr_mlp_train_step", "cfr_mlp_destroy",
-           "cfr_num_infosets", "cfr_features", "cfr_regret_unit", "cfr_warm_start"]
+           "cfr_num_infosets", "cfr_features", "cfr_regret_unit", "cfr_warm_start", "cfr_set_payoffs",
+           "cfr_set_root_chance"]
 
 
 def load():
@@ -153,6 +154,8 @@ def load():
         "cfr_num_infosets": (S, [_P, ctypes.POINTER(ctypes.c_int64)]),
         "cfr_features": (S, [_P, _P, _P, _P, ctypes.c_int32, _P, ctypes.c_int64, _P]),
         "cfr_regret_unit": (S, [_P, _P, ctypes.c_int64, _P]),
+        "cfr_set_payoffs": (S, [_P, ctypes.c_int32, _P, ctypes.c_int64, _P]),
+        "cfr_set_root_chance": (S, [_P, ctypes.c_int32, _P, ctypes.c_int64, _P]),
         "cfr_warm_start": (S, [_P, _P, _P, ctypes.c_int64, ctypes.c_float, ctypes.c_int32, _P]),
     }
     for name, (res, args) in sig.items():
@@ -440,13 +443,14 @@ class Solver:
 
     def __init__(self, game, rule=CFR_RULE_CFR_PLUS, averaging=CFR_AVG_LINEAR, order=CFR_ORDER_SIMULTANEOUS,
                  iters_per_graph=1, layout=CFR_LAYOUT_PUBLIC, use_graph=True, device=0, test_fail_capture=False,
-                 precision=CFR_PRECISION_FP32, persistent=False, wg_nodes=0):
+                 precision=CFR_PRECISION_FP32, persistent=False, wg_nodes=0, lifecycle=False):
         o = cfr_default_options()
         o.rule, o.averaging, o.order = rule, averaging, order
         o.iters_per_graph, o.layout, o.use_graph = iters_per_graph, layout, int(use_graph)
         o.device, o.test_fail_capture = device, int(test_fail_capture)
         o.precision = precision
         o.persistent, o.wg_nodes = int(persistent), int(wg_nodes)
+        o.lifecycle = int(lifecycle)
         self.options = o
         if isinstance(game, (list, tuple)):
             self.h = cfr_compile_batch(game, o)
@@ -519,6 +523,16 @@ class Solver:
         """Feature rows of every information set into the device tensor x (bf16 [I, 128]); resets,
         then runs probe_iters iterations (their strategies fill columns 120-127)."""
         cfr_features(self.h, bucket, history, scalars, x, self.n_infosets, probe_iters, self._stream(stream))
+
+    def set_payoffs(self, payoff, game: int = 0, stream=None):
+        """Rewrite game `game`'s terminal payoffs (array over its description's nodes) in place."""
+        a = np.ascontiguousarray(payoff, np.float64)
+        _check(load().cfr_set_payoffs(self.h, int(game), _ptr(a), a.size, self._stream(stream)))
+
+    def set_root_chance(self, prob, game: int = 0, stream=None):
+        """Rewrite game `game`'s root chance probabilities (root children in description order)."""
+        a = np.ascontiguousarray(prob, np.float64)
+        _check(load().cfr_set_root_chance(self.h, int(game), _ptr(a), a.size, self._stream(stream)))
 
     def regret_unit(self, unit, stream=None):
         """m(I) of every set into the device float32 tensor unit [I] (after features())."""

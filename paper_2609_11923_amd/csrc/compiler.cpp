@@ -153,6 +153,7 @@ cfr_status build_layout(const cfr_game_desc *g, Layout &L, std::string &err) {
         for (int64_t i = 0; i < I; i++) L.slot_off[i + 1] = L.slot_off[i] + iset_nA[i];
         L.A = L.slot_off[I];
         if (L.A > (1LL << 28)) { err = "more than 2^28 information-set actions"; return CFR_EINVAL; }
+        if (L.keep_maps) L.input_id = order;
         // ---- pass 4/6: edge arrays in canonical numbering, chance folding, perfect recall
         L.parent.assign((size_t)N, -1);
         L.child_off.assign((size_t)N + 1, 0);
@@ -289,6 +290,7 @@ cfr_status build_device_layout(const Layout &L, int kind, int group_actions, Dev
             }
         }
         D.explicit_kids = pub;
+        if (L.keep_maps) D.node_dev = perm;
         // information sets renumbered by first member in device order
         std::vector<int32_t> iset_dev((size_t)I, -1), iset_canon;
         iset_canon.reserve((size_t)I);

@@ -34,6 +34,9 @@ struct Layout {
     std::vector<int64_t> iset_key;       // [I]
     std::vector<int32_t> iset_depth_off; // [max_depth + 2] infosets whose members sit at depth d
     std::vector<int64_t> public_key;     // [N] canonical order, empty if not given
+    // set before build_layout to keep the canonical -> input node map (in-place re-solve support)
+    bool keep_maps = false;
+    std::vector<int32_t> input_id;       // [N] input node id of canonical node k (keep_maps only)
 };
 
 // Validate and compile.  Returns CFR_OK or CFR_EINVAL / CFR_ENOMEM with a message in err.
@@ -67,6 +70,7 @@ struct DeviceLayout {
     std::vector<float> tmpl;             // [N]
     std::vector<double> tmpl64;          // [N]
     std::vector<int32_t> slot_canon_to_dev; // [A], empty when identical
+    std::vector<int32_t> node_dev;       // [N] device id of canonical node k (Layout::keep_maps only)
     // update groups: runs of consecutive information sets of one depth with at most group_members
     // members and at most GROUP_SETS sets in total (a set with more members forms a group of its
     // own); group g holds sets [grp_iset_off[g], grp_iset_off[g + 1]); the groups of depth d are

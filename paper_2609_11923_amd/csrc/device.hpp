@@ -106,6 +106,12 @@ hipError_t launch_gather_float(const DevGame &g, const float *src, float *dst, h
 hipError_t launch_regrets_from_float(const DevGame &g, const float *src, hipStream_t s);
 // R[map q] += src[q] (canonical float source)
 hipError_t launch_regrets_add_float(const DevGame &g, const float *src, hipStream_t s);
+// in-place re-solve: u[j] <- payoff_in[in[j]] for records [lo, hi); then the template of those
+// terminals: v = vbr = (root ? root[branch] * pic : pic) * u
+hipError_t launch_gather_payoffs(int64_t lo, int64_t hi, const int32_t *in, const double *payoff_in, double *u,
+                                 hipStream_t s);
+hipError_t launch_template(const DevGame &g, int64_t lo, int64_t hi, const int32_t *node, const int32_t *branch,
+                           const double *u, const double *pic, const double *root, hipStream_t s);
 // best response pieces (FP64); br = 1 or 2 selects the best responder, 0 evaluates the average profile
 hipError_t launch_br_forward(const DevGame &g, int32_t lo, int32_t hi, int br, hipStream_t s);
 hipError_t launch_br_argmax(const DevGame &g, int32_t ilo, int32_t ihi, int br, hipStream_t s);

@@ -477,6 +477,26 @@ __global__ void __launch_bounds__(BLOCK) k_scatter_add(int32_t n, const int32_t 
     }
 }
 
+// ---- in-place re-solve: the chance-folded template of a game's terminals ---------------------
+__global__ void __launch_bounds__(BLOCK) k_gather_payoffs(int64_t lo, int64_t hi, const int32_t *__restrict__ in,
+                                                          const double *__restrict__ pay, double *__restrict__ u) {
+    const int64_t j = lo + (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (j < hi) u[j] = pay[in[j]];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_template(int64_t lo, int64_t hi, const int32_t *__restrict__ node,
+                                                    const int32_t *__restrict__ branch, const double *__restrict__ u,
+                                                    const double *__restrict__ pic, const double *__restrict__ root,
+                                                    T *__restrict__ v, double *__restrict__ vbr) {
+    const int64_t j = lo + (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (j >= hi) return;
+    const double c = root ? root[branch[j]] * pic[j] : pic[j];
+    const double t = c * u[j];
+    v[node[j]] = (T)t;
+    vbr[node[j]] = t;
+}
+
 // ---- best response (FP64) -------------------------------------------------
 
 __global__ void __launch_bounds__(BLOCK) k_br_forward(int32_t lo, int32_t hi, const int2 *__restrict__ up,
@@ -735,6 +755,27 @@ hipError_t launch_regrets_add_float(const DevGame &g, const float *src, hipStrea
     else
         hipLaunchKernelGGL((k_scatter_add<float, float>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, g.slot_map,
                            src, (float *)g.R);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_payoffs(int64_t lo, int64_t hi, const int32_t *in, const double *payoff_in, double *u,
+                                 hipStream_t s) {
+    if (hi <= lo) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_payoffs, dim3((unsigned)((hi - lo + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, lo, hi,
+                       in, payoff_in, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_template(const DevGame &g, int64_t lo, int64_t hi, const int32_t *node, const int32_t *branch,
+                           const double *u, const double *pic, const double *root, hipStream_t s) {
+    if (hi <= lo) return hipSuccess;
+    const dim3 grid((unsigned)((hi - lo + BLOCK - 1) / BLOCK));
+    if (g.fp64)
+        hipLaunchKernelGGL(k_template<double>, grid, dim3(BLOCK), 0, s, lo, hi, node, branch, u, pic, root,
+                           (double *)g.v, g.vbr);
+    else
+        hipLaunchKernelGGL(k_template<float>, grid, dim3(BLOCK), 0, s, lo, hi, node, branch, u, pic, root,
+                           (float *)g.v, g.vbr);
     return hipGetLastError();
 }
 

@@ -96,6 +96,17 @@ struct cfr_handle {
     float *warm_z = nullptr;           // [I * 4] logits, allocated on first warm start
     float *warm_mag = nullptr;         // [I] regret unit of each set, written by cfr_features
     bool have_mag = false;
+    // in-place re-solve (options.lifecycle): per terminal of every game, games in order
+    std::vector<int64_t> lc_term_off;  // [n + 1] terminal records of game s
+    std::vector<int64_t> lc_root_off;  // [n + 1] root children of game s (none when the root is not chance)
+    std::vector<int64_t> lc_nodes;     // [n] input node count of game s
+    int32_t *lc_node = nullptr;        // device node
+    int32_t *lc_in = nullptr;          // input node id within its game
+    int32_t *lc_branch = nullptr;      // root child above it, -1 when the root is not chance
+    double *lc_u = nullptr;            // payoff
+    double *lc_pic = nullptr;          // chance product below the root (the whole product without a chance root)
+    double *lc_root = nullptr;         // root chance probabilities
+    double *lc_stage = nullptr;        // staging for a game's payoff array
 };
 
 // Per-launch event timing for cfr_profile: class 0 tick, 1 forward, 2 level.
@@ -316,6 +327,7 @@ void cfr_default_options(cfr_options *o) {
     o->precision = CFR_PRECISION_FP32;
     o->persistent = 0;
     o->wg_nodes = 0;
+    o->lifecycle = 0;
 }
 
 const char *cfr_last_error(void) { return g_err.c_str(); }
@@ -491,6 +503,53 @@ static cfr_status persistent_iterate(cfr_handle *h, int64_t n, hipStream_t s) {
     return CFR_OK;
 }
 
+// Per-terminal records of the in-place re-solve: device node (of the game's own device layout
+// until the forest renumbers it), input id, payoff, chance product below the root, root branch.
+struct LifecycleHost {
+    std::vector<int64_t> term_off{0}, root_off{0}, nodes;
+    std::vector<int32_t> node, in, branch, depth;
+    std::vector<double> u, pic, root;
+    std::vector<std::vector<int32_t>> depth_off;   // per game
+};
+
+static void lifecycle_records(const cfr_game_desc &g, const Layout &L, const DeviceLayout &D, LifecycleHost &lc) {
+    const int64_t N = L.N;
+    const bool chance_root = L.node_type[0] == CFR_NODE_CHANCE;
+    std::vector<double> pic((size_t)N, 1.0);
+    std::vector<int32_t> br((size_t)N, -1);
+    for (int64_t k = 0; k < N; k++) {
+        const int32_t h = L.input_id[(size_t)k];
+        for (int32_t c = L.child_off[k]; c < L.child_off[k + 1]; c++) {
+            const int32_t a = c - L.child_off[k];
+            if (k == 0 && chance_root) {
+                br[c] = a;
+                pic[c] = 1.0;
+            } else {
+                br[c] = br[k];
+                pic[c] = L.node_type[k] == CFR_NODE_CHANCE ? pic[k] * g.chance_prob[g.child_begin[h] + a] : pic[k];
+            }
+        }
+    }
+    int d = 0;
+    for (int64_t k = 0; k < N; k++) {
+        while (k >= L.depth_off[d + 1]) d++;
+        if (L.node_type[k] != CFR_NODE_TERMINAL) continue;
+        const int32_t h = L.input_id[(size_t)k];
+        lc.node.push_back(D.node_dev[(size_t)k]);
+        lc.in.push_back(h);
+        lc.branch.push_back(br[k]);
+        lc.depth.push_back(d);
+        lc.u.push_back(g.payoff[h]);
+        lc.pic.push_back(pic[k]);
+    }
+    if (chance_root)
+        for (int32_t a = 0; a < g.num_children[g.root]; a++) lc.root.push_back(g.chance_prob[g.child_begin[g.root] + a]);
+    lc.term_off.push_back((int64_t)lc.node.size());
+    lc.root_off.push_back((int64_t)lc.root.size());
+    lc.nodes.push_back(g.num_nodes);
+    lc.depth_off.push_back(L.depth_off);
+}
+
 // Compile one game or a batch of independent games (a depth-major forest, see build_forest).
 static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_options *opt, cfr_handle **out) {
     if (!out) return fail(CFR_EINVAL, "out is NULL");
@@ -514,6 +573,7 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     std::vector<int32_t> canon_off;
     std::vector<int8_t> canon_player;
     for (int s = 0; s < n; s++) {
+        Ls[s].keep_maps = o.lifecycle != 0;
         st = build_layout(&games[s], Ls[s], err);
         if (st != CFR_OK) return fail(st, n > 1 ? "game " + std::to_string(s) + ": " + err : err);
         if (!Ls[s].br_ok)
@@ -536,15 +596,27 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     HIP_TRY(hipSetDevice(o.device));
 
     DeviceLayout DL;
+    LifecycleHost lc;
     {
         std::vector<DeviceLayout> Ds((size_t)n);
         for (int s = 0; s < n; s++) {
             st = build_device_layout(Ls[s], o.layout, max_actions, Ds[s], err);
             if (st != CFR_OK) return fail(st, err);
+            if (o.lifecycle) lifecycle_records(games[s], Ls[s], Ds[s], lc);
             if (n > 1) Ls[s] = Layout();  // free the canonical arrays early
         }
         st = build_forest(Ls, Ds, DL, err);
         if (st != CFR_OK) return fail(st, err);
+    }
+    if (o.lifecycle && n > 1) {
+        // device ids of each game -> forest ids: the game's depth-d nodes start at its range lo
+        const int MD = max_depth;
+        for (int s = 0; s < n; s++)
+            for (int64_t j = lc.term_off[s]; j < lc.term_off[s + 1]; j++) {
+                const int d = lc.depth[(size_t)j];
+                const int32_t lo = DL.game_range[((size_t)s * (MD + 1) + d) * GR_FIELDS];
+                lc.node[(size_t)j] = lo + (lc.node[(size_t)j] - lc.depth_off[s][(size_t)d]);
+            }
     }
     cfr_handle *h = new cfr_handle();
     h->opt = o;
@@ -643,6 +715,20 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     UP(g.bigc_node, DL.bigc_node);
     UP(h->canon_off, canon_off);
     UP(h->canon_player, canon_player);
+    if (o.lifecycle) {
+        const int64_t nt = (int64_t)lc.node.size(), nr = (int64_t)lc.root.size();
+        int64_t maxn = 1;
+        for (int64_t v : lc.nodes) maxn = std::max(maxn, v);
+#define LA(ptr, cnt) do { st = dev_alloc(h, &(ptr), (cnt)); if (st != CFR_OK) { free_handle(h); return st; } } while (0)
+        LA(h->lc_node, nt); LA(h->lc_in, nt); LA(h->lc_branch, nt); LA(h->lc_u, nt); LA(h->lc_pic, nt);
+        LA(h->lc_root, nr); LA(h->lc_stage, maxn);
+#undef LA
+        UP(h->lc_node, lc.node); UP(h->lc_in, lc.in); UP(h->lc_branch, lc.branch); UP(h->lc_u, lc.u);
+        UP(h->lc_pic, lc.pic); UP(h->lc_root, lc.root);
+        h->lc_term_off = lc.term_off;
+        h->lc_root_off = lc.root_off;
+        h->lc_nodes = lc.nodes;
+    }
     if (g.fp64) { UP((double *)g.v, DL.tmpl64); } else { UP((float *)g.v, DL.tmpl); }
     UP(g.vbr, DL.tmpl64);
     {
@@ -1046,6 +1132,60 @@ cfr_status cfr_autotune(cfr_handle *h, int64_t iters, void *stream, const char *
 cfr_status cfr_debug_rebind(cfr_handle *h, int which, int64_t delta) {
     if (!h || which < 0 || which > 2) return fail(CFR_EINVAL, "bad argument");
     h->rebind[which] = delta;
+    return CFR_OK;
+}
+
+static cfr_status lifecycle_check(cfr_handle *h, int32_t game) {
+    if (!h) return fail(CFR_EINVAL, "handle is NULL");
+    if (!h->lc_node) return fail(CFR_ESTATE, "compile with options.lifecycle = 1 to rewrite payoffs or root chance");
+    if (game < 0 || game >= h->n_games) return fail(CFR_EINVAL, "game index out of range");
+    return CFR_OK;
+}
+
+static cfr_status lifecycle_template(cfr_handle *h, int32_t game, hipStream_t s) {
+    const int64_t lo = h->lc_term_off[(size_t)game], hi = h->lc_term_off[(size_t)game + 1];
+    const bool has_root = h->lc_root_off[(size_t)game + 1] > h->lc_root_off[(size_t)game];
+    HIP_TRY(launch_template(h->g, lo, hi, h->lc_node, h->lc_branch, h->lc_u, h->lc_pic,
+                            has_root ? h->lc_root + h->lc_root_off[(size_t)game] : nullptr, s));
+    return CFR_OK;
+}
+
+cfr_status cfr_set_payoffs(cfr_handle *h, int32_t game, const double *payoff, int64_t num_nodes, void *stream) {
+    cfr_status st = lifecycle_check(h, game);
+    if (st != CFR_OK) return st;
+    if (!payoff) return fail(CFR_EINVAL, "payoff is NULL");
+    if (num_nodes != h->lc_nodes[(size_t)game]) return fail(CFR_EINVAL, "num_nodes differs from the compiled game");
+    for (int64_t k = 0; k < num_nodes; k++)
+        if (!std::isfinite(payoff[k])) return fail(CFR_EINVAL, "non-finite payoff");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(h->lc_stage, payoff, (size_t)num_nodes * sizeof(double), hipMemcpyHostToDevice, s));
+    const int64_t lo = h->lc_term_off[(size_t)game], hi = h->lc_term_off[(size_t)game + 1];
+    HIP_TRY(launch_gather_payoffs(lo, hi, h->lc_in, h->lc_stage, h->lc_u, s));
+    st = lifecycle_template(h, game, s);
+    if (st != CFR_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s));   // the staging buffer is reused by the next call
+    return CFR_OK;
+}
+
+cfr_status cfr_set_root_chance(cfr_handle *h, int32_t game, const double *prob, int64_t n, void *stream) {
+    cfr_status st = lifecycle_check(h, game);
+    if (st != CFR_OK) return st;
+    const int64_t r0 = h->lc_root_off[(size_t)game], r1 = h->lc_root_off[(size_t)game + 1];
+    if (r1 == r0) return fail(CFR_EINVAL, "the game's root is not a chance node");
+    if (!prob || n != r1 - r0) return fail(CFR_EINVAL, "prob must hold one probability per root child");
+    double sum = 0.0;
+    for (int64_t a = 0; a < n; a++) {
+        if (!(prob[a] >= 0.0) || !std::isfinite(prob[a])) return fail(CFR_EINVAL, "invalid chance probability");
+        sum += prob[a];
+    }
+    if (std::fabs(sum - 1.0) > 1e-9) return fail(CFR_EINVAL, "root chance probabilities do not sum to 1");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(h->lc_root + r0, prob, (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
+    st = lifecycle_template(h, game, s);
+    if (st != CFR_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s));
     return CFR_OK;
 }
 
