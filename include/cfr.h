@@ -120,6 +120,10 @@ typedef struct {
     int wg_nodes;          /* persistent form: target nodes per workgroup (0 = 16384); cfr_autotune picks it */
     int lifecycle;         /* 1: keep per terminal its node, payoff and chance product (and each game's root
                               chance) on the device, for cfr_set_payoffs / cfr_set_root_chance (default 0) */
+    int affine;            /* 1 (default): when the PUBLIC layout places child a of every member h of a set
+                              at h + offset(set, a), the update pass reads one offset per slot instead of
+                              the explicit child list (same arithmetic, bitwise equal results); 0: always
+                              read the child list */
 } cfr_options;
 
 /* Sizes of a compiled game.  blocks = number of depth levels that hold edges (D of eq. blocks). */
@@ -129,6 +133,7 @@ typedef struct {
     int64_t device_bytes;          /* device memory held by the handle */
     int64_t kernels_per_iteration; /* launches in one iteration (the operation-count gate) */
     double  pot;
+    int32_t child_addressing;      /* update pass: 0 implicit (BFS), 1 explicit child list, 2 affine offsets */
 } cfr_counts_t;
 
 /* Canonical compiled arrays (host copies), all in canonical numbering:

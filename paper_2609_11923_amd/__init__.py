@@ -45,7 +45,8 @@ class cfr_options(ctypes.Structure):
     _fields_ = [("rule", ctypes.c_int), ("averaging", ctypes.c_int), ("order", ctypes.c_int),
                 ("iters_per_graph", ctypes.c_int), ("layout", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("device", ctypes.c_int), ("test_fail_capture", ctypes.c_int), ("precision", ctypes.c_int),
-                ("persistent", ctypes.c_int), ("wg_nodes", ctypes.c_int), ("lifecycle", ctypes.c_int)]
+                ("persistent", ctypes.c_int), ("wg_nodes", ctypes.c_int), ("lifecycle", ctypes.c_int),
+                ("affine", ctypes.c_int)]
 
 
 class cfr_tune_result(ctypes.Structure):
@@ -58,7 +59,8 @@ class cfr_counts_t(ctypes.Structure):
                 ("decision_nodes", ctypes.c_int64), ("infosets", ctypes.c_int64), ("slots", ctypes.c_int64),
                 ("max_depth", ctypes.c_int32), ("blocks", ctypes.c_int32), ("max_actions", ctypes.c_int32),
                 ("br_supported", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
-                ("kernels_per_iteration", ctypes.c_int64), ("pot", ctypes.c_double)]
+                ("kernels_per_iteration", ctypes.c_int64), ("pot", ctypes.c_double),
+                ("child_addressing", ctypes.c_int32)]
 
 
 class cfr_layout(ctypes.Structure):
@@ -443,7 +445,7 @@ class Solver:
 
     def __init__(self, game, rule=CFR_RULE_CFR_PLUS, averaging=CFR_AVG_LINEAR, order=CFR_ORDER_SIMULTANEOUS,
                  iters_per_graph=1, layout=CFR_LAYOUT_PUBLIC, use_graph=True, device=0, test_fail_capture=False,
-                 precision=CFR_PRECISION_FP32, persistent=False, wg_nodes=0, lifecycle=False):
+                 precision=CFR_PRECISION_FP32, persistent=False, wg_nodes=0, lifecycle=False, affine=True):
         o = cfr_default_options()
         o.rule, o.averaging, o.order = rule, averaging, order
         o.iters_per_graph, o.layout, o.use_graph = iters_per_graph, layout, int(use_graph)
@@ -451,6 +453,7 @@ class Solver:
         o.precision = precision
         o.persistent, o.wg_nodes = int(persistent), int(wg_nodes)
         o.lifecycle = int(lifecycle)
+        o.affine = int(affine)
         self.options = o
         if isinstance(game, (list, tuple)):
             self.h = cfr_compile_batch(game, o)

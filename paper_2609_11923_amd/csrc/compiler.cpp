@@ -428,6 +428,27 @@ cfr_status build_device_layout(const Layout &L, int kind, int group_actions, Dev
     }
 }
 
+bool slot_child_offsets(const DeviceLayout &D, std::vector<int32_t> &koff) {
+    koff.clear();
+    if (!D.explicit_kids) return false;
+    const int64_t I = (int64_t)D.slot_off.size() - 1;
+    std::vector<int32_t> out((size_t)(I > 0 ? D.slot_off[I] : 0), 0);
+    for (int64_t i = 0; i < I; i++) {
+        const int32_t s0 = D.slot_off[i], nA = D.slot_off[i + 1] - s0;
+        for (int32_t m = D.mem_off[i]; m < D.mem_off[i + 1]; m++) {
+            const int32_t h = D.mem_node[m] & 0x7fffffff;
+            if (D.kid_off[h + 1] - D.kid_off[h] != nA) return false;
+            for (int32_t a = 0; a < nA; a++) {
+                const int32_t d = D.kid[D.kid_off[h] + a] - h;
+                if (m == D.mem_off[i]) out[s0 + a] = d;
+                else if (out[s0 + a] != d) return false;
+            }
+        }
+    }
+    koff = std::move(out);
+    return true;
+}
+
 cfr_status build_forest(std::vector<Layout> &Ls, std::vector<DeviceLayout> &Ds, DeviceLayout &F, std::string &err) {
     try {
         const int n = (int)Ds.size();

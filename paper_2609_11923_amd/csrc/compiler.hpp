@@ -98,12 +98,20 @@ constexpr int GR_FIELDS = 8;  // node lo/hi, group lo/hi, chance lo/hi, big chan
 constexpr int BIG_FANOUT = 64;
 
 constexpr int GROUP_SETS = 256;
-// members per update group: two per thread of a 256-thread block when sets have at most 4 actions
+// members per update group: two per thread of a 256-thread block when sets have at most 4 actions,
+// else one (four per thread measured slower for FP32 state: the registers cut the resident waves)
 inline int group_members(int max_actions) { return max_actions <= 4 ? 512 : 256; }
 
 // group_actions: the action bound the update groups are sized for (>= L.max_actions)
 cfr_status build_device_layout(const Layout &L, int layout_kind, int group_actions, DeviceLayout &out,
                                std::string &err);
+
+// Affine children: in an explicit layout, when every member h of every information set reaches its
+// child under action a at h + koff[slot a] (one offset per slot, shared by the set's members), fill
+// koff [A] and return true; otherwise return false (koff cleared).  Public-state layouts of card
+// games have this property: the members of a set lie in one public-state block and the child
+// block of an action keeps the block's node order.
+bool slot_child_offsets(const DeviceLayout &D, std::vector<int32_t> &koff);
 
 // Merge the device layouts of independent games into one depth-major forest (see DeviceLayout).
 // Ls and Ds are consumed (moved or cleared).  A single game is moved through unchanged.

@@ -36,6 +36,11 @@ struct DevGame {
     int2 *up = nullptr;           // [N]   (parent, edge code)
     int32_t *kid_off = nullptr;   // [N+1] edges of n are [kid_off[n], kid_off[n+1])
     int32_t *kid = nullptr;       // [E]   child of each edge (explicit layouts only)
+    // affine layouts (explicit, and child a of every member h of a set is h + koff[slot a]): the
+    // update pass reads the per-slot offsets and a compact member list instead of kid[] and mem[]
+    int affine = 0;
+    int32_t *koff = nullptr;      // [A]   child offset of each slot (affine only)
+    int32_t *mnode = nullptr;     // [Ndec] member node | MEMBER_P2 bit (affine only)
     int32_t *slot_map = nullptr;  // [A]   canonical slot -> device slot (nullptr: identity)
     int32_t *node_slot = nullptr; // [N]   first slot of a decision node, -1 otherwise
     int32_t *node_iset = nullptr; // [N]   information set of a decision node, -1 otherwise

@@ -16,6 +16,8 @@
 // configured dtype -- or double; strategy sums are double in both.  Every
 // reduction runs in a fixed order inside one thread, so results are bitwise
 // reproducible run to run (no float atomics).
+#include <type_traits>
+
 #include "device.hpp"
 
 namespace cfrx {
@@ -66,6 +68,7 @@ struct LevelArgs {
     const int2 *mem;
     const int8_t *iset_player;
     const int32_t *kid_off, *kid, *chance_node, *bigc_node;
+    const int32_t *koff, *mnode;   // affine layouts: per-slot child offset, compact member list
     T *v;
     T *r1, *r2;   // reach lanes (the level only reads them; the persistent form's forward levels write)
     T *R;
@@ -125,6 +128,102 @@ __device__ void big_chance_value(int32_t h, const LevelArgs<T> &a, T *red) {
     }
     if (tid == 0) a.v[h] = red[0];
     __syncthreads();
+}
+
+// The update of one information set from its instantaneous regrets r (already summed over the
+// members, player 1's sign) and its state as loaded (R, sigma^t, sbar): R <- R + sign r with the
+// rule's clamp or discount, sbar += w pi_i(I) sigma^t (FP64; DCFR discounts it), then
+// sigma^{t+1} = regret matching of R (PCFR+: of R plus the prediction, which becomes this
+// iteration's instantaneous regret).
+template <typename T, int MAXA, bool EXT>
+__device__ __forceinline__ void set_update_from(const RuleArgs &ru, const LevelArgs<T> &a, int32_t s0, int32_t nA,
+                                                int pl, double pown, const T (&r)[MAXA], T (&Rk)[MAXA],
+                                                const T (&sk)[MAXA], double (&sb)[MAXA]) {
+    const T sign = pl == 1 ? T(1) : T(-1);
+    T tot = T(0);
+    T Rn[MAXA];
+    if constexpr (!EXT) {
+        const bool clamp = ru.rule != CFR_RULE_CFR;
+#pragma unroll
+        for (int k = 0; k < MAXA; k++)
+            if (k < nA) {
+                sb[k] += ru.w * pown * (double)sk[k];
+                T y = fma_t(sign, r[k], Rk[k]);
+                if (clamp) y = max_t(y, T(0));
+                Rk[k] = y;
+                Rn[k] = max_t(y, T(0));
+                tot += Rn[k];
+            }
+    } else {
+        if (ru.rule == CFR_RULE_DCFR) {
+            const T pos = (T)ru.pos, neg = (T)ru.neg;
+#pragma unroll
+            for (int k = 0; k < MAXA; k++)
+                if (k < nA) {
+                    sb[k] = (sb[k] + pown * (double)sk[k]) * ru.sdisc;
+                    T y = fma_t(sign, r[k], Rk[k]);
+                    y = y > T(0) ? y * pos : y * neg;
+                    Rk[k] = y;
+                    Rn[k] = max_t(y, T(0));
+                    tot += Rn[k];
+                }
+        } else if (ru.rule == CFR_RULE_PCFR_PLUS) {
+#pragma unroll
+            for (int k = 0; k < MAXA; k++)
+                if (k < nA) {
+                    sb[k] += ru.w * pown * (double)sk[k];
+                    const T y = max_t(fma_t(sign, r[k], Rk[k]), T(0));
+                    const T m = sign * r[k];
+                    Rk[k] = y;
+                    a.pred[s0 + k] = m;
+                    Rn[k] = max_t(y + m, T(0));
+                    tot += Rn[k];
+                }
+        } else {
+            const bool clamp = ru.rule != CFR_RULE_CFR;
+#pragma unroll
+            for (int k = 0; k < MAXA; k++)
+                if (k < nA) {
+                    sb[k] += ru.w * pown * (double)sk[k];
+                    T y = fma_t(sign, r[k], Rk[k]);
+                    if (clamp) y = max_t(y, T(0));
+                    Rk[k] = y;
+                    Rn[k] = max_t(y, T(0));
+                    tot += Rn[k];
+                }
+        }
+    }
+    const T inv = tot > T(0) ? T(1) / tot : T(0);
+    const T uni = T(1) / (T)nA;
+#pragma unroll
+    for (int k = 0; k < MAXA; k++)
+        if (k < nA) {
+            a.R[s0 + k] = Rk[k];
+            a.sbar[s0 + k] = sb[k];
+            a.sigma[s0 + k] = tot > T(0) ? Rn[k] * inv : uni;
+        }
+}
+
+// Load the set's state, then set_update_from.
+template <typename T, int MAXA>
+__device__ __forceinline__ void load_set_state(const LevelArgs<T> &a, int32_t s0, int32_t nA, T (&Rk)[MAXA],
+                                               T (&sk)[MAXA], double (&sb)[MAXA]) {
+#pragma unroll
+    for (int k = 0; k < MAXA; k++)
+        if (k < nA) {
+            Rk[k] = a.R[s0 + k];
+            sk[k] = a.sigma[s0 + k];
+            sb[k] = a.sbar[s0 + k];
+        }
+}
+
+template <typename T, int MAXA, bool EXT>
+__device__ __forceinline__ void set_update(const RuleArgs &ru, const LevelArgs<T> &a, int32_t s0, int32_t nA, int pl,
+                                           double pown, const T (&r)[MAXA]) {
+    T Rk[MAXA], sk[MAXA];
+    double sb[MAXA];
+    load_set_state<T, MAXA>(a, s0, nA, Rk, sk, sb);
+    set_update_from<T, MAXA, EXT>(ru, a, s0, nA, pl, pown, r, Rk, sk, sb);
 }
 
 // LDS staging of one update group (members of a chunk, the group's set offsets)
@@ -224,94 +323,133 @@ __device__ void group_update(int32_t g, const RuleArgs &ru, const LevelArgs<T> &
     // alternating order: the other player's half leaves this set's state alone (values only)
     if (!((ru.upd >> (pl - 1)) & 1)) return;
     const T *own = pl == 1 ? a.r1 : a.r2;
-    const T sign = pl == 1 ? T(1) : T(-1);
-    const double pown = (double)own[a.mem[m0].x & MEMBER_NODE_MASK];
-    T tot = T(0);
-    T Rn[MAXA];
-    if constexpr (!EXT) {
-        const bool clamp = ru.rule != CFR_RULE_CFR;
-#pragma unroll
-        for (int k = 0; k < MAXA; k++) {
-            if (k < nA) {
-                const int32_t q = s0 + k;
-                a.sbar[q] += ru.w * pown * (double)a.sigma[q];
-                T y = fma_t(sign, r[k], a.R[q]);
-                if (clamp) y = max_t(y, T(0));
-                a.R[q] = y;
-                Rn[k] = max_t(y, T(0));
-                tot += Rn[k];
-            }
-        }
-    } else {
-        // all loads of the set first, one branch on the rule, then the stores
-        T Rk[MAXA], sk[MAXA];
-        double sb[MAXA];
-#pragma unroll
-        for (int k = 0; k < MAXA; k++)
-            if (k < nA) {
-                Rk[k] = a.R[s0 + k];
-                sk[k] = a.sigma[s0 + k];
-                sb[k] = a.sbar[s0 + k];
-            }
-        if (ru.rule == CFR_RULE_DCFR) {
-            const T pos = (T)ru.pos, neg = (T)ru.neg;
-#pragma unroll
-            for (int k = 0; k < MAXA; k++)
-                if (k < nA) {
-                    sb[k] = (sb[k] + pown * (double)sk[k]) * ru.sdisc;
-                    T y = fma_t(sign, r[k], Rk[k]);
-                    y = y > T(0) ? y * pos : y * neg;
-                    Rk[k] = y;
-                    Rn[k] = max_t(y, T(0));
-                    tot += Rn[k];
-                }
-        } else if (ru.rule == CFR_RULE_PCFR_PLUS) {
-#pragma unroll
-            for (int k = 0; k < MAXA; k++)
-                if (k < nA) {
-                    sb[k] += ru.w * pown * (double)sk[k];
-                    const T y = max_t(fma_t(sign, r[k], Rk[k]), T(0));
-                    const T m = sign * r[k];
-                    Rk[k] = y;
-                    a.pred[s0 + k] = m;
-                    Rn[k] = max_t(y + m, T(0));
-                    tot += Rn[k];
-                }
-        } else {
-            const bool clamp = ru.rule != CFR_RULE_CFR;
-#pragma unroll
-            for (int k = 0; k < MAXA; k++)
-                if (k < nA) {
-                    sb[k] += ru.w * pown * (double)sk[k];
-                    T y = fma_t(sign, r[k], Rk[k]);
-                    if (clamp) y = max_t(y, T(0));
-                    Rk[k] = y;
-                    Rn[k] = max_t(y, T(0));
-                    tot += Rn[k];
-                }
-        }
-#pragma unroll
-        for (int k = 0; k < MAXA; k++)
-            if (k < nA) {
-                a.R[s0 + k] = Rk[k];
-                a.sbar[s0 + k] = sb[k];
-            }
+    set_update<T, MAXA, EXT>(ru, a, s0, nA, pl, (double)own[a.mem[m0].x & MEMBER_NODE_MASK], r);
+}
+
+// LDS staging of one update group in an affine layout: the set offsets, the set of each member
+// of the chunk and each set's own reach, besides the member values of group_update
+template <typename T, int MAXA, int MPT>
+struct GroupLdsA {
+    T po[MPT * BLOCK];
+    T diff[MPT * BLOCK * MAXA];
+    T pown[BLOCK];
+    int32_t moff[BLOCK + 1];
+    int32_t slot[BLOCK + 1];
+    uint8_t mset[MPT * BLOCK];
+};
+
+// group_update for affine layouts (child a of member h is h + koff[slot a]): the same arithmetic
+// in the same order, so the results are bitwise those of group_update.  What changes is the load
+// chain of a member: its compact record and the set's offsets (from the member -> set map in LDS,
+// no search) are independent loads, the child values follow them, and every load of a chunk is
+// issued before its stores; the first member of each set also stages the set's own reach.
+template <typename T, int MAXA, int MPT, bool EXT>
+__device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelArgs<T> &a,
+                                    GroupLdsA<T, MAXA, MPT> &L) {
+    constexpr int CHUNK = MPT * BLOCK;
+    const int tid = threadIdx.x;
+    const int32_t i0 = a.grp_iset_off[g], i1 = a.grp_iset_off[g + 1];
+    const int32_t nsets = i1 - i0;
+    const int32_t mbeg = a.mem_off[i0], mend = a.mem_off[i1];
+    const bool has_set = tid < nsets;
+    int32_t s0 = 0, nA = 0, m0 = 0, m1 = 0, pl = 1;
+    if (has_set) {
+        m0 = a.mem_off[i0 + tid];
+        m1 = a.mem_off[i0 + tid + 1];
+        s0 = a.slot_off[i0 + tid];
+        nA = a.slot_off[i0 + tid + 1] - s0;
+        pl = a.iset_player[i0 + tid];
+        L.moff[tid] = m0;
+        L.slot[tid] = s0;
+        if (tid == nsets - 1) L.slot[nsets] = s0 + nA;
+        // member -> set map of the first chunk: a group of several sets fits one chunk, and a group
+        // that needs more chunks holds a single set (index 0 throughout)
+        const int32_t e = min(m1, mbeg + CHUNK);
+        for (int32_t m = m0; m < e; m++) L.mset[m - mbeg] = (uint8_t)tid;
     }
-    const T inv = tot > T(0) ? T(1) / tot : T(0);
-    const T uni = T(1) / (T)nA;
+    __syncthreads();
+    const T *__restrict__ r1 = a.r1;
+    const T *__restrict__ r2 = a.r2;
+    const T *__restrict__ sig = a.sigma;
+    const int32_t *__restrict__ koff = a.koff;
+    T r[MAXA];
 #pragma unroll
-    for (int k = 0; k < MAXA; k++)
-        if (k < nA) a.sigma[s0 + k] = tot > T(0) ? Rn[k] * inv : uni;
+    for (int k = 0; k < MAXA; k++) r[k] = T(0);
+    for (int32_t cb = mbeg; cb < mend; cb += CHUNK) {
+        const int32_t ce = min(cb + CHUNK, mend);
+        bool in[MPT], first[MPT];
+        int32_t hn[MPT], st[MPT], sb[MPT], na[MPT];
+#pragma unroll
+        for (int u = 0; u < MPT; u++) {
+            const int32_t j = u * BLOCK + tid;
+            in[u] = cb + j < ce;
+            hn[u] = in[u] ? a.mnode[cb + j] : 0;
+            st[u] = in[u] ? (int32_t)L.mset[j] : 0;
+            sb[u] = L.slot[st[u]];
+            na[u] = in[u] ? L.slot[st[u] + 1] - sb[u] : 0;
+            first[u] = in[u] && cb + j == L.moff[st[u]];
+        }
+        T po[MPT], pw[MPT], cv[MPT][MAXA];
+#pragma unroll
+        for (int u = 0; u < MPT; u++) {
+            const int32_t h = hn[u] & MEMBER_NODE_MASK;
+            const bool p2 = (hn[u] & MEMBER_P2) != 0;
+            po[u] = in[u] ? (p2 ? r1[h] : r2[h]) : T(0);
+            pw[u] = first[u] ? (p2 ? r2[h] : r1[h]) : T(0);
+#pragma unroll
+            for (int k = 0; k < MAXA; k++)
+                if (k < na[u]) cv[u][k] = a.v[h + koff[sb[u] + k]];
+        }
+#pragma unroll
+        for (int u = 0; u < MPT; u++) {
+            if (!in[u]) continue;
+            const int32_t j = u * BLOCK + tid;
+            T vh = T(0);
+#pragma unroll
+            for (int k = 0; k < MAXA; k++)
+                if (k < na[u]) vh = fma_t(sig[sb[u] + k], cv[u][k], vh);
+            a.v[hn[u] & MEMBER_NODE_MASK] = vh;
+            L.po[j] = po[u];
+#pragma unroll
+            for (int k = 0; k < MAXA; k++)
+                if (k < na[u]) L.diff[j * MAXA + k] = cv[u][k] - vh;
+            if (first[u]) L.pown[st[u]] = pw[u];
+        }
+        __syncthreads();
+        if (has_set) {
+            const int32_t lo = max(m0, cb), hi = min(m1, ce);
+            for (int32_t k = lo - cb; k < hi - cb; k++) {
+                const T p = L.po[k];
+#pragma unroll
+                for (int q = 0; q < MAXA; q++)
+                    if (q < nA) r[q] = fma_t(p, L.diff[k * MAXA + q], r[q]);
+            }
+        }
+        __syncthreads();
+    }
+    if (!has_set) return;
+    if (!((ru.upd >> (pl - 1)) & 1)) return;
+    set_update<T, MAXA, EXT>(ru, a, s0, nA, pl, (double)L.pown[tid], r);
 }
 
 // One backward level fused with the update of its information sets, launched once per depth d
 // (deepest first): blocks [0, ngroups) take one update group each, the remaining blocks one thread
 // per internal chance node of the level.
-template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT>
+template <typename T, int MAXA, int MPT, bool EXPLICIT, bool AFF>
+using LevelLds = std::conditional_t<AFF, GroupLdsA<T, MAXA, MPT>, GroupLds<T, MAXA, MPT>>;
+
+template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT, bool AFF>
+__device__ __forceinline__ void update_group(int32_t g, const RuleArgs &ru, const LevelArgs<T> &a,
+                                             LevelLds<T, MAXA, MPT, EXPLICIT, AFF> &L) {
+    if constexpr (AFF) group_update_affine<T, MAXA, MPT, EXT>(g, ru, a, L);
+    else group_update<T, MAXA, MPT, EXPLICIT, EXT>(g, ru, a, L);
+}
+
+template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT, bool AFF>
 __global__ void __launch_bounds__(BLOCK) k_level(int32_t gbeg, int32_t ngroups, int32_t bbeg, int32_t nbig,
                                                  int32_t cbeg, int32_t nchance, LevelArgs<T> a,
                                                  const int32_t *__restrict__ tcount, int rule, int linear, int upd) {
-    __shared__ GroupLds<T, MAXA, MPT> L;
+    __shared__ LevelLds<T, MAXA, MPT, EXPLICIT, AFF> L;
     const int32_t blk = (int32_t)blockIdx.x;
     if (blk >= ngroups + nbig) {
         const int32_t j = (blk - ngroups - nbig) * BLOCK + (int32_t)threadIdx.x;
@@ -323,7 +461,7 @@ __global__ void __launch_bounds__(BLOCK) k_level(int32_t gbeg, int32_t ngroups, 
         return;
     }
     const RuleArgs ru = rule_args(rule, linear, upd, tcount[0]);
-    group_update<T, MAXA, MPT, EXPLICIT, EXT>(gbeg + (int32_t)blockIdx.x, ru, a, L);
+    update_group<T, MAXA, MPT, EXPLICIT, EXT, AFF>(gbeg + (int32_t)blockIdx.x, ru, a, L);
 }
 
 // Per-game barrier among the W blocks of one game.  Thread 0 publishes the block's writes
@@ -367,7 +505,7 @@ __device__ __forceinline__ bool game_barrier(int32_t *ctr, int32_t W, int32_t &e
 // backward level's update groups and chance nodes, meeting at a per-game barrier between levels;
 // games never wait for each other.  Iteration t0 + k (k = 1..T) uses the same arithmetic, in the
 // same order per set, as the level-synchronous kernels.  n_iter is the number of iterations.
-template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT>
+template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT, bool AFF>
 __global__ void __launch_bounds__(BLOCK) k_persistent(const int4 *__restrict__ wg_table,
                                                       const int32_t *__restrict__ game_range,
                                                       const int32_t *__restrict__ game_depth, int32_t MD, int32_t n_iter,
@@ -375,7 +513,7 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(const int4 *__restrict__ w
                                                       const int32_t *__restrict__ tcount, int32_t *barrier,
                                                       int32_t *err, int64_t timeout_ticks, int rule, int linear,
                                                       int alternating) {
-    __shared__ GroupLds<T, MAXA, MPT> L;
+    __shared__ LevelLds<T, MAXA, MPT, EXPLICIT, AFF> L;
     const int4 wt = wg_table[blockIdx.x];
     const int32_t gm = wt.x, rank = wt.y, W = wt.z;
     if (gm < 0) return;
@@ -396,7 +534,7 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(const int4 *__restrict__ w
             }
             for (int32_t d = Ds - 1; d >= 0; d--) {
                 const int32_t *r = gr + d * GR_FIELDS_DEV;
-                for (int32_t g = r[2] + rank; g < r[3]; g += W) group_update<T, MAXA, MPT, EXPLICIT, EXT>(g, ru, a, L);
+                for (int32_t g = r[2] + rank; g < r[3]; g += W) update_group<T, MAXA, MPT, EXPLICIT, EXT, AFF>(g, ru, a, L);
                 for (int32_t b = r[6] + rank; b < r[7]; b += W) big_chance_value<T, EXPLICIT>(a.bigc_node[b], a, L.po);
                 for (int32_t j = r[4] + rank * BLOCK + tid; j < r[5]; j += W * BLOCK) chance_value<T, EXPLICIT>(a.chance_node[j], a);
                 if (!game_barrier(barrier + gm, W, epoch, err, timeout_ticks)) return;
@@ -589,6 +727,7 @@ static LevelArgs<T> level_args(const DevGame &g) {
     a.grp_iset_off = g.grp_iset_off; a.slot_off = g.slot_off; a.mem_off = g.mem_off; a.mem = g.mem;
     a.iset_player = g.iset_player; a.kid_off = g.kid_off; a.kid = g.kid; a.chance_node = g.chance_node;
     a.bigc_node = g.bigc_node;
+    a.koff = g.koff; a.mnode = g.mnode;
     a.v = (T *)g.v;
     a.r1 = (T *)g.reach;
     a.r2 = (T *)g.reach + g.N;
@@ -597,103 +736,81 @@ static LevelArgs<T> level_args(const DevGame &g) {
     return a;
 }
 
-template <typename T, int MAXA, int MPT, bool EX, bool XT>
+template <typename T, int MAXA, int MPT, bool EX, bool XT, bool AF>
 static hipError_t level_t(const DevGame &g, int d, IterFlags f, hipStream_t s) {
     const int32_t gbeg = g.grp_depth_off[d], ng = g.grp_depth_off[d + 1] - gbeg;
     const int32_t cbeg = g.chance_off[d], nc = g.chance_off[d + 1] - cbeg;
     const int32_t bbeg = g.bigc_off[d], nb = g.bigc_off[d + 1] - bbeg;
     const unsigned blocks = (unsigned)ng + (unsigned)nb + grid_for(nc);
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_level<T, MAXA, MPT, EX, XT>), dim3(blocks), dim3(BLOCK), 0, s, gbeg, ng, bbeg, nb, cbeg, nc,
-                       level_args<T>(g), g.t, f.rule, f.linear, f.upd);
+    hipLaunchKernelGGL((k_level<T, MAXA, MPT, EX, XT, AF>), dim3(blocks), dim3(BLOCK), 0, s, gbeg, ng, bbeg, nb, cbeg,
+                       nc, level_args<T>(g), g.t, f.rule, f.linear, f.upd);
     return hipGetLastError();
 }
 
 // the discounted and predictive rules get their own instantiation, so CFR and CFR+ keep a lean update
 inline bool ext_rule(int rule) { return rule == CFR_RULE_DCFR || rule == CFR_RULE_PCFR_PLUS; }
 
-template <typename T, bool EX, bool XT>
-static hipError_t level_dispatch_xt(const DevGame &g, int d, IterFlags f, hipStream_t s) {
-    // members per thread must match the group capacity the compiler used (group_members)
-    if (g.max_actions <= 4) return level_t<T, 4, 2, EX, XT>(g, d, f, s);
-    if (g.max_actions <= 16) return level_t<T, 16, 1, EX, XT>(g, d, f, s);
-    return level_t<T, 64, 1, EX, XT>(g, d, f, s);
+// Instantiation selector shared by the level and persistent launches: state type, action bound
+// (members per thread must match the group capacity the compiler used, group_members), child
+// addressing (implicit, explicit, affine) and rule class.
+template <typename T, bool EX, bool XT, bool AF, typename F>
+static auto by_actions(const DevGame &g, F &&f) {
+    if (g.max_actions <= 4) return f.template operator()<T, 4, 2, EX, XT, AF>();
+    if (g.max_actions <= 16) return f.template operator()<T, 16, 1, EX, XT, AF>();
+    return f.template operator()<T, 64, 1, EX, XT, AF>();
 }
 
-template <typename T, bool EX>
-static hipError_t level_dispatch_ex(const DevGame &g, int d, IterFlags f, hipStream_t s) {
-    return ext_rule(f.rule) ? level_dispatch_xt<T, EX, true>(g, d, f, s) : level_dispatch_xt<T, EX, false>(g, d, f, s);
+template <typename T, typename F>
+static auto by_kind(const DevGame &g, int rule, F &&f) {
+    const bool x = ext_rule(rule);
+    if (g.affine) return x ? by_actions<T, true, true, true>(g, f) : by_actions<T, true, false, true>(g, f);
+    if (g.explicit_kids) return x ? by_actions<T, true, true, false>(g, f) : by_actions<T, true, false, false>(g, f);
+    return x ? by_actions<T, false, true, false>(g, f) : by_actions<T, false, false, false>(g, f);
 }
 
-template <typename T>
-static hipError_t level_dispatch(const DevGame &g, int d, IterFlags f, hipStream_t s) {
-    return g.explicit_kids ? level_dispatch_ex<T, true>(g, d, f, s) : level_dispatch_ex<T, false>(g, d, f, s);
-}
+struct LevelLaunch {
+    const DevGame &g; int d; IterFlags f; hipStream_t s;
+    template <typename T, int MAXA, int MPT, bool EX, bool XT, bool AF>
+    hipError_t operator()() const { return level_t<T, MAXA, MPT, EX, XT, AF>(g, d, f, s); }
+};
 
 hipError_t launch_level(const DevGame &g, int d, IterFlags f, hipStream_t s) {
-    return g.fp64 ? level_dispatch<double>(g, d, f, s) : level_dispatch<float>(g, d, f, s);
+    const LevelLaunch L{g, d, f, s};
+    return g.fp64 ? by_kind<double>(g, f.rule, L) : by_kind<float>(g, f.rule, L);
 }
 
-template <typename T, int MAXA, int MPT, bool EX, bool XT>
-static const void *persistent_fn() {
-    return reinterpret_cast<const void *>(&k_persistent<T, MAXA, MPT, EX, XT>);
-}
-
-template <typename T, int MAXA, int MPT, bool EX, bool XT>
-static hipError_t persistent_t(const DevGame &g, const PersistentPlan &p, int32_t T_, IterFlags f, int alt,
-                               hipStream_t s) {
-    hipLaunchKernelGGL((k_persistent<T, MAXA, MPT, EX, XT>), dim3(p.blocks), dim3(BLOCK), 0, s, p.wg_table,
-                       p.game_range, p.game_depth, p.max_depth, T_, g.up, level_args<T>(g), g.t, p.barrier, p.err,
-                       p.timeout_ticks, f.rule, f.linear, alt);
-    return hipGetLastError();
-}
-
-template <typename T, bool EX, bool XT>
-static hipError_t persistent_dispatch_xt(const DevGame &g, const PersistentPlan &p, int32_t T_, IterFlags f,
-                                         int alt, hipStream_t s) {
-    if (g.max_actions <= 4) return persistent_t<T, 4, 2, EX, XT>(g, p, T_, f, alt, s);
-    if (g.max_actions <= 16) return persistent_t<T, 16, 1, EX, XT>(g, p, T_, f, alt, s);
-    return persistent_t<T, 64, 1, EX, XT>(g, p, T_, f, alt, s);
-}
-
-template <typename T, bool EX>
-static hipError_t persistent_dispatch_ex(const DevGame &g, const PersistentPlan &p, int32_t T_, IterFlags f,
-                                         int alt, hipStream_t s) {
-    return ext_rule(f.rule) ? persistent_dispatch_xt<T, EX, true>(g, p, T_, f, alt, s)
-                            : persistent_dispatch_xt<T, EX, false>(g, p, T_, f, alt, s);
-}
+struct PersistentLaunch {
+    const DevGame &g; const PersistentPlan &p; int32_t T_; IterFlags f; int alt; hipStream_t s;
+    template <typename T, int MAXA, int MPT, bool EX, bool XT, bool AF>
+    hipError_t operator()() const {
+        hipLaunchKernelGGL((k_persistent<T, MAXA, MPT, EX, XT, AF>), dim3(p.blocks), dim3(BLOCK), 0, s, p.wg_table,
+                           p.game_range, p.game_depth, p.max_depth, T_, g.up, level_args<T>(g), g.t, p.barrier,
+                           p.err, p.timeout_ticks, f.rule, f.linear, alt);
+        return hipGetLastError();
+    }
+};
 
 hipError_t launch_persistent(const DevGame &g, const PersistentPlan &p, int32_t T_, IterFlags f, int alt,
                              hipStream_t s) {
     hipLaunchKernelGGL(k_fill_int, dim3((p.n_games + 255) / 256), dim3(256), 0, s, p.n_games, p.barrier, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (g.fp64) e = g.explicit_kids ? persistent_dispatch_ex<double, true>(g, p, T_, f, alt, s)
-                                    : persistent_dispatch_ex<double, false>(g, p, T_, f, alt, s);
-    else e = g.explicit_kids ? persistent_dispatch_ex<float, true>(g, p, T_, f, alt, s)
-                             : persistent_dispatch_ex<float, false>(g, p, T_, f, alt, s);
+    const PersistentLaunch L{g, p, T_, f, alt, s};
+    e = g.fp64 ? by_kind<double>(g, f.rule, L) : by_kind<float>(g, f.rule, L);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_add_counter, dim3(1), dim3(64), 0, s, g.t, T_);
     return hipGetLastError();
 }
 
-template <typename T, bool EX, bool XT>
-static const void *persistent_fn_for(const DevGame &g) {
-    if (g.max_actions <= 4) return persistent_fn<T, 4, 2, EX, XT>();
-    if (g.max_actions <= 16) return persistent_fn<T, 16, 1, EX, XT>();
-    return persistent_fn<T, 64, 1, EX, XT>();
-}
-
-template <typename T>
-static const void *persistent_fn_t(const DevGame &g) {
-    const bool x = ext_rule(g.rule);
-    if (g.explicit_kids) return x ? persistent_fn_for<T, true, true>(g) : persistent_fn_for<T, true, false>(g);
-    return x ? persistent_fn_for<T, false, true>(g) : persistent_fn_for<T, false, false>(g);
-}
+struct PersistentFn {
+    template <typename T, int MAXA, int MPT, bool EX, bool XT, bool AF>
+    const void *operator()() const { return reinterpret_cast<const void *>(&k_persistent<T, MAXA, MPT, EX, XT, AF>); }
+};
 
 // the instantiation launch_persistent uses for this game
 hipError_t persistent_occupancy(const DevGame &g, int *blocks_per_cu) {
-    const void *fn = g.fp64 ? persistent_fn_t<double>(g) : persistent_fn_t<float>(g);
+    const void *fn = g.fp64 ? by_kind<double>(g, g.rule, PersistentFn{}) : by_kind<float>(g, g.rule, PersistentFn{});
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, BLOCK, 0);
 }
 

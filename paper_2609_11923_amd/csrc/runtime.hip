@@ -221,7 +221,9 @@ void model_bytes(cfr_handle *h, const DeviceLayout &D) {
         // decision members: id, edge offset, value write, opponent reach; edges: child (index), value;
         // sets: member and slot offsets, player, own reach; slots: sigma read + write, R read + write,
         // sbar read + write
-        lv += (8 + 2 * es) * Md[d] + (kb + es) * Ed[d] + (9 + es) * Id[d] + (4 * es + 16) * Ad[d];
+        // (affine layouts: a 4-byte member record, no child index per edge, one offset per slot)
+        if (h->g.affine) lv += (4 + 2 * es) * Md[d] + es * Ed[d] + (9 + es) * Id[d] + (4 * es + 20) * Ad[d];
+        else lv += (8 + 2 * es) * Md[d] + (kb + es) * Ed[d] + (9 + es) * Id[d] + (4 * es + 16) * Ad[d];
         // chance nodes: list entry, edge offset, value write; edges: child (index), value
         for (int32_t j = D.chance_off[d]; j < D.chance_off[d + 1]; j++) {
             const int32_t x = D.chance_node[j];
@@ -328,6 +330,7 @@ void cfr_default_options(cfr_options *o) {
     o->persistent = 0;
     o->wg_nodes = 0;
     o->lifecycle = 0;
+    o->affine = 1;
 }
 
 const char *cfr_last_error(void) { return g_err.c_str(); }
@@ -643,6 +646,8 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     g.rule = o.rule;
     g.explicit_kids = DL.explicit_kids ? 1 : 0;
     h->es = g.fp64 ? 8 : 4;
+    std::vector<int32_t> koff;
+    g.affine = o.affine && slot_child_offsets(DL, koff) ? 1 : 0;
 
     std::vector<int2> up((size_t)N);
     for (int64_t k = 0; k < N; k++) up[k] = make_int2(DL.up_parent[k], DL.up_code[k]);
@@ -659,6 +664,10 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     ALLOC(g.slot_off, I + 1);
     ALLOC(g.mem_off, I + 1);
     ALLOC(g.mem, Ndec);
+    if (g.affine) {
+        ALLOC(g.koff, A > 0 ? A : 1);
+        ALLOC(g.mnode, Ndec > 0 ? Ndec : 1);
+    }
     ALLOC(g.iset_player, I);
     g.G = (int32_t)DL.grp_iset_off.size() - 1;
     ALLOC(g.grp_iset_off, (int64_t)DL.grp_iset_off.size());
@@ -708,6 +717,10 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
         for (int64_t k = 0; k < Ndec; k++)
             mem[k] = make_int2(DL.mem_node[k], DL.kid_off[DL.mem_node[k] & MEMBER_NODE_MASK]);
         UP(g.mem, mem);
+    }
+    if (g.affine) {
+        UP(g.koff, koff);
+        UP(g.mnode, DL.mem_node);
     }
     UP(g.iset_player, DL.iset_player);
     UP(g.grp_iset_off, DL.grp_iset_off);
@@ -982,6 +995,7 @@ cfr_status cfr_counts(cfr_handle *h, cfr_counts_t *c) {
     c->infosets = h->g.I; c->slots = h->g.A; c->max_depth = h->g.max_depth; c->blocks = h->D;
     c->max_actions = h->g.max_actions; c->br_supported = h->br_ok ? 1 : 0;
     c->device_bytes = h->device_bytes; c->kernels_per_iteration = h->launches; c->pot = h->pot;
+    c->child_addressing = h->g.affine ? 2 : h->g.explicit_kids ? 1 : 0;
     return CFR_OK;
 }
 
