@@ -107,7 +107,19 @@ template <typename T, bool EXPLICIT>
 __device__ __forceinline__ void chance_value(int32_t h, const LevelArgs<T> &a) {
     const int32_t b = a.kid_off[h], e = a.kid_off[h + 1];
     T acc = T(0);
-    for (int32_t c = b; c < e; c++) acc += a.v[child_of<EXPLICIT>(a.kid, c)];
+    // eight children per step, loads unconditional (past the last child they repeat it) so they
+    // are in flight together; the sum keeps child order
+    constexpr int U = 8;
+    for (int32_t c0 = b; c0 < e; c0 += U) {
+        int32_t ch[U];
+        T x[U];
+#pragma unroll
+        for (int i = 0; i < U; i++) ch[i] = child_of<EXPLICIT>(a.kid, min(c0 + i, e - 1));
+#pragma unroll
+        for (int i = 0; i < U; i++) x[i] = a.v[ch[i]];
+#pragma unroll
+        for (int i = 0; i < U; i++) acc = c0 + i < e ? acc + x[i] : acc;
+    }
     a.v[h] = acc;
 }
 
@@ -208,13 +220,14 @@ __device__ __forceinline__ void set_update_from(const RuleArgs &ru, const LevelA
 template <typename T, int MAXA>
 __device__ __forceinline__ void load_set_state(const LevelArgs<T> &a, int32_t s0, int32_t nA, T (&Rk)[MAXA],
                                                T (&sk)[MAXA], double (&sb)[MAXA]) {
+    // unconditional loads (past the last action they repeat it): all in flight at once
 #pragma unroll
-    for (int k = 0; k < MAXA; k++)
-        if (k < nA) {
-            Rk[k] = a.R[s0 + k];
-            sk[k] = a.sigma[s0 + k];
-            sb[k] = a.sbar[s0 + k];
-        }
+    for (int k = 0; k < MAXA; k++) {
+        const int32_t q = s0 + min(k, nA - 1);
+        Rk[k] = a.R[q];
+        sk[k] = a.sigma[q];
+        sb[k] = a.sbar[q];
+    }
 }
 
 template <typename T, int MAXA, bool EXT>
@@ -230,7 +243,7 @@ __device__ __forceinline__ void set_update(const RuleArgs &ru, const LevelArgs<T
 template <typename T, int MAXA, int MPT>
 struct GroupLds {
     T po[MPT * BLOCK];
-    T diff[MPT * BLOCK * MAXA];
+    alignas(16) T diff[MPT * BLOCK * MAXA];
     int32_t moff[BLOCK + 1];
     int32_t slot[BLOCK + 1];
 };
@@ -277,44 +290,54 @@ __device__ void group_update(int32_t g, const RuleArgs &ru, const LevelArgs<T> &
     for (int k = 0; k < MAXA; k++) r[k] = T(0);
     for (int32_t cb = mbeg; cb < mend; cb += CHUNK) {
         const int32_t ce = min(cb + CHUNK, mend);
+        // loads first and unconditional (past the chunk's end a lane repeats its first member, past
+        // a set's last action the last child and slot), then the arithmetic and the masked stores
+        bool in[MPT];
+        int32_t sb[MPT], na[MPT], hh[MPT];
+        T po[MPT], sg[MPT][MAXA], cv[MPT][MAXA];
 #pragma unroll
         for (int u = 0; u < MPT; u++) {
             const int32_t j = u * BLOCK + tid;
-            const int32_t m = cb + j;
-            if (m < ce) {
-                // the set of member m: the last k with moff[k] <= m
-                int32_t lo = 0, hi = nsets - 1;
-                while (lo < hi) {
-                    const int32_t mid = (lo + hi + 1) >> 1;
-                    if (L.moff[mid] <= m) lo = mid; else hi = mid - 1;
-                }
-                const int32_t sb = L.slot[lo], na = L.slot[lo + 1] - sb;
-                const int2 x = a.mem[m];
-                const int32_t h = x.x & MEMBER_NODE_MASK;
-                const T po = (x.x & MEMBER_P2) ? a.r1[h] : a.r2[h];
-                T cv[MAXA];
-                T vh = T(0);
-#pragma unroll
-                for (int k = 0; k < MAXA; k++)
-                    if (k < na) cv[k] = a.v[child_of<EXPLICIT>(a.kid, x.y + k)];
-#pragma unroll
-                for (int k = 0; k < MAXA; k++)
-                    if (k < na) vh = fma_t(a.sigma[sb + k], cv[k], vh);
-                a.v[h] = vh;
-                L.po[j] = po;
-#pragma unroll
-                for (int k = 0; k < MAXA; k++)
-                    if (k < na) L.diff[j * MAXA + k] = cv[k] - vh;
+            in[u] = cb + j < ce;
+            const int32_t m = cb + (in[u] ? j : 0);
+            // the set of member m: the last k with moff[k] <= m
+            int32_t lo = 0, hi = nsets - 1;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (L.moff[mid] <= m) lo = mid; else hi = mid - 1;
             }
+            sb[u] = L.slot[lo];
+            na[u] = L.slot[lo + 1] - sb[u];
+            const int2 x = a.mem[m];
+            hh[u] = x.x & MEMBER_NODE_MASK;
+            po[u] = ((x.x & MEMBER_P2) ? a.r1 : a.r2)[hh[u]];
+#pragma unroll
+            for (int k = 0; k < MAXA; k++) {
+                const int32_t kk = min(k, na[u] - 1);
+                cv[u][k] = a.v[child_of<EXPLICIT>(a.kid, x.y + kk)];
+                sg[u][k] = a.sigma[sb[u] + kk];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < MPT; u++) {
+            T vh = T(0);
+#pragma unroll
+            for (int k = 0; k < MAXA; k++) vh = k < na[u] ? fma_t(sg[u][k], cv[u][k], vh) : vh;
+            if (!in[u]) continue;
+            const int32_t j = u * BLOCK + tid;
+            a.v[hh[u]] = vh;
+            L.po[j] = po[u];
+#pragma unroll
+            for (int k = 0; k < MAXA; k++) L.diff[j * MAXA + k] = cv[u][k] - vh;
         }
         __syncthreads();
         if (has_set) {
             const int32_t lo = max(m0, cb), hi = min(m1, ce);
             for (int32_t k = lo - cb; k < hi - cb; k++) {
-                const T po = L.po[k];
+                const T p = L.po[k];
+                // every column: past the set's actions they hold repeats, never read afterwards
 #pragma unroll
-                for (int q = 0; q < MAXA; q++)
-                    if (q < nA) r[q] = fma_t(po, L.diff[k * MAXA + q], r[q]);
+                for (int q = 0; q < MAXA; q++) r[q] = fma_t(p, L.diff[k * MAXA + q], r[q]);
             }
         }
         __syncthreads();
@@ -326,13 +349,12 @@ __device__ void group_update(int32_t g, const RuleArgs &ru, const LevelArgs<T> &
     set_update<T, MAXA, EXT>(ru, a, s0, nA, pl, (double)own[a.mem[m0].x & MEMBER_NODE_MASK], r);
 }
 
-// LDS staging of one update group in an affine layout: the set offsets, the set of each member
-// of the chunk and each set's own reach, besides the member values of group_update
+// LDS staging of one update group in an affine layout: the set offsets and the set of each member
+// of the chunk, besides the member values of group_update
 template <typename T, int MAXA, int MPT>
 struct GroupLdsA {
     T po[MPT * BLOCK];
-    T diff[MPT * BLOCK * MAXA];
-    T pown[BLOCK];
+    alignas(16) T diff[MPT * BLOCK * MAXA];
     int32_t moff[BLOCK + 1];
     int32_t slot[BLOCK + 1];
     uint8_t mset[MPT * BLOCK];
@@ -340,9 +362,13 @@ struct GroupLdsA {
 
 // group_update for affine layouts (child a of member h is h + koff[slot a]): the same arithmetic
 // in the same order, so the results are bitwise those of group_update.  What changes is the load
-// chain of a member: its compact record and the set's offsets (from the member -> set map in LDS,
-// no search) are independent loads, the child values follow them, and every load of a chunk is
-// issued before its stores; the first member of each set also stages the set's own reach.
+// chain.  A member's compact record and its set's offsets and strategy (the set from the member ->
+// set map in LDS, no search) are independent loads and the child values follow them.  Loads are
+// unconditional: past a set's last action they repeat its last slot and child (an address already
+// read, no new traffic) and lanes past the chunk's end repeat its first member, so every load of a
+// chunk is in flight at once instead of one guarded load and wait per action; only the stores and
+// the arithmetic are masked.  Each set thread fetches its own reach through its first member beside
+// the member loads.
 template <typename T, int MAXA, int MPT, bool EXT>
 __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelArgs<T> &a,
                                     GroupLdsA<T, MAXA, MPT> &L) {
@@ -352,13 +378,12 @@ __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelAr
     const int32_t nsets = i1 - i0;
     const int32_t mbeg = a.mem_off[i0], mend = a.mem_off[i1];
     const bool has_set = tid < nsets;
-    int32_t s0 = 0, nA = 0, m0 = 0, m1 = 0, pl = 1;
+    const int32_t ti = i0 + (has_set ? tid : nsets - 1);
+    const int32_t m0 = a.mem_off[ti], m1 = a.mem_off[ti + 1];
+    const int32_t s0 = a.slot_off[ti], nA = a.slot_off[ti + 1] - s0;
+    const int pl = a.iset_player[ti];
+    const int32_t h0 = a.mnode[m0] & MEMBER_NODE_MASK;
     if (has_set) {
-        m0 = a.mem_off[i0 + tid];
-        m1 = a.mem_off[i0 + tid + 1];
-        s0 = a.slot_off[i0 + tid];
-        nA = a.slot_off[i0 + tid + 1] - s0;
-        pl = a.iset_player[i0 + tid];
         L.moff[tid] = m0;
         L.slot[tid] = s0;
         if (tid == nsets - 1) L.slot[nsets] = s0 + nA;
@@ -372,69 +397,68 @@ __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelAr
     const T *__restrict__ r2 = a.r2;
     const T *__restrict__ sig = a.sigma;
     const int32_t *__restrict__ koff = a.koff;
+    const T pown = (pl == 1 ? r1 : r2)[h0];
     T r[MAXA];
 #pragma unroll
     for (int k = 0; k < MAXA; k++) r[k] = T(0);
     for (int32_t cb = mbeg; cb < mend; cb += CHUNK) {
         const int32_t ce = min(cb + CHUNK, mend);
-        bool in[MPT], first[MPT];
-        int32_t hn[MPT], st[MPT], sb[MPT], na[MPT];
+        bool in[MPT];
+        int32_t hn[MPT], sb[MPT], na[MPT];
 #pragma unroll
         for (int u = 0; u < MPT; u++) {
             const int32_t j = u * BLOCK + tid;
             in[u] = cb + j < ce;
-            hn[u] = in[u] ? a.mnode[cb + j] : 0;
-            st[u] = in[u] ? (int32_t)L.mset[j] : 0;
-            sb[u] = L.slot[st[u]];
-            na[u] = in[u] ? L.slot[st[u] + 1] - sb[u] : 0;
-            first[u] = in[u] && cb + j == L.moff[st[u]];
+            const int32_t jj = in[u] ? j : 0;
+            hn[u] = a.mnode[cb + jj];
+            const int32_t st = L.mset[jj];
+            sb[u] = L.slot[st];
+            na[u] = L.slot[st + 1] - sb[u];
         }
-        T po[MPT], pw[MPT], cv[MPT][MAXA];
+        T po[MPT], sg[MPT][MAXA], cv[MPT][MAXA];
 #pragma unroll
         for (int u = 0; u < MPT; u++) {
             const int32_t h = hn[u] & MEMBER_NODE_MASK;
-            const bool p2 = (hn[u] & MEMBER_P2) != 0;
-            po[u] = in[u] ? (p2 ? r1[h] : r2[h]) : T(0);
-            pw[u] = first[u] ? (p2 ? r2[h] : r1[h]) : T(0);
+            po[u] = ((hn[u] & MEMBER_P2) ? r1 : r2)[h];
+            int32_t ko[MAXA];
 #pragma unroll
-            for (int k = 0; k < MAXA; k++)
-                if (k < na[u]) cv[u][k] = a.v[h + koff[sb[u] + k]];
+            for (int k = 0; k < MAXA; k++) {
+                const int32_t q = sb[u] + min(k, na[u] - 1);
+                ko[k] = koff[q];
+                sg[u][k] = sig[q];
+            }
+#pragma unroll
+            for (int k = 0; k < MAXA; k++) cv[u][k] = a.v[h + ko[k]];
         }
 #pragma unroll
         for (int u = 0; u < MPT; u++) {
-            if (!in[u]) continue;
-            const int32_t j = u * BLOCK + tid;
             T vh = T(0);
 #pragma unroll
-            for (int k = 0; k < MAXA; k++)
-                if (k < na[u]) vh = fma_t(sig[sb[u] + k], cv[u][k], vh);
+            for (int k = 0; k < MAXA; k++) vh = k < na[u] ? fma_t(sg[u][k], cv[u][k], vh) : vh;
+            if (!in[u]) continue;
+            const int32_t j = u * BLOCK + tid;
             a.v[hn[u] & MEMBER_NODE_MASK] = vh;
             L.po[j] = po[u];
 #pragma unroll
-            for (int k = 0; k < MAXA; k++)
-                if (k < na[u]) L.diff[j * MAXA + k] = cv[u][k] - vh;
-            if (first[u]) L.pown[st[u]] = pw[u];
+            for (int k = 0; k < MAXA; k++) L.diff[j * MAXA + k] = cv[u][k] - vh;
         }
         __syncthreads();
         if (has_set) {
             const int32_t lo = max(m0, cb), hi = min(m1, ce);
             for (int32_t k = lo - cb; k < hi - cb; k++) {
                 const T p = L.po[k];
+                // every column: past the set's actions they hold repeats, never read afterwards
 #pragma unroll
-                for (int q = 0; q < MAXA; q++)
-                    if (q < nA) r[q] = fma_t(p, L.diff[k * MAXA + q], r[q]);
+                for (int q = 0; q < MAXA; q++) r[q] = fma_t(p, L.diff[k * MAXA + q], r[q]);
             }
         }
         __syncthreads();
     }
     if (!has_set) return;
     if (!((ru.upd >> (pl - 1)) & 1)) return;
-    set_update<T, MAXA, EXT>(ru, a, s0, nA, pl, (double)L.pown[tid], r);
+    set_update<T, MAXA, EXT>(ru, a, s0, nA, pl, (double)pown, r);
 }
 
-// One backward level fused with the update of its information sets, launched once per depth d
-// (deepest first): blocks [0, ngroups) take one update group each, the remaining blocks one thread
-// per internal chance node of the level.
 template <typename T, int MAXA, int MPT, bool EXPLICIT, bool AFF>
 using LevelLds = std::conditional_t<AFF, GroupLdsA<T, MAXA, MPT>, GroupLds<T, MAXA, MPT>>;
 
