@@ -240,7 +240,8 @@ inline int32_t edge_code(int owner, bool internal, int32_t slot) {
 }
 }  // namespace
 
-cfr_status build_device_layout(const Layout &L, int kind, int group_actions, DeviceLayout &D, std::string &err) {
+cfr_status build_device_layout(const Layout &L, int kind, int group_actions, bool fp64, DeviceLayout &D,
+                               std::string &err) {
     try {
         const int64_t N = L.N, I = L.I, A = L.A;
         const int md = L.max_depth;
@@ -379,7 +380,7 @@ cfr_status build_device_layout(const Layout &L, int kind, int group_actions, Dev
         // update groups in device information-set order, never spanning two depths
         D.grp_iset_off.assign(1, 0);
         D.grp_depth_off.assign((size_t)md + 2, 0);
-        const int32_t cap = group_members(group_actions > L.max_actions ? group_actions : L.max_actions);
+        const int32_t cap = group_members(group_actions > L.max_actions ? group_actions : L.max_actions, fp64);
         for (int d = 0; d <= md; d++) {
             int32_t members = 0, sets = 0;
             for (int32_t i = D.iset_depth_off[d]; i < D.iset_depth_off[d + 1]; i++) {

@@ -98,12 +98,14 @@ constexpr int GR_FIELDS = 8;  // node lo/hi, group lo/hi, chance lo/hi, big chan
 constexpr int BIG_FANOUT = 64;
 
 constexpr int GROUP_SETS = 256;
-// members per update group: two per thread of a 256-thread block when sets have at most 4 actions,
-// else one (four per thread measured slower for FP32 state: the registers cut the resident waves)
-inline int group_members(int max_actions) { return max_actions <= 4 ? 512 : 256; }
+// members per update group (members per thread times the 256-thread block): with at most 4 actions
+// per set four per thread for FP32 state and two for FP64 (whose LDS staging is twice as large),
+// else one.  The update kernels' members per thread must match.
+inline int group_members(int max_actions, bool fp64) { return max_actions <= 4 ? (fp64 ? 512 : 1024) : 256; }
 
-// group_actions: the action bound the update groups are sized for (>= L.max_actions)
-cfr_status build_device_layout(const Layout &L, int layout_kind, int group_actions, DeviceLayout &out,
+// group_actions: the action bound the update groups are sized for (>= L.max_actions); fp64: the state
+// type of the kernels, which sets the group capacity (group_members)
+cfr_status build_device_layout(const Layout &L, int layout_kind, int group_actions, bool fp64, DeviceLayout &out,
                                std::string &err);
 
 // Affine children: in an explicit layout, when every member h of every information set reaches its

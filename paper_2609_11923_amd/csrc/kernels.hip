@@ -52,13 +52,38 @@ __device__ __forceinline__ void forward_node(int32_t c, const int2 *__restrict__
     r2[c] = owner == 2 ? b * s : b;
 }
 
+// nodes per thread of k_forward
+constexpr int FWD_NPT = 4;
+
+// One forward level, FWD_NPT nodes per thread (strided by the block size, so each wave's accesses
+// stay contiguous): all edge codes are loaded first, then all parent reaches and strategies, with
+// the strategy load unconditional (chance parents carry slot 0, a valid address) and only the
+// stores masked, so a thread keeps every load of its nodes in flight together.
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_forward(int32_t lo, int32_t hi, const int2 *__restrict__ up,
                                                    const T *__restrict__ sigma, T *__restrict__ r1,
                                                    T *__restrict__ r2, int32_t *tick) {
     if (tick && blockIdx.x == 0 && threadIdx.x == 0) tick[0] += 1;
-    const int32_t c = lo + (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
-    if (c < hi) forward_node<T>(c, up, sigma, r1, r2);
+    if (hi <= lo) return;
+    const int32_t base = lo + (int32_t)blockIdx.x * (BLOCK * FWD_NPT) + (int32_t)threadIdx.x;
+    int2 u[FWD_NPT];
+#pragma unroll
+    for (int i = 0; i < FWD_NPT; i++) u[i] = up[min(base + i * BLOCK, hi - 1)];
+    T sv[FWD_NPT], a[FWD_NPT], b[FWD_NPT];
+#pragma unroll
+    for (int i = 0; i < FWD_NPT; i++) {
+        sv[i] = sigma[u[i].y >> CODE_SLOT_SHIFT];
+        a[i] = r1[u[i].x];
+        b[i] = r2[u[i].x];
+    }
+#pragma unroll
+    for (int i = 0; i < FWD_NPT; i++) {
+        const int32_t c = base + i * BLOCK;
+        if (c >= hi || !(u[i].y & CODE_INTERNAL)) continue;
+        const int owner = u[i].y & CODE_OWNER_MASK;
+        r1[c] = owner == 1 ? a[i] * sv[i] : a[i];
+        r2[c] = owner == 2 ? b[i] * sv[i] : b[i];
+    }
 }
 
 // Arrays read and written by the backward/update level.
@@ -734,7 +759,8 @@ __global__ void __launch_bounds__(BLOCK) k_br_backward(int32_t lo, int32_t hi, c
 template <typename T>
 static hipError_t forward_t(const DevGame &g, int32_t lo, int32_t hi, int32_t *tick, hipStream_t s) {
     T *r = (T *)g.reach;
-    const unsigned blocks = hi > lo ? grid_for(hi - lo) : 1u;   // one block still runs the counter bump
+    // one block still runs the counter bump
+    const unsigned blocks = hi > lo ? (unsigned)((hi - lo + BLOCK * FWD_NPT - 1) / (BLOCK * FWD_NPT)) : 1u;
     hipLaunchKernelGGL(k_forward<T>, dim3(blocks), dim3(BLOCK), 0, s, lo, hi, g.up, (const T *)g.sigma, r,
                        r + g.N, tick);
     return hipGetLastError();
@@ -776,11 +802,12 @@ static hipError_t level_t(const DevGame &g, int d, IterFlags f, hipStream_t s) {
 inline bool ext_rule(int rule) { return rule == CFR_RULE_DCFR || rule == CFR_RULE_PCFR_PLUS; }
 
 // Instantiation selector shared by the level and persistent launches: state type, action bound
-// (members per thread must match the group capacity the compiler used, group_members), child
-// addressing (implicit, explicit, affine) and rule class.
+// (members per thread must match the group capacity the compiler used, group_members: four for
+// FP32 state with at most 4 actions, two for FP64, else one), child addressing (implicit,
+// explicit, affine) and rule class.
 template <typename T, bool EX, bool XT, bool AF, typename F>
 static auto by_actions(const DevGame &g, F &&f) {
-    if (g.max_actions <= 4) return f.template operator()<T, 4, 2, EX, XT, AF>();
+    if (g.max_actions <= 4) return f.template operator()<T, 4, sizeof(T) == 4 ? 4 : 2, EX, XT, AF>();
     if (g.max_actions <= 16) return f.template operator()<T, 16, 1, EX, XT, AF>();
     return f.template operator()<T, 64, 1, EX, XT, AF>();
 }

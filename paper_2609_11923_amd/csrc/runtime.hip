@@ -603,7 +603,7 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     {
         std::vector<DeviceLayout> Ds((size_t)n);
         for (int s = 0; s < n; s++) {
-            st = build_device_layout(Ls[s], o.layout, max_actions, Ds[s], err);
+            st = build_device_layout(Ls[s], o.layout, max_actions, o.precision == CFR_PRECISION_FP64, Ds[s], err);
             if (st != CFR_OK) return fail(st, err);
             if (o.lifecycle) lifecycle_records(games[s], Ls[s], Ds[s], lc);
             if (n > 1) Ls[s] = Layout();  // free the canonical arrays early
