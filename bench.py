@@ -293,6 +293,43 @@ def measure_game(cfr, torch, game, args, precision, log):
 WARM_RULES = {}
 
 
+def run_tiny(cfr, torch, log, iters=2000):
+    """Tiny standalone games under the level schedule (graph replay, one launch per depth level) and
+    the LDS schedule (one workgroup, the whole iteration in LDS, one launch per call): time per
+    iteration over `iters` iterations on a fresh handle after a warm-up call of the same length."""
+    import gamegen as gg
+    games = [("kuhn", gg.kuhn(), cfr.CFR_PRECISION_FP32), ("kuhn", gg.kuhn(), cfr.CFR_PRECISION_FP64),
+             ("leduc3x2", gg.leduc(3, 2), cfr.CFR_PRECISION_FP32), ("random7", gg.random_game(7, 4, 3, 6),
+                                                                   cfr.CFR_PRECISION_FP32)]
+    out = []
+    for name, g, prec in games:
+        row = {"game": name, "precision": "fp64" if prec == cfr.CFR_PRECISION_FP64 else "fp32",
+               "nodes": int(len(g.type))}
+        for sched, key in ((cfr.CFR_SCHEDULE_LEVEL, "level"), (cfr.CFR_SCHEDULE_LDS, "lds")):
+            try:
+                s = cfr.Solver(g, precision=prec, persistent=sched)
+            except cfr.CfrError as e:
+                row[key + "_ms_per_iteration"] = None
+                row[key + "_error"] = str(e)
+                continue
+            st = torch.cuda.Stream()
+            s.iterate(iters, stream=st)
+            st.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            s.iterate(iters, stream=st)
+            e1.record(st)
+            e1.synchronize()
+            row[key + "_ms_per_iteration"] = e0.elapsed_time(e1) / iters
+            s.close()
+        if row.get("level_ms_per_iteration") and row.get("lds_ms_per_iteration"):
+            row["speedup"] = row["level_ms_per_iteration"] / row["lds_ms_per_iteration"]
+        log(f"[tiny] {row}")
+        out.append(row)
+    return out
+
+
 def run_warm(cfr, torch, args, log):
     """Learned warm start: train the network on average strategies of solved subgames (their own
     payoff seeds, so nothing about the test payoffs can be memorised), pick the regret scale on a
@@ -419,6 +456,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-subgame measurement")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm-start measurement")
     ap.add_argument("--no-rules", action="store_true", help="skip the update-rule comparison on the batch")
+    ap.add_argument("--no-tiny", action="store_true", help="skip the tiny-game schedule comparison")
     ap.add_argument("--warm-train-games", type=int, default=2000)
     ap.add_argument("--warm-train-hi", type=float, default=1e6, help="largest training subgame (edges)")
     ap.add_argument("--warm-target-iters", type=int, default=500)
@@ -518,6 +556,8 @@ def main():
             out["batch"]["rules"] = run_rules(cfr, torch, games, log)
         out["batch"]["lifecycle"] = run_lifecycle(cfr, torch, games, bspecs, log)
         del games
+    if not args.no_tiny:
+        out["tiny_games"] = run_tiny(cfr, torch, log)
     if not args.no_warm:
         out["warm_start"] = run_warm(cfr, torch, args, log)
     if not args.no_cpu_baseline:

@@ -102,6 +102,17 @@ enum { CFR_ORDER_SIMULTANEOUS = 0, CFR_ORDER_ALTERNATING = 1 };
 enum { CFR_LAYOUT_BFS = 0, CFR_LAYOUT_PUBLIC = 1 };
 enum { CFR_STRATEGY_CURRENT = 0, CFR_STRATEGY_AVERAGE = 1 };
 enum { CFR_PRECISION_FP32 = 0, CFR_PRECISION_FP64 = 1 };
+/* Schedules (cfr_options.persistent, cfr_set_schedule):
+ *   LEVEL       one launch per depth level, the iteration captured once and replayed (default)
+ *   PERSISTENT  one launch per cfr_iterate call running all n iterations of every game of a batch,
+ *               per-game barriers between levels
+ *   LDS         one workgroup per cfr_iterate call running all n iterations of one tiny standalone
+ *               game with its whole state in LDS (paper Sec. Results, cross-framework timing: the fixed
+ *               launch-and-replay floor per iteration that small games cannot fill):
+ *               values, both reach lanes, strategy, regrets, strategy sums (and the PCFR+
+ *               prediction) must fit the device's LDS per workgroup, and sets have at most 16
+ *               actions; same arithmetic as LEVEL, bitwise equal iterates */
+enum { CFR_SCHEDULE_LEVEL = 0, CFR_SCHEDULE_PERSISTENT = 1, CFR_SCHEDULE_LDS = 2 };
 
 typedef struct {
     int rule;              /* CFR_RULE_* (default CFR+) */
@@ -115,8 +126,8 @@ typedef struct {
     int test_fail_capture; /* test hook: treat graph capture as failed (warns once, launches directly) */
     int precision;         /* CFR_PRECISION_*: type of reach, values, regrets and strategy (default FP32);
                               strategy sums are FP64 in both */
-    int persistent;        /* 1: each cfr_iterate call is one persistent launch running all n iterations
-                              of every game, with per-game barriers (default 0: one launch per level) */
+    int persistent;        /* schedule, CFR_SCHEDULE_* (default LEVEL); LDS fails with CFR_EINVAL when the
+                              game does not fit or is a batch */
     int wg_nodes;          /* persistent form: target nodes per workgroup (0 = 16384); cfr_autotune picks it */
     int lifecycle;         /* 1: keep per terminal its node, payoff and chance product (and each game's root
                               chance) on the device, for cfr_set_payoffs / cfr_set_root_chance (default 0) */
@@ -184,23 +195,26 @@ cfr_status cfr_compile_batch(const cfr_game_desc *games, int32_t n, const cfr_op
 
 /* Schedule chosen by cfr_autotune. */
 typedef struct {
-    int32_t persistent;        /* 1 persistent launch, 0 one launch per level (graph replay) */
+    int32_t persistent;        /* chosen schedule, CFR_SCHEDULE_* */
     int32_t wg_nodes;          /* persistent form: target nodes per workgroup */
-    int32_t blocks;            /* persistent form: workgroups of the launch */
+    int32_t blocks;            /* workgroups of the launch (persistent form; 1 for LDS; 0 for LEVEL) */
     int32_t candidates;        /* schedules measured (0 when read from the cache) */
     double  ms_per_iteration;  /* measured time of the chosen schedule */
     int32_t failed;            /* persistent candidates dropped because a per-game barrier timed out */
 } cfr_tune_result;
 
-/* Autotuner: time `iters` iterations under each candidate schedule -- one launch per level, and
- * the persistent launch at several workgroup sizes -- keep the fastest, and reset the solver
+/* Autotuner: time `iters` iterations under each candidate schedule -- one launch per level, the
+ * persistent launch at several workgroup sizes, and for one game that fits, the LDS schedule --
+ * keep the fastest, and reset the solver
  * state (the measurement iterations are discarded).  With cache_path != NULL the choice is read
  * from / appended to that text file, keyed by device name, precision and the handle's sizes.
  * Synchronous. */
 cfr_status cfr_autotune(cfr_handle *h, int64_t iters, void *stream, const char *cache_path, cfr_tune_result *out);
 
-/* Select a schedule explicitly (as cfr_autotune would): persistent 0/1 and, for the persistent
- * form, the target nodes per workgroup (0 = 16384). */
+/* Select a schedule explicitly (as cfr_autotune would): persistent = CFR_SCHEDULE_* and, for the
+ * persistent form, the target nodes per workgroup (0 = 16384).  The solver state is kept.  Errors:
+ * CFR_EINVAL for an unknown schedule, or LDS for a batch, a game over the LDS budget or sets with
+ * more than 16 actions (the schedule then stays as it was). */
 cfr_status cfr_set_schedule(cfr_handle *h, int32_t persistent, int32_t wg_nodes);
 
 /* Number of games in the handle and (if slot_base != NULL) the n + 1 offsets of each game's

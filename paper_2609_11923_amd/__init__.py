@@ -26,6 +26,7 @@ CFR_ORDER_SIMULTANEOUS, CFR_ORDER_ALTERNATING = 0, 1
 CFR_LAYOUT_BFS, CFR_LAYOUT_PUBLIC = 0, 1
 CFR_STRATEGY_CURRENT, CFR_STRATEGY_AVERAGE = 0, 1
 CFR_PRECISION_FP32, CFR_PRECISION_FP64 = 0, 1
+CFR_SCHEDULE_LEVEL, CFR_SCHEDULE_PERSISTENT, CFR_SCHEDULE_LDS = 0, 1, 2
 CFR_FEATURES, CFR_MLP_OUT = 128, 4
 CFR_MLP_PARAMS, CFR_MLP_GRADS, CFR_MLP_ADAM_M, CFR_MLP_ADAM_V = 0, 1, 2, 3
 
@@ -274,7 +275,7 @@ def cfr_autotune(h, iters: int, stream=None, cache_path: str | None = None) -> d
     return {f: getattr(r, f) for f, _ in cfr_tune_result._fields_}
 
 
-def cfr_set_schedule(h, persistent: bool, wg_nodes: int = 0):
+def cfr_set_schedule(h, persistent: int, wg_nodes: int = 0):
     _check(load().cfr_set_schedule(h, int(persistent), int(wg_nodes)))
 
 
@@ -508,7 +509,7 @@ class Solver:
     def autotune(self, iters: int, stream=None, cache_path=None) -> dict:
         return cfr_autotune(self.h, iters, self._stream(stream), cache_path)
 
-    def set_schedule(self, persistent: bool, wg_nodes: int = 0):
+    def set_schedule(self, persistent: int, wg_nodes: int = 0):
         cfr_set_schedule(self.h, persistent, wg_nodes)
 
     def batch_exploitability(self, stream=None):

@@ -100,6 +100,15 @@ hipError_t launch_persistent(const DevGame &g, const PersistentPlan &p, int32_t 
                              hipStream_t s);
 // resident blocks per compute unit of the persistent kernel for this game's configuration
 hipError_t persistent_occupancy(const DevGame &g, int *blocks_per_cu);
+// The LDS-resident schedule of a single tiny game: one workgroup runs T iterations (both halves
+// when alternating) with the whole state in LDS, then the counter advances by T.  game_range is the
+// game's per-depth range table on the device.  lds_schedule_bytes is the dynamic LDS it needs;
+// prepare_lds raises the kernel's limit to it (once, before launches or capture) and fails for
+// more than 16 actions per set.
+size_t lds_schedule_bytes(int32_t N, int32_t A, int fp64, int pred);
+hipError_t prepare_lds(const DevGame &g, int rule, size_t *bytes);
+hipError_t launch_lds(const DevGame &g, const int32_t *game_range, int32_t T, IterFlags f, int alternating,
+                      hipStream_t s);
 // counter bump for games without edges
 hipError_t launch_tick(const DevGame &g, hipStream_t s);
 // out2[q] <- normalised average strategy (float, device order), sigbar[q] <- same in double

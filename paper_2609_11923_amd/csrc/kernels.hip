@@ -592,6 +592,114 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(const int4 *__restrict__ w
     }
 }
 
+// ---- the LDS-resident schedule for tiny standalone games --------------------------------------
+//
+// One workgroup runs n_iter whole iterations of a game whose state fits in LDS: the values (with
+// the terminal template), both reach lanes, strategy, regrets, strategy sums and (PCFR+) the
+// prediction are staged in, every level of every iteration runs between block barriers, and the
+// state is written back at the end.  No launch per level and no trip to HBM inside the loop.  The
+// structure arrays stay in global memory (read-only and small, so cache-resident).  One thread
+// per information set walks its members in ascending order with the level kernels' arithmetic,
+// so the iterates are bitwise those of the level launches.
+
+// The update of one set by one thread: member values v(h) = sum_a sigma v(h.a), the set's
+// instantaneous regrets summed over its members in ascending order, then set_update.
+template <typename T, int MAXA, bool EXPLICIT, bool EXT>
+__device__ void set_serial(int32_t i, const RuleArgs &ru, const LevelArgs<T> &a) {
+    const int32_t s0 = a.slot_off[i], nA = a.slot_off[i + 1] - s0;
+    const int32_t m0 = a.mem_off[i], m1 = a.mem_off[i + 1];
+    const int pl = a.iset_player[i];
+    T sg[MAXA], r[MAXA];
+#pragma unroll
+    for (int k = 0; k < MAXA; k++) {
+        sg[k] = a.sigma[s0 + min(k, nA - 1)];
+        r[k] = T(0);
+    }
+    for (int32_t m = m0; m < m1; m++) {
+        const int2 x = a.mem[m];
+        const int32_t h = x.x & MEMBER_NODE_MASK;
+        const T po = ((x.x & MEMBER_P2) ? a.r1 : a.r2)[h];
+        T cv[MAXA];
+#pragma unroll
+        for (int k = 0; k < MAXA; k++) cv[k] = a.v[child_of<EXPLICIT>(a.kid, x.y + min(k, nA - 1))];
+        T vh = T(0);
+#pragma unroll
+        for (int k = 0; k < MAXA; k++) vh = k < nA ? fma_t(sg[k], cv[k], vh) : vh;
+        a.v[h] = vh;
+#pragma unroll
+        for (int q = 0; q < MAXA; q++) r[q] = fma_t(po, cv[q] - vh, r[q]);
+    }
+    if (!((ru.upd >> (pl - 1)) & 1)) return;
+    const T *own = pl == 1 ? a.r1 : a.r2;
+    set_update<T, MAXA, EXT>(ru, a, s0, nA, pl, (double)own[a.mem[m0].x & MEMBER_NODE_MASK], r);
+}
+
+// Dynamic LDS of k_lds: strategy sums (double) first, then v, r1, r2 [N] and sigma, R (and the
+// PCFR+ prediction) [A] in the state type, then BLOCK reduction slots for big chance nodes.
+size_t lds_schedule_bytes(int32_t N, int32_t A, int fp64, int pred) {
+    const size_t es = fp64 ? 8 : 4;
+    return 8 * (size_t)A + es * (3 * (size_t)N + (pred ? 3 : 2) * (size_t)A + BLOCK);
+}
+
+template <typename T, int MAXA, bool EXPLICIT, bool EXT>
+__global__ void __launch_bounds__(BLOCK) k_lds(const int32_t *__restrict__ gr, int32_t D, int32_t N, int32_t A,
+                                               int32_t n_iter, const int2 *__restrict__ up, LevelArgs<T> g,
+                                               const int32_t *__restrict__ tcount, int rule, int linear,
+                                               int alternating) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *sb = reinterpret_cast<double *>(smem);
+    T *v = reinterpret_cast<T *>(sb + A);
+    T *r1 = v + N, *r2 = r1 + N, *sig = r2 + N, *R = sig + A;
+    T *pred = g.pred ? R + A : nullptr;
+    T *red = R + A + (g.pred ? A : 0);
+    const int tid = threadIdx.x;
+    for (int32_t i = tid; i < N; i += BLOCK) {
+        v[i] = g.v[i];
+        r1[i] = g.r1[i];
+        r2[i] = g.r2[i];
+    }
+    for (int32_t q = tid; q < A; q += BLOCK) {
+        sb[q] = g.sbar[q];
+        sig[q] = g.sigma[q];
+        R[q] = g.R[q];
+        if (pred) pred[q] = g.pred[q];
+    }
+    __syncthreads();
+    LevelArgs<T> a = g;
+    a.v = v; a.r1 = r1; a.r2 = r2; a.sigma = sig; a.R = R; a.sbar = sb; a.pred = pred;
+    const int32_t t0 = tcount[0];
+    const int halves = alternating ? 2 : 1;
+    for (int32_t it = 1; it <= n_iter; it++) {
+        for (int half = 0; half < halves; half++) {
+            const RuleArgs ru = rule_args(rule, linear, alternating ? 1 << half : 3, t0 + it);
+            for (int32_t d = 1; d <= D; d++) {
+                const int32_t lo = gr[d * GR_FIELDS_DEV], hi = gr[d * GR_FIELDS_DEV + 1];
+                for (int32_t c = lo + tid; c < hi; c += BLOCK) forward_node<T>(c, up, sig, r1, r2);
+                __syncthreads();
+            }
+            for (int32_t d = D - 1; d >= 0; d--) {
+                const int32_t *r = gr + d * GR_FIELDS_DEV;
+                const int32_t ib = a.grp_iset_off[r[2]], ie = a.grp_iset_off[r[3]];
+                for (int32_t i = ib + tid; i < ie; i += BLOCK) set_serial<T, MAXA, EXPLICIT, EXT>(i, ru, a);
+                for (int32_t j = r[4] + tid; j < r[5]; j += BLOCK) chance_value<T, EXPLICIT>(a.chance_node[j], a);
+                for (int32_t b = r[6]; b < r[7]; b++) big_chance_value<T, EXPLICIT>(a.bigc_node[b], a, red);
+                __syncthreads();
+            }
+        }
+    }
+    for (int32_t i = tid; i < N; i += BLOCK) {
+        g.v[i] = v[i];
+        g.r1[i] = r1[i];
+        g.r2[i] = r2[i];
+    }
+    for (int32_t q = tid; q < A; q += BLOCK) {
+        g.sbar[q] = sb[q];
+        g.sigma[q] = sig[q];
+        g.R[q] = R[q];
+        if (pred) g.pred[q] = pred[q];
+    }
+}
+
 __global__ void k_fill_int(int32_t n, int32_t *p, int32_t value) {
     const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i < n) p[i] = value;
@@ -849,6 +957,50 @@ hipError_t launch_persistent(const DevGame &g, const PersistentPlan &p, int32_t 
     if (e != hipSuccess) return e;
     const PersistentLaunch L{g, p, T_, f, alt, s};
     e = g.fp64 ? by_kind<double>(g, f.rule, L) : by_kind<float>(g, f.rule, L);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_add_counter, dim3(1), dim3(64), 0, s, g.t, T_);
+    return hipGetLastError();
+}
+
+struct LdsLaunch {
+    const DevGame &g; const int32_t *gr; int32_t T_; IterFlags f; int alt; hipStream_t s; size_t bytes;
+    bool prepare;   // true: only raise the kernel's dynamic LDS limit to bytes
+    template <typename T, int MAXA, int MPT, bool EX, bool XT, bool AF>
+    hipError_t operator()() const {
+        if constexpr (MAXA > 16) {
+            return hipErrorInvalidValue;
+        } else {
+            auto fn = k_lds<T, MAXA, EX, XT>;
+            if (prepare)
+                return hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+            hipLaunchKernelGGL(fn, dim3(1), dim3(BLOCK), bytes, s, gr, g.max_depth, g.N, g.A, T_, g.up,
+                               level_args<T>(g), g.t, f.rule, f.linear, alt);
+            return hipGetLastError();
+        }
+    }
+};
+
+// the serial update reads the child list when the layout has one (affine offsets serve only the
+// member-parallel form)
+template <typename T>
+static hipError_t lds_dispatch(const DevGame &g, const LdsLaunch &L) {
+    const bool x = ext_rule(L.f.rule);
+    if (g.explicit_kids) return x ? by_actions<T, true, true, false>(g, L) : by_actions<T, true, false, false>(g, L);
+    return x ? by_actions<T, false, true, false>(g, L) : by_actions<T, false, false, false>(g, L);
+}
+
+hipError_t prepare_lds(const DevGame &g, int rule, size_t *bytes) {
+    *bytes = lds_schedule_bytes(g.N, g.A, g.fp64, g.pred != nullptr);
+    if (g.max_actions > 16) return hipErrorInvalidValue;
+    const LdsLaunch L{g, nullptr, 0, IterFlags{rule, 0, 3}, 0, nullptr, *bytes, true};
+    return g.fp64 ? lds_dispatch<double>(g, L) : lds_dispatch<float>(g, L);
+}
+
+hipError_t launch_lds(const DevGame &g, const int32_t *game_range, int32_t T_, IterFlags f, int alt, hipStream_t s) {
+    const size_t bytes = lds_schedule_bytes(g.N, g.A, g.fp64, g.pred != nullptr);
+    const LdsLaunch L{g, game_range, T_, f, alt, s, bytes, false};
+    hipError_t e = g.fp64 ? lds_dispatch<double>(g, L) : lds_dispatch<float>(g, L);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_add_counter, dim3(1), dim3(64), 0, s, g.t, T_);
     return hipGetLastError();

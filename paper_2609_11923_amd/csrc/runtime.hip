@@ -62,6 +62,9 @@ struct cfr_handle {
     std::vector<double> game_pot;
     // persistent schedule
     bool persistent = false;
+    // LDS-resident schedule (one tiny game, one workgroup): per-depth ranges on the device
+    bool lds = false;
+    int32_t *lds_range = nullptr;
     int32_t wg_nodes = 16384;
     PersistentPlan pp{};
     std::vector<void *> pp_allocs;
@@ -467,6 +470,7 @@ static cfr_status build_persistent_plan(cfr_handle *h, int32_t wg_nodes) {
     return CFR_OK;
 }
 
+// One launch (captured once per n) that runs all n iterations: the persistent or the LDS schedule.
 static cfr_status persistent_iterate(cfr_handle *h, int64_t n, hipStream_t s) {
     if (n > 0x7fffffffLL) return fail(CFR_EINVAL, "n too large for one persistent launch");
     const IterFlags f{h->opt.rule, h->opt.averaging == CFR_AVG_LINEAR ? 1 : 0, 3};
@@ -477,7 +481,8 @@ static cfr_status persistent_iterate(cfr_handle *h, int64_t n, hipStream_t s) {
         h->pgraph_n = -1;
         hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t le = launch_persistent(h->g, h->pp, (int32_t)n, f, alt, h->cap_stream);
+            hipError_t le = h->lds ? launch_lds(h->g, h->lds_range, (int32_t)n, f, alt, h->cap_stream)
+                                   : launch_persistent(h->g, h->pp, (int32_t)n, f, alt, h->cap_stream);
             hipGraph_t gr = nullptr;
             e = hipStreamEndCapture(h->cap_stream, &gr);
             if (le == hipSuccess && e == hipSuccess && gr) {
@@ -495,8 +500,14 @@ static cfr_status persistent_iterate(cfr_handle *h, int64_t n, hipStream_t s) {
     if (h->pexec && h->pgraph_n == n) {
         hipError_t e = hipGraphLaunch(h->pexec, s);
         if (e != hipSuccess) return fail(CFR_EGRAPH, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    } else if (h->lds) {
+        HIP_TRY(launch_lds(h->g, h->lds_range, (int32_t)n, f, alt, s));
     } else {
         HIP_TRY(launch_persistent(h->g, h->pp, (int32_t)n, f, alt, s));
+    }
+    if (h->lds) {   // no barriers, no error flag to read back
+        h->iters += n;
+        return CFR_OK;
     }
     int32_t err = 0;
     HIP_TRY(hipMemcpyAsync(&err, h->pp.err, sizeof err, hipMemcpyDeviceToHost, s));
@@ -567,6 +578,7 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     if (o.layout != CFR_LAYOUT_BFS && o.layout != CFR_LAYOUT_PUBLIC) return fail(CFR_EINVAL, "unknown layout");
     if (o.iters_per_graph < 1 || o.iters_per_graph > 1000) return fail(CFR_EINVAL, "iters_per_graph must be in [1, 1000]");
     if (o.precision != CFR_PRECISION_FP32 && o.precision != CFR_PRECISION_FP64) return fail(CFR_EINVAL, "unknown precision");
+    if (o.persistent < CFR_SCHEDULE_LEVEL || o.persistent > CFR_SCHEDULE_LDS) return fail(CFR_EINVAL, "unknown schedule");
     std::string err;
     cfr_status st = CFR_OK;
     // canonical layouts first: the update groups of every game are sized for the batch's action bound
@@ -765,10 +777,9 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, o.device) == hipSuccess) h->device_name = prop.gcnArchName;
     }
-    if (o.persistent) {
-        st = build_persistent_plan(h, o.wg_nodes);
+    if (o.persistent != CFR_SCHEDULE_LEVEL) {
+        st = cfr_set_schedule(h, o.persistent, o.wg_nodes);
         if (st != CFR_OK) { free_handle(h); return st; }
-        h->persistent = true;
     }
     st = cfr_reset(h);
     if (st != CFR_OK) { free_handle(h); return st; }
@@ -816,7 +827,7 @@ cfr_status cfr_iterate(cfr_handle *h, int64_t n, void *stream) {
     if (n == 0) return CFR_OK;
     HIP_TRY(hipSetDevice(h->opt.device));
     hipStream_t s = (hipStream_t)stream;
-    if (h->persistent) return persistent_iterate(h, n, s);
+    if (h->persistent || h->lds) return persistent_iterate(h, n, s);
     if (h->captured && h->pinned != persistent_ptrs(h))
         return fail(CFR_ESTATE, "a persistent buffer changed since graph capture; refusing to replay");
     if (!h->use_graph) {
@@ -1048,15 +1059,44 @@ cfr_status cfr_profile(cfr_handle *h, int64_t n, void *stream, cfr_kernel_stat *
     return CFR_OK;
 }
 
-cfr_status cfr_set_schedule(cfr_handle *h, int32_t persistent, int32_t wg_nodes) {
-    if (!h) return fail(CFR_EINVAL, "handle is NULL");
-    HIP_TRY(hipSetDevice(h->opt.device));
-    HIP_TRY(hipDeviceSynchronize());
-    if (persistent) {
-        cfr_status st = build_persistent_plan(h, wg_nodes);
+// The LDS-resident schedule: one game whose state fits in the device's LDS per workgroup and
+// whose sets have at most 16 actions.
+static cfr_status set_lds_schedule(cfr_handle *h) {
+    if (h->n_games != 1) return fail(CFR_EINVAL, "the LDS schedule runs one standalone game, not a batch");
+    size_t bytes = lds_schedule_bytes(h->g.N, h->g.A, h->g.fp64, h->g.pred != nullptr);
+    int limit = 0;
+    HIP_TRY(hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, h->opt.device));
+    if (bytes > (size_t)limit)
+        return fail(CFR_EINVAL, "the game needs " + std::to_string(bytes) + " bytes of LDS for the LDS schedule; "
+                                "a workgroup has " + std::to_string(limit));
+    if (prepare_lds(h->g, h->opt.rule, &bytes) != hipSuccess)
+        return fail(CFR_EINVAL, "the LDS schedule supports at most 16 actions per information set");
+    if (!h->lds_range) {
+        cfr_status st = dev_alloc(h, &h->lds_range, (int64_t)h->game_range.size());
+        if (st != CFR_OK) return st;
+        st = upload(h->lds_range, h->game_range);
         if (st != CFR_OK) return st;
     }
-    h->persistent = persistent != 0;
+    if (h->pexec) { (void)hipGraphExecDestroy(h->pexec); h->pexec = nullptr; }
+    if (h->pgraph) { (void)hipGraphDestroy(h->pgraph); h->pgraph = nullptr; }
+    h->pgraph_n = -1;
+    return CFR_OK;
+}
+
+cfr_status cfr_set_schedule(cfr_handle *h, int32_t persistent, int32_t wg_nodes) {
+    if (!h) return fail(CFR_EINVAL, "handle is NULL");
+    if (persistent < CFR_SCHEDULE_LEVEL || persistent > CFR_SCHEDULE_LDS) return fail(CFR_EINVAL, "unknown schedule");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    HIP_TRY(hipDeviceSynchronize());
+    if (persistent == CFR_SCHEDULE_PERSISTENT) {
+        cfr_status st = build_persistent_plan(h, wg_nodes);
+        if (st != CFR_OK) return st;
+    } else if (persistent == CFR_SCHEDULE_LDS) {
+        cfr_status st = set_lds_schedule(h);
+        if (st != CFR_OK) return st;
+    }
+    h->persistent = persistent == CFR_SCHEDULE_PERSISTENT;
+    h->lds = persistent == CFR_SCHEDULE_LDS;
     return CFR_OK;
 }
 
@@ -1089,8 +1129,9 @@ cfr_status cfr_autotune(cfr_handle *h, int64_t iters, void *stream, const char *
     }
     int candidates = 0, failed = 0;
     if (best.ms_per_iteration < 0) {
-        std::vector<std::pair<int, int>> cand = {{0, 0}};
-        for (int wg : {1024, 4096, 16384, 65536, 262144}) cand.push_back({1, wg});
+        std::vector<std::pair<int, int>> cand = {{CFR_SCHEDULE_LEVEL, 0}};
+        for (int wg : {1024, 4096, 16384, 65536, 262144}) cand.push_back({CFR_SCHEDULE_PERSISTENT, wg});
+        if (h->n_games == 1) cand.push_back({CFR_SCHEDULE_LDS, 0});   // skipped unless the game fits in LDS
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
@@ -1098,12 +1139,13 @@ cfr_status cfr_autotune(cfr_handle *h, int64_t iters, void *stream, const char *
         for (auto c : cand) {
             cfr_status st = cfr_set_schedule(h, c.first, c.second);
             if (st != CFR_OK) continue;
-            if (c.first && h->pp.blocks == last_blocks) continue;  // same launch shape as the previous size
-            if (c.first) last_blocks = h->pp.blocks;
+            const bool pers = c.first == CFR_SCHEDULE_PERSISTENT;
+            if (pers && h->pp.blocks == last_blocks) continue;  // same launch shape as the previous size
+            if (pers) last_blocks = h->pp.blocks;
             st = cfr_iterate(h, iters, stream);            // warm-up (capture)
             if (st == CFR_OK) HIP_TRY(hipEventRecord(e0, s));
             if (st == CFR_OK) st = cfr_iterate(h, iters, stream);
-            if (st == CFR_EDEVICE && c.first) {
+            if (st == CFR_EDEVICE && pers) {
                 // a per-game barrier of this launch shape timed out (its blocks were not all
                 // resident): drop the candidate; the next plan build clears the error flag
                 std::fprintf(stderr, "cfr: autotune dropped persistent schedule wg_nodes=%d (%s)\n", h->wg_nodes,
@@ -1119,7 +1161,7 @@ cfr_status cfr_autotune(cfr_handle *h, int64_t iters, void *stream, const char *
             const double per = ms / (double)iters;
             candidates++;
             if (best.ms_per_iteration < 0 || per < best.ms_per_iteration) {
-                best.persistent = c.first; best.wg_nodes = c.first ? h->wg_nodes : 0; best.ms_per_iteration = per;
+                best.persistent = c.first; best.wg_nodes = pers ? h->wg_nodes : 0; best.ms_per_iteration = per;
             }
         }
         (void)hipEventDestroy(e0);
@@ -1136,7 +1178,7 @@ cfr_status cfr_autotune(cfr_handle *h, int64_t iters, void *stream, const char *
     if (st != CFR_OK) return st;
     st = cfr_reset(h);
     if (st != CFR_OK) return st;
-    best.blocks = h->persistent ? h->pp.blocks : 0;
+    best.blocks = h->persistent ? h->pp.blocks : h->lds ? 1 : 0;
     best.candidates = candidates;
     best.failed = failed;
     if (out) *out = best;
