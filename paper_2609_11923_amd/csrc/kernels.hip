@@ -374,30 +374,39 @@ __device__ void group_update(int32_t g, const RuleArgs &ru, const LevelArgs<T> &
     set_update<T, MAXA, EXT>(ru, a, s0, nA, pl, (double)own[a.mem[m0].x & MEMBER_NODE_MASK], r);
 }
 
-// LDS staging of one update group in an affine layout: the set offsets and the set of each member
-// of the chunk, besides the member values of group_update
+// LDS staging of one update group in an affine layout: the set offsets, the set of each member
+// of the chunk and (FP32 state, up to 16 actions) each set's child offsets and strategy row,
+// besides the member values of group_update.  For FP64 the rows would cost a resident block per
+// compute unit (measured slower), so members read them through the cache instead.
 template <typename T, int MAXA, int MPT>
 struct GroupLdsA {
+    static constexpr bool ROWS = MAXA <= 16 && sizeof(T) == 4;
+    static constexpr int RA = ROWS ? MAXA : 1;
     T po[MPT * BLOCK];
     alignas(16) T diff[MPT * BLOCK * MAXA];
+    alignas(16) int32_t ko[BLOCK * RA];
+    alignas(16) T sg[BLOCK * RA];
     int32_t moff[BLOCK + 1];
     int32_t slot[BLOCK + 1];
     uint8_t mset[MPT * BLOCK];
 };
 
 // group_update for affine layouts (child a of member h is h + koff[slot a]): the same arithmetic
-// in the same order, so the results are bitwise those of group_update.  What changes is the load
-// chain.  A member's compact record and its set's offsets and strategy (the set from the member ->
-// set map in LDS, no search) are independent loads and the child values follow them.  Loads are
-// unconditional: past a set's last action they repeat its last slot and child (an address already
-// read, no new traffic) and lanes past the chunk's end repeat its first member, so every load of a
-// chunk is in flight at once instead of one guarded load and wait per action; only the stores and
-// the arithmetic are masked.  Each set thread fetches its own reach through its first member beside
-// the member loads.
+// in the same order, so the results are bitwise those of group_update.  What changes is how the
+// loads are issued.  The vector-memory pipeline (address and data units at ~90 % busy) bounds
+// this pass, so the per-slot child offsets and strategy, the same for every member of a set, are
+// loaded once per set (by its thread, into an LDS row) instead of once per member; a member then
+// loads only its record, its opponent reach and its child values.  Loads are unconditional: past
+// a set's last action they repeat its last child (an address already read), lanes past the
+// chunk's end repeat its first member, so a chunk's loads are in flight together; only stores
+// and arithmetic are masked.  (A guard that skips a load no lane needs compiles to a branch with
+// a full wait at its join, which costs more than the load.)  Each set thread fetches its own
+// reach through its first member.
 template <typename T, int MAXA, int MPT, bool EXT>
 __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelArgs<T> &a,
                                     GroupLdsA<T, MAXA, MPT> &L) {
     constexpr int CHUNK = MPT * BLOCK;
+    constexpr bool ROWS = GroupLdsA<T, MAXA, MPT>::ROWS;
     const int tid = threadIdx.x;
     const int32_t i0 = a.grp_iset_off[g], i1 = a.grp_iset_off[g + 1];
     const int32_t nsets = i1 - i0;
@@ -408,6 +417,27 @@ __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelAr
     const int32_t s0 = a.slot_off[ti], nA = a.slot_off[ti + 1] - s0;
     const int pl = a.iset_player[ti];
     const int32_t h0 = a.mnode[m0] & MEMBER_NODE_MASK;
+    const T *__restrict__ r1 = a.r1;
+    const T *__restrict__ r2 = a.r2;
+    const T *__restrict__ sig = a.sigma;
+    const int32_t *__restrict__ koff = a.koff;
+    if constexpr (ROWS) {
+        int32_t kr[MAXA];
+        T sr[MAXA];
+#pragma unroll
+        for (int k = 0; k < MAXA; k++) {
+            const int32_t q = s0 + min(k, nA - 1);
+            kr[k] = koff[q];
+            sr[k] = sig[q];
+        }
+        if (has_set) {
+#pragma unroll
+            for (int k = 0; k < MAXA; k++) {
+                L.ko[tid * MAXA + k] = kr[k];
+                L.sg[tid * MAXA + k] = sr[k];
+            }
+        }
+    }
     if (has_set) {
         L.moff[tid] = m0;
         L.slot[tid] = s0;
@@ -418,10 +448,6 @@ __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelAr
         for (int32_t m = m0; m < e; m++) L.mset[m - mbeg] = (uint8_t)tid;
     }
     __syncthreads();
-    const T *__restrict__ r1 = a.r1;
-    const T *__restrict__ r2 = a.r2;
-    const T *__restrict__ sig = a.sigma;
-    const int32_t *__restrict__ koff = a.koff;
     const T pown = (pl == 1 ? r1 : r2)[h0];
     T r[MAXA];
 #pragma unroll
@@ -429,18 +455,18 @@ __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelAr
     for (int32_t cb = mbeg; cb < mend; cb += CHUNK) {
         const int32_t ce = min(cb + CHUNK, mend);
         bool in[MPT];
-        int32_t hn[MPT], sb[MPT], na[MPT];
+        int32_t hn[MPT], st[MPT], sb[MPT], na[MPT];
 #pragma unroll
         for (int u = 0; u < MPT; u++) {
             const int32_t j = u * BLOCK + tid;
             in[u] = cb + j < ce;
             const int32_t jj = in[u] ? j : 0;
             hn[u] = a.mnode[cb + jj];
-            const int32_t st = L.mset[jj];
-            sb[u] = L.slot[st];
-            na[u] = L.slot[st + 1] - sb[u];
+            st[u] = L.mset[jj];
+            sb[u] = L.slot[st[u]];
+            na[u] = L.slot[st[u] + 1] - sb[u];
         }
-        T po[MPT], sg[MPT][MAXA], cv[MPT][MAXA];
+        T po[MPT], cv[MPT][MAXA], sg[MPT][ROWS ? 1 : MAXA];
 #pragma unroll
         for (int u = 0; u < MPT; u++) {
             const int32_t h = hn[u] & MEMBER_NODE_MASK;
@@ -448,9 +474,13 @@ __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelAr
             int32_t ko[MAXA];
 #pragma unroll
             for (int k = 0; k < MAXA; k++) {
-                const int32_t q = sb[u] + min(k, na[u] - 1);
-                ko[k] = koff[q];
-                sg[u][k] = sig[q];
+                if constexpr (ROWS) {
+                    ko[k] = L.ko[st[u] * MAXA + k];
+                } else {
+                    const int32_t q = sb[u] + min(k, na[u] - 1);
+                    ko[k] = koff[q];
+                    sg[u][k] = sig[q];
+                }
             }
 #pragma unroll
             for (int k = 0; k < MAXA; k++) cv[u][k] = a.v[h + ko[k]];
@@ -459,7 +489,12 @@ __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelAr
         for (int u = 0; u < MPT; u++) {
             T vh = T(0);
 #pragma unroll
-            for (int k = 0; k < MAXA; k++) vh = k < na[u] ? fma_t(sg[u][k], cv[u][k], vh) : vh;
+            for (int k = 0; k < MAXA; k++) {
+                T sk;
+                if constexpr (ROWS) sk = L.sg[st[u] * MAXA + k];
+                else sk = sg[u][k];
+                vh = k < na[u] ? fma_t(sk, cv[u][k], vh) : vh;
+            }
             if (!in[u]) continue;
             const int32_t j = u * BLOCK + tid;
             a.v[hn[u] & MEMBER_NODE_MASK] = vh;
