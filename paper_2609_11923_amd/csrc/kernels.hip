@@ -156,7 +156,19 @@ __device__ void big_chance_value(int32_t h, const LevelArgs<T> &a, T *red) {
     const int tid = threadIdx.x;
     const int32_t b = a.kid_off[h], e = a.kid_off[h + 1];
     T acc = T(0);
-    for (int32_t c = b + tid; c < e; c += BLOCK) acc += a.v[child_of<EXPLICIT>(a.kid, c)];
+    // this thread's children b + tid, b + tid + BLOCK, ... summed in that order, eight loads in
+    // flight at a time (past the last child the index is clamped and the value not added)
+    constexpr int U = 8;
+    for (int32_t c0 = b + tid; c0 < e; c0 += U * BLOCK) {
+        int32_t ch[U];
+        T x[U];
+#pragma unroll
+        for (int i = 0; i < U; i++) ch[i] = child_of<EXPLICIT>(a.kid, min(c0 + i * BLOCK, e - 1));
+#pragma unroll
+        for (int i = 0; i < U; i++) x[i] = a.v[ch[i]];
+#pragma unroll
+        for (int i = 0; i < U; i++) acc = c0 + i * BLOCK < e ? acc + x[i] : acc;
+    }
     red[tid] = acc;
     __syncthreads();
     for (int w = BLOCK / 2; w > 0; w >>= 1) {
@@ -264,6 +276,35 @@ __device__ __forceinline__ void set_update(const RuleArgs &ru, const LevelArgs<T
     set_update_from<T, MAXA, EXT>(ru, a, s0, nA, pl, pown, r, Rk, sk, sb);
 }
 
+// Phase 2 of a group: a set's instantaneous regrets r(I, a) += po(h) * diff(h, a) over its staged
+// members [k0, k1) in ascending order, one fused multiply-add chain per action.  The LDS reads of
+// U members are issued before their multiply-adds (the order of the chain is unchanged), so a set
+// with many members does not wait one LDS round trip per member.  Every column is accumulated:
+// past a set's actions the columns hold repeats that are never read afterwards.
+template <typename T, int MAXA>
+__device__ __forceinline__ void reduce_members(const T *po, const T *diff, int32_t k0, int32_t k1, T (&r)[MAXA]) {
+    constexpr int U = MAXA <= 4 ? (sizeof(T) == 4 ? 8 : 4) : 2;
+    int32_t k = k0;
+    for (; k + U <= k1; k += U) {
+        T p[U], d[U][MAXA];
+#pragma unroll
+        for (int i = 0; i < U; i++) {
+            p[i] = po[k + i];
+#pragma unroll
+            for (int q = 0; q < MAXA; q++) d[i][q] = diff[(k + i) * MAXA + q];
+        }
+#pragma unroll
+        for (int i = 0; i < U; i++)
+#pragma unroll
+            for (int q = 0; q < MAXA; q++) r[q] = fma_t(p[i], d[i][q], r[q]);
+    }
+    for (; k < k1; k++) {
+        const T p = po[k];
+#pragma unroll
+        for (int q = 0; q < MAXA; q++) r[q] = fma_t(p, diff[k * MAXA + q], r[q]);
+    }
+}
+
 // LDS staging of one update group (members of a chunk, the group's set offsets)
 template <typename T, int MAXA, int MPT>
 struct GroupLds {
@@ -356,15 +397,7 @@ __device__ void group_update(int32_t g, const RuleArgs &ru, const LevelArgs<T> &
             for (int k = 0; k < MAXA; k++) L.diff[j * MAXA + k] = cv[u][k] - vh;
         }
         __syncthreads();
-        if (has_set) {
-            const int32_t lo = max(m0, cb), hi = min(m1, ce);
-            for (int32_t k = lo - cb; k < hi - cb; k++) {
-                const T p = L.po[k];
-                // every column: past the set's actions they hold repeats, never read afterwards
-#pragma unroll
-                for (int q = 0; q < MAXA; q++) r[q] = fma_t(p, L.diff[k * MAXA + q], r[q]);
-            }
-        }
+        if (has_set) reduce_members<T, MAXA>(L.po, L.diff, max(m0, cb) - cb, min(m1, ce) - cb, r);
         __syncthreads();
     }
     if (!has_set) return;
@@ -503,15 +536,7 @@ __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelAr
             for (int k = 0; k < MAXA; k++) L.diff[j * MAXA + k] = cv[u][k] - vh;
         }
         __syncthreads();
-        if (has_set) {
-            const int32_t lo = max(m0, cb), hi = min(m1, ce);
-            for (int32_t k = lo - cb; k < hi - cb; k++) {
-                const T p = L.po[k];
-                // every column: past the set's actions they hold repeats, never read afterwards
-#pragma unroll
-                for (int q = 0; q < MAXA; q++) r[q] = fma_t(p, L.diff[k * MAXA + q], r[q]);
-            }
-        }
+        if (has_set) reduce_members<T, MAXA>(L.po, L.diff, max(m0, cb) - cb, min(m1, ce) - cb, r);
         __syncthreads();
     }
     if (!has_set) return;
