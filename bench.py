@@ -560,6 +560,17 @@ def main():
         out["tiny_games"] = run_tiny(cfr, torch, log)
     if not args.no_warm:
         out["warm_start"] = run_warm(cfr, torch, args, log)
+    if "batch" in out and "warm_start" in out:
+        # the same 256 subgames three ways, CFR+ to exploitability <= 1e-3 pot for every game
+        plain = out["batch"]["one_at_a_time"]["time_to_1e3pot_all_ms"]
+        cold = out["warm_start"]["cold"]["time_ms_all"]
+        warm_ = out["warm_start"]["warm"]["time_ms_all"]
+        out["time_to_target"] = {
+            "what": "wall time until every one of the 256 subgames reaches exploitability <= 1e-3 pot (CFR+)",
+            "plain_cold_one_at_a_time_ms": plain, "batched_cold_ms": cold, "batched_warm_ms": warm_,
+            "reduction_batched_warm_vs_plain_cold": 1.0 - warm_ / plain if plain else None,
+            "reduction_batched_warm_vs_batched_cold": 1.0 - warm_ / cold if cold else None,
+        }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(sample_fn, n_nodes, args.cpu_seconds)
