@@ -475,8 +475,8 @@ def main():
                     help="also run a plain device copy of this many MiB (counter calibration for profilers)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU design is "
-              f"described in DESIGN.md but not built)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (several GPUs are a design "
+              f"only: sharding by the first public card, not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -4,7 +4,7 @@ The paper has no learned part.  This module trains the warm-start network (cfr_m
 strategies the solver itself produced, and measures what it buys: iterations and wall time to
 exploitability <= 1e-3 pot for the warm-started batch against plain cold-start CFR+ on the same
 GPU, with an untrained network as a control.  Exact exploitability (the device best response)
-is the judge; scale 0 (the cold start) is the fallback.
+decides; scale 0 (the cold start) is the fallback.
 
 Everything numeric runs in libcfr.so: the solver, the feature rows, the network's forward,
 backward and Adam steps, the warm-start injection.  torch holds device memory and streams;
