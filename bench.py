@@ -58,10 +58,10 @@ def kernels_digest():
     return hashlib.sha256(open(path, "rb").read()).hexdigest()
 
 
-def stored_traffic(kernel, workload, precision, launches):
+def stored_traffic(kernel, workload, precision, launches, path=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, when it was
     taken on the same kernel source, workload and precision; None otherwise."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = path or os.path.join(ROOT, "profiles", "traffic.json")
     try:
         rec = json.load(open(path)).get(f"{kernel}/{workload}/{precision}")
     except (OSError, ValueError):
