@@ -183,11 +183,12 @@ __device__ void big_chance_value(int32_t h, const LevelArgs<T> &a, T *red) {
 // members, player 1's sign) and its state as loaded (R, sigma^t, sbar): R <- R + sign r with the
 // rule's clamp or discount, sbar += w pi_i(I) sigma^t (FP64; DCFR discounts it), then
 // sigma^{t+1} = regret matching of R (PCFR+: of R plus the prediction, which becomes this
-// iteration's instantaneous regret).
+// iteration's instantaneous regret and is stored here).  Rk and sb are updated in place and the
+// new strategy is returned in sn.
 template <typename T, int MAXA, bool EXT>
-__device__ __forceinline__ void set_update_from(const RuleArgs &ru, const LevelArgs<T> &a, int32_t s0, int32_t nA,
-                                                int pl, double pown, const T (&r)[MAXA], T (&Rk)[MAXA],
-                                                const T (&sk)[MAXA], double (&sb)[MAXA]) {
+__device__ __forceinline__ void set_update_compute(const RuleArgs &ru, const LevelArgs<T> &a, int32_t s0, int32_t nA,
+                                                   int pl, double pown, const T (&r)[MAXA], T (&Rk)[MAXA],
+                                                   const T (&sk)[MAXA], double (&sb)[MAXA], T (&sn)[MAXA]) {
     const T sign = pl == 1 ? T(1) : T(-1);
     T tot = T(0);
     T Rn[MAXA];
@@ -245,11 +246,22 @@ __device__ __forceinline__ void set_update_from(const RuleArgs &ru, const LevelA
     const T inv = tot > T(0) ? T(1) / tot : T(0);
     const T uni = T(1) / (T)nA;
 #pragma unroll
+    for (int k = 0; k < MAXA; k++) sn[k] = tot > T(0) ? Rn[k] * inv : uni;
+}
+
+// set_update_compute, then the set's new regrets, strategy sums and strategy stored in place.
+template <typename T, int MAXA, bool EXT>
+__device__ __forceinline__ void set_update_from(const RuleArgs &ru, const LevelArgs<T> &a, int32_t s0, int32_t nA,
+                                                int pl, double pown, const T (&r)[MAXA], T (&Rk)[MAXA],
+                                                const T (&sk)[MAXA], double (&sb)[MAXA]) {
+    T sn[MAXA];
+    set_update_compute<T, MAXA, EXT>(ru, a, s0, nA, pl, pown, r, Rk, sk, sb, sn);
+#pragma unroll
     for (int k = 0; k < MAXA; k++)
         if (k < nA) {
             a.R[s0 + k] = Rk[k];
             a.sbar[s0 + k] = sb[k];
-            a.sigma[s0 + k] = tot > T(0) ? Rn[k] * inv : uni;
+            a.sigma[s0 + k] = sn[k];
         }
 }
 
@@ -539,9 +551,51 @@ __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelAr
         if (has_set) reduce_members<T, MAXA>(L.po, L.diff, max(m0, cb) - cb, min(m1, ce) - cb, r);
         __syncthreads();
     }
-    if (!has_set) return;
-    if (!((ru.upd >> (pl - 1)) & 1)) return;
-    set_update<T, MAXA, EXT>(ru, a, s0, nA, pl, (double)pown, r);
+    if constexpr (ROWS && MAXA <= 4) {
+        // The group's slots [S0, S1) are contiguous: move their regrets, strategy sums and strategy
+        // through LDS (the member staging is free now) with coalesced passes of the whole block,
+        // instead of each set thread loading and storing its few slots.  Slots of sets this half
+        // leaves alone are written back unchanged.
+        const int32_t S0 = L.slot[0], S1 = L.slot[nsets];
+        double *sbs = reinterpret_cast<double *>(L.diff);            // [<= CHUNK]
+        T *Rs = reinterpret_cast<T *>(sbs + CHUNK), *Ss = Rs + CHUNK; // [<= CHUNK] each
+        for (int32_t q = tid; q < S1 - S0; q += BLOCK) {
+            sbs[q] = a.sbar[S0 + q];
+            Rs[q] = a.R[S0 + q];
+            Ss[q] = sig[S0 + q];
+        }
+        __syncthreads();
+        if (has_set && ((ru.upd >> (pl - 1)) & 1)) {
+            const int32_t b = s0 - S0;
+            T Rk[MAXA], sk[MAXA], sn[MAXA];
+            double sb[MAXA];
+#pragma unroll
+            for (int k = 0; k < MAXA; k++) {
+                const int32_t q = b + min(k, nA - 1);
+                Rk[k] = Rs[q];
+                sk[k] = Ss[q];
+                sb[k] = sbs[q];
+            }
+            set_update_compute<T, MAXA, EXT>(ru, a, s0, nA, pl, (double)pown, r, Rk, sk, sb, sn);
+#pragma unroll
+            for (int k = 0; k < MAXA; k++)
+                if (k < nA) {
+                    Rs[b + k] = Rk[k];
+                    sbs[b + k] = sb[k];
+                    Ss[b + k] = sn[k];
+                }
+        }
+        __syncthreads();
+        for (int32_t q = tid; q < S1 - S0; q += BLOCK) {
+            a.sbar[S0 + q] = sbs[q];
+            a.R[S0 + q] = Rs[q];
+            a.sigma[S0 + q] = Ss[q];
+        }
+    } else {
+        if (!has_set) return;
+        if (!((ru.upd >> (pl - 1)) & 1)) return;
+        set_update<T, MAXA, EXT>(ru, a, s0, nA, pl, (double)pown, r);
+    }
 }
 
 template <typename T, int MAXA, int MPT, bool EXPLICIT, bool AFF>
