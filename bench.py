@@ -189,17 +189,17 @@ def run_lifecycle(cfr, torch, games, specs, log, solves=5):
     s.iterate(2)
     reuse, rebuild = [], []
     for _ in range(solves):
-        probs = []
+        ranges = []
         new_specs = []
         for g, sp in zip(games, specs):
             r1 = rng.dirichlet(np.ones(len(sp["hands1"])))
             r2 = rng.dirichlet(np.ones(len(sp["hands2"])))
-            probs.append(gg.subgame_root_probs(g, r1, r2))
+            ranges.append((r1, r2))
             new_specs.append(dict({k: v for k, v in sp.items() if k != "target"}, r1=r1, r2=r2))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k, p in enumerate(probs):
-            s.set_root_chance(p, game=k)
+        for k, (r1, r2) in enumerate(ranges):
+            s.set_root_ranges(r1, r2, game=k)
         s.reset()
         s.iterate(1)
         torch.cuda.synchronize()
@@ -214,7 +214,7 @@ def run_lifecycle(cfr, torch, games, specs, log, solves=5):
     s.close()
     out = dict(solves=solves, reuse_ms_median=1e3 * float(np.median(reuse)),
                rebuild_ms_median=1e3 * float(np.median(rebuild)),
-               what="new root ranges for all games: in-place root chance + reset + first iteration, versus "
+               what="new root ranges for all games: cfr_set_root_ranges + reset + first iteration, versus "
                     "compile + first iteration (graph capture); game generation excluded")
     out["speedup"] = out["rebuild_ms_median"] / out["reuse_ms_median"]
     log(f"[bench] lifecycle: {out}")

@@ -501,18 +501,3 @@ def warm_descriptors(game: Game, mem_off=None, mem_node=None, iset_player=None):
     sc[:, 6] = np.log(np.array(K, np.float64))[opp] / np.log(630.0)
     sc[:, 7] = np.array(ent)[own]
     return bucket, history, sc.astype(np.float32)
-
-
-def subgame_root_probs(game: Game, r1, r2) -> np.ndarray:
-    """Root chance of a subgame (joint deal over its compatible hand pairs, in child order) for
-    new range weights r1, r2 over its hand lists: proportional to r1(h1) r2(h2), with the
-    generator's own arithmetic (left-to-right total, then each product over it)."""
-    m = game.meta
-    p1, p2 = np.asarray(m["pair_h1"]), np.asarray(m["pair_h2"])
-    r1 = [float(x) for x in r1]
-    r2 = [float(x) for x in r2]
-    w = 0.0
-    for a, b in zip(p1, p2):
-        w += r1[a] * r2[b]
-    return np.array([r1[a] * r2[b] / w for a, b in zip(p1, p2)])
-

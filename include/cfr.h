@@ -65,6 +65,13 @@ enum { CFR_NODE_CHANCE = 0, CFR_NODE_P1 = 1, CFR_NODE_P2 = 2, CFR_NODE_TERMINAL 
  *   public_key     [num_nodes] optional (NULL): public-state id of every node; enables
  *                  CFR_LAYOUT_PUBLIC
  *   pot            exploitability unit (> 0) reported back by cfr_counts
+ *   root_hand1, root_hand2
+ *                  optional (NULL): for a game whose root is a chance node dealing one private hand
+ *                  to each player (a subgame's joint deal), the hands dealt by root child a, as indices
+ *                  into the range vectors of cfr_set_root_ranges: [num_children[root]] each, in
+ *                  [0, num_hands1) and [0, num_hands2)
+ *   num_hands1, num_hands2
+ *                  lengths of the two range vectors (read only when root_hand1 is given)
  * Validation (Algorithm 'alg:compile', first pass, plus perfect recall): a tree reachable
  * from root with one parent per non-root node, valid types, chance sums, information sets
  * owned by one player with equal action counts, and identical own-action sequences for all
@@ -81,6 +88,8 @@ typedef struct {
     const double  *payoff;
     const int64_t *public_key;
     double         pot;
+    const int32_t *root_hand1, *root_hand2;
+    int32_t        num_hands1, num_hands2;
 } cfr_game_desc;
 
 /* Update rules (paper Sec. 6, "Update rule and update order"); the constants the paper leaves out
@@ -135,6 +144,8 @@ typedef struct {
                               at h + offset(set, a), the update pass reads one offset per slot instead of
                               the explicit child list (same arithmetic, bitwise equal results); 0: always
                               read the child list */
+    int keep_layout;       /* 1: keep every game's canonical arrays on the host for cfr_get_layout (about
+                              30 bytes per node of host memory; default 0) */
 } cfr_options;
 
 /* Sizes of a compiled game.  blocks = number of depth levels that hold edges (D of eq. blocks). */
@@ -174,9 +185,16 @@ typedef struct cfr_handle cfr_handle;
 void cfr_default_options(cfr_options *opt);
 
 /* Host-only compile (no GPU touched): validate the game and return its canonical arrays
- * in *out (library-allocated; release with cfr_layout_free). */
+ * in *out (library-allocated; release with cfr_layout_free).  The arrays are those cfr_compile
+ * builds for the same description (Appendix H, Algorithm 'alg:compile', passes 1-7). */
 cfr_status cfr_layout_host(const cfr_game_desc *game, cfr_layout *out);
 void cfr_layout_free(cfr_layout *layout);
+
+/* The canonical arrays of game `game` (in [0, n_games)) of a compiled handle, as cfr_layout_host
+ * returns them (library-allocated host copies; release with cfr_layout_free).  The handle must have
+ * been compiled with options.keep_layout = 1 (CFR_ESTATE otherwise); counts.device_bytes and
+ * counts.kernels_per_iteration are those of the whole handle. */
+cfr_status cfr_get_layout(cfr_handle *h, int32_t game, cfr_layout *out);
 
 /* Compile a game onto the device (Algorithm 'alg:compile'): validate, number nodes
  * breadth-first, build depth offsets, information sets and slots, the CSR arrays and
@@ -226,20 +244,24 @@ cfr_status cfr_batch_size(cfr_handle *h, int32_t *n_games, int64_t *slot_base);
 cfr_status cfr_batch_exploitability(cfr_handle *h, void *stream, double *expl, double *br1, double *br2,
                                     double *value_avg, int32_t n);
 
-/* Run n CFR iterations on `stream` (asynchronous).  The first call captures the iteration
- * body into a hipGraph (after one direct iteration that counts toward n) and later calls
- * replay it.  n == 0 is a no-op.  Returns CFR_ESTATE if a persistent buffer recorded at
- * capture time has changed.  Under the persistent schedule the call is one launch that runs all
- * n iterations and synchronises `stream`, so that a per-game barrier time-out (CFR_EDEVICE) is
- * reported by the call that hit it. */
+/* Run n CFR iterations on `stream` (asynchronous): per iteration, regret matching (eq. rm), the
+ * forward reach pass and the backward value pass level by level with the regret, clamp and average
+ * updates fused into the backward levels (Algorithm 'alg:iteration'; Table 'tab:opsteps').  The first
+ * call captures the iteration body into a hipGraph (after one direct iteration that counts toward n)
+ * and later calls replay it (Sec. 4, "CUDA-graph execution").  n == 0 is a no-op.  Returns CFR_ESTATE
+ * if a persistent buffer recorded at capture time has changed, or after a persistent launch stopped
+ * part-way (until cfr_reset or cfr_set_state).  Under the persistent schedule the call is one launch
+ * that runs all n iterations and synchronises `stream`, so that a per-game barrier time-out
+ * (CFR_EDEVICE) is reported by the call that hit it. */
 cfr_status cfr_iterate(cfr_handle *h, int64_t n, void *stream);
 
 /* Iterations completed so far (host count). */
 cfr_status cfr_iterations(cfr_handle *h, int64_t *t);
 
-/* Write the current strategy (regret matching of the latest regrets, i.e. the strategy
- * the next iteration plays) or the normalised average strategy (uniform where the strategy
- * sum is 0) as float32 into dst[len] in canonical slot order; len must equal the slot count.
+/* Write the current strategy (regret matching of the latest regrets, eq. rm: the strategy
+ * the next iteration plays) or the normalised average strategy (the strategy sums of eq. rm over
+ * their total; uniform where the sum is 0) as float32 into dst[len] in canonical slot order; len
+ * must equal the slot count.
  * dst_on_device selects a device (1) or host (0) pointer; a host destination synchronises
  * the stream. */
 cfr_status cfr_strategy(cfr_handle *h, int which, float *dst, int64_t len, int dst_on_device, void *stream);
@@ -261,10 +283,26 @@ cfr_status cfr_reset(cfr_handle *h);
  * NULL), canonical order; FP32 regrets are widened exactly.  Synchronises `stream`. */
 cfr_status cfr_get_state(cfr_handle *h, double *regrets, double *strategy_sum, int64_t len, void *stream);
 
-/* Replace the cumulative regrets with r0[len] (canonical order; host or device pointer per
- * src_on_device) and recompute the current strategy from them: a warm start.  Strategy sums and
- * the counter are left as they are (call cfr_reset first for a fresh solve). */
+/* Replace the cumulative regrets R (eq. regret) with r0[len] (canonical order; host or device pointer
+ * per src_on_device) and recompute the current strategy from them by regret matching (eq. rm): a warm
+ * start.  Strategy sums and the counter are left as they are (call cfr_reset first for a fresh solve);
+ * under PCFR+ the prediction is cleared.  Host sources synchronise `stream`. */
 cfr_status cfr_set_regrets(cfr_handle *h, const float *r0, int64_t len, int src_on_device, void *stream);
+
+/* Checkpoint/resume: replace the solver state with host FP64 arrays of `len` slots in canonical order
+ * -- cumulative regrets (eq. regret), strategy sums (eq. rm) and, under PCFR+, the prediction (the
+ * previous iteration's instantaneous regret) -- and set the iteration counter to t (the next
+ * iteration is t + 1, with that iteration's averaging weight and discounts).  Any array may be NULL:
+ * regrets and sums are then left as they are, the prediction is cleared.  Values are rounded to the
+ * state type; the current strategy is recomputed (eq. rm).  A state taken with cfr_get_state (and
+ * cfr_get_prediction) after t iterations resumes the solve exactly.  CFR_EINVAL for a prediction
+ * under another rule.  Synchronous. */
+cfr_status cfr_set_state(cfr_handle *h, const double *regrets, const double *strategy_sum, const double *prediction,
+                         int64_t len, int64_t t, void *stream);
+
+/* PCFR+ prediction (the latest instantaneous regret) as host FP64 [len], canonical order; CFR_EINVAL
+ * under another rule.  Synchronises `stream`. */
+cfr_status cfr_get_prediction(cfr_handle *h, double *prediction, int64_t len, void *stream);
 
 /* In-place re-solve (paper Appendix H, set_payoffs and set_root_chance; Table 'tab:lifecycle'):
  * rewrite the chance-folded template v_tmpl(z) = pi_c(z) u(z) of one game of the handle (game in
@@ -280,6 +318,17 @@ cfr_status cfr_set_regrets(cfr_handle *h, const float *r0, int64_t len, int src_
  *   child a get pi_c(z) = prob[a] * (the chance product below the root). */
 cfr_status cfr_set_payoffs(cfr_handle *h, int32_t game, const double *payoff, int64_t num_nodes, void *stream);
 cfr_status cfr_set_root_chance(cfr_handle *h, int32_t game, const double *prob, int64_t n, void *stream);
+
+/* In-place re-solve with new root ranges (paper Appendix H, set_root_ranges; Table 'tab:lifecycle'):
+ * for a game compiled with options.lifecycle = 1 whose description gave root_hand1/root_hand2, the
+ * root chance becomes p(a) = r1[root_hand1[a]] r2[root_hand2[a]] / W with W the sum of those products
+ * over the root's children in child order (the joint deal of the two private hands, restricted to the
+ * dealt pairs), and the template is rewritten as by cfr_set_root_chance.  r1 [n1], r2 [n2]: host,
+ * finite, >= 0, n1 = num_hands1 and n2 = num_hands2 of the description.  CFR_ESTATE without lifecycle
+ * records or without the hand map; CFR_EINVAL if W is 0.  Returns with the rewrite queued on
+ * `stream` (the host arrays are read before it returns). */
+cfr_status cfr_set_root_ranges(cfr_handle *h, int32_t game, const double *r1, int64_t n1, const double *r2, int64_t n2,
+                               void *stream);
 
 /* Sizes and per-iteration launch count of a compiled game. */
 cfr_status cfr_counts(cfr_handle *h, cfr_counts_t *out);

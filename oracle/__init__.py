@@ -59,6 +59,8 @@ def _load(f32_state: bool = False):
         lib.or_iterations.restype = ctypes.c_int64
         lib.or_get.argtypes = [_P, _P, _P, _P, _P]
         lib.or_set_state.argtypes = [_P, _P, _P, ctypes.c_int64]
+        lib.or_get_pred.argtypes = [_P, _P]
+        lib.or_set_pred.argtypes = [_P, _P]
         lib.or_best_response.argtypes = [_P, ctypes.c_int, _P, _P]
         lib.or_best_response.restype = ctypes.c_double
         lib.or_profile_value.argtypes = [_P, _P]
@@ -149,10 +151,19 @@ class Oracle:
         self._lib.or_get(self._h, _ptr(R), _ptr(S), _ptr(sc), _ptr(sa))
         return R[: self.A], S[: self.A], sc[: self.A], sa[: self.A]
 
-    def set_state(self, R=None, sbar=None, t=0):
+    def set_state(self, R=None, sbar=None, t=0, pred=None):
         R = None if R is None else np.ascontiguousarray(R, np.float64)
         sbar = None if sbar is None else np.ascontiguousarray(sbar, np.float64)
         self._lib.or_set_state(self._h, _ptr(R), _ptr(sbar), int(t))
+        if pred is not None:
+            p = np.ascontiguousarray(pred, np.float64)
+            self._lib.or_set_pred(self._h, _ptr(p))
+
+    def prediction(self) -> np.ndarray:
+        """PCFR+ prediction (the latest instantaneous regret; zero for the other rules), canonical order."""
+        p = np.zeros(max(self.A, 1))
+        self._lib.or_get_pred(self._h, _ptr(p))
+        return p[: self.A]
 
     def best_response(self, player: int, profile) -> tuple[float, np.ndarray]:
         prof = np.ascontiguousarray(profile, np.float64)

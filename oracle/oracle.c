@@ -471,7 +471,17 @@ void or_set_state(oracle *o, const double *R, const double *sbar, int64_t t) {
     if (R) for (int64_t q = 0; q < o->na; q++) o->R[q] = (st_t)R[q];
     if (sbar) memcpy(o->sbar, sbar, (size_t)o->na * 8);
     memset(o->pred, 0, (size_t)(o->na ? o->na : 1) * sizeof(st_t));   /* no prediction yet */
+    for (int64_t i = 0; i < o->ni; i++) o->avg_stamp[i] = -1;          /* the next iteration adds its average */
     o->t = t;
+}
+
+/* PCFR+ prediction (the latest instantaneous regret), canonical slot order */
+void or_get_pred(const oracle *o, double *pred) {
+    for (int64_t q = 0; q < o->na; q++) pred[q] = (double)o->pred[q];
+}
+
+void or_set_pred(oracle *o, const double *pred) {
+    for (int64_t q = 0; q < o->na; q++) o->pred[q] = (st_t)pred[q];
 }
 
 /* ---------------- evaluation of a fixed profile ---------------- */

@@ -39,7 +39,8 @@ _P = ctypes.c_void_p
 class cfr_game_desc(ctypes.Structure):
     _fields_ = [("num_nodes", ctypes.c_int64), ("root", ctypes.c_int64), ("node_type", _P), ("child_begin", _P),
                 ("num_children", _P), ("children", _P), ("chance_prob", _P), ("infoset_key", _P), ("payoff", _P),
-                ("public_key", _P), ("pot", ctypes.c_double)]
+                ("public_key", _P), ("pot", ctypes.c_double), ("root_hand1", _P), ("root_hand2", _P),
+                ("num_hands1", ctypes.c_int32), ("num_hands2", ctypes.c_int32)]
 
 
 class cfr_options(ctypes.Structure):
@@ -47,7 +48,7 @@ class cfr_options(ctypes.Structure):
                 ("iters_per_graph", ctypes.c_int), ("layout", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("device", ctypes.c_int), ("test_fail_capture", ctypes.c_int), ("precision", ctypes.c_int),
                 ("persistent", ctypes.c_int), ("wg_nodes", ctypes.c_int), ("lifecycle", ctypes.c_int),
-                ("affine", ctypes.c_int)]
+                ("affine", ctypes.c_int), ("keep_layout", ctypes.c_int)]
 
 
 class cfr_tune_result(ctypes.Structure):
@@ -98,7 +99,7 @@ EXPORTS = ["cfr_default_options", "cfr_layout_host", "cfr_layout_free", "cfr_com
            "cfr_mlp_default_desc", "cfr_mlp_create", "cfr_mlp_num_params", "cfr_mlp_set_params", "cfr_mlp_get",
            "cfr_mlp_forward", "cfr_mlp_backward", "cfr_mlp_adam", "cfr_mlp_train_step", "cfr_mlp_destroy",
            "cfr_num_infosets", "cfr_features", "cfr_regret_unit", "cfr_warm_start", "cfr_set_payoffs",
-           "cfr_set_root_chance"]
+           "cfr_set_root_chance", "cfr_set_root_ranges", "cfr_set_state", "cfr_get_prediction", "cfr_get_layout"]
 
 
 def load():
@@ -159,6 +160,10 @@ def load():
         "cfr_regret_unit": (S, [_P, _P, ctypes.c_int64, _P]),
         "cfr_set_payoffs": (S, [_P, ctypes.c_int32, _P, ctypes.c_int64, _P]),
         "cfr_set_root_chance": (S, [_P, ctypes.c_int32, _P, ctypes.c_int64, _P]),
+        "cfr_set_root_ranges": (S, [_P, ctypes.c_int32, _P, ctypes.c_int64, _P, ctypes.c_int64, _P]),
+        "cfr_set_state": (S, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int64, _P]),
+        "cfr_get_prediction": (S, [_P, _P, ctypes.c_int64, _P]),
+        "cfr_get_layout": (S, [_P, ctypes.c_int32, ctypes.POINTER(cfr_layout)]),
         "cfr_warm_start": (S, [_P, _P, _P, ctypes.c_int64, ctypes.c_float, ctypes.c_int32, _P]),
     }
     for name, (res, args) in sig.items():
@@ -197,6 +202,14 @@ class GameDesc:
         d = cfr_game_desc()
         d.num_nodes = len(self.arrays["node_type"])
         d.root = int(getattr(game, "root", 0))
+        # a joint deal of the two private hands at the root (subgames): the hands of each root child
+        meta = getattr(game, "meta", None) or {}
+        if "pair_h1" in meta and "hands1" in meta and "hands2" in meta:
+            h1 = np.ascontiguousarray(meta["pair_h1"], np.int32)
+            if len(h1) == int(self.arrays["num_children"][d.root]):
+                self.arrays["root_hand1"] = h1
+                self.arrays["root_hand2"] = np.ascontiguousarray(meta["pair_h2"], np.int32)
+                d.num_hands1, d.num_hands2 = len(meta["hands1"]), len(meta["hands2"])
         for k, v in self.arrays.items():
             setattr(d, k, _ptr(v))
         d.pot = float(getattr(game, "pot", 1.0))
@@ -214,6 +227,17 @@ def cfr_layout_host(game) -> dict:
     gd = game if isinstance(game, GameDesc) else GameDesc(game)
     lay = cfr_layout()
     _check(load().cfr_layout_host(ctypes.byref(gd.desc), ctypes.byref(lay)))
+    return _layout_dict(lay)
+
+
+def cfr_get_layout(h, game: int = 0) -> dict:
+    """Canonical arrays of one game of a handle compiled with keep_layout."""
+    lay = cfr_layout()
+    _check(load().cfr_get_layout(h, int(game), ctypes.byref(lay)))
+    return _layout_dict(lay)
+
+
+def _layout_dict(lay) -> dict:
     try:
         c = lay.counts
         N, I, A, Nd = c.nodes, c.infosets, c.slots, c.decision_nodes
@@ -313,6 +337,17 @@ def cfr_get_state(h, length: int, stream=None):
 
 def cfr_set_regrets(h, src_ptr, length: int, src_on_device: bool, stream=None):
     _check(load().cfr_set_regrets(h, src_ptr, int(length), int(src_on_device), stream))
+
+
+def cfr_set_state(h, length: int, t: int, regrets=None, strategy_sum=None, prediction=None, stream=None):
+    arrs = [None if a is None else np.ascontiguousarray(a, np.float64) for a in (regrets, strategy_sum, prediction)]
+    _check(load().cfr_set_state(h, *[_ptr(a) for a in arrs], int(length), int(t), stream))
+
+
+def cfr_get_prediction(h, length: int, stream=None):
+    p = np.zeros(max(length, 1), np.float64)
+    _check(load().cfr_get_prediction(h, _ptr(p), int(length), stream))
+    return p[:length]
 
 
 def cfr_counts(h) -> dict:
@@ -446,7 +481,8 @@ class Solver:
 
     def __init__(self, game, rule=CFR_RULE_CFR_PLUS, averaging=CFR_AVG_LINEAR, order=CFR_ORDER_SIMULTANEOUS,
                  iters_per_graph=1, layout=CFR_LAYOUT_PUBLIC, use_graph=True, device=0, test_fail_capture=False,
-                 precision=CFR_PRECISION_FP32, persistent=False, wg_nodes=0, lifecycle=False, affine=True):
+                 precision=CFR_PRECISION_FP32, persistent=False, wg_nodes=0, lifecycle=False, affine=True,
+                 keep_layout=False):
         o = cfr_default_options()
         o.rule, o.averaging, o.order = rule, averaging, order
         o.iters_per_graph, o.layout, o.use_graph = iters_per_graph, layout, int(use_graph)
@@ -455,6 +491,7 @@ class Solver:
         o.persistent, o.wg_nodes = int(persistent), int(wg_nodes)
         o.lifecycle = int(lifecycle)
         o.affine = int(affine)
+        o.keep_layout = int(keep_layout)
         self.options = o
         if isinstance(game, (list, tuple)):
             self.h = cfr_compile_batch(game, o)
@@ -492,6 +529,22 @@ class Solver:
 
     def state(self, stream=None):
         return cfr_get_state(self.h, self.A, self._stream(stream))
+
+    def set_state(self, regrets=None, strategy_sum=None, t: int = 0, prediction=None, stream=None):
+        """Resume from host arrays (canonical order); the next iteration is t + 1."""
+        cfr_set_state(self.h, self.A, t, regrets, strategy_sum, prediction, self._stream(stream))
+
+    def prediction(self, stream=None) -> np.ndarray:
+        return cfr_get_prediction(self.h, self.A, self._stream(stream))
+
+    def layout(self, game: int = 0) -> dict:
+        return cfr_get_layout(self.h, game)
+
+    def set_root_ranges(self, r1, r2, game: int = 0, stream=None):
+        """New root ranges of game `game` (a subgame's joint deal): the library recomputes its root chance."""
+        a = np.ascontiguousarray(r1, np.float64)
+        b = np.ascontiguousarray(r2, np.float64)
+        _check(load().cfr_set_root_ranges(self.h, int(game), _ptr(a), a.size, _ptr(b), b.size, self._stream(stream)))
 
     def set_regrets(self, r0, stream=None):
         if hasattr(r0, "data_ptr"):

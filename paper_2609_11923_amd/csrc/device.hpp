@@ -120,6 +120,10 @@ hipError_t launch_gather_float(const DevGame &g, const float *src, float *dst, h
 hipError_t launch_regrets_from_float(const DevGame &g, const float *src, hipStream_t s);
 // R[map q] += src[q] (canonical float source)
 hipError_t launch_regrets_add_float(const DevGame &g, const float *src, hipStream_t s);
+// dst[map q] <- src[q] for a canonical FP64 source, into the state type (state_type) or into FP64
+hipError_t launch_scatter_double(const DevGame &g, const double *src, void *dst, bool state_type, hipStream_t s);
+// zero A slots of the state type
+hipError_t launch_fill_state(const DevGame &g, void *dst, hipStream_t s);
 // in-place re-solve: u[j] <- payoff_in[in[j]] for records [lo, hi); then the template of those
 // terminals: v = vbr = (root ? root[branch] * pic : pic) * u
 hipError_t launch_gather_payoffs(int64_t lo, int64_t hi, const int32_t *in, const double *payoff_in, double *u,

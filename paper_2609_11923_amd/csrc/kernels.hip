@@ -643,10 +643,14 @@ __device__ __forceinline__ bool game_barrier(int32_t *ctr, int32_t W, int32_t &e
         epoch += 1;
         __threadfence();
         atomicAdd(ctr, 1);
-        const int32_t target = epoch * W;
+        // Arrivals are counted modulo 2^32 and compared by signed difference, so the count may wrap
+        // over a long launch.  The poll is a relaxed load: an acquiring load per poll would
+        // invalidate this compute unit's caches on every spin.  One fence after the count is
+        // reached makes the other blocks' writes visible.
+        const uint32_t target = (uint32_t)epoch * (uint32_t)W;
         const int64_t t_start = (int64_t)wall_clock64();
         int32_t ok = 1;
-        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while ((int32_t)((uint32_t)__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
             if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
                 (int64_t)wall_clock64() - t_start > timeout_ticks) {
                 atomicExch(err, 1);
@@ -1189,6 +1193,36 @@ hipError_t launch_regrets_add_float(const DevGame &g, const float *src, hipStrea
     else
         hipLaunchKernelGGL((k_scatter_add<float, float>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, g.slot_map,
                            src, (float *)g.R);
+    return hipGetLastError();
+}
+
+// dst[map q] <- src[q] for a canonical FP64 source: into the state type (R, prediction) or into the FP64
+// strategy sums
+hipError_t launch_scatter_double(const DevGame &g, const double *src, void *dst, bool state_type, hipStream_t s) {
+    if (g.A == 0) return hipSuccess;
+    if (!state_type)
+        hipLaunchKernelGGL((k_scatter<double, double>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, g.slot_map, src,
+                           (double *)dst);
+    else if (g.fp64)
+        hipLaunchKernelGGL((k_scatter<double, double>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, g.slot_map, src,
+                           (double *)dst);
+    else
+        hipLaunchKernelGGL((k_scatter<double, float>), dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, g.slot_map, src,
+                           (float *)dst);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_zero(int32_t n, T *__restrict__ p) {
+    const int32_t i = (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
+    if (i < n) p[i] = T(0);
+}
+
+// A slots of the state type set to zero (a fill kernel, so it may sit in a captured graph)
+hipError_t launch_fill_state(const DevGame &g, void *dst, hipStream_t s) {
+    if (g.A == 0) return hipSuccess;
+    if (g.fp64) hipLaunchKernelGGL(k_zero<double>, dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, (double *)dst);
+    else hipLaunchKernelGGL(k_zero<float>, dim3(grid_for(g.A)), dim3(BLOCK), 0, s, g.A, (float *)dst);
     return hipGetLastError();
 }
 

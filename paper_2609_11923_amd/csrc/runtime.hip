@@ -62,6 +62,9 @@ struct cfr_handle {
     std::vector<double> game_pot;
     // persistent schedule
     bool persistent = false;
+    // set when a persistent launch stopped part-way (a barrier timed out): the state is partial, so
+    // cfr_iterate refuses until cfr_reset starts over
+    bool broken = false;
     // LDS-resident schedule (one tiny game, one workgroup): per-depth ranges on the device
     bool lds = false;
     int32_t *lds_range = nullptr;
@@ -110,6 +113,12 @@ struct cfr_handle {
     double *lc_pic = nullptr;          // chance product below the root (the whole product without a chance root)
     double *lc_root = nullptr;         // root chance probabilities
     double *lc_stage = nullptr;        // staging for a game's payoff array
+    // root hand map of each game (cfr_set_root_ranges): root child a of game s deals hands
+    // (lc_hand1[k], lc_hand2[k]), k = lc_hand_off[s] + a; lc_nh1/lc_nh2 are the range lengths
+    std::vector<int64_t> lc_hand_off;
+    std::vector<int32_t> lc_hand1, lc_hand2, lc_nh1, lc_nh2;
+    // canonical arrays of every game (options.keep_layout), for cfr_get_layout
+    std::vector<Layout> layouts;
 };
 
 // Per-launch event timing for cfr_profile: class 0 tick, 1 forward, 2 level.
@@ -338,6 +347,8 @@ void cfr_default_options(cfr_options *o) {
 
 const char *cfr_last_error(void) { return g_err.c_str(); }
 
+static cfr_status layout_out(const Layout &L, double pot, cfr_layout *out);
+
 cfr_status cfr_layout_host(const cfr_game_desc *game, cfr_layout *out) {
     if (!out) return fail(CFR_EINVAL, "out is NULL");
     std::memset(out, 0, sizeof *out);
@@ -345,7 +356,23 @@ cfr_status cfr_layout_host(const cfr_game_desc *game, cfr_layout *out) {
     std::string err;
     cfr_status st = build_layout(game, L, err);
     if (st != CFR_OK) return fail(st, err);
-    fill_counts(L, &out->counts, game->pot);
+    return layout_out(L, game->pot, out);
+}
+
+cfr_status cfr_get_layout(cfr_handle *h, int32_t game, cfr_layout *out) {
+    if (!h || !out) return fail(CFR_EINVAL, "NULL argument");
+    std::memset(out, 0, sizeof *out);
+    if (game < 0 || game >= h->n_games) return fail(CFR_EINVAL, "game index out of range");
+    if (h->layouts.empty()) return fail(CFR_ESTATE, "compile with options.keep_layout = 1 to keep the canonical arrays");
+    cfr_status st = layout_out(h->layouts[(size_t)game], h->game_pot[(size_t)game], out);
+    if (st != CFR_OK) return st;
+    out->counts.device_bytes = h->device_bytes;
+    out->counts.kernels_per_iteration = h->launches;
+    return CFR_OK;
+}
+
+static cfr_status layout_out(const Layout &L, double pot, cfr_layout *out) {
+    fill_counts(L, &out->counts, pot);
     out->depth_off = copy_out(L.depth_off);
     out->parent = copy_out(L.parent);
     out->child_off = copy_out(L.child_off);
@@ -512,7 +539,11 @@ static cfr_status persistent_iterate(cfr_handle *h, int64_t n, hipStream_t s) {
     int32_t err = 0;
     HIP_TRY(hipMemcpyAsync(&err, h->pp.err, sizeof err, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (err) return fail(CFR_EDEVICE, "a per-game barrier of the persistent launch timed out");
+    if (err) {
+        h->broken = true;
+        return fail(CFR_EDEVICE, "a per-game barrier of the persistent launch timed out; the solver state is "
+                                 "partial (call cfr_reset)");
+    }
     h->iters += n;
     return CFR_OK;
 }
@@ -587,10 +618,33 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     int max_actions = 0, max_depth = 0, blocks = 0;
     std::vector<int32_t> canon_off;
     std::vector<int8_t> canon_player;
+    std::vector<int64_t> hand_off{0};
+    std::vector<int32_t> hand1, hand2, nh1, nh2;
     for (int s = 0; s < n; s++) {
         Ls[s].keep_maps = o.lifecycle != 0;
         st = build_layout(&games[s], Ls[s], err);
         if (st != CFR_OK) return fail(st, n > 1 ? "game " + std::to_string(s) + ": " + err : err);
+        const cfr_game_desc &gd = games[s];
+        if (gd.root_hand1 || gd.root_hand2) {
+            const std::string pre = n > 1 ? "game " + std::to_string(s) + ": " : "";
+            if (!gd.root_hand1 || !gd.root_hand2) return fail(CFR_EINVAL, pre + "root_hand1 and root_hand2 go together");
+            if (gd.node_type[gd.root] != CFR_NODE_CHANCE)
+                return fail(CFR_EINVAL, pre + "a root hand map needs a chance root");
+            if (gd.num_hands1 <= 0 || gd.num_hands2 <= 0) return fail(CFR_EINVAL, pre + "num_hands1/2 must be positive");
+            for (int32_t a = 0; a < gd.num_children[gd.root]; a++) {
+                const int32_t x = gd.root_hand1[a], y = gd.root_hand2[a];
+                if (x < 0 || x >= gd.num_hands1 || y < 0 || y >= gd.num_hands2)
+                    return fail(CFR_EINVAL, pre + "root hand index out of range at root child " + std::to_string(a));
+                hand1.push_back(x);
+                hand2.push_back(y);
+            }
+            nh1.push_back(gd.num_hands1);
+            nh2.push_back(gd.num_hands2);
+        } else {
+            nh1.push_back(0);
+            nh2.push_back(0);
+        }
+        hand_off.push_back((int64_t)hand1.size());
         if (!Ls[s].br_ok)
             return fail(CFR_EUNSUPPORTED, "an information set has members at different depths; the level-fused "
                                           "update needs every set on one depth");
@@ -618,7 +672,7 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
             st = build_device_layout(Ls[s], o.layout, max_actions, o.precision == CFR_PRECISION_FP64, Ds[s], err);
             if (st != CFR_OK) return fail(st, err);
             if (o.lifecycle) lifecycle_records(games[s], Ls[s], Ds[s], lc);
-            if (n > 1) Ls[s] = Layout();  // free the canonical arrays early
+            if (n > 1 && !o.keep_layout) Ls[s] = Layout();  // free the canonical arrays early
         }
         st = build_forest(Ls, Ds, DL, err);
         if (st != CFR_OK) return fail(st, err);
@@ -648,6 +702,11 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     h->game_depth = DL.game_depth;
     h->game_range = DL.game_range;
     for (int s = 0; s < n; s++) h->game_pot.push_back(games[s].pot);
+    h->lc_hand_off = std::move(hand_off);
+    h->lc_hand1 = std::move(hand1);
+    h->lc_hand2 = std::move(hand2);
+    h->lc_nh1 = std::move(nh1);
+    h->lc_nh2 = std::move(nh2);
     h->D = blocks;
     h->br_ok = true;
     h->E = E; h->Z = Z; h->pot = games[0].pot;
@@ -783,6 +842,7 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     }
     st = cfr_reset(h);
     if (st != CFR_OK) { free_handle(h); return st; }
+    if (o.keep_layout) h->layouts = std::move(Ls);
     *out = h;
     return CFR_OK;
 }
@@ -815,9 +875,11 @@ cfr_status cfr_reset(cfr_handle *h) {
     if (g.pred) HIP_TRY(hipMemsetAsync(g.pred, 0, (size_t)(g.A > 0 ? g.A : 1) * h->es, s));
     HIP_TRY(hipMemsetAsync(g.sbar, 0, (size_t)(g.A > 0 ? g.A : 1) * sizeof(double), s));
     HIP_TRY(hipMemsetAsync(g.t, 0, sizeof(int32_t), s));
+    if (h->pp.err) HIP_TRY(hipMemsetAsync(h->pp.err, 0, sizeof(int32_t), s));
     HIP_TRY(launch_regret_matching(g, s));
     HIP_TRY(hipStreamSynchronize(s));
     h->iters = 0;
+    h->broken = false;
     return CFR_OK;
 }
 
@@ -827,6 +889,7 @@ cfr_status cfr_iterate(cfr_handle *h, int64_t n, void *stream) {
     if (n == 0) return CFR_OK;
     HIP_TRY(hipSetDevice(h->opt.device));
     hipStream_t s = (hipStream_t)stream;
+    if (h->broken) return fail(CFR_ESTATE, "a persistent launch stopped part-way; call cfr_reset first");
     if (h->persistent || h->lds) return persistent_iterate(h, n, s);
     if (h->captured && h->pinned != persistent_ptrs(h))
         return fail(CFR_ESTATE, "a persistent buffer changed since graph capture; refusing to replay");
@@ -940,6 +1003,68 @@ cfr_status cfr_set_regrets(cfr_handle *h, const float *r0, int64_t len, int src_
     HIP_TRY(launch_regrets_from_float(h->g, h->g.out, s));
     HIP_TRY(launch_regret_matching(h->g, s));
     if (!src_on_device) HIP_TRY(hipStreamSynchronize(s));
+    return CFR_OK;
+}
+
+cfr_status cfr_set_state(cfr_handle *h, const double *regrets, const double *strategy_sum, const double *prediction,
+                         int64_t len, int64_t t, void *stream) {
+    if (!h) return fail(CFR_EINVAL, "handle is NULL");
+    if (len != h->g.A) return fail(CFR_EINVAL, "len must equal the slot count " + std::to_string(h->g.A));
+    if (t < 0 || t > 0x7fffffffLL) return fail(CFR_EINVAL, "t must be in [0, 2^31)");
+    if (prediction && !h->g.pred) return fail(CFR_EINVAL, "only PCFR+ keeps a prediction");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    hipStream_t s = (hipStream_t)stream;
+    const DevGame &g = h->g;
+    // every array goes through the FP64 evaluation scratch (sigbar, A doubles) and is scattered to
+    // device slot order in the state type; the stream is synchronised before the staging is reused
+    auto put = [&](const double *src, void *dst, bool state_type) -> cfr_status {
+        HIP_TRY(hipMemcpyAsync(g.sigbar, src, (size_t)len * sizeof(double), hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_scatter_double(g, g.sigbar, dst, state_type, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return CFR_OK;
+    };
+    cfr_status st = CFR_OK;
+    if (len > 0) {
+        if (regrets && (st = put(regrets, g.R, true)) != CFR_OK) return st;
+        if (strategy_sum && (st = put(strategy_sum, g.sbar, false)) != CFR_OK) return st;
+        if (g.pred) {
+            if (prediction) {
+                if ((st = put(prediction, g.pred, true)) != CFR_OK) return st;
+            } else {
+                HIP_TRY(launch_fill_state(g, g.pred, s));
+            }
+        }
+    }
+    const int32_t t32 = (int32_t)t;
+    HIP_TRY(hipMemcpyAsync(g.t, &t32, sizeof t32, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_regret_matching(g, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    h->iters = t;
+    h->broken = false;
+    return CFR_OK;
+}
+
+cfr_status cfr_get_prediction(cfr_handle *h, double *prediction, int64_t len, void *stream) {
+    if (!h || (!prediction && len > 0)) return fail(CFR_EINVAL, "NULL argument");
+    if (len != h->g.A) return fail(CFR_EINVAL, "len must equal the slot count " + std::to_string(h->g.A));
+    if (!h->g.pred) return fail(CFR_EINVAL, "only PCFR+ keeps a prediction");
+    if (len == 0) return CFR_OK;
+    HIP_TRY(hipSetDevice(h->opt.device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<double> pd((size_t)len);
+    std::vector<float> pf;
+    if (h->g.fp64) {
+        HIP_TRY(hipMemcpyAsync(pd.data(), h->g.pred, (size_t)len * 8, hipMemcpyDeviceToHost, s));
+    } else {
+        pf.resize((size_t)len);
+        HIP_TRY(hipMemcpyAsync(pf.data(), h->g.pred, (size_t)len * 4, hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    const bool ident = h->slot_map.empty();
+    for (int64_t q = 0; q < len; q++) {
+        const size_t dq = ident ? (size_t)q : (size_t)h->slot_map[(size_t)q];
+        prediction[q] = h->g.fp64 ? pd[dq] : (double)pf[dq];
+    }
     return CFR_OK;
 }
 
@@ -1151,6 +1276,8 @@ cfr_status cfr_autotune(cfr_handle *h, int64_t iters, void *stream, const char *
                 std::fprintf(stderr, "cfr: autotune dropped persistent schedule wg_nodes=%d (%s)\n", h->wg_nodes,
                              g_err.c_str());
                 failed++;
+                st = cfr_reset(h);   // the failed launch left a partial state behind
+                if (st != CFR_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return st; }
                 continue;
             }
             if (st != CFR_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return st; }
@@ -1224,6 +1351,17 @@ cfr_status cfr_set_payoffs(cfr_handle *h, int32_t game, const double *payoff, in
     return CFR_OK;
 }
 
+// Root chance of `game` <- prob[n] (validated by the caller) and the game's template rewritten.
+static cfr_status write_root_chance(cfr_handle *h, int32_t game, const double *prob, int64_t n, hipStream_t s) {
+    const int64_t r0 = h->lc_root_off[(size_t)game];
+    HIP_TRY(hipSetDevice(h->opt.device));
+    HIP_TRY(hipMemcpyAsync(h->lc_root + r0, prob, (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
+    cfr_status st = lifecycle_template(h, game, s);
+    if (st != CFR_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s));
+    return CFR_OK;
+}
+
 cfr_status cfr_set_root_chance(cfr_handle *h, int32_t game, const double *prob, int64_t n, void *stream) {
     cfr_status st = lifecycle_check(h, game);
     if (st != CFR_OK) return st;
@@ -1236,13 +1374,31 @@ cfr_status cfr_set_root_chance(cfr_handle *h, int32_t game, const double *prob, 
         sum += prob[a];
     }
     if (std::fabs(sum - 1.0) > 1e-9) return fail(CFR_EINVAL, "root chance probabilities do not sum to 1");
-    HIP_TRY(hipSetDevice(h->opt.device));
-    hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(hipMemcpyAsync(h->lc_root + r0, prob, (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
-    st = lifecycle_template(h, game, s);
+    return write_root_chance(h, game, prob, n, (hipStream_t)stream);
+}
+
+cfr_status cfr_set_root_ranges(cfr_handle *h, int32_t game, const double *r1, int64_t n1, const double *r2, int64_t n2,
+                               void *stream) {
+    cfr_status st = lifecycle_check(h, game);
     if (st != CFR_OK) return st;
-    HIP_TRY(hipStreamSynchronize(s));
-    return CFR_OK;
+    const int64_t k0 = h->lc_hand_off[(size_t)game], k1 = h->lc_hand_off[(size_t)game + 1];
+    if (k1 == k0) return fail(CFR_ESTATE, "the game was compiled without a root hand map (root_hand1/root_hand2)");
+    if (!r1 || !r2) return fail(CFR_EINVAL, "NULL range");
+    if (n1 != h->lc_nh1[(size_t)game] || n2 != h->lc_nh2[(size_t)game])
+        return fail(CFR_EINVAL, "range lengths must equal num_hands1 and num_hands2 of the description");
+    for (int64_t i = 0; i < n1; i++)
+        if (!(r1[i] >= 0.0) || !std::isfinite(r1[i])) return fail(CFR_EINVAL, "invalid range weight for player 1");
+    for (int64_t i = 0; i < n2; i++)
+        if (!(r2[i] >= 0.0) || !std::isfinite(r2[i])) return fail(CFR_EINVAL, "invalid range weight for player 2");
+    // p(a) = r1(h1(a)) r2(h2(a)) / W, W the sum of the products over the root's children in child order
+    const int64_t n = k1 - k0;
+    std::vector<double> prob((size_t)n);
+    double W = 0.0;
+    for (int64_t a = 0; a < n; a++) W += r1[h->lc_hand1[(size_t)(k0 + a)]] * r2[h->lc_hand2[(size_t)(k0 + a)]];
+    if (!(W > 0.0) || !std::isfinite(W)) return fail(CFR_EINVAL, "the ranges give no dealt pair a positive weight");
+    for (int64_t a = 0; a < n; a++)
+        prob[(size_t)a] = r1[h->lc_hand1[(size_t)(k0 + a)]] * r2[h->lc_hand2[(size_t)(k0 + a)]] / W;
+    return write_root_chance(h, game, prob.data(), n, (hipStream_t)stream);
 }
 
 cfr_status cfr_num_infosets(cfr_handle *h, int64_t *count) {

@@ -1,4 +1,4 @@
-"""GPU tests of the in-place re-solve (paper Appendix H, set_payoffs / set_root_chance; Table
+"""GPU tests of the in-place re-solve (paper Appendix H, set_payoffs / set_root_chance / set_root_ranges; Table
 'tab:lifecycle'): rewriting a compiled game's payoffs or root chance reproduces a fresh compile of
 the changed game, without reallocating and with the captured graph still replaying."""
 import dataclasses
@@ -42,7 +42,7 @@ def new_ranges(sp, seed):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("layout", ["public", "bfs"])
-def test_set_root_chance_equals_a_fresh_compile(precision, layout):
+def test_set_root_ranges_equals_a_fresh_compile(precision, layout):
     """New ranges for every subgame of a batch, written after a solve whose graph was captured: a
     reset and a new solve then equal, bitwise, a batch compiled from the new subgames."""
     sps = specs(6, 2)
@@ -54,7 +54,7 @@ def test_set_root_chance_equals_a_fresh_compile(precision, layout):
     sps2 = [new_ranges(sp, 10 + k) for k, sp in enumerate(sps)]
     games2 = [gg.subgame(**sp) for sp in sps2]
     for k, (g, sp) in enumerate(zip(games, sps2)):
-        s.set_root_chance(gg.subgame_root_probs(g, sp["r1"], sp["r2"]), game=k)
+        s.set_root_ranges(sp["r1"], sp["r2"], game=k)
     s.reset()
     s.iterate(40)
     t = cfr.Solver(games2, precision=p, layout=lay)
@@ -117,7 +117,7 @@ def test_resolve_continues_from_the_previous_solution():
     s = cfr.Solver(g, precision=cfr.CFR_PRECISION_FP64, lifecycle=True)
     s.iterate(300)
     sp2 = new_ranges(sp, 7)
-    s.set_root_chance(gg.subgame_root_probs(g, sp2["r1"], sp2["r2"]))
+    s.set_root_ranges(sp2["r1"], sp2["r2"])
     e_before = s.exploitability()[0]
     _, S_before = s.state()
     s.iterate(300)
@@ -149,3 +149,25 @@ def test_lifecycle_errors():
     with pytest.raises(cfr.CfrError) as e:
         d.set_root_chance(np.ones(1))
     assert e.value.status == cfr.CFR_EINVAL and "chance" in str(e.value)
+
+
+def test_set_root_ranges_errors():
+    g = gg.kuhn()   # a sequential deal: no joint-deal hand map at the root
+    s = cfr.Solver(g, lifecycle=True)
+    with pytest.raises(cfr.CfrError) as e:
+        s.set_root_ranges(np.ones(3), np.ones(3))
+    assert e.value.status == cfr.CFR_ESTATE
+    sp = specs(1, 5)[0]
+    sub = gg.subgame(**sp)
+    t = cfr.Solver(sub)   # no lifecycle records
+    with pytest.raises(cfr.CfrError) as e:
+        t.set_root_ranges(sp["r1"], sp["r2"])
+    assert e.value.status == cfr.CFR_ESTATE
+    u = cfr.Solver(sub, lifecycle=True)
+    n1, n2 = len(sp["hands1"]), len(sp["hands2"])
+    for r1, r2 in ((np.ones(n1 + 1), np.ones(n2)), (np.zeros(n1), np.ones(n2)), (np.full(n1, -1.0), np.ones(n2)),
+                   (np.full(n1, np.nan), np.ones(n2))):
+        with pytest.raises(cfr.CfrError) as e:
+            u.set_root_ranges(r1, r2)
+        assert e.value.status == cfr.CFR_EINVAL
+    u.set_root_ranges(np.ones(n1), np.ones(n2))   # uniform ranges are valid
