@@ -52,6 +52,7 @@ def _load(f32_state: bool = False):
         lib.or_layout.argtypes = [_P] + [_P] * 12
         lib.or_set_options.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         lib.or_set_rule.argtypes = [_P, ctypes.c_int]
+        lib.or_set_reverse.argtypes = [_P, ctypes.c_int]
         lib.or_reset.argtypes = [_P]
         lib.or_iterate.argtypes = [_P, ctypes.c_int64]
         lib.or_iterate.restype = ctypes.c_double
@@ -81,11 +82,12 @@ RULES = {"cfr": 0, "cfr+": 1, "dcfr": 2, "pcfr+": 3}
 
 class Oracle:
     """FP64 CFR oracle over one explicit game (a ``gamegen.Game``-like object).
-    f32_state=True selects the FP32-state control build.  rule (optional) overrides plus:
+    f32_state=True selects the FP32-state control build; reverse=True sums children in reverse order
+    (a control: another correct rounding pattern).  rule (optional) overrides plus:
     "cfr", "cfr+", "dcfr" or "pcfr+" (see oracle.c for their definitions)."""
 
     def __init__(self, game, plus: bool = True, linear: bool = True, alternating: bool = False,
-                 f32_state: bool = False, rule: str | None = None):
+                 f32_state: bool = False, rule: str | None = None, reverse: bool = False):
         self._lib = lib = _load(f32_state)
         self._keep = [np.ascontiguousarray(game.type, np.int8), np.ascontiguousarray(game.child_begin, np.int64),
                       np.ascontiguousarray(game.n_children, np.int32), np.ascontiguousarray(game.children, np.int64),
@@ -105,6 +107,8 @@ class Oracle:
         self.set_options(plus, linear, alternating)
         if rule is not None:
             self._lib.or_set_rule(self._h, RULES[rule])
+        if reverse:
+            self._lib.or_set_reverse(self._h, 1)
 
     def __del__(self):
         h = getattr(self, "_h", None)

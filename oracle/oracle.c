@@ -23,6 +23,7 @@
  *        R^t       = R^{t-1} + r      (CFR+: then R^t <- max(R^t, 0))
  *        sbar(I,a) += w_t pi_i(I) sigma^t(I,a),  w_t = t (linear) or 1
  *    Simultaneous updates: both players' regrets come from one profile.
+ *    (A control option sums each node's children in reverse order: another rounding pattern.)
  *    Alternating updates: player 1's half-iteration (regret and average of
  *    player 1 only) runs first; player 2's half then sees player 1's updated
  *    strategy.
@@ -87,6 +88,7 @@ typedef struct {
     double *sbar;
     int64_t *avg_stamp;           /* per infoset: last (iteration, player) stamp the average was added */
     int rule, linear, alternating; /* rule: RULE_CFR, RULE_CFR_PLUS, RULE_DCFR, RULE_PCFR_PLUS */
+    int reverse;                  /* control option: sum each node's children in reverse order */
     int64_t t;                    /* iterations done */
     /* scratch for BR */
     double *memo, *q;
@@ -327,6 +329,11 @@ void or_set_options(oracle *o, int plus, int linear, int alternating) {
 /* rule: RULE_CFR .. RULE_PCFR_PLUS (linear applies to CFR and CFR+ only) */
 void or_set_rule(oracle *o, int rule) { o->rule = rule; }
 
+/* Control option: values summed over each node's children in reverse order -- another correct
+ * summation order, whose rounding differs from the default's (used to sample how far runs of one
+ * precision spread; the iterates agree with the default order up to rounding). */
+void or_set_reverse(oracle *o, int reverse) { o->reverse = reverse; }
+
 void or_reset(oracle *o) {
     int64_t A = o->na;
     memset(o->R, 0, (size_t)(A ? A : 1) * sizeof(st_t));
@@ -368,7 +375,8 @@ static st_t walk(oracle *o, int64_t h, st_t pi1, st_t pi2, st_t pic, int upd, do
     if (ty == TERM) return (st_t)o->payoff[h];
     if (ty == CH) {
         st_t v = 0;
-        for (int32_t a = 0; a < o->nk[h]; a++) {
+        for (int32_t k = 0; k < o->nk[h]; k++) {
+            const int32_t a = o->reverse ? o->nk[h] - 1 - k : k;
             st_t p = (st_t)o->prob[o->kb[h] + a];
             v += p * walk(o, o->kids[o->kb[h] + a], pi1, pi2, pic * p, upd, w, stamp);
         }
@@ -379,7 +387,8 @@ static st_t walk(oracle *o, int64_t h, st_t pi1, st_t pi2, st_t pic, int upd, do
     const st_t *sig = o->sigma + I->slot;
     st_t va[64];
     st_t v = 0;
-    for (int32_t a = 0; a < I->nA; a++) {
+    for (int32_t k = 0; k < I->nA; k++) {
+        const int32_t a = o->reverse ? I->nA - 1 - k : k;
         st_t c1 = ty == PL1 ? pi1 * sig[a] : pi1;
         st_t c2 = ty == PL2 ? pi2 * sig[a] : pi2;
         va[a] = walk(o, o->kids[o->kb[h] + a], c1, c2, pic, upd, w, stamp);

@@ -394,6 +394,15 @@ cfr_status build_device_layout(const Layout &L, int kind, int group_actions, boo
             if (sets > 0) D.grp_iset_off.push_back(D.iset_depth_off[d + 1]);
             D.grp_depth_off[d + 1] = (int32_t)D.grp_iset_off.size() - 1;
         }
+        // the update kernels stream a group through LDS in chunks of `cap` members and map members to
+        // sets for the first chunk only: a group that needs several chunks must hold a single set
+        for (size_t gi = 0; gi + 1 < D.grp_iset_off.size(); gi++) {
+            const int32_t i0 = D.grp_iset_off[gi], i1 = D.grp_iset_off[gi + 1];
+            if (i1 - i0 > 1 && D.mem_off[i1] - D.mem_off[i0] > cap) {
+                err = "internal: an update group of several sets exceeds one staging chunk";
+                return CFR_EINVAL;
+            }
+        }
         // internal chance nodes by depth
         D.chance_off.assign((size_t)md + 2, 0);
         D.bigc_off.assign((size_t)md + 2, 0);

@@ -136,3 +136,15 @@ def test_default_options():
     o = cfr.cfr_default_options()
     assert (o.rule, o.averaging, o.order, o.iters_per_graph, o.layout, o.use_graph, o.precision) == \
         (0, 0, 0, 1, cfr.CFR_LAYOUT_PUBLIC, 1, cfr.CFR_PRECISION_FP32)
+
+
+def test_big_set_games_reach_the_staging_paths():
+    """The wide games of the GPU big-set tests have what those tests are for: sets larger than one LDS
+    staging chunk (1,100 > 1,024 FP32 / 512 FP64 members with 3 actions; 300 > 256 with 6 and with 20
+    actions) and sets of more than 16 actions (host compile only)."""
+    from test_gpu_big_sets import GAMES
+    want = {"members1100_actions3": (1100, 3), "members300_actions6": (300, 6), "members300_actions20": (300, 20)}
+    for name, f in GAMES.items():
+        lay = cfr.cfr_layout_host(f())
+        assert np.diff(lay["mem_off"]).max() == want[name][0]
+        assert np.diff(lay["slot_off"]).max() == want[name][1]

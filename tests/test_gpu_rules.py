@@ -1,10 +1,17 @@
 """GPU parity of the update rules and orders (paper Sec. 6, update rule and update order): CFR, CFR+,
 DCFR and PCFR+, simultaneous and alternating, against the FP64 oracle's same rule after 100
-iterations.  The bar is that of the plain parity tests (regrets and strategies <= 1e-5 normwise,
-exploitability <= 1e-6 pot); where the rule's own dynamics amplify a rounding-level change of the
-inputs beyond it, and for FP32 state, the tolerance is 10 x the oracle's measured drift (see
-tolerances())."""
-import dataclasses
+free-running iterations.
+
+The bar is that of the plain parity tests: regrets and strategies <= 1e-5 normwise, exploitability
+within 1e-6 pot, reach-weighted strategy and regret errors <= 1e-5.  Some rules amplify a
+rounding-level difference from iteration to iteration (the clamp and the discount switch on signs;
+alternating updates feed one player's change straight into the other's half).  How far is measured,
+not assumed: the oracle itself is run again with its children summed in reverse order (another
+correct rounding pattern; FP32 state: its FP32-state build in both orders) and the spread of those
+runs around the FP64 run sets the tolerance, 4 x the spread.  A tolerance must stay below 1e-3
+(exploitability: below 1e-5 pot).  A cell whose own runs spread further cannot be compared after a
+free run -- there the test records an expected failure with the measured spread -- and is held to the
+1e-5 bar at every one of its 100 iterations by the one-step test (tests/test_gpu_step_parity.py)."""
 import sys
 
 import numpy as np
@@ -13,29 +20,23 @@ import pytest
 import gamegen as gg
 import oracle
 import paper_2609_11923_amd as cfr
+from parity_metrics import jitter, rel_err, set_reach, slot_weights, weighted_err
 
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
 EXPL_TOL = 1e-6
+CAP = 1e-3
+EXPL_CAP = 1e-5
+MULT = 4
 RULES = {"cfr": cfr.CFR_RULE_CFR, "cfr+": cfr.CFR_RULE_CFR_PLUS, "dcfr": cfr.CFR_RULE_DCFR,
          "pcfr+": cfr.CFR_RULE_PCFR_PLUS}
 ORDERS = {"sim": cfr.CFR_ORDER_SIMULTANEOUS, "alt": cfr.CFR_ORDER_ALTERNATING}
 PREC = {"fp64": cfr.CFR_PRECISION_FP64, "fp32": cfr.CFR_PRECISION_FP32}
 
-
-def jitter(game, seed, eps=1e-3):
-    """The game with every terminal payoff moved by up to eps (seeded).  Kuhn and Leduc have exact
-    symmetries that park some regrets exactly at zero; there regret matching (plus) switches
-    between uniform and pure on the last bit, and two correct summation orders part ways (see
-    test_alternating_kuhn_divergence_is_the_discontinuity).  Generic payoffs avoid those ties."""
-    rng = np.random.default_rng(seed)
-    pay = np.array(game.payoff, np.float64)
-    term = np.asarray(game.type) == 3
-    pay[term] += eps * rng.uniform(-1, 1, int(term.sum()))
-    return dataclasses.replace(game, payoff=pay)
-
-
+# Kuhn and Leduc have exact symmetries that park some regrets exactly at zero, where regret matching
+# (plus) switches between uniform and pure on the last bit (test_alternating_kuhn_divergence_is_the_
+# discontinuity); generic payoffs (moved by up to 1e-3) avoid those ties.
 GAMES = {
     "kuhn": lambda: jitter(gg.kuhn(), 1),
     "leduc3x2": lambda: jitter(gg.leduc(3, 2), 2),
@@ -49,46 +50,63 @@ def note(msg):
     sys.stdout.flush()
 
 
-def rel_err(x, ref):
-    if ref.size == 0:
-        return 0.0
-    return float(np.abs(np.asarray(x, np.float64) - ref).max() / max(np.abs(ref).max(), 1e-30))
-
-
 def solver(game, rule, order, precision="fp64", **kw):
     return cfr.Solver(game, rule=RULES[rule], order=ORDERS[order], precision=PREC[precision], **kw)
 
 
-def ref(game, rule, order, T, f32_state=False):
-    o = oracle.Oracle(game, alternating=(order == "alt"), rule=rule, f32_state=f32_state)
+def ref(game, rule, order, T, f32_state=False, reverse=False):
+    o = oracle.Oracle(game, alternating=(order == "alt"), rule=rule, f32_state=f32_state, reverse=reverse)
     o.iterate(T)
     return o
 
 
-def tolerances(game, rule, order, T, precision, o):
-    """(regrets, average, current, exploitability) tolerances.  The bar, unless the oracle's own
-    iterates move more than that under a change of the inputs at the level of one rounding
-    (payoffs moved by 1e-15): alternating CFR+ and DCFR on Leduc amplify such a change to ~1e-4 in
-    100 iterations (the clamp and the discount switch on signs), so two correct summation orders
-    cannot agree closer.  Then, and for FP32 state (the oracle's FP32-state control build, plain and
-    with inputs moved at the FP32 rounding level), the tolerance is 10 x the largest measured
-    drift.  For the most sensitive FP32 cells that tolerance is loose; FP64 state is the parity
-    check there."""
+def spread(game, rule, order, T, precision, o):
+    """(regrets, average, current, exploitability) spread of the oracle's own runs of this precision
+    around its FP64 run: FP64 in reverse summation order; FP32 state in both orders."""
     Ro, _, sco, sao = o.state()
     eo = o.exploitability()[0]
-    scale = max(1.0, float(np.abs(game.payoff).max()))
-    drifts = [ref(jitter(game, 99, 1e-15 * scale), rule, order, T)]
-    if precision == "fp32":
-        # one FP32-state run understates the spread of FP32 runs: two more whose inputs differ at
-        # the FP32 rounding level
-        drifts += [ref(game, rule, order, T, f32_state=True)]
-        drifts += [ref(jitter(game, sd, 1e-7 * scale), rule, order, T, f32_state=True) for sd in (5, 6)]
-    tR, tavg, tcur, te = TOL, TOL, TOL, EXPL_TOL * game.pot
-    for c in drifts:
+    runs = [(False, True)] if precision == "fp64" else [(True, False), (True, True)]
+    d = [0.0, 0.0, 0.0, 0.0]
+    for f32, rev in runs:
+        c = ref(game, rule, order, T, f32, rev)
         Rc, _, scc, sac = c.state()
-        tR, tavg, tcur = max(tR, 10 * rel_err(Rc, Ro)), max(tavg, 10 * rel_err(sac, sao)), max(tcur, 10 * rel_err(scc, sco))
-        te = max(te, 10 * abs(c.exploitability()[0] - eo))
-    return tR, tavg, tcur, te
+        d = [max(d[0], rel_err(Rc, Ro)), max(d[1], rel_err(sac, sao)), max(d[2], rel_err(scc, sco)),
+             max(d[3], abs(c.exploitability()[0] - eo))]
+    return d
+
+
+def compare(game, rule, order, precision, s, o, T):
+    """Free-run comparison of solver s with oracle o after T iterations (see the module docstring)."""
+    dR, davg, dcur, dexp = spread(game, rule, order, T, precision, o)
+    tR, tavg, tcur = (max(TOL, MULT * x) for x in (dR, davg, dcur))
+    te = max(EXPL_TOL * game.pot, MULT * dexp)
+    R, _ = s.state()
+    avg, cur = s.strategy(average=True), s.strategy(average=False)
+    Ro, _, sco, sao = o.state()
+    eR, eavg, ecur = rel_err(R, Ro), rel_err(avg, sao), rel_err(cur, sco)
+    e, _, _, v = s.exploitability()
+    eo, _, _, vo = o.exploitability()
+    note(f"  spread R {dR:.1e} avg {davg:.1e} cur {dcur:.1e} expl {dexp:.1e}; gpu R {eR:.2e} avg {eavg:.2e} "
+         f"cur {ecur:.2e} expl {e:.6e} vs {eo:.6e}")
+    if tR >= CAP or tavg >= CAP or te >= EXPL_CAP * game.pot:
+        pytest.xfail(f"{rule} {order} {precision}: the oracle's own runs part by R {dR:.1e}, average {davg:.1e}, "
+                     f"exploitability {dexp:.1e} after {T} free iterations (the rule amplifies rounding); the "
+                     f"one-step test pins this rule and order at 1e-5 (gpu here: R {eR:.1e}, average {eavg:.1e}, "
+                     f"exploitability {e:.4e} vs {eo:.4e})")
+    lay = o.layout()
+    w = slot_weights(lay, set_reach(game, lay, sao))
+    wavg, wcur = weighted_err(avg, sao, w), weighted_err(cur, sco, w)
+    wR = weighted_err(R, Ro, w, max(float(np.abs(Ro).max()), 1e-30))
+    note(f"  reach-weighted R {wR:.2e} avg {wavg:.2e} cur {wcur:.2e}; tol R {tR:.1e} avg {tavg:.1e} cur {tcur:.1e}")
+    assert wR <= TOL and wavg <= TOL and wcur <= TOL
+    assert eR <= tR and eavg <= tavg
+    assert abs(e - eo) <= te and abs(v - vo) <= te
+    if rule in ("cfr+", "pcfr+"):
+        assert (R >= 0).all()
+    if tcur >= CAP:
+        pytest.xfail(f"current strategy: the oracle's own runs part by {dcur:.1e} (gpu {ecur:.1e}); regrets, average "
+                     f"and exploitability pinned above")
+    assert ecur <= tcur
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -102,34 +120,17 @@ def test_rule_parity(rule, order, name, precision):
     s = solver(game, rule, order, precision)
     s.iterate(T)
     o = ref(game, rule, order, T)
-    R, _ = s.state()
-    Ro, _, sco, sao = o.state()
-    tR, tavg, tcur, te = tolerances(game, rule, order, T, precision, o)
-    eR = rel_err(R, Ro)
-    eavg = rel_err(s.strategy(average=True), sao)
-    ecur = rel_err(s.strategy(average=False), sco)
-    e, _, _, v = s.exploitability()
-    eo, _, _, vo = o.exploitability()
-    note(f"  R {eR:.2e} (tol {tR:.1e}) avg {eavg:.2e} (tol {tavg:.1e}) cur {ecur:.2e} expl {e:.6e} vs {eo:.6e}")
-    assert eR <= tR and eavg <= tavg and ecur <= tcur
-    assert abs(e - eo) <= te and abs(v - vo) <= te
-    if rule in ("cfr+", "pcfr+"):
-        assert (R >= 0).all()
+    compare(game, rule, order, precision, s, o, T)
 
 
 @pytest.mark.parametrize("rule,order", [("dcfr", "alt"), ("pcfr+", "sim"), ("pcfr+", "alt")])
 def test_rule_parity_mid_game_full_size(rule, order):
     game = jitter(gg.leduc(13, 2), 3)
+    note(f"[rules mid] {rule} {order}")
     s = solver(game, rule, order)
     s.iterate(100)
     o = ref(game, rule, order, 100)
-    Ro, _, _, sao = o.state()
-    tR, tavg, _, te = tolerances(game, rule, order, 100, "fp64", o)
-    note(f"[rules mid] {rule} {order}: R {rel_err(s.state()[0], Ro):.2e} (tol {tR:.1e}) "
-         f"avg {rel_err(s.strategy(average=True), sao):.2e} (tol {tavg:.1e})")
-    assert rel_err(s.state()[0], Ro) <= tR
-    assert rel_err(s.strategy(average=True), sao) <= tavg
-    assert abs(s.exploitability()[0] - o.exploitability()[0]) <= te
+    compare(game, rule, order, "fp64", s, o, 100)
 
 
 def test_alternating_plan_has_two_halves():
@@ -170,11 +171,14 @@ def test_persistent_and_batch_follow_the_rule(rule, order):
     assert np.array_equal(Ra, b.state()[0]) and np.array_equal(Sa, b.state()[1])
     base = b.slot_base
     avg = b.strategy(average=True)
+    R = b.state()[0]
     for k, g in enumerate(games):
         o = ref(g, rule, order, 40)
         Ro, _, _, sao = o.state()
-        tR, tavg, _, _ = tolerances(g, rule, order, 40, "fp64", o)
-        assert rel_err(b.state()[0][base[k]:base[k + 1]], Ro) <= tR, k
+        dR, davg, _, _ = spread(g, rule, order, 40, "fp64", o)
+        tR, tavg = max(TOL, MULT * dR), max(TOL, MULT * davg)
+        assert tR < CAP and tavg < CAP, k
+        assert rel_err(R[base[k]:base[k + 1]], Ro) <= tR, k
         assert rel_err(avg[base[k]:base[k + 1]], sao) <= tavg, k
 
 
