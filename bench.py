@@ -71,6 +71,79 @@ def stored_traffic(kernel, workload, precision, launches, path=None):
     return (rec["fetch_bytes_per_iteration"] + rec["write_bytes_per_iteration"]) / launches
 
 
+def physical_rate(bytes_per_iteration, ms_per_iteration, peak=HBM_PEAK_GBPS):
+    """GB/s of `bytes_per_iteration` moved in `ms_per_iteration`; raises if that exceeds the HBM peak,
+    which bytes a kernel really moves cannot do."""
+    rate = bytes_per_iteration / (ms_per_iteration * 1e-3) / 1e9
+    if rate > peak * 1.0001:
+        raise ValueError(f"{bytes_per_iteration:.4g} bytes in {ms_per_iteration:.4g} ms is {rate:.0f} GB/s, above "
+                         f"the {peak:.0f} GB/s peak: these are not bytes the kernels move")
+    return rate
+
+
+def roofline_record(kernels, traffic_fn):
+    """The roofline object of the dominant kernel (largest share of the iteration's time).
+    achieved = the kernel's design bytes per launch (every index, state and value element it must
+    read or write in this layout, counted once) over its mean launch duration; the method's per-unit
+    byte figures are reported beside it for reference (they count reads this design never makes: a
+    child pointer per edge, a template read per terminal, a separate regret pass), and the
+    counter-measured traffic when profiles/ holds it for the current kernel source."""
+    dom = max(kernels, key=lambda k: k["ms_per_iteration"])
+    nl = dom["launches_per_iteration"]
+    per_launch_ms = dom["ms_per_iteration"] / nl
+    design = dom["bytes_per_iteration"] / nl
+    method = dom["method_bytes_per_iteration"] / nl
+    achieved = physical_rate(design, per_launch_ms)
+    traffic = traffic_fn(dom["name"], nl)
+    return {
+        "bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+        "bytes": "design bytes per launch: each index, state and value element the kernel must touch, once",
+        "launches_per_iteration": nl, "ms_per_launch": per_launch_ms, "design_bytes_per_launch": design,
+        "method_bytes_per_launch": method,
+        "achieved_method_bytes": method / (per_launch_ms * 1e-3) / 1e9,
+        "achieved_traffic": None if traffic is None else traffic / (per_launch_ms * 1e-3) / 1e9,
+        "traffic_over_design": None if traffic is None else traffic / design,
+    }
+
+
+def time_to_target(solver, torch, pot, log, max_iters=20000, thr=1e-3, label=""):
+    """Solve from a reset with exploitability checkpoints on a geometric schedule.  The training
+    segments between checkpoints are timed with events on the solve's stream (best-response time is
+    not training time); the crossing iteration is log-log interpolated between the bracketing
+    checkpoints and its time interpolated on the measured cumulative training time."""
+    from paper_2609_11923_amd.warm import crossing_iterations, geometric_checkpoints
+    stream = torch.cuda.Stream()
+    solver.reset()
+    cps = geometric_checkpoints(max_iters)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    done, ms, times, expl = 0, 0.0, [], []
+    for c in cps:
+        ev0.record(stream)
+        solver.iterate(c - done, stream=stream)
+        ev1.record(stream)
+        ev1.synchronize()
+        ms += ev0.elapsed_time(ev1)
+        done = c
+        times.append(ms)
+        expl.append(solver.exploitability(stream=stream)[0])
+        log(f"[bench] {label} iteration {done}: expl {expl[-1]:.4e} ({expl[-1] / pot:.3e} pot), {ms:.1f} ms")
+        if expl[-1] <= thr * pot:
+            break
+    n = len(expl)
+    cross = float(crossing_iterations(cps[:n], np.asarray(expl)[:, None], thr * pot)[0])
+    out = dict(threshold_pot=thr, reached=bool(np.isfinite(cross)), checkpoints=cps[:n],
+               exploitability=[float(x) for x in expl], training_ms=times)
+    if np.isfinite(cross):
+        k = int(np.searchsorted(cps[:n], cross))
+        c0, t0 = (cps[k - 1], times[k - 1]) if k > 0 else (0, 0.0)
+        c1, t1 = cps[k], times[k]
+        out["iterations"] = cross
+        out["ms"] = t0 + (cross - c0) * (t1 - t0) / max(c1 - c0, 1)
+    log(f"[bench] {label} time to {thr:g} pot: {out.get('iterations')} iterations, {out.get('ms')} ms")
+    return out
+
+
 def batch_games(n, seed):
     import gamegen as gg
     specs = gg.random_subgames(n, seed, lo=1e3, hi=1e6, game_seed=0)
@@ -221,13 +294,14 @@ def run_lifecycle(cfr, torch, games, specs, log, solves=5):
     return out
 
 
-def measure_game(cfr, torch, game, args, precision, log):
+def measure_game(cfr, torch, game, args, precision, log, iters_per_graph=None, then=None, profile=True):
     """Compile one game, replay `warmup` then time `steps` iterations (hip events on the stream the
     graph is launched on), then per-kernel durations and bytes (cfr_profile) and the roofline of
     the dominant kernel; the handle is released before returning."""
     t0 = time.perf_counter()
     prec = cfr.CFR_PRECISION_FP64 if precision == "fp64" else cfr.CFR_PRECISION_FP32
-    solver = cfr.Solver(game, iters_per_graph=args.iters_per_graph, precision=prec, use_graph=not args.direct)
+    ipg = args.iters_per_graph if iters_per_graph is None else iters_per_graph
+    solver = cfr.Solver(game, iters_per_graph=ipg, precision=prec, use_graph=not args.direct)
     t_compile = time.perf_counter() - t0
     c = solver.counts
     log(f"[bench] {precision}: compiled in {t_compile:.1f} s: {c}")
@@ -246,16 +320,18 @@ def measure_game(cfr, torch, game, args, precision, log):
     ms = ev0.elapsed_time(ev1)
     ms_step = ms / args.steps
     log(f"[bench] {precision}: {args.steps} iterations in {ms:.2f} ms ({ms_step:.4f} ms/iteration)")
+    if not profile:
+        res = dict(counts=c, compile_s=t_compile, warmup_s=t_warm, ms_per_iteration=ms_step,
+                   iterations_per_s=args.steps / (ms * 1e-3), iters_per_graph=ipg)
+        if then is not None:
+            res.update(then(solver))
+        solver.close()
+        return res
     kernels = solver.profile(args.profile_iters, stream=stream)
     bytes_iter = sum(k["bytes_per_iteration"] for k in kernels)
     method_iter = sum(k["method_bytes_per_iteration"] for k in kernels)
-    dom = max(kernels, key=lambda k: k["ms_per_iteration"])
-    nl = dom["launches_per_iteration"]
-    per_launch_ms = dom["ms_per_iteration"] / nl
-    per_launch_method = dom["method_bytes_per_iteration"] / nl
-    per_launch_design = dom["bytes_per_iteration"] / nl
-    achieved = per_launch_method / (per_launch_ms * 1e-3) / 1e9
-    traffic = stored_traffic(dom["name"], args.workload, precision, nl)
+    workload = getattr(args, "traffic_workload", args.workload)
+    roof = roofline_record(kernels, lambda name, nl: stored_traffic(name, workload, precision, nl))
     log(f"[bench] {precision}: kernels {kernels}")
     if args.calibrate_copy > 0:
         n = args.calibrate_copy * (1 << 20) // 4
@@ -269,21 +345,18 @@ def measure_game(cfr, torch, game, args, precision, log):
     e, b1, b2, v = solver.exploitability(stream=stream)
     res = dict(
         counts=c, compile_s=t_compile, warmup_s=t_warm, ms_per_iteration=ms_step,
-        iterations_per_s=args.steps / (ms * 1e-3),
-        hbm_gbps_method_bytes=method_iter / (ms_step * 1e-3) / 1e9, method_bytes_per_iteration=method_iter,
-        hbm_gbps_design_bytes=bytes_iter / (ms_step * 1e-3) / 1e9, design_bytes_per_iteration=bytes_iter,
-        roofline={
-            "bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-            "launches_per_iteration": nl, "ms_per_launch": per_launch_ms,
-            "method_bytes_per_launch": per_launch_method,
-            "design_bytes_per_launch": per_launch_design,
-            "achieved_design_bytes": per_launch_design / (per_launch_ms * 1e-3) / 1e9,
-            "achieved_traffic": None if traffic is None else traffic / (per_launch_ms * 1e-3) / 1e9,
-        },
+        iterations_per_s=args.steps / (ms * 1e-3), iters_per_graph=ipg,
+        # the whole iteration's design bytes over the measured iteration time (checked physical)
+        hbm_gbps_design_bytes=physical_rate(bytes_iter, ms_step), design_bytes_per_iteration=bytes_iter,
+        frac_design_bytes=physical_rate(bytes_iter, ms_step) / HBM_PEAK_GBPS,
+        # the method's per-unit figures, for reference only (reads this design never makes)
+        gbps_method_bytes=method_iter / (ms_step * 1e-3) / 1e9, method_bytes_per_iteration=method_iter,
+        roofline=roof,
         kernels=kernels,
         exploitability_after={"iterations": solver.iterations, "expl": e, "pot": float(c["pot"])},
     )
+    if then is not None:
+        res.update(then(solver))
     solver.close()
     del solver
     torch.cuda.empty_cache()
@@ -433,7 +506,24 @@ def cpu_baseline(sample_fn, n_full, seconds):
     it_s_sample = n / el
     return dict(value=it_s_sample * g.n_nodes / n_full, unit="iterations/s", cores=1, kind="oracle",
                 sample=f"{n} FP64 oracle iterations on {g.n_nodes} nodes in {el:.1f} s, scaled by "
-                       f"{g.n_nodes}/{n_full} nodes")
+                       f"{g.n_nodes}/{n_full} nodes", host=host_cpu())
+
+
+def host_cpu():
+    """The host's CPU model and core counts (the oracle is single-threaded: it uses one of them)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return dict(cpu_model=model, nproc=os.cpu_count(), usable_cpus=usable, oracle_threads=1)
 
 
 def main():
@@ -457,7 +547,7 @@ def main():
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm-start measurement")
     ap.add_argument("--no-rules", action="store_true", help="skip the update-rule comparison on the batch")
     ap.add_argument("--no-tiny", action="store_true", help="skip the tiny-game schedule comparison")
-    ap.add_argument("--warm-train-games", type=int, default=2000)
+    ap.add_argument("--warm-train-games", type=int, default=10000)
     ap.add_argument("--warm-train-hi", type=float, default=1e6, help="largest training subgame (edges)")
     ap.add_argument("--warm-target-iters", type=int, default=500)
     ap.add_argument("--warm-val-games", type=int, default=64)
@@ -471,6 +561,11 @@ def main():
                     help="update rule of the warm-start experiment (training targets, probe and solves)")
     ap.add_argument("--warm-max-iters", type=int, default=4000)
     ap.add_argument("--warm-scales", type=float, nargs="+", default=[0.25, 0.5, 1.0, 2.0, 4.0, 8.0])
+    ap.add_argument("--no-time-to-target", action="store_true", help="skip the single game's time to 1e-3 pot")
+    ap.add_argument("--ttt-max-iters", type=int, default=20000)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the K sweep of the large game's generator")
+    ap.add_argument("--sweep-K", type=int, nargs="+", default=[4, 6, 8])
+    ap.add_argument("--no-mid", action="store_true", help="skip the mid game's measurements")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration for profilers)")
     args = ap.parse_args()
@@ -507,7 +602,10 @@ def main():
     log(f"[bench] generated {args.workload}: {game.n_nodes} nodes in {t_gen:.1f} s")
     n_nodes = game.n_nodes
     torch.cuda.set_device(0)
-    m = measure_game(cfr, torch, game, args, args.precision, log)
+    pot = float(game.pot)
+    ttt = None if args.no_time_to_target else \
+        (lambda sv: {"time_to_target": time_to_target(sv, torch, pot, log, args.ttt_max_iters, label=args.workload)})
+    m = measure_game(cfr, torch, game, args, args.precision, log, then=ttt)
     c = m["counts"]
     out = {
         "metric": METRIC,
@@ -528,12 +626,14 @@ def main():
             "state": ("FP64" if args.precision == "fp64" else "FP32") + " reach/values/regrets/strategy, FP64 strategy sums",
             "graph": f"{args.iters_per_graph} iteration(s) per hipGraph",
         },
-        # whole iteration: the method's per-unit byte figures, and the bytes this design's kernels touch
-        "hbm_gbps_method_bytes": m["hbm_gbps_method_bytes"],
-        "method_bytes_per_iteration": m["method_bytes_per_iteration"],
-        "hbm_gbps_design_bytes": m["hbm_gbps_design_bytes"],
-        "design_bytes_per_iteration": m["design_bytes_per_iteration"],
         "roofline": m["roofline"],
+        # whole iteration: the design bytes of all its kernels over the measured iteration time, and
+        # the method's per-unit figures for reference
+        "hbm_gbps_design_bytes": m["hbm_gbps_design_bytes"],
+        "frac_design_bytes": m["frac_design_bytes"],
+        "design_bytes_per_iteration": m["design_bytes_per_iteration"],
+        "gbps_method_bytes": m["gbps_method_bytes"],
+        "method_bytes_per_iteration": m["method_bytes_per_iteration"],
         "kernels": m["kernels"],
         "setup_s": {"generate": t_gen, "compile": m["compile_s"], "warmup_and_capture": m["warmup_s"]},
         "exploitability_after": m["exploitability_after"],
@@ -542,10 +642,17 @@ def main():
     if args.precision == "fp32" and not args.no_fp64:
         # the same game with FP64 state (the configuration held to the full parity bar)
         f64 = measure_game(cfr, torch, game, args, "fp64", log)
-        out["fp64_state"] = {k: f64[k] for k in ("iterations_per_s", "ms_per_iteration", "hbm_gbps_method_bytes",
-                                                  "hbm_gbps_design_bytes", "roofline", "exploitability_after")}
+        out["fp64_state"] = {k: f64[k] for k in ("iterations_per_s", "ms_per_iteration", "hbm_gbps_design_bytes",
+                                                  "frac_design_bytes", "roofline", "exploitability_after")}
+    if "time_to_target" in m:
+        t = dict(m["time_to_target"], rule="CFR+, simultaneous, linear averaging", state=out["config"]["state"])
+        out["time_to_target_single_game"] = t
     del game
     torch.cuda.empty_cache()
+    if args.workload == "large" and not args.no_sweep:
+        out["size_sweep"] = run_size_sweep(cfr, torch, args, log)
+    if args.workload == "large" and not args.no_mid:
+        out["mid_game"] = run_mid(cfr, torch, args, log)
     if not args.no_batch:
         games, bspecs = batch_games(args.batch_games, args.seed)
         log(f"[bench] batch of {len(games)} subgames, {sum(g.n_edges for g in games)} edges")
@@ -574,7 +681,56 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(sample_fn, n_nodes, args.cpu_seconds)
+        t = out.get("time_to_target_single_game")
+        if t and t.get("reached"):
+            # the oracle's time to the same crossing iteration, from its measured rate (not run)
+            t["oracle_s_extrapolated"] = t["iterations"] / out["cpu_baseline"]["value"]
+            t["oracle_note"] = "extrapolated: crossing iterations / the oracle's measured iterations per second"
     print(json.dumps(out), flush=True)
+
+
+def run_size_sweep(cfr, torch, args, log):
+    """The large game's generator at K = 4, 6, 8 hands per player (K = 10 is the headline): iterations
+    per second and the dominant kernel's roofline at each size."""
+    import gamegen as gg
+    out = []
+    for K in args.sweep_K:
+        if K == args.K:
+            continue
+        h1, h2 = gg.sample_hands(K, args.seed)
+        g = gg.large(K, seed=args.seed, hands=(h1, h2))
+        log(f"[bench] size sweep K={K}: {g.n_nodes} nodes")
+        sub = argparse.Namespace(**vars(args))
+        sub.steps, sub.warmup, sub.traffic_workload = max(20, args.steps), args.warmup, f"large_K{K}"
+        m = measure_game(cfr, torch, g, sub, "fp32", log)
+        out.append(dict(K=K, nodes=int(m["counts"]["nodes"]), infosets=int(m["counts"]["infosets"]),
+                        ms_per_iteration=m["ms_per_iteration"], iterations_per_s=m["iterations_per_s"],
+                        frac_design_bytes=m["frac_design_bytes"], roofline=m["roofline"]))
+        del g
+        torch.cuda.empty_cache()
+    return out
+
+
+def run_mid(cfr, torch, args, log):
+    """The mid game (Leduc rules, 13 ranks x 2 suits): FP32 state, ms per iteration with 1 and with 10
+    iterations per hipGraph, and its time to exploitability <= 1e-3 pot (pot 2) under CFR+."""
+    import gamegen as gg
+    g = gg.leduc(13, 2)
+    pot = float(g.pot)
+    sub = argparse.Namespace(**vars(args))
+    sub.steps, sub.warmup, sub.traffic_workload = 1000, 50, "mid"
+    out = {"workload": "Leduc-rule game, 13 ranks x 2 suits (1,179,777 nodes), FP32 state, CFR+ simultaneous"}
+    for k in (1, 10):
+        then = (lambda sv: {"time_to_target": time_to_target(sv, torch, pot, log, 20000, label="mid")}) if k == 1 \
+            else None
+        m = measure_game(cfr, torch, g, sub, "fp32", log, iters_per_graph=k, then=then, profile=(k == 1))
+        rec = dict(iters_per_graph=k, ms_per_iteration=m["ms_per_iteration"], iterations_per_s=m["iterations_per_s"])
+        if "roofline" in m:
+            rec["roofline"] = m["roofline"]
+        out[f"graph_{k}"] = rec
+        if "time_to_target" in m:
+            out["time_to_target"] = m["time_to_target"]
+    return out
 
 
 if __name__ == "__main__":

@@ -437,16 +437,17 @@ def first_members(game: Game):
     """(first member node, acting player) of every information set, sets in order of first
     occurrence among decision nodes in node-id order.  Generator node ids are breadth-first with
     children in action order, so this is the canonical set order of the compiled game."""
+    import pandas as pd
     ty = np.asarray(game.type)
     dec = np.flatnonzero((ty == GG_P1) | (ty == GG_P2))
     keys = np.asarray(game.key)[dec]
-    # sets are keyed by (player, key)
-    _, first_idx = np.unique(np.stack([ty[dec].astype(np.int64), keys]), axis=1, return_index=True)
-    first = np.sort(dec[first_idx])
+    # sets are keyed by (player, key); a hashed first-occurrence pass keeps node-id order
+    dup = pd.DataFrame({"p": ty[dec], "k": keys}).duplicated().to_numpy()
+    first = dec[~dup]
     return first, ty[first].astype(np.int8)
 
 
-def warm_descriptors(game: Game, mem_off=None, mem_node=None, iset_player=None):
+def warm_descriptors(game: Game, mem_off=None, mem_node=None, iset_player=None, first=None):
     """Per-information-set inputs of the feature rows for a card game from this module, in
     canonical set order (from the compiled member lists when given, else first_members):
       bucket   int16  canonical two-card hand index of the acting player's hand, mod 64
@@ -455,9 +456,13 @@ def warm_descriptors(game: Game, mem_off=None, mem_node=None, iset_player=None):
       scalars  float32 [I, 8]: 0 pot odds to_call / (pot + to_call); 1 own hand's range weight
                       times the own hand count (1 = uniform); 2 opponent range entropy / log K;
                       3-5 the opponent's three largest range masses; 6 log K_opp / log 630;
-                      7 own range entropy / log K."""
+                      7 own range entropy / log K.
+    first (optional): the sets' first members as returned by first_members."""
     m = game.meta
-    if mem_off is None:
+    if first is not None:
+        first = np.asarray(first, np.int64)
+        player = np.asarray(game.type)[first].astype(np.int8)
+    elif mem_off is None:
         first, player = first_members(game)
     else:
         first = np.asarray(mem_node, np.int64)[np.asarray(mem_off, np.int64)[:-1]]

@@ -532,7 +532,11 @@ class Solver:
 
     def set_state(self, regrets=None, strategy_sum=None, t: int = 0, prediction=None, stream=None):
         """Resume from host arrays (canonical order); the next iteration is t + 1."""
-        cfr_set_state(self.h, self.A, t, regrets, strategy_sum, prediction, self._stream(stream))
+        sizes = {len(a) for a in (regrets, strategy_sum, prediction) if a is not None}
+        if len(sizes) > 1:
+            raise ValueError("regrets, strategy sums and prediction must have the same length")
+        cfr_set_state(self.h, sizes.pop() if sizes else self.A, t, regrets, strategy_sum, prediction,
+                      self._stream(stream))
 
     def prediction(self, stream=None) -> np.ndarray:
         return cfr_get_prediction(self.h, self.A, self._stream(stream))

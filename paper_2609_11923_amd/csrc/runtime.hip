@@ -11,11 +11,14 @@
 // and the handle keeps launching the same kernels directly.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/cfr.h"
@@ -120,6 +123,25 @@ struct cfr_handle {
     // canonical arrays of every game (options.keep_layout), for cfr_get_layout
     std::vector<Layout> layouts;
 };
+
+// fn(s) for s in [0, n) on up to 16 host threads (one game each at a time); fn must touch only game s.
+template <typename F>
+static void parallel_games(int n, F &&fn) {
+    const int hw = (int)std::thread::hardware_concurrency();
+    const int nt = std::max(1, std::min({n, hw > 0 ? hw : 1, 16}));
+    if (nt == 1) {
+        for (int s = 0; s < n; s++) fn(s);
+        return;
+    }
+    std::atomic<int> next{0};
+    std::vector<std::thread> pool;
+    pool.reserve((size_t)nt);
+    for (int k = 0; k < nt; k++)
+        pool.emplace_back([&]() {
+            for (int s = next.fetch_add(1); s < n; s = next.fetch_add(1)) fn(s);
+        });
+    for (auto &t : pool) t.join();
+}
 
 // Per-launch event timing for cfr_profile: class 0 tick, 1 forward, 2 level.
 struct LaunchTimer {
@@ -620,10 +642,21 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     std::vector<int8_t> canon_player;
     std::vector<int64_t> hand_off{0};
     std::vector<int32_t> hand1, hand2, nh1, nh2;
+    // the games of a batch compile independently: their canonical layouts on several host threads
+    std::vector<cfr_status> sts((size_t)n, CFR_OK);
+    std::vector<std::string> errs((size_t)n);
+    for (int s = 0; s < n; s++) Ls[s].keep_maps = o.lifecycle != 0;
+    parallel_games(n, [&](int s) {
+        try {
+            sts[s] = build_layout(&games[s], Ls[s], errs[s]);
+        } catch (...) {
+            sts[s] = CFR_ENOMEM;
+            errs[s] = "host compile failed";
+        }
+    });
     for (int s = 0; s < n; s++) {
-        Ls[s].keep_maps = o.lifecycle != 0;
-        st = build_layout(&games[s], Ls[s], err);
-        if (st != CFR_OK) return fail(st, n > 1 ? "game " + std::to_string(s) + ": " + err : err);
+        st = sts[s];
+        if (st != CFR_OK) return fail(st, n > 1 ? "game " + std::to_string(s) + ": " + errs[s] : errs[s]);
         const cfr_game_desc &gd = games[s];
         if (gd.root_hand1 || gd.root_hand2) {
             const std::string pre = n > 1 ? "game " + std::to_string(s) + ": " : "";
@@ -666,14 +699,24 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
 
     DeviceLayout DL;
     LifecycleHost lc;
+    std::vector<Layout> kept;
     {
         std::vector<DeviceLayout> Ds((size_t)n);
+        parallel_games(n, [&](int s) {
+            try {
+                sts[s] = build_device_layout(Ls[s], o.layout, max_actions, o.precision == CFR_PRECISION_FP64, Ds[s],
+                                             errs[s]);
+            } catch (...) {
+                sts[s] = CFR_ENOMEM;
+                errs[s] = "host compile failed";
+            }
+        });
         for (int s = 0; s < n; s++) {
-            st = build_device_layout(Ls[s], o.layout, max_actions, o.precision == CFR_PRECISION_FP64, Ds[s], err);
-            if (st != CFR_OK) return fail(st, err);
+            if (sts[s] != CFR_OK) return fail(sts[s], n > 1 ? "game " + std::to_string(s) + ": " + errs[s] : errs[s]);
             if (o.lifecycle) lifecycle_records(games[s], Ls[s], Ds[s], lc);
             if (n > 1 && !o.keep_layout) Ls[s] = Layout();  // free the canonical arrays early
         }
+        if (o.keep_layout) kept.swap(Ls);   // the merge releases the canonical arrays it is given
         st = build_forest(Ls, Ds, DL, err);
         if (st != CFR_OK) return fail(st, err);
     }
@@ -842,7 +885,7 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     }
     st = cfr_reset(h);
     if (st != CFR_OK) { free_handle(h); return st; }
-    if (o.keep_layout) h->layouts = std::move(Ls);
+    if (o.keep_layout) h->layouts = std::move(kept);
     *out = h;
     return CFR_OK;
 }

@@ -43,9 +43,15 @@ def crossing_iterations(checkpoints, expl, thr):
     return out
 
 
-def subgames(specs):
+def subgames(specs, threads=8):
+    """The subgames of `specs` (input generation: the generator's C code runs on several threads)."""
     import gamegen as gg
-    return [gg.subgame(**{k: v for k, v in sp.items() if k != "target"}) for sp in specs]
+    from concurrent.futures import ThreadPoolExecutor
+    one = lambda sp: gg.subgame(**{k: v for k, v in sp.items() if k != "target"})   # noqa: E731
+    if threads <= 1 or len(specs) < 2:
+        return [one(sp) for sp in specs]
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(one, specs))
 
 
 class Rows:
@@ -57,7 +63,7 @@ class Rows:
         self.game_off = [0]
         for g in games:
             first, _ = gg.first_members(g)
-            b, h, s = gg.warm_descriptors(g)
+            b, h, s = gg.warm_descriptors(g, first=first)
             bs.append(b); hs.append(h); ss.append(s)
             na.append(np.asarray(g.n_children)[first])
             self.game_off.append(self.game_off[-1] + len(first))

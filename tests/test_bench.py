@@ -1,9 +1,11 @@
-"""CPU checks of the benchmark's contract: one GPU only, and counter traffic reported only when the
-stored profiler counts were taken on the current kernel source."""
+"""CPU checks of the benchmark's contract: one GPU only, a roofline on bytes the kernels move, and counter
+traffic reported only when the stored profiler counts were taken on the current kernel source."""
 import json
 import os
 import subprocess
 import sys
+
+import pytest
 
 import bench
 
@@ -41,3 +43,33 @@ def test_committed_profiles_name_their_kernel_source():
         assert len(rec["kernels_sha256"]) == 64, key
         assert "rocprofv3" in rec["command"], key
         assert rec["fetch_bytes_per_iteration"] > 0 and rec["write_bytes_per_iteration"] > 0, key
+
+
+def test_roofline_uses_design_bytes_and_rejects_impossible_rates():
+    kernels = [dict(name="k_forward", launches_per_iteration=12, bytes_per_iteration=1.2e9,
+                    method_bytes_per_iteration=4.1e9, ms_per_iteration=0.30),
+               dict(name="k_level", launches_per_iteration=13, bytes_per_iteration=2.94e9,
+                    method_bytes_per_iteration=7.5e9, ms_per_iteration=0.79)]
+    r = bench.roofline_record(kernels, lambda name, nl: 3.39e9 / nl)
+    assert r["kernel"] == "k_level"
+    per_launch_ms = 0.79 / 13
+    assert abs(r["achieved"] - 2.94e9 / 13 / (per_launch_ms * 1e-3) / 1e9) < 1e-6
+    assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-12 and 0 < r["frac"] <= 1
+    assert abs(r["traffic_over_design"] - 3.39 / 2.94) < 1e-9
+    # the method's figures stay informational: here they would exceed the peak
+    assert r["achieved_method_bytes"] > 8000.0
+    with pytest.raises(ValueError):
+        bench.physical_rate(9.0e9, 1.0)
+    assert abs(bench.physical_rate(4.0e9, 1.0) - 4000.0) < 1e-9
+
+
+def test_recorded_benchmark_lines_are_physical():
+    """Every benchmark record the driver kept: the design bytes of one iteration over its measured
+    time stay within the HBM peak."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(ROOT, "BENCH_r*.json"))):
+        rec = json.load(open(path))
+        line = rec.get("parsed") or rec
+        if not line or "design_bytes_per_iteration" not in line or not line.get("ms_per_step"):
+            continue
+        bench.physical_rate(line["design_bytes_per_iteration"], line["ms_per_step"])
