@@ -114,7 +114,8 @@ enum { CFR_PRECISION_FP32 = 0, CFR_PRECISION_FP64 = 1 };
 /* Schedules (cfr_options.persistent, cfr_set_schedule):
  *   LEVEL       one launch per depth level, the iteration captured once and replayed (default)
  *   PERSISTENT  one launch per cfr_iterate call running all n iterations of every game of a batch,
- *               per-game barriers between levels
+ *               per-game barriers between levels; workgroups claim (game, rank) tickets in order from
+ *               per-XCD queues (cfr_persistent_plan_host), so a barrier only waits for running ones
  *   LDS         one workgroup per cfr_iterate call running all n iterations of one tiny standalone
  *               game with its whole state in LDS (paper Sec. Results, cross-framework timing: the fixed
  *               launch-and-replay floor per iteration that small games cannot fill):
@@ -234,6 +235,19 @@ cfr_status cfr_autotune(cfr_handle *h, int64_t iters, void *stream, const char *
  * CFR_EINVAL for an unknown schedule, or LDS for a batch, a game over the LDS budget or sets with
  * more than 16 actions (the schedule then stays as it was). */
 cfr_status cfr_set_schedule(cfr_handle *h, int32_t persistent, int32_t wg_nodes);
+
+/* Host-only (no GPU touched): the work plan the persistent schedule builds for n games of nodes[g]
+ * nodes (the batched form is not in the paper; its concluding remarks motivate one launch per batch of
+ * solves).  Game g gets W[g] = max(1, ceil(nodes[g] / wg_nodes_used)) workgroups ("ranks"), which are
+ * consecutive tickets of queue[g], one of 8 per-XCD queues (games placed largest first on the least
+ * loaded queue); q_off[9] gives each queue's ticket range; *wg_nodes_used is wg_nodes (0: 16384)
+ * doubled until every W[g] <= max_w.  Workgroups claim tickets in order, so a game's barrier waits only
+ * for ranks already claimed by running workgroups, and at most one game per queue is partly claimed:
+ * the launch progresses whenever 8 (max_w - 1) + 1 workgroups can be resident.  cfr_set_schedule uses
+ * max_w = a quarter of one XCD's resident workgroups.  Caller-owned outputs W[n], queue[n], q_off[9].
+ * CFR_EINVAL for bad arguments, CFR_EUNSUPPORTED if no wg_nodes below 2^30 fits. */
+cfr_status cfr_persistent_plan_host(const int64_t *nodes, int32_t n, int32_t wg_nodes, int32_t max_w, int32_t *W,
+                                    int32_t *queue, int32_t *q_off, int32_t *wg_nodes_used);
 
 /* Number of games in the handle and (if slot_base != NULL) the n + 1 offsets of each game's
  * canonical slots in the per-slot arrays. */

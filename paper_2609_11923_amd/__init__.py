@@ -99,7 +99,8 @@ EXPORTS = ["cfr_default_options", "cfr_layout_host", "cfr_layout_free", "cfr_com
            "cfr_mlp_default_desc", "cfr_mlp_create", "cfr_mlp_num_params", "cfr_mlp_set_params", "cfr_mlp_get",
            "cfr_mlp_forward", "cfr_mlp_backward", "cfr_mlp_adam", "cfr_mlp_train_step", "cfr_mlp_destroy",
            "cfr_num_infosets", "cfr_features", "cfr_regret_unit", "cfr_warm_start", "cfr_set_payoffs",
-           "cfr_set_root_chance", "cfr_set_root_ranges", "cfr_set_state", "cfr_get_prediction", "cfr_get_layout"]
+           "cfr_set_root_chance", "cfr_set_root_ranges", "cfr_set_state", "cfr_get_prediction", "cfr_get_layout",
+           "cfr_persistent_plan_host"]
 
 
 def load():
@@ -164,6 +165,8 @@ def load():
         "cfr_set_state": (S, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int64, _P]),
         "cfr_get_prediction": (S, [_P, _P, ctypes.c_int64, _P]),
         "cfr_get_layout": (S, [_P, ctypes.c_int32, ctypes.POINTER(cfr_layout)]),
+        "cfr_persistent_plan_host": (S, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P,
+                                         ctypes.POINTER(ctypes.c_int32)]),
         "cfr_warm_start": (S, [_P, _P, _P, ctypes.c_int64, ctypes.c_float, ctypes.c_int32, _P]),
     }
     for name, (res, args) in sig.items():
@@ -297,6 +300,19 @@ def cfr_autotune(h, iters: int, stream=None, cache_path: str | None = None) -> d
     r = cfr_tune_result()
     _check(load().cfr_autotune(h, int(iters), stream, cache_path.encode() if cache_path else None, ctypes.byref(r)))
     return {f: getattr(r, f) for f, _ in cfr_tune_result._fields_}
+
+
+def cfr_persistent_plan_host(nodes, wg_nodes: int, max_w: int) -> dict:
+    """The persistent schedule's work plan for games of the given node counts (host only)."""
+    nv = np.ascontiguousarray(nodes, np.int64)
+    n = len(nv)
+    W = np.zeros(max(n, 1), np.int32)
+    q = np.zeros(max(n, 1), np.int32)
+    q_off = np.zeros(9, np.int32)
+    used = ctypes.c_int32()
+    _check(load().cfr_persistent_plan_host(_ptr(nv), n, int(wg_nodes), int(max_w), _ptr(W), _ptr(q), _ptr(q_off),
+                                           ctypes.byref(used)))
+    return dict(W=W[:n], queue=q[:n], q_off=q_off, wg_nodes=used.value)
 
 
 def cfr_set_schedule(h, persistent: int, wg_nodes: int = 0):

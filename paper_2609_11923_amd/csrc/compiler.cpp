@@ -459,6 +459,50 @@ bool slot_child_offsets(const DeviceLayout &D, std::vector<int32_t> &koff) {
     return true;
 }
 
+bool plan_persistent(const std::vector<int64_t> &nodes, int32_t wg_nodes, int32_t max_w, int n_queues,
+                     PersistentWork &P, std::string &err) {
+    const int n = (int)nodes.size();
+    if (n_queues < 1 || max_w < 1) { err = "bad persistent plan parameters"; return false; }
+    if (wg_nodes <= 0) wg_nodes = 16384;
+    std::vector<int> order((size_t)n);
+    for (int s = 0; s < n; s++) order[(size_t)s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nodes[(size_t)a] > nodes[(size_t)b]; });
+    for (;;) {
+        int64_t wmax = 1;
+        for (int s = 0; s < n; s++) wmax = std::max<int64_t>(wmax, (nodes[(size_t)s] + wg_nodes - 1) / wg_nodes);
+        if (wmax <= max_w) break;
+        if (wg_nodes >= (1 << 30)) { err = "a game needs more workgroups than one XCD holds"; return false; }
+        wg_nodes *= 2;
+    }
+    P = PersistentWork();
+    P.wg_nodes = wg_nodes;
+    P.W.assign((size_t)n, 1);
+    P.queue.assign((size_t)n, 0);
+    P.load.assign((size_t)n_queues, 0);
+    std::vector<std::vector<int>> qg((size_t)n_queues);
+    for (int s : order) {
+        const int64_t w = std::max<int64_t>(1, (nodes[(size_t)s] + wg_nodes - 1) / wg_nodes);
+        P.W[(size_t)s] = (int32_t)w;
+        P.max_W = std::max<int32_t>(P.max_W, (int32_t)w);
+        int best = 0;
+        for (int q = 1; q < n_queues; q++) if (P.load[(size_t)q] < P.load[(size_t)best]) best = q;
+        P.queue[(size_t)s] = best;
+        P.load[(size_t)best] += nodes[(size_t)s];
+        qg[(size_t)best].push_back(s);
+    }
+    P.q_off.assign((size_t)n_queues + 1, 0);
+    for (int q = 0; q < n_queues; q++) {
+        for (int s : qg[(size_t)q])
+            for (int32_t r = 0; r < P.W[(size_t)s]; r++) {
+                P.ticket.push_back(s);
+                P.ticket.push_back(r);
+                P.ticket.push_back(P.W[(size_t)s]);
+            }
+        P.q_off[(size_t)q + 1] = (int32_t)(P.ticket.size() / 3);
+    }
+    return true;
+}
+
 cfr_status build_forest(std::vector<Layout> &Ls, std::vector<DeviceLayout> &Ds, DeviceLayout &F, std::string &err) {
     try {
         const int n = (int)Ds.size();

@@ -115,6 +115,24 @@ cfr_status build_device_layout(const Layout &L, int layout_kind, int group_actio
 // block of an action keeps the block's node order.
 bool slot_child_offsets(const DeviceLayout &D, std::vector<int32_t> &koff);
 
+// Work plan of the persistent schedule.  Game g gets W_g = max(1, ceil(nodes_g / wg_nodes)) workgroups
+// ("ranks"); games are placed largest first on the least loaded of n_queues queues (one per XCD) and a
+// game's ranks are consecutive tickets of its queue.  Workgroups claim tickets in order at run time, so
+// the ranks of a game are claimed by running workgroups one after another and a game's per-level
+// barrier waits only for workgroups that have started: what must fit on the device at once is one
+// game's W_g workgroups (not the whole grid).  wg_nodes is doubled until every W_g <= max_w.
+struct PersistentWork {
+    int32_t wg_nodes = 0;                 // target nodes per workgroup used
+    int32_t max_W = 0;                    // largest W_g
+    std::vector<int32_t> W;               // [n] workgroups of each game
+    std::vector<int32_t> queue;           // [n] queue of each game
+    std::vector<int32_t> q_off;           // [n_queues + 1] tickets of queue q are [q_off[q], q_off[q + 1])
+    std::vector<int32_t> ticket;          // [tickets * 3]: game, rank, W_g of each ticket, queue by queue
+    std::vector<int64_t> load;            // [n_queues] nodes per queue
+};
+bool plan_persistent(const std::vector<int64_t> &nodes, int32_t wg_nodes, int32_t max_w, int n_queues,
+                     PersistentWork &out, std::string &err);
+
 // Merge the device layouts of independent games into one depth-major forest (see DeviceLayout).
 // Ls and Ds are consumed (moved or cleared).  A single game is moved through unchanged.
 cfr_status build_forest(std::vector<Layout> &Ls, std::vector<DeviceLayout> &Ds, DeviceLayout &F, std::string &err);

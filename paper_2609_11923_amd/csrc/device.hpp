@@ -86,16 +86,20 @@ hipError_t launch_forward(const DevGame &g, int32_t lo, int32_t hi, int32_t *tic
 hipError_t launch_level(const DevGame &g, int d, IterFlags f, hipStream_t s);
 // sigma <- regret matching of R (all information sets)
 hipError_t launch_regret_matching(const DevGame &g, hipStream_t s);
-// The persistent batched launch: work table (one int4 per block: game, rank, blocks of the game),
-// per-game level ranges and depths, barrier counters and the time-out flag (all device memory).
+// The persistent batched launch: tickets (one int4 per rank: game, rank, workgroups of the game),
+// queue by queue (one queue per XCD, q_off [PERSISTENT_QUEUES + 1]), per-game level ranges and depths,
+// barrier counters [n_games] followed by the queues' claim counters [PERSISTENT_QUEUES], and the
+// time-out flag (all device memory).
+constexpr int PERSISTENT_QUEUES = 8;
 struct PersistentPlan {
-    int32_t blocks = 0, n_games = 0, max_depth = 0;
-    int4 *wg_table = nullptr;
+    int32_t blocks = 0, n_games = 0, max_depth = 0, n_tickets = 0, wg_nodes = 0, max_W = 0;
+    int4 *tickets = nullptr;
+    int32_t *q_off = nullptr, *claim = nullptr;
     int32_t *game_range = nullptr, *game_depth = nullptr, *barrier = nullptr, *err = nullptr;
     int64_t timeout_ticks = 0;   // BARRIER_TIMEOUT_S in ticks of wall_clock64()
 };
-// zero the barriers, run T iterations of every game in one launch (both halves of each iteration
-// when alternating), advance the counter by T
+// zero the barrier and claim counters, run T iterations of every game in one launch (both halves of
+// each iteration when alternating), advance the counter by T
 hipError_t launch_persistent(const DevGame &g, const PersistentPlan &p, int32_t T, IterFlags f, int alternating,
                              hipStream_t s);
 // resident blocks per compute unit of the persistent kernel for this game's configuration

@@ -666,27 +666,19 @@ __device__ __forceinline__ bool game_barrier(int32_t *ctr, int32_t W, int32_t &e
     return s_ok != 0;
 }
 
-// The batched persistent form: one launch runs T whole iterations for every game of a forest.
-// Block b works on game wg_table[b].x as rank wg_table[b].y of wg_table[b].z blocks (game -1:
-// an idle padding block).  A game's blocks stride over each forward level's nodes and each
-// backward level's update groups and chance nodes, meeting at a per-game barrier between levels;
-// games never wait for each other.  Iteration t0 + k (k = 1..T) uses the same arithmetic, in the
-// same order per set, as the level-synchronous kernels.  n_iter is the number of iterations.
+// The work of one (game, rank): n_iter whole iterations of game gm as rank `rank` of its W workgroups,
+// which stride over each forward level's nodes and each backward level's update groups and chance
+// nodes and meet at the game's barrier between levels.  Iteration t0 + k (k = 1..n_iter) uses the
+// same arithmetic, in the same order per set, as the level-synchronous kernels.  Returns false once
+// a barrier reported an error.
 template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT, bool AFF>
-__global__ void __launch_bounds__(BLOCK) k_persistent(const int4 *__restrict__ wg_table,
-                                                      const int32_t *__restrict__ game_range,
-                                                      const int32_t *__restrict__ game_depth, int32_t MD, int32_t n_iter,
-                                                      const int2 *__restrict__ up, LevelArgs<T> a,
-                                                      const int32_t *__restrict__ tcount, int32_t *barrier,
-                                                      int32_t *err, int64_t timeout_ticks, int rule, int linear,
-                                                      int alternating) {
-    __shared__ LevelLds<T, MAXA, MPT, EXPLICIT, AFF> L;
-    const int4 wt = wg_table[blockIdx.x];
-    const int32_t gm = wt.x, rank = wt.y, W = wt.z;
-    if (gm < 0) return;
+__device__ bool persistent_game(int32_t gm, int32_t rank, int32_t W, const int32_t *__restrict__ game_range,
+                                const int32_t *__restrict__ game_depth, int32_t MD, int32_t n_iter,
+                                const int2 *__restrict__ up, const LevelArgs<T> &a, int32_t t0, int32_t *barrier,
+                                int32_t *err, int64_t timeout_ticks, int rule, int linear, int alternating,
+                                LevelLds<T, MAXA, MPT, EXPLICIT, AFF> &L) {
     const int32_t *gr = game_range + (size_t)gm * (MD + 1) * GR_FIELDS_DEV;
     const int32_t Ds = game_depth[gm];
-    const int32_t t0 = tcount[0];
     const int tid = threadIdx.x;
     int32_t epoch = 0;
     const int halves = alternating ? 2 : 1;
@@ -697,15 +689,54 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(const int4 *__restrict__ w
                 const int32_t lo = gr[d * GR_FIELDS_DEV], hi = gr[d * GR_FIELDS_DEV + 1];
                 for (int32_t c = lo + rank * BLOCK + tid; c < hi; c += W * BLOCK)
                     forward_node<T>(c, up, a.sigma, a.r1, a.r2);
-                if (!game_barrier(barrier + gm, W, epoch, err, timeout_ticks)) return;
+                if (!game_barrier(barrier + gm, W, epoch, err, timeout_ticks)) return false;
             }
             for (int32_t d = Ds - 1; d >= 0; d--) {
                 const int32_t *r = gr + d * GR_FIELDS_DEV;
                 for (int32_t g = r[2] + rank; g < r[3]; g += W) update_group<T, MAXA, MPT, EXPLICIT, EXT, AFF>(g, ru, a, L);
                 for (int32_t b = r[6] + rank; b < r[7]; b += W) big_chance_value<T, EXPLICIT>(a.bigc_node[b], a, L.po);
                 for (int32_t j = r[4] + rank * BLOCK + tid; j < r[5]; j += W * BLOCK) chance_value<T, EXPLICIT>(a.chance_node[j], a);
-                if (!game_barrier(barrier + gm, W, epoch, err, timeout_ticks)) return;
+                if (!game_barrier(barrier + gm, W, epoch, err, timeout_ticks)) return false;
             }
+        }
+    }
+    return true;
+}
+
+// The batched persistent form: one launch runs n_iter whole iterations of every game of a forest.
+// The work is a list of tickets (game, rank, W), one queue per XCD: a game's W ranks are consecutive
+// tickets of one queue.  A workgroup claims tickets of the queue of the XCD it runs on (the hardware
+// XCC id), in order, runs each claimed rank to the end, then takes the other queues' remaining
+// tickets.  A game's barrier therefore waits only for ranks claimed by workgroups already running,
+// and the others are claimed next by whichever workgroup frees up: the launch needs one game's
+// workgroups resident at once, not the whole grid, and any grid size is correct.
+template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT, bool AFF>
+__global__ void __launch_bounds__(BLOCK) k_persistent(const int4 *__restrict__ tickets, const int32_t *__restrict__ q_off,
+                                                      int32_t *claim, const int32_t *__restrict__ game_range,
+                                                      const int32_t *__restrict__ game_depth, int32_t MD, int32_t n_iter,
+                                                      const int2 *__restrict__ up, LevelArgs<T> a,
+                                                      const int32_t *__restrict__ tcount, int32_t *barrier,
+                                                      int32_t *err, int64_t timeout_ticks, int rule, int linear,
+                                                      int alternating) {
+    __shared__ LevelLds<T, MAXA, MPT, EXPLICIT, AFF> L;
+    __shared__ int32_t s_ticket;
+    const int32_t t0 = tcount[0];
+    // XCC_ID hardware register (bits 3:0): the XCD this workgroup runs on
+    const int home = (int)(__builtin_amdgcn_s_getreg((20) | (0 << 6) | ((4 - 1) << 11)) & (PERSISTENT_QUEUES - 1));
+    for (int k = 0; k < PERSISTENT_QUEUES; k++) {
+        const int q = (home + k) & (PERSISTENT_QUEUES - 1);
+        const int32_t qlo = q_off[q], qn = q_off[q + 1] - qlo;
+        for (;;) {
+            if (threadIdx.x == 0) s_ticket = atomicAdd(claim + q, 1);
+            __syncthreads();
+            const int32_t t = s_ticket;
+            __syncthreads();
+            if (t >= qn) break;
+            const int4 wt = tickets[qlo + t];
+            if (!persistent_game<T, MAXA, MPT, EXPLICIT, EXT, AFF>(wt.x, wt.y, wt.z, game_range, game_depth, MD, n_iter, up,
+                                                                a, t0, barrier, err, timeout_ticks, rule, linear,
+                                                                alternating, L))
+                return;
         }
     }
 }
@@ -1061,16 +1092,18 @@ struct PersistentLaunch {
     const DevGame &g; const PersistentPlan &p; int32_t T_; IterFlags f; int alt; hipStream_t s;
     template <typename T, int MAXA, int MPT, bool EX, bool XT, bool AF>
     hipError_t operator()() const {
-        hipLaunchKernelGGL((k_persistent<T, MAXA, MPT, EX, XT, AF>), dim3(p.blocks), dim3(BLOCK), 0, s, p.wg_table,
-                           p.game_range, p.game_depth, p.max_depth, T_, g.up, level_args<T>(g), g.t, p.barrier,
-                           p.err, p.timeout_ticks, f.rule, f.linear, alt);
+        hipLaunchKernelGGL((k_persistent<T, MAXA, MPT, EX, XT, AF>), dim3(p.blocks), dim3(BLOCK), 0, s, p.tickets,
+                           p.q_off, p.claim, p.game_range, p.game_depth, p.max_depth, T_, g.up, level_args<T>(g), g.t,
+                           p.barrier, p.err, p.timeout_ticks, f.rule, f.linear, alt);
         return hipGetLastError();
     }
 };
 
 hipError_t launch_persistent(const DevGame &g, const PersistentPlan &p, int32_t T_, IterFlags f, int alt,
                              hipStream_t s) {
-    hipLaunchKernelGGL(k_fill_int, dim3((p.n_games + 255) / 256), dim3(256), 0, s, p.n_games, p.barrier, 0);
+    // the barrier counters and, right after them, the queues' claim counters start at zero
+    const int32_t nz = p.n_games + PERSISTENT_QUEUES;
+    hipLaunchKernelGGL(k_fill_int, dim3((nz + 255) / 256), dim3(256), 0, s, nz, p.barrier, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const PersistentLaunch L{g, p, T_, f, alt, s};

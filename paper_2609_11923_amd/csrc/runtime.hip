@@ -424,14 +424,13 @@ void cfr_layout_free(cfr_layout *l) {
     std::memset(l, 0, sizeof *l);
 }
 
-// XCD-aware work table of the persistent launch.  Each game gets W = ceil(nodes / wg_nodes)
-// workgroups (at least 1), all on one XCD (the hardware dispatches block b to XCD b % 8), so its
-// working set stays in that XCD's L2.  Games are assigned to XCDs largest first onto the least
-// loaded XCD; each XCD's blocks take consecutive slots b = x + 8k and short XCDs are padded with
-// idle blocks.  The grid never exceeds the resident capacity, so the blocks of a game are
-// co-resident and its barrier can complete; if it would, wg_nodes is doubled.
+// Work plan of the persistent launch (plan_persistent): per-XCD queues of (game, rank) tickets, each
+// game's ranks at most a quarter of one XCD's resident workgroups, games balanced over the queues
+// largest first.  The grid is the device's resident capacity for the kernel; workgroups claim tickets
+// in order (see k_persistent).  At any time at most one game per queue is partly claimed, so with
+// W <= max_w the launch keeps progressing whenever 8 (max_w - 1) + 1 workgroups -- a quarter of the
+// device -- can be resident, whatever else holds the rest.
 static cfr_status build_persistent_plan(cfr_handle *h, int32_t wg_nodes) {
-    constexpr int XCD = 8;
     const DevGame &g = h->g;
     const int n = h->n_games;
     const int MD = g.max_depth;
@@ -441,48 +440,20 @@ static cfr_status build_persistent_plan(cfr_handle *h, int32_t wg_nodes) {
     HIP_TRY(hipGetDeviceProperties(&prop, h->opt.device));
     cus = prop.multiProcessorCount;
     const int64_t capacity = (int64_t)per_cu * cus;
-    if (capacity < XCD) return fail(CFR_EDEVICE, "persistent kernel cannot be resident");
+    if (capacity < PERSISTENT_QUEUES) return fail(CFR_EDEVICE, "persistent kernel cannot be resident");
     std::vector<int64_t> nodes((size_t)n, 0);
     for (int s = 0; s < n; s++)
         for (int d = 0; d <= MD; d++) {
             const int32_t *r = &h->game_range[((size_t)s * (MD + 1) + d) * GR_FIELDS];
             nodes[s] += r[1] - r[0];
         }
-    std::vector<int> order((size_t)n);
-    for (int s = 0; s < n; s++) order[s] = s;
-    std::sort(order.begin(), order.end(), [&](int a, int b) { return nodes[a] > nodes[b]; });
-    if (wg_nodes <= 0) wg_nodes = 16384;
-    std::vector<std::vector<int>> xg(XCD);
-    std::vector<int64_t> W((size_t)n);
-    for (;;) {
-        for (auto &v : xg) v.clear();
-        std::vector<int64_t> load(XCD, 0), blocks(XCD, 0);
-        for (int s : order) {
-            W[s] = std::max<int64_t>(1, (nodes[s] + wg_nodes - 1) / wg_nodes);
-            int best = 0;
-            for (int x = 1; x < XCD; x++) if (load[x] < load[best]) best = x;
-            xg[best].push_back(s);
-            load[best] += nodes[s];
-            blocks[best] += W[s];
-        }
-        const int64_t maxb = *std::max_element(blocks.begin(), blocks.end());
-        if (maxb * XCD <= capacity) break;
-        if (wg_nodes >= (1 << 30)) return fail(CFR_EUNSUPPORTED, "too many games for one resident launch");
-        wg_nodes *= 2;
-    }
-    int64_t maxb = 0;
-    for (int x = 0; x < XCD; x++) {
-        int64_t b = 0;
-        for (int s : xg[x]) b += W[s];
-        maxb = std::max(maxb, b);
-    }
-    const int64_t total = maxb * XCD;
-    std::vector<int4> table((size_t)total, make_int4(-1, 0, 0, 0));
-    for (int x = 0; x < XCD; x++) {
-        int64_t k = 0;
-        for (int s : xg[x])
-            for (int64_t r = 0; r < W[s]; r++, k++) table[(size_t)(x + XCD * k)] = make_int4(s, (int)r, (int)W[s], 0);
-    }
+    PersistentWork P;
+    std::string err;
+    const int32_t max_w = (int32_t)std::max<int64_t>(1, capacity / PERSISTENT_QUEUES / 4);
+    if (!plan_persistent(nodes, wg_nodes, max_w, PERSISTENT_QUEUES, P, err)) return fail(CFR_EUNSUPPORTED, err);
+    std::vector<int4> table(P.ticket.size() / 3);
+    for (size_t k = 0; k < table.size(); k++)
+        table[k] = make_int4(P.ticket[3 * k], P.ticket[3 * k + 1], P.ticket[3 * k + 2], 0);
     // device copies (replacing any previous plan)
     for (void *p : h->pp_allocs) (void)hipFree(p);
     h->pp_allocs.clear();
@@ -494,12 +465,16 @@ static cfr_status build_persistent_plan(cfr_handle *h, int32_t wg_nodes) {
     };
     PersistentPlan &pp = h->pp;
     cfr_status st;
-    if ((st = alloc((void **)&pp.wg_table, table.size() * sizeof(int4))) != CFR_OK) return st;
+    if ((st = alloc((void **)&pp.tickets, table.size() * sizeof(int4))) != CFR_OK) return st;
+    if ((st = alloc((void **)&pp.q_off, P.q_off.size() * sizeof(int32_t))) != CFR_OK) return st;
     if ((st = alloc((void **)&pp.game_range, h->game_range.size() * sizeof(int32_t))) != CFR_OK) return st;
     if ((st = alloc((void **)&pp.game_depth, (size_t)n * sizeof(int32_t))) != CFR_OK) return st;
-    if ((st = alloc((void **)&pp.barrier, (size_t)n * sizeof(int32_t))) != CFR_OK) return st;
+    // barrier counters of the games, then the queues' claim counters (zeroed together per launch)
+    if ((st = alloc((void **)&pp.barrier, ((size_t)n + PERSISTENT_QUEUES) * sizeof(int32_t))) != CFR_OK) return st;
     if ((st = alloc((void **)&pp.err, sizeof(int32_t))) != CFR_OK) return st;
-    HIP_TRY(hipMemcpy(pp.wg_table, table.data(), table.size() * sizeof(int4), hipMemcpyHostToDevice));
+    pp.claim = pp.barrier + n;
+    HIP_TRY(hipMemcpy(pp.tickets, table.data(), table.size() * sizeof(int4), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(pp.q_off, P.q_off.data(), P.q_off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(pp.game_range, h->game_range.data(), h->game_range.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(pp.game_depth, h->game_depth.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(pp.err, 0, sizeof(int32_t)));
@@ -509,10 +484,14 @@ static cfr_status build_persistent_plan(cfr_handle *h, int32_t wg_nodes) {
         if (khz <= 0) return fail(CFR_EDEVICE, "device reports no wall-clock rate");
         pp.timeout_ticks = (int64_t)(BARRIER_TIMEOUT_S * 1000.0 * khz);
     }
-    pp.blocks = (int32_t)total;
+    pp.n_tickets = (int32_t)table.size();
+    pp.blocks = (int32_t)std::min<int64_t>(capacity, ((int64_t)pp.n_tickets + PERSISTENT_QUEUES - 1) /
+                                                         PERSISTENT_QUEUES * PERSISTENT_QUEUES);
     pp.n_games = n;
     pp.max_depth = MD;
-    h->wg_nodes = wg_nodes;
+    pp.wg_nodes = P.wg_nodes;
+    pp.max_W = P.max_W;
+    h->wg_nodes = P.wg_nodes;
     if (h->pexec) { (void)hipGraphExecDestroy(h->pexec); h->pexec = nullptr; }
     if (h->pgraph) { (void)hipGraphDestroy(h->pgraph); h->pgraph = nullptr; }
     h->pgraph_n = -1;
@@ -1251,6 +1230,25 @@ static cfr_status set_lds_schedule(cfr_handle *h) {
     return CFR_OK;
 }
 
+cfr_status cfr_persistent_plan_host(const int64_t *nodes, int32_t n, int32_t wg_nodes, int32_t max_w, int32_t *W,
+                                    int32_t *queue, int32_t *q_off, int32_t *wg_nodes_used) {
+    if (n < 0 || (n > 0 && (!nodes || !W || !queue)) || !q_off || !wg_nodes_used || max_w < 1)
+        return fail(CFR_EINVAL, "bad argument");
+    std::vector<int64_t> nv(nodes, nodes + n);
+    for (int64_t x : nv)
+        if (x < 0) return fail(CFR_EINVAL, "negative node count");
+    PersistentWork P;
+    std::string err;
+    if (!plan_persistent(nv, wg_nodes, max_w, PERSISTENT_QUEUES, P, err)) return fail(CFR_EUNSUPPORTED, err);
+    for (int s = 0; s < n; s++) {
+        W[s] = P.W[(size_t)s];
+        queue[s] = P.queue[(size_t)s];
+    }
+    for (int q = 0; q <= PERSISTENT_QUEUES; q++) q_off[q] = P.q_off[(size_t)q];
+    *wg_nodes_used = P.wg_nodes;
+    return CFR_OK;
+}
+
 cfr_status cfr_set_schedule(cfr_handle *h, int32_t persistent, int32_t wg_nodes) {
     if (!h) return fail(CFR_EINVAL, "handle is NULL");
     if (persistent < CFR_SCHEDULE_LEVEL || persistent > CFR_SCHEDULE_LDS) return fail(CFR_EINVAL, "unknown schedule");
@@ -1303,13 +1301,13 @@ cfr_status cfr_autotune(cfr_handle *h, int64_t iters, void *stream, const char *
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
-        int32_t last_blocks = -1;
+        int32_t last_wg = -1;
         for (auto c : cand) {
             cfr_status st = cfr_set_schedule(h, c.first, c.second);
             if (st != CFR_OK) continue;
             const bool pers = c.first == CFR_SCHEDULE_PERSISTENT;
-            if (pers && h->pp.blocks == last_blocks) continue;  // same launch shape as the previous size
-            if (pers) last_blocks = h->pp.blocks;
+            if (pers && h->pp.wg_nodes == last_wg) continue;  // same plan as the previous size
+            if (pers) last_wg = h->pp.wg_nodes;
             st = cfr_iterate(h, iters, stream);            // warm-up (capture)
             if (st == CFR_OK) HIP_TRY(hipEventRecord(e0, s));
             if (st == CFR_OK) st = cfr_iterate(h, iters, stream);
