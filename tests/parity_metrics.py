@@ -96,63 +96,80 @@ MULT = 4            # tolerance over the spread of the oracle's own runs
 def free_run_compare(game, s, o, T, precision, control, perturb_inputs, current=True, note=print):
     """Compare solver s with oracle o (FP64) after T free-running iterations.
 
-    The tolerance of each quantity comes from how far runs of the same method in the same precision
-    spread around the FP64 run on this game, measured on the oracle: control(game, f32_state, reverse)
-    returns a finished run of it.  Samples: FP32 state in the default and the reverse summation order
-    (FP64: reverse order only); with perturb_inputs also on payoffs moved by up to one unit of
-    rounding of the precision (1e-7 FP32, 1e-15 FP64, two seeds), which models the library rounding
-    the chance-folded template once per terminal (games with exact payoff ties are left out: such a
-    move breaks ties the library keeps).  tol = max(bar, MULT x spread).
+    Six state metrics -- normwise (rel_err) and reach-weighted (weighted_err, weights from the oracle's
+    average profile) errors of the regrets (over max |R|), the average and the current strategy -- and
+    exploitability.  The tolerance of each comes from how far runs of the same method in the same
+    precision spread around the FP64 run on this game, measured on the oracle: control(game, f32_state,
+    reverse) returns a finished run.  Samples: FP32 state in the default and the reverse summation order
+    (FP64: reverse order only); with perturb_inputs also on payoffs moved by up to one unit of rounding
+    of the precision (1e-7 FP32, 1e-15 FP64, two seeds), which models the library rounding the
+    chance-folded template once per terminal (games with exact payoff ties are left out: such a move
+    breaks ties the library keeps).  tol = max(bar, MULT x spread): the bar (TOL, EXPL_TOL pot) wherever
+    the method's own runs agree to better than a quarter of it.
 
-    Hard checks: exploitability and the average profile's value within their tolerance (< EXPL_CAP
-    pot), the reach-weighted average strategy <= TOL, and every normwise quantity whose tolerance is
-    below CAP.  A cell where exploitability itself spreads beyond EXPL_CAP, or any normwise tolerance
-    reaches CAP, cannot be pinned by a free run: it is recorded as an expected failure with the
-    measured spread (the one-step test pins such cells at every iteration); the reach-weighted regret
-    and current-strategy errors are asserted only when every normwise quantity is pinned."""
+    Exploitability and the average profile's value are checked first; if their tolerance reaches
+    EXPL_CAP pot nothing is pinnable and the cell is an expected failure.  Then each state metric whose
+    tolerance is below CAP is asserted -- except that the reach-weighted regret and current-strategy
+    errors are held only where their normwise counterparts are (where those are not, regret matching has
+    switched sets between pure and mixed strategies along the run, and a few samples cannot bound where);
+    anything not asserted makes the cell an expected failure naming the measured spread (the one-step
+    test pins every such cell at every iteration)."""
     import pytest
     R, _ = s.state()
     avg, cur = s.strategy(average=True), s.strategy(average=False)
     Ro, _, sco, sao = o.state()
     e, _, _, v = s.exploitability()
     eo, _, _, vo = o.exploitability()
-    eR, eavg, ecur = rel_err(R, Ro), rel_err(avg, sao), rel_err(cur, sco)
+    lay = o.layout()
+    w = slot_weights(lay, set_reach(game, lay, sao))
+    scale_R = max(float(np.abs(Ro).max()), 1e-30)
+
+    def metrics(Rx, ax, cx):
+        return dict(regrets=rel_err(Rx, Ro), average=rel_err(ax, sao), current=rel_err(cx, sco),
+                    w_regrets=weighted_err(Rx, Ro, w, scale_R), w_average=weighted_err(ax, sao, w),
+                    w_current=weighted_err(cx, sco, w))
+
+    got = metrics(R, avg, cur)
     f32 = precision == "fp32"
     samples = [control(game, True, False), control(game, True, True)] if f32 else [control(game, False, True)]
     if perturb_inputs:
         scale = max(1.0, float(np.abs(game.payoff).max()))
         eps = 1e-7 if f32 else 1e-15
         samples += [control(jitter(game, sd, eps * scale), f32, False) for sd in (5, 6)]
-    sp = [0.0, 0.0, 0.0, 0.0]
+    spread = {k: 0.0 for k in got}
+    sp_e = 0.0
     for c in samples:
         Rc, _, scc, sac = c.state()
-        sp = [max(sp[0], rel_err(Rc, Ro)), max(sp[1], rel_err(sac, sao)), max(sp[2], rel_err(scc, sco)),
-              max(sp[3], abs(c.exploitability()[0] - eo))]
-    tR, tavg, tcur = (max(TOL, MULT * x) for x in sp[:3])
-    te = max(EXPL_TOL * game.pot, MULT * sp[3])
-    note(f"  spread over {len(samples)} oracle runs: R {sp[0]:.1e} avg {sp[1]:.1e} cur {sp[2]:.1e} expl {sp[3]:.1e}; "
-         f"gpu R {eR:.2e} avg {eavg:.2e} cur {ecur:.2e} expl {e:.9e} vs {eo:.9e}")
+        for k, x in metrics(Rc, sac, scc).items():
+            spread[k] = max(spread[k], x)
+        sp_e = max(sp_e, abs(c.exploitability()[0] - eo))
+    te = max(EXPL_TOL * game.pot, MULT * sp_e)
+    note(f"  {len(samples)} oracle runs spread: " + " ".join(f"{k} {x:.1e}" for k, x in spread.items()) +
+         f" expl {sp_e:.1e}")
+    note(f"  gpu: " + " ".join(f"{k} {x:.2e}" for k, x in got.items()) + f" expl {e:.9e} vs {eo:.9e}")
     if te >= EXPL_CAP * game.pot:
-        pytest.xfail(f"{precision} free run: the oracle's own runs differ in exploitability by {sp[3]:.1e} after {T} "
-                     f"iterations (R {sp[0]:.1e}, average {sp[1]:.1e}): nothing to pin; the one-step test pins "
-                     f"this cell (gpu: expl {e:.4e} vs {eo:.4e}, R {eR:.1e}, average {eavg:.1e})")
+        pytest.xfail(f"{precision} free run: the oracle's own runs differ in exploitability by {sp_e:.1e} after {T} "
+                     f"iterations (regrets {spread['regrets']:.1e}, average {spread['average']:.1e}): nothing to "
+                     f"pin; the one-step test pins this cell (gpu: expl {e:.4e} vs {eo:.4e}, regrets "
+                     f"{got['regrets']:.1e}, average {got['average']:.1e})")
     assert abs(e - eo) <= te and abs(v - vo) <= te
-    lay = o.layout()
-    w = slot_weights(lay, set_reach(game, lay, sao))
-    wavg, wcur = weighted_err(avg, sao, w), weighted_err(cur, sco, w)
-    wR = weighted_err(R, Ro, w, max(float(np.abs(Ro).max()), 1e-30))
-    note(f"  reach-weighted R {wR:.2e} avg {wavg:.2e} cur {wcur:.2e}; tol R {tR:.1e} avg {tavg:.1e} cur {tcur:.1e} "
-         f"expl {te:.1e}")
-    assert wavg <= TOL
-    checks = [("regrets", eR, tR, sp[0]), ("average", eavg, tavg, sp[1])] + \
-             ([("current", ecur, tcur, sp[2])] if current else [])
+    tol = {k: max(TOL, MULT * x) for k, x in spread.items()}
     unpinned = []
-    for name, err, tol, spread in checks:
-        if tol < CAP:
-            assert err <= tol, name
-        else:
-            unpinned.append(f"{name} {err:.1e} (own runs {spread:.1e})")
+    # the average strategy is the solver's output: its reach-weighted error is held wherever its own
+    # tolerance allows; regrets and the current strategy are internal state whose free-run divergence is
+    # regret matching switching sets, so their reach-weighted error is held where the normwise one is
+    groups = [("average", ["average"], ["w_average"]), ("regrets", ["regrets"], ["w_regrets"])]
+    if current:
+        groups.append(("current", ["current"], ["w_current"]))
+    for name, norm, wtd in groups:
+        keys = wtd + (norm if tol[norm[0]] < CAP else [])
+        if tol[norm[0]] >= CAP and name != "average":
+            keys = []
+        for k in norm + wtd:
+            if k in keys and tol[k] < CAP:
+                assert got[k] <= tol[k], (k, got[k], tol[k])
+            else:
+                unpinned.append(f"{k} {got[k]:.1e} (own runs {spread[k]:.1e})")
     if unpinned:
         pytest.xfail(f"{precision} free run: the oracle's own runs spread too far to pin " + ", ".join(unpinned) +
-                     "; exploitability and the reach-weighted average are pinned, the one-step test pins the rest")
-    assert wR <= TOL and wcur <= TOL
+                     "; exploitability and the other metrics are pinned, the one-step test pins the rest")
