@@ -431,6 +431,17 @@ cfr_status cfr_mlp_forward(cfr_mlp *n, const void *x, int64_t rows, float *z, vo
 cfr_status cfr_mlp_backward(cfr_mlp *n, const void *x, const float *target, const float *weight,
                             const uint8_t *nact, const int32_t *idx, int64_t n_data, int64_t rows, double *loss,
                             void *stream);
+/* Logits as cfr_mlp_forward computes them (the same kernels, bitwise equal results), for callers that
+ * cannot allocate device memory: code under hipGraph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  The call allocates nothing (no hipMalloc, hipFree or allocating library call):
+ * the hidden activations go to one static device array of 2 x 8192 x 256 bf16 (8 MiB) that each GPU
+ * the library runs on holds until the process ends; its device address is looked up on the first
+ * call on a device.  rows <= 8192 (CFR_EINVAL beyond; cfr_mlp_forward has no such limit), the network's
+ * hidden width <= 256.  Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (other streams, other threads, other networks) race and must be serialised by the caller; each call
+ * writes the activations it reads, so nothing has to be cleared between calls.  x, z as for
+ * cfr_mlp_forward; enqueued on `stream`. */
+cfr_status cfr_mlp_forward_noalloc(cfr_mlp *n, const void *x, int64_t rows, float *z, void *stream);
 /* One Adam step with learning rate lr on the gradients of the last backward call. */
 cfr_status cfr_mlp_adam(cfr_mlp *n, float lr, void *stream);
 /* cfr_mlp_backward followed by cfr_mlp_adam. */

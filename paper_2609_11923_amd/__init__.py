@@ -100,7 +100,7 @@ EXPORTS = ["cfr_default_options", "cfr_layout_host", "cfr_layout_free", "cfr_com
            "cfr_mlp_forward", "cfr_mlp_backward", "cfr_mlp_adam", "cfr_mlp_train_step", "cfr_mlp_destroy",
            "cfr_num_infosets", "cfr_features", "cfr_regret_unit", "cfr_warm_start", "cfr_set_payoffs",
            "cfr_set_root_chance", "cfr_set_root_ranges", "cfr_set_state", "cfr_get_prediction", "cfr_get_layout",
-           "cfr_persistent_plan_host"]
+           "cfr_persistent_plan_host", "cfr_mlp_forward_noalloc"]
 
 
 def load():
@@ -150,6 +150,7 @@ def load():
         "cfr_mlp_set_params": (S, [_P, _P, ctypes.c_int64]),
         "cfr_mlp_get": (S, [_P, ctypes.c_int, _P, ctypes.c_int64]),
         "cfr_mlp_forward": (S, [_P, _P, ctypes.c_int64, _P, _P]),
+        "cfr_mlp_forward_noalloc": (S, [_P, _P, ctypes.c_int64, _P, _P]),
         "cfr_mlp_backward": (S, [_P, _P, _P, _P, _P, _P, ctypes.c_int64, ctypes.c_int64,
                                  ctypes.POINTER(ctypes.c_double), _P]),
         "cfr_mlp_adam": (S, [_P, ctypes.c_float, _P]),
@@ -461,6 +462,10 @@ class Mlp:
 
     def forward(self, x, rows: int, z, stream=None):
         _check(load().cfr_mlp_forward(self.h, _dptr(x), int(rows), _dptr(z), _stream_arg(stream)))
+
+    def forward_noalloc(self, x, rows: int, z, stream=None):
+        """cfr_mlp_forward without device allocation (activations in the library's static scratch; rows <= 8192)."""
+        _check(load().cfr_mlp_forward_noalloc(self.h, _dptr(x), int(rows), _dptr(z), _stream_arg(stream)))
 
     def backward(self, x, target, weight, nact, rows: int, idx=None, n_data: int = 0, want_loss=True, stream=None):
         loss = ctypes.c_double()

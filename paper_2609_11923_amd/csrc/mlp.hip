@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -517,24 +518,57 @@ hipError_t head(const cfr_mlp *n, const HeadArgs &a, bool train, int blocks, hip
 
 constexpr int HEAD_BLOCKS = 256;
 
-// forward pass of `rows` (<= max_rows) rows; leaves the hidden activations in n->H
-cfr_status forward_rows(cfr_mlp *n, const uint16_t *x, int rows, float *z, bool train, hipStream_t s) {
+// forward pass of `rows` (<= the buffers' rows) rows; hidden layer l writes its activations to act(l)
+template <typename Act>
+cfr_status forward_rows_into(cfr_mlp *n, const uint16_t *x, int rows, float *z, bool train, Act act, hipStream_t s) {
     const int L = n->d.n_hidden;
     const uint16_t *in = x;
     for (int l = 0; l < L; l++) {
         GemmArgs g{};
         g.A = in; g.B = n->theta16 + n->woff[l];
         g.M = rows; g.N = n->fout[l]; g.K = n->fin[l]; g.lda = n->fin[l]; g.ldb = n->fout[l]; g.kchunk = g.K;
-        g.bias = n->theta + n->boff[l]; g.C16 = n->H[l];
+        g.bias = n->theta + n->boff[l]; g.C16 = act(l);
         MHIP((gemm<false, false, EPI_BIAS_RELU>(g, 1, s)));
-        in = n->H[l];
+        in = act(l);
     }
     if (!train) {
         HeadArgs a{};
-        a.H = n->H[L - 1]; a.W = n->theta16 + n->woff[L]; a.b = n->theta + n->boff[L]; a.rows = rows; a.z = z;
+        a.H = act(L - 1); a.W = n->theta16 + n->woff[L]; a.b = n->theta + n->boff[L]; a.rows = rows; a.z = z;
         const int blocks = std::min(HEAD_BLOCKS, (rows + 3) / 4);
         MHIP(head(n, a, false, blocks, s));
     }
+    return CFR_OK;
+}
+
+// forward pass of `rows` (<= max_rows) rows; leaves the hidden activations in n->H (training reads them)
+cfr_status forward_rows(cfr_mlp *n, const uint16_t *x, int rows, float *z, bool train, hipStream_t s) {
+    return forward_rows_into(n, x, rows, z, train, [n](int l) { return n->H[(size_t)l]; }, s);
+}
+
+// ---- the allocation-free inference entry point: its activations live in a file-scope device array ----
+// Two ping-pong buffers of NOALLOC_ROWS rows x 256 hidden units (bf16): 8 MiB that every GPU the
+// library runs on holds for the life of the process.  In host code `noalloc_scratch` is the symbol's
+// host-side stand-in, never a device address: its device address is looked up once per device.
+constexpr int NOALLOC_ROWS = 8192;
+constexpr int NOALLOC_HIDDEN = 256;
+static __device__ __align__(256) uint16_t noalloc_scratch[2 * NOALLOC_ROWS * NOALLOC_HIDDEN];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+uint16_t *g_noalloc_ptr[MAX_DEVICES] = {};
+
+// Device address of this device's scratch (the device must be current); looked up on first use.
+cfr_status noalloc_scratch_ptr(int device, uint16_t **out) {
+    if (device < 0 || device >= MAX_DEVICES) return mfail(CFR_EINVAL, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+        if (e != hipSuccess || !p)
+            return mfail(CFR_EDEVICE, std::string("hipGetSymbolAddress of the inference scratch: ") + hipGetErrorString(e));
+        g_noalloc_ptr[device] = (uint16_t *)p;
+    }
+    *out = g_noalloc_ptr[device];
     return CFR_OK;
 }
 
@@ -663,6 +697,22 @@ cfr_status cfr_mlp_forward(cfr_mlp *n, const void *x, int64_t rows, float *z, vo
         if (st != CFR_OK) return st;
     }
     return CFR_OK;
+}
+
+cfr_status cfr_mlp_forward_noalloc(cfr_mlp *n, const void *x, int64_t rows, float *z, void *stream) {
+    if (!n || ((!x || !z) && rows > 0) || rows < 0) return mfail(CFR_EINVAL, "bad argument");
+    if (rows > NOALLOC_ROWS)
+        return mfail(CFR_EINVAL, "cfr_mlp_forward_noalloc takes at most " + std::to_string(NOALLOC_ROWS) +
+                                 " rows per call (" + std::to_string(rows) + " given)");
+    if (n->d.hidden > NOALLOC_HIDDEN) return mfail(CFR_EINVAL, "hidden width above the scratch's 256 units");
+    MHIP(hipSetDevice(n->d.device));
+    uint16_t *buf = nullptr;
+    cfr_status st = noalloc_scratch_ptr(n->d.device, &buf);
+    if (st != CFR_OK || rows == 0) return st;
+    // hidden layer l writes buffer l % 2 and reads the other one (the rows come in x for layer 0)
+    const size_t half = (size_t)NOALLOC_ROWS * NOALLOC_HIDDEN;
+    return forward_rows_into(n, (const uint16_t *)x, (int)rows, z, false,
+                             [buf, half](int l) { return buf + (size_t)(l & 1) * half; }, (hipStream_t)stream);
 }
 
 cfr_status cfr_mlp_backward(cfr_mlp *n, const void *x, const float *target, const float *weight,
