@@ -4,7 +4,7 @@ A step is one complete CFR+ iteration (regret matching, forward reach pass, back
 pass, regret and average updates), replayed from one hipGraph, with the game already resident
 in HBM.  Prints ONE JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|mid|tiny]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|mid|tiny|batch|batch-steps|mlp|warm]
 
 Workloads (seeded, synthetic):
   large  36-card deck, K=10 two-card hands per player, two public rounds of pot betting,
@@ -171,6 +171,10 @@ def run_batch(cfr, torch, games, iters, precision, log, tune_iters=20, warm=None
     ev1.synchronize()
     ms = ev0.elapsed_time(ev1)
     e_final = s.batch_exploitability(stream=stream)[0]
+    # per-kernel design bytes and durations of the level kernels (direct launches) for the roofline
+    kernels = s.profile(5, stream=stream)
+    design_iter = sum(k["bytes_per_iteration"] for k in kernels)
+    roof = roofline_record(kernels, lambda name, nl: stored_traffic(name, "batch", "fp32", nl))
     # checkpointed solve for time to threshold
     s.reset()
     if warm is not None:
@@ -193,6 +197,9 @@ def run_batch(cfr, torch, games, iters, precision, log, tune_iters=20, warm=None
     bat_ms = float(np.max(cross[fin]) * ms_it) if fin.any() else None
     return dict(
         compile_s=t_compile, schedule=tune, iterations=iters, ms_total=ms, ms_per_iteration=ms_it,
+        roofline=roof, design_bytes_per_iteration=design_iter,
+        hbm_gbps_design_bytes=physical_rate(design_iter, ms_it),
+        frac_design_bytes=physical_rate(design_iter, ms_it) / HBM_PEAK_GBPS, kernels=kernels,
         edges=int(sum(g.n_edges for g in games)),
         edge_iterations_per_s=sum(g.n_edges for g in games) * iters / (ms * 1e-3),
         expl_final_median=float(np.median(e_final)), expl_final_max=float(np.max(e_final)),
@@ -211,6 +218,83 @@ def run_batch(cfr, torch, games, iters, precision, log, tune_iters=20, warm=None
             "wall_time_reduction": (1.0 - bat_ms / seq_ms) if bat_ms and seq_ms > 0 else None,
         },
     ), cross
+
+
+def run_batch_steps(cfr, torch, args, log):
+    """The 256-subgame batch under one schedule (level launches or the persistent launch): `warmup`
+    then `steps` timed iterations, and for the level schedule the per-kernel roofline.  A light mode for
+    profilers (no checkpointed solves)."""
+    games, _ = batch_games(args.batch_games, args.seed)
+    log(f"[bench] batch of {len(games)} subgames, {sum(g.n_edges for g in games)} edges, {args.batch_schedule}")
+    s = cfr.Solver(games, use_graph=not args.direct)
+    if args.batch_schedule == "persistent":
+        s.set_schedule(cfr.CFR_SCHEDULE_PERSISTENT, args.wg_nodes)
+    stream = torch.cuda.Stream()
+    s.iterate(max(args.warmup, 1), stream=stream)
+    stream.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    s.iterate(args.steps, stream=stream)
+    ev1.record(stream)
+    ev1.synchronize()
+    ms_it = ev0.elapsed_time(ev1) / args.steps
+    out = dict(schedule=args.batch_schedule, ms_per_iteration=ms_it, n_games=len(games),
+               edges=int(sum(g.n_edges for g in games)))
+    if args.batch_schedule == "level":
+        kernels = s.profile(args.profile_iters, stream=stream)
+        design_iter = sum(k["bytes_per_iteration"] for k in kernels)
+        out.update(kernels=kernels, design_bytes_per_iteration=design_iter,
+                   roofline=roofline_record(kernels, lambda name, nl: stored_traffic(name, "batch", "fp32", nl)),
+                   frac_design_bytes=physical_rate(design_iter, ms_it) / HBM_PEAK_GBPS)
+    log(f"[bench] batch {args.batch_schedule}: {ms_it:.4f} ms/iteration")
+    s.close()
+    return out
+
+
+def run_mlp(cfr, torch, args, log, rows=1 << 18):
+    """The warm-start network's kernels alone: inference over `rows` feature rows and Adam training steps
+    on minibatches of 4,096 (seeded synthetic rows and targets), with the hidden GEMMs' rate against the
+    BF16 matrix-core peak."""
+    import gamegen as gg
+    torch.manual_seed(0)
+    sizes = [(cfr.CFR_FEATURES, 256), (256, 256), (256, 256), (256, cfr.CFR_MLP_OUT)]
+    net = cfr.Mlp(max_rows=4096)
+    net.set_params(gg.mlp_init(sizes, seed=1))
+    x = torch.randn(rows, cfr.CFR_FEATURES, device="cuda").to(torch.bfloat16)
+    z = torch.empty(rows, 4, dtype=torch.float32, device="cuda")
+    flops_row = 2 * sum(a * b for a, b in sizes)
+    net.forward(x, rows, z)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    ev0.record()
+    for _ in range(reps):
+        net.forward(x, rows, z)
+    ev1.record()
+    ev1.synchronize()
+    ms_inf = ev0.elapsed_time(ev1) / reps
+    B = 4096
+    t = torch.softmax(torch.randn(rows, 4, device="cuda"), dim=1).float().contiguous()
+    w = torch.ones(rows, device="cuda")
+    nact = torch.full((rows,), 4, dtype=torch.uint8, device="cuda")
+    steps = 50
+    net.train_step(x, t, w, nact, B, 1e-3)
+    torch.cuda.synchronize()
+    ev0.record()
+    for k in range(steps):
+        off = (k * B) % (rows - B)
+        net.train_step(x[off:], t[off:], w[off:], nact[off:], B, 1e-3)
+    ev1.record()
+    ev1.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / steps
+    out = dict(rows=rows, inference_ms=ms_inf, inference_tflops=flops_row * rows / (ms_inf * 1e-3) / 1e12,
+               train_batch=B, train_step_ms=ms_step,
+               train_tflops=3 * flops_row * B / (ms_step * 1e-3) / 1e12, peak_tflops=2500.0,
+               what="128 -> 3 x 256 -> 4 ReLU network, BF16 matrix cores, FP32 accumulation; training counts "
+                    "forward, data and weight gradients (3x the forward flops)")
+    log(f"[bench] mlp: {out}")
+    net.close()
+    return out
 
 
 def run_rules(cfr, torch, games, log, max_iters=4000):
@@ -544,6 +628,9 @@ def main():
     ap.add_argument("--batch-games", type=int, default=256)
     ap.add_argument("--batch-iters", type=int, default=500)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-subgame measurement")
+    ap.add_argument("--batch-schedule", choices=["level", "persistent"], default="level",
+                    help="schedule of --workload batch-steps")
+    ap.add_argument("--wg-nodes", type=int, default=0, help="persistent schedule: target nodes per workgroup")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm-start measurement")
     ap.add_argument("--no-rules", action="store_true", help="skip the update-rule comparison on the batch")
     ap.add_argument("--no-tiny", action="store_true", help="skip the tiny-game schedule comparison")
@@ -587,6 +674,12 @@ def main():
     if args.workload == "warm":
         res = run_warm(cfr, torch, args, log)
         print(json.dumps({"workload": "warm", **res}), flush=True)
+        return
+    if args.workload == "batch-steps":
+        print(json.dumps({"workload": "batch-steps", **run_batch_steps(cfr, torch, args, log)}), flush=True)
+        return
+    if args.workload == "mlp":
+        print(json.dumps({"workload": "mlp", **run_mlp(cfr, torch, args, log)}), flush=True)
         return
     if args.workload == "batch":
         games, _ = batch_games(args.batch_games, args.seed)

@@ -102,7 +102,7 @@ def free_run_compare(game, s, o, T, precision, control, perturb_inputs, current=
     precision spread around the FP64 run on this game, measured on the oracle: control(game, f32_state,
     reverse) returns a finished run.  Samples: FP32 state in the default and the reverse summation order
     (FP64: reverse order only); with perturb_inputs also on payoffs moved by up to one unit of rounding
-    of the precision (1e-7 FP32, 1e-15 FP64, two seeds), which models the library rounding the
+    of the precision (1e-7 FP32, 1e-15 FP64; three seeds, both orders), which models the library rounding the
     chance-folded template once per terminal (games with exact payoff ties are left out: such a move
     breaks ties the library keeps).  tol = max(bar, MULT x spread): the bar (TOL, EXPL_TOL pot) wherever
     the method's own runs agree to better than a quarter of it.
@@ -135,7 +135,7 @@ def free_run_compare(game, s, o, T, precision, control, perturb_inputs, current=
     if perturb_inputs:
         scale = max(1.0, float(np.abs(game.payoff).max()))
         eps = 1e-7 if f32 else 1e-15
-        samples += [control(jitter(game, sd, eps * scale), f32, False) for sd in (5, 6)]
+        samples += [control(jitter(game, sd, eps * scale), f32, rev) for sd in (5, 6, 7) for rev in (False, True)]
     spread = {k: 0.0 for k in got}
     sp_e = 0.0
     for c in samples:
