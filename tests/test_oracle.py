@@ -135,8 +135,7 @@ def test_lp_equilibrium_random_games(seed):
     g = gg.random_game(seed, n_types1=2, n_types2=3, max_depth=5)
     o = oracle.Oracle(g)
     lay = o.layout()
-    if o.I == 0:
-        pytest.skip("no decisions")
+    assert o.I > 0, "a game without decisions pins nothing"
     v, sig, (v1, v2) = lp.solve(lay, lp.folded_payoffs(lay, g))
     assert abs(v1 - v2) < 1e-8
     b1, _ = o.best_response(1, sig)
@@ -161,8 +160,7 @@ def _random_profile(o, rng):
 def test_best_response_brute_force(name):
     g = {"kuhn": gg.kuhn, "example11": gg.example11}.get(name, lambda: gg.random_game(int(name[1:]), 2, 2, 4))()
     o = oracle.Oracle(g)
-    if o.I == 0:
-        pytest.skip("no decisions")
+    assert o.I > 0, "a game without decisions pins nothing"
     P, isets, ns = brute.paths(g)
     rng = np.random.default_rng(1)
     for _ in range(3):
@@ -175,13 +173,12 @@ def test_best_response_brute_force(name):
             assert abs(got - want) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["kuhn", "example11", "r2", "r4", "r6", "r8"])
+@pytest.mark.parametrize("name", ["kuhn", "example11", "r2", "r4", "r6", "r9"])
 @pytest.mark.parametrize("plus,linear", [(True, True), (True, False), (False, True), (False, False)])
 def test_cfr_against_terminal_sums(name, plus, linear):
     g = {"kuhn": gg.kuhn, "example11": gg.example11}.get(name, lambda: gg.random_game(int(name[1:]), 2, 2, 5))()
     o = oracle.Oracle(g, plus=plus, linear=linear)
-    if o.I == 0:
-        pytest.skip("no decisions")
+    assert o.I > 0, "a game without decisions pins nothing"
     P, isets, ns = brute.paths(g)
     R_b, S_b = brute.cfr(P, isets, ns, 15, plus, linear)
     o.iterate(15)
@@ -191,13 +188,12 @@ def test_cfr_against_terminal_sums(name, plus, linear):
     assert np.abs(S - S_b).max() <= 1e-12 * max(1.0, np.abs(S_b).max())
 
 
-@pytest.mark.parametrize("name", ["kuhn", "example11", "r2", "r4", "r6", "r8"])
+@pytest.mark.parametrize("name", ["kuhn", "example11", "r2", "r4", "r6", "r9"])
 @pytest.mark.parametrize("rule", ["dcfr", "pcfr+"])
 def test_discounted_and_predictive_rules_against_terminal_sums(name, rule):
     g = {"kuhn": gg.kuhn, "example11": gg.example11}.get(name, lambda: gg.random_game(int(name[1:]), 2, 2, 5))()
     o = oracle.Oracle(g, rule=rule)
-    if o.I == 0:
-        pytest.skip("no decisions")
+    assert o.I > 0, "a game without decisions pins nothing"
     P, isets, ns = brute.paths(g)
     R_b, S_b = brute.cfr(P, isets, ns, 15, rule=rule)
     o.iterate(15)
@@ -335,3 +331,56 @@ def test_fp32_state_control(name):
     if name == "c1":
         assert drift_avg > 1e-5
     assert abs(a.exploitability()[0] - b.exploitability()[0]) <= 1e-6 * game.pot
+
+
+def test_reverse_summation_control():
+    """The reverse-order control sums each node's children in the opposite order and nothing else: in
+    FP64 it agrees with the default order to rounding (1e-12 over 50 iterations of a random game, the
+    exploitability to 1e-12 pot); in FP32 state it moves the regrets, which is what makes it a spread
+    sample."""
+    game = gg.random_game(11, 5, 5, 6, max_actions=4, max_chance=3)
+    a = oracle.Oracle(game)
+    b = oracle.Oracle(game, reverse=True)
+    a.iterate(50)
+    b.iterate(50)
+    Ra, Sa, _, sa = a.state()
+    Rb, Sb, _, sb = b.state()
+    assert np.abs(Rb - Ra).max() <= 1e-12 * max(np.abs(Ra).max(), 1.0)
+    assert np.abs(sb - sa).max() <= 1e-12
+    assert abs(a.exploitability()[0] - b.exploitability()[0]) <= 1e-12 * game.pot
+    c = oracle.Oracle(game, f32_state=True)
+    d = oracle.Oracle(game, f32_state=True, reverse=True)
+    c.iterate(50)
+    d.iterate(50)
+    assert np.abs(c.state()[0] - d.state()[0]).max() > 0
+
+
+@pytest.mark.parametrize("rule", ["cfr+", "dcfr", "pcfr+"])
+@pytest.mark.parametrize("name", ["leduc3x2", "r11"])
+def test_fp32_state_control_is_the_fp64_map_rounded(name, rule):
+    """A pin of the FP32-state control build that does not go through the GPU: from the same state, one
+    of its iterations equals one FP64 iteration up to float32 rounding (normwise <= 1e-6 on regrets,
+    strategy sums and prediction, every one of 30 steps along its own trajectory), its regrets are
+    float32 numbers, and it is not the FP64 build (some step differs).  A dropped term, a wrong sign or
+    a misplaced rounding that changes the map fails the first check."""
+    g = gg.leduc(3, 2) if name == "leduc3x2" else gg.random_game(11, 2, 2, 5)
+    c = oracle.Oracle(g, f32_state=True, rule=rule)
+    o = oracle.Oracle(g, rule=rule)
+    differs = False
+    for t in range(30):
+        R, S, _, _ = c.state()
+        pred = c.prediction() if rule == "pcfr+" else None
+        o.set_state(R, S, t, pred)
+        o.iterate(1)
+        c.iterate(1)
+        Rc, Sc, _, _ = c.state()
+        Ro, So, _, _ = o.state()
+        assert np.array_equal(Rc.astype(np.float32).astype(np.float64), Rc)
+        eR = np.abs(Rc - Ro).max() / max(np.abs(Ro).max(), 1e-30)
+        eS = np.abs(Sc - So).max() / max(np.abs(So).max(), 1e-30)
+        assert eR <= 1e-6 and eS <= 1e-6, (t, eR, eS)
+        if rule == "pcfr+":
+            pc, po = c.prediction(), o.prediction()
+            assert np.abs(pc - po).max() <= 1e-6 * max(np.abs(po).max(), 1e-30)
+        differs |= eR > 0
+    assert differs
