@@ -217,6 +217,35 @@ def solve_curves(s: Solver, rows: Rows, torch, checkpoints, mlp=None, scale=0.0,
     return np.array(expl), warm_ms, iter_ms, checkpoints
 
 
+def stopwatch(s: Solver, rows: Rows, torch, iters, mlp=None, scale=0.0, probe=0, add=False, thr=None):
+    """One uninterrupted solve from scratch to `iters` iterations counted from the start (a warm start's
+    probe included), timed as a whole: on the stream with events and on the host clock from the first
+    launch to the stream's end.  Exploitability is evaluated once, after the timed region, to count the
+    games that reached `thr`."""
+    stream = torch.cuda.Stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    s.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    done = 0
+    if mlp is not None:
+        rows.features(s, probe=probe, stream=stream)
+        s.warm_start(mlp, rows.x, scale, add=add, stream=stream)
+        done = probe
+    if iters > done:
+        s.iterate(int(iters) - done, stream=stream)
+    ev[1].record(stream)
+    ev[1].synchronize()
+    host_ms = (time.perf_counter() - t0) * 1e3
+    e = s.batch_exploitability(stream=stream)[0]
+    out = dict(iterations=int(iters), ms_events=float(ev[0].elapsed_time(ev[1])), ms_host=float(host_ms))
+    if thr is not None:
+        out["reached"] = int((np.asarray(e) <= thr).sum())
+        out["games"] = int(np.asarray(e).size)
+    return out
+
+
 LEVEL_SYNC = {"persistent": 0, "wg_nodes": 0}
 
 
@@ -307,6 +336,10 @@ def evaluate(games, torch, mlp, scale, t_max, control=None, probe=0, schedule=LE
         out[name] = summarize(cross, iter_ms / (used[-1] - skip), warm_ms, skip)
         out[name]["expl_final_median"] = float(np.median(e[-1]))
         out[name]["_cross"] = cross
+        if np.isfinite(cross).all():
+            # the same solve run straight through to the last game's crossing, timed as a whole
+            out[name]["stopwatch"] = stopwatch(s, rows, torch, int(np.ceil(cross.max())), mlp=net, scale=c,
+                                               probe=probe, add=add, thr=thr)
         log(f"[warm] {name}: {({k: v for k, v in out[name].items() if not k.startswith('_')})}")
     s.close()
     return out
