@@ -271,6 +271,17 @@ cfr_status build_device_layout(const Layout &L, int kind, int group_actions, boo
                         if (r == R) R++;
                         rank[j] = r;
                     }
+                    // then order the states by the action count of their decision nodes (ties by
+                    // first occurrence), so that consecutive information sets, and hence the update
+                    // groups cut from them, mostly share one action count
+                    std::vector<int32_t> na((size_t)R, 0), order((size_t)R), to((size_t)R);
+                    for (int64_t j = 0; j < n; j++)
+                        if (L.node_type[lo + j] == CFR_NODE_P1 || L.node_type[lo + j] == CFR_NODE_P2)
+                            na[rank[j]] = std::max<int32_t>(na[rank[j]], L.child_off[lo + j + 1] - L.child_off[lo + j]);
+                    for (int32_t r = 0; r < R; r++) order[r] = r;
+                    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return na[x] < na[y]; });
+                    for (int32_t r = 0; r < R; r++) to[order[r]] = r;
+                    for (int64_t j = 0; j < n; j++) rank[j] = to[rank[j]];
                 }
                 // stable counting sort by (class, rank): decision, chance, terminal
                 auto cls = [&](int64_t k) -> int64_t {

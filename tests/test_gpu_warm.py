@@ -51,3 +51,9 @@ def test_trained_network_beats_cold_start_and_untrained_network():
     assert np.median(wst) < np.median(unt)
     # wall time includes the feature pass, probe, network and injection
     assert ev["warm"]["time_ms_median"] < ev["cold"]["time_ms_median"]
+    for arm in ("cold", "warm"):
+        sw = ev[arm].get("stopwatch")
+        if sw is not None:
+            # run straight through to the last crossing, (almost) every game is at the threshold
+            note(f"[warm test] {arm} stopwatch: {sw}")
+            assert sw["ms_events"] > 0 and sw["reached"] >= sw["games"] - 2
