@@ -420,7 +420,11 @@ cfr_status cfr_mlp_set_params(cfr_mlp *n, const float *params, int64_t len);
 /* Copy a flat host vector out: CFR_MLP_PARAMS, CFR_MLP_GRADS (of the last backward call),
  * CFR_MLP_ADAM_M or CFR_MLP_ADAM_V.  Synchronous. */
 cfr_status cfr_mlp_get(cfr_mlp *n, int which, float *dst, int64_t len);
-/* Logits z[rows][4] (device, float32) of device rows x[rows][in_dim] (bf16), on `stream`. */
+/* Logits z[rows][4] (device, float32) of device rows x[rows][in_dim] (bf16), on `stream`.  Any
+ * number of rows: one fused launch per 2^27 rows keeps each block's activations in LDS (no row limit,
+ * no activation buffers), after a small launch that refreshes the network's transposed bf16 weight
+ * copy; calls on one network that overlap on different streams (with each other or with training)
+ * race on that copy and must be ordered by the caller. */
 cfr_status cfr_mlp_forward(cfr_mlp *n, const void *x, int64_t rows, float *z, void *stream);
 /* Loss and parameter gradients of one minibatch of rows <= max_rows, on `stream`.  Device
  * arrays: x [.][in_dim] bf16, target [.][4] float32 (entries past a row's legal actions are
@@ -431,7 +435,8 @@ cfr_status cfr_mlp_forward(cfr_mlp *n, const void *x, int64_t rows, float *z, vo
 cfr_status cfr_mlp_backward(cfr_mlp *n, const void *x, const float *target, const float *weight,
                             const uint8_t *nact, const int32_t *idx, int64_t n_data, int64_t rows, double *loss,
                             void *stream);
-/* Logits as cfr_mlp_forward computes them (the same kernels, bitwise equal results), for callers that
+/* Logits bitwise equal to cfr_mlp_forward's (computed layer by layer, each hidden layer's activations
+ * staged in device memory), for callers that
  * cannot allocate device memory: code under hipGraph capture, tight serving loops, harnesses that
  * forbid hipMalloc.  The call allocates nothing (no hipMalloc, hipFree or allocating library call):
  * the hidden activations go to one static device array of 2 x 8192 x 256 bf16 (8 MiB) that each GPU

@@ -301,6 +301,152 @@ __global__ void k_to_bf16(const float *x, uint16_t *y, int64_t n) {
     if (i < n) y[i] = to_bf16(x[i]);
 }
 
+// ---- fused inference ------------------------------------------------------------------------
+// Inference needs no activations outside the kernel, so one launch runs every layer: a block takes
+// FB_ROWS rows, keeps their activations in LDS from the input row to the last hidden layer, and
+// writes only the four logits.  Each hidden layer is the product of the LDS activations with the
+// layer's weights, streamed through LDS in chunks of 32 input units (double-buffered, the next
+// chunk's global loads in flight while the matrix cores work on the current one); the four waves
+// each own a 64-row x HID/2-column slab (2 x HID/64 accumulators of 32 x 32).  The arithmetic is the
+// layer-by-layer path's, in its order: the same MFMA on the same 16-wide k steps from k = 0 up,
+// relu(acc + bias) rounded to bf16, and the output layer's per-lane FMA chain, butterfly and bias
+// of k_head, so the logits are bitwise those of the layered kernels.
+constexpr int FB_ROWS = 128, FB_BK = 32, FB_LDB = FB_BK + 8;
+
+struct FusedArgs {
+    const uint16_t *x;        // [rows][K0] bf16
+    const uint16_t *wt;       // hidden layers' weights transposed, layer l at wt_off[l]: [HID][fin_l]
+    const float *theta;       // FP32 parameters (biases at boff[l])
+    const uint16_t *w_out;    // [HID][4] bf16 output weights
+    const float *b_out;       // [4]
+    int64_t wt_off[4], boff[4];
+    int rows, n_hidden;
+    float *z;                 // [rows][4]
+};
+
+template <int HID, int K0>
+__global__ __launch_bounds__(256) void k_mlp_fused(FusedArgs f) {
+    constexpr int LDA = (K0 > HID ? K0 : HID) + 8;   // LDS row stride (bf16), rows stay 16-byte aligned
+    constexpr int CT = HID / 64;                     // 32-wide column tiles per wave
+    __shared__ __attribute__((aligned(16))) uint16_t act[FB_ROWS * LDA];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][HID * FB_LDB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r0 = blockIdx.x * FB_ROWS;
+    // the block's input rows (zeros past the last row)
+    for (int i = tid; i < FB_ROWS * K0 / 8; i += 256) {
+        const int r = i / (K0 / 8), c = (i % (K0 / 8)) * 8;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (r0 + r < f.rows) v = *(const uint4 *)(f.x + (int64_t)(r0 + r) * K0 + c);
+        *(uint4 *)&act[r * LDA + c] = v;
+    }
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * (HID / 2);
+    for (int l = 0; l < f.n_hidden; l++) {
+        const int K = l == 0 ? K0 : HID;
+        const uint16_t *W = f.wt + f.wt_off[l];
+        // chunk k0 of W^T: HID rows of 32 units = HID * 4 16-byte pieces, CT per thread
+        uint4 pre[CT];
+        auto load_chunk = [&](int k0) {
+#pragma unroll
+            for (int j = 0; j < CT; j++) {
+                const int idx = tid + j * 256, n = idx >> 2, q = (idx & 3) * 8;
+                pre[j] = *(const uint4 *)(W + (int64_t)n * K + k0 + q);
+            }
+        };
+        auto store_chunk = [&](int buf) {
+#pragma unroll
+            for (int j = 0; j < CT; j++) {
+                const int idx = tid + j * 256, n = idx >> 2, q = (idx & 3) * 8;
+                *(uint4 *)&Bs[buf][n * FB_LDB + q] = pre[j];
+            }
+        };
+        f32x16 acc[2][CT];
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < CT; b++)
+#pragma unroll
+                for (int i = 0; i < 16; i++) acc[a][b][i] = 0.f;
+        load_chunk(0);
+        store_chunk(0);
+        __syncthreads();
+        const int nk = K / FB_BK;
+        for (int kc = 0; kc < nk; kc++) {
+            const int buf = kc & 1;
+            if (kc + 1 < nk) load_chunk((kc + 1) * FB_BK);
+#pragma unroll
+            for (int ks = 0; ks < FB_BK; ks += 16) {
+                // lane l supplies row (column) l % 32 and k = ks + 8 (l / 32) .. + 7 of both operands
+                bf16x8 av[2], bv[CT];
+#pragma unroll
+                for (int a = 0; a < 2; a++)
+                    av[a] = *(const bf16x8 *)&act[(wm + a * 32 + (lane & 31)) * LDA + kc * FB_BK + ks + (lane >> 5) * 8];
+#pragma unroll
+                for (int b = 0; b < CT; b++)
+                    bv[b] = *(const bf16x8 *)&Bs[buf][(wn + b * 32 + (lane & 31)) * FB_LDB + ks + (lane >> 5) * 8];
+#pragma unroll
+                for (int a = 0; a < 2; a++)
+#pragma unroll
+                    for (int b = 0; b < CT; b++)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+            }
+            if (kc + 1 < nk) store_chunk(buf ^ 1);
+            __syncthreads();
+        }
+        // every wave has read this layer's input: overwrite it with relu(acc + bias) in bf16
+        // (accumulator i of lane l holds row 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32)
+        const float *bias = f.theta + f.boff[l];
+#pragma unroll
+        for (int b = 0; b < CT; b++) {
+            const int col = wn + b * 32 + (lane & 31);
+            const float bc = bias[col];
+#pragma unroll
+            for (int a = 0; a < 2; a++)
+#pragma unroll
+                for (int i = 0; i < 16; i++) {
+                    const int row = wm + a * 32 + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
+                    act[row * LDA + col] = to_bf16(fmaxf(acc[a][b][i] + bc, 0.f));
+                }
+        }
+        __syncthreads();
+    }
+    // output layer as k_head computes it: lane l holds hidden units l * HPL .. + HPL - 1
+    constexpr int HPL = HID / 64;
+    float wk[HPL][4];
+#pragma unroll
+    for (int j = 0; j < HPL; j++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) wk[j][c] = from_bf16(f.w_out[(lane * HPL + j) * 4 + c]);
+    const float bo0 = f.b_out[0], bo1 = f.b_out[1], bo2 = f.b_out[2], bo3 = f.b_out[3];
+    for (int rr = wave; rr < FB_ROWS && r0 + rr < f.rows; rr += 4) {
+        float h[HPL];
+#pragma unroll
+        for (int j = 0; j < HPL; j++) h[j] = from_bf16(act[rr * LDA + lane * HPL + j]);
+        float z[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            float sum = 0.f;
+#pragma unroll
+            for (int j = 0; j < HPL; j++) sum = fmaf(h[j], wk[j][c], sum);
+            z[c] = sum;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+            for (int c = 0; c < 4; c++) z[c] += __shfl_xor(z[c], off, 64);
+        z[0] += bo0; z[1] += bo1; z[2] += bo2; z[3] += bo3;
+        if (lane < 4) f.z[(int64_t)(r0 + rr) * 4 + lane] = lane == 0 ? z[0] : lane == 1 ? z[1] : lane == 2 ? z[2] : z[3];
+    }
+}
+
+// wt[n * fin + k] = W[k * HID + n] for one hidden layer (bf16 copies, so the fused kernel's weight
+// chunks are contiguous per output unit)
+__global__ void k_transpose_bf16(const uint16_t *W, int fin, int hid, uint16_t *wt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)fin * hid) return;
+    const int n = (int)(i / fin), k = (int)(i % fin);
+    wt[i] = W[(int64_t)k * hid + n];
+}
+
 // minibatch rows idx[r] (clamped into [0, n_data)) of the training arrays into staging
 __global__ void k_gather_rows(const uint16_t *X, const float *T, const float *w, const uint8_t *nact,
                               const int32_t *idx, int rows, int64_t n_data, int feat, uint16_t *Xs, float *Ts,
@@ -455,6 +601,8 @@ struct cfr_mlp {
     float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr, *part = nullptr, *inv_w = nullptr,
           *lossd = nullptr;
     uint16_t *theta16 = nullptr;
+    uint16_t *wt = nullptr;              // hidden layers' bf16 weights transposed (fused inference)
+    int64_t wt_off[4] = {0, 0, 0, 0};
     std::vector<uint16_t *> H;           // [n_hidden] activations, [max_rows][hidden]
     uint16_t *dA[2] = {nullptr, nullptr};
     uint16_t *xs = nullptr;              // gathered minibatch
@@ -634,6 +782,11 @@ cfr_status cfr_mlp_create(const cfr_mlp_desc *desc, cfr_mlp **out) {
     MA(n->theta, n->P); MA(n->grad, n->P); MA(n->m, n->P); MA(n->v, n->P); MA(n->theta16, n->P);
     MA(n->part, std::max<int64_t>(std::max<int64_t>((int64_t)n->splits_max * maxw, (int64_t)HEAD_BLOCKS * (hid * 4 + 5)),
                                   (R + 255) / 256 * hid));
+    {
+        int64_t off = 0;
+        for (int l = 0; l < d.n_hidden; l++) { n->wt_off[l] = off; off += (int64_t)n->fin[(size_t)l] * hid; }
+        MA(n->wt, off);
+    }
     MA(n->inv_w, 1);
     MA(n->lossd, 1);
     n->H.resize((size_t)d.n_hidden);
@@ -689,12 +842,34 @@ cfr_status cfr_mlp_forward(cfr_mlp *n, const void *x, int64_t rows, float *z, vo
     if (!n || ((!x || !z) && rows > 0) || rows < 0) return mfail(CFR_EINVAL, "bad argument");
     MHIP(hipSetDevice(n->d.device));
     hipStream_t s = (hipStream_t)stream;
-    const int64_t cap = n->d.max_rows;
-    const uint16_t *xp = (const uint16_t *)x;
-    for (int64_t r0 = 0; r0 < rows; r0 += cap) {
-        const int r = (int)std::min(cap, rows - r0);
-        cfr_status st = forward_rows(n, xp + r0 * n->d.in_dim, r, z + r0 * 4, false, s);
-        if (st != CFR_OK) return st;
+    if (rows == 0) return CFR_OK;
+    // the weights as they are now (set_params and every Adam step change them), transposed
+    for (int l = 0; l < n->d.n_hidden; l++) {
+        const int64_t cnt = (int64_t)n->fin[(size_t)l] * n->d.hidden;
+        k_transpose_bf16<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(n->theta16 + n->woff[(size_t)l], n->fin[(size_t)l],
+                                                                      n->d.hidden, n->wt + n->wt_off[l]);
+        MHIP(hipGetLastError());
+    }
+    FusedArgs f{};
+    f.wt = n->wt; f.theta = n->theta;
+    f.w_out = n->theta16 + n->woff[(size_t)n->d.n_hidden];
+    f.b_out = n->theta + n->boff[(size_t)n->d.n_hidden];
+    for (int l = 0; l < n->d.n_hidden; l++) { f.wt_off[l] = n->wt_off[l]; f.boff[l] = n->boff[(size_t)l]; }
+    f.n_hidden = n->d.n_hidden;
+    // launches of at most 2^20 blocks (2^27 rows) each keep every row index in int
+    const int64_t step = (int64_t)FB_ROWS << 20;
+    for (int64_t r0 = 0; r0 < rows; r0 += step) {
+        f.rows = (int)std::min(step, rows - r0);
+        f.x = (const uint16_t *)x + r0 * n->d.in_dim;
+        f.z = z + r0 * 4;
+        const unsigned blocks = (unsigned)((f.rows + FB_ROWS - 1) / FB_ROWS);
+#define FUSED(H_, K_)                                                                              \
+        if (n->d.hidden == H_ && n->d.in_dim == K_) k_mlp_fused<H_, K_><<<blocks, 256, 0, s>>>(f); else
+        FUSED(64, 64) FUSED(64, 128) FUSED(64, 256) FUSED(128, 64) FUSED(128, 128) FUSED(128, 256)
+        FUSED(256, 64) FUSED(256, 128) FUSED(256, 256)
+        return mfail(CFR_EINVAL, "unsupported network shape");
+#undef FUSED
+        MHIP(hipGetLastError());
     }
     return CFR_OK;
 }

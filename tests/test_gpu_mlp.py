@@ -98,6 +98,34 @@ def test_forward_matches_oracle(shape, rows):
     assert e <= 4e-3
 
 
+@pytest.mark.parametrize("shape", [(128, 256, 3), (64, 64, 1), (256, 128, 2), (128, 64, 4), (64, 256, 2),
+                                   (256, 256, 1)])
+@pytest.mark.parametrize("rows", [1, 127, 129, 5000])
+def test_fused_inference_equals_the_layered_kernels(shape, rows):
+    """cfr_mlp_forward runs every layer in one kernel (activations kept in LDS); its logits equal bitwise
+    those of the layer-by-layer kernels (cfr_mlp_forward_noalloc), for every hidden width and input
+    width, ragged row tiles and more rows than max_rows, and again after an Adam step has moved the
+    weights (the transposed weight copy is refreshed by every call)."""
+    n_in, hidden, nh = shape
+    note(f"[mlp fused] shape={shape} rows={rows}")
+    m, sizes, theta = net(n_in, hidden, nh, max_rows=2048, seed=4)
+    X, T, w, nact = dataset(rows, n_in, seed=5)
+    x = bf16_dev(X)
+    for step in range(2):
+        za = torch.full((rows, 4), float("nan"), dtype=torch.float32, device=DEV)
+        zb = torch.full((rows, 4), float("nan"), dtype=torch.float32, device=DEV)
+        m.forward(x, rows, za)
+        m.forward_noalloc(x, rows, zb)
+        torch.cuda.synchronize()
+        a, b = za.cpu().numpy(), zb.cpu().numpy()
+        assert np.isfinite(a).all()
+        assert np.array_equal(a, b), (step, np.abs(a - b).max())
+        k = min(rows, 2048)
+        d = to_dev(X[:k], T[:k], w[:k], nact[:k])
+        m.backward(*d, k)
+        m.adam(1e-2)
+
+
 @pytest.mark.parametrize("shape", [(128, 256, 3), (64, 64, 1)])
 @pytest.mark.parametrize("rows", [37, 1000, 4096])
 def test_gradients_match_oracle(shape, rows):
