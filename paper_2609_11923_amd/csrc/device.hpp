@@ -40,7 +40,12 @@ struct DevGame {
     // update pass reads the per-slot offsets and a compact member list instead of kid[] and mem[]
     int affine = 0;
     int32_t *koff = nullptr;      // [A]   child offset of each slot (affine only)
-    int32_t *mnode = nullptr;     // [Ndec] member node | MEMBER_P2 bit (affine only)
+    // member node | MEMBER_P2 bit, per update group in set-major order, or in node order where that
+    // touches far fewer cache lines (grp_perm[g] = 1; mpos then gives each member's set-major position
+    // in its group) (affine only)
+    int32_t *mnode = nullptr;     // [Ndec]
+    uint16_t *mpos = nullptr;     // [Ndec]
+    int8_t *grp_perm = nullptr;   // [G]
     int32_t *slot_map = nullptr;  // [A]   canonical slot -> device slot (nullptr: identity)
     int32_t *node_slot = nullptr; // [N]   first slot of a decision node, -1 otherwise
     int32_t *node_iset = nullptr; // [N]   information set of a decision node, -1 otherwise

@@ -113,6 +113,8 @@ struct LevelArgs {
     const int8_t *iset_player;
     const int32_t *kid_off, *kid, *chance_node, *bigc_node;
     const int32_t *koff, *mnode;   // affine layouts: per-slot child offset, compact member list
+    const uint16_t *mpos;          // affine layouts: set-major position of each member of a node-order group
+    const int8_t *grp_perm;        // affine layouts: 1 where a group's member list is in node order
     T *v;
     T *r1, *r2;   // reach lanes (the level only reads them; the persistent form's forward levels write)
     T *R;
@@ -459,7 +461,9 @@ struct GroupLdsA {
 
 // Calls f with the smallest action bound of {2, 3, MAXA} (MAXA = 4) or {4, MAXA} (wider
 // instantiations) that is at least n, as a compile-time constant, so a pass over sets or members
-// that need fewer actions issues fewer loads.  n must be uniform over the wave (or the block).
+// that need fewer actions issues fewer loads (large game: FP64 state 5 % faster, FP32 unchanged; a
+// 16-action instantiation would otherwise load 16 children per member of a 2-action set).  n must
+// be uniform over the wave (or the block).
 template <int MAXA, typename F>
 __device__ __forceinline__ void with_action_bound(int32_t n, F &&f) {
     if constexpr (MAXA <= 4) {
@@ -484,7 +488,12 @@ __device__ __forceinline__ void with_action_bound(int32_t n, F &&f) {
 // a full wait at its join, which costs more than the load.)  The number of child loads per member
 // is the group's widest set, bucketed (with_action_bound; the public-state layout orders states by
 // action count, so most groups are uniform): a block-uniform choice made once per group, outside
-// the loops.  Each set thread fetches its own reach through its first member.
+// the loops.  Where a group's sets interleave -- a player-2 set's members are strided by the
+// opponent's hand count -- the host lists the group's members in node order instead (grp_perm) with
+// each one's set-major position: consecutive lanes then touch consecutive nodes, children and values
+// instead of one cache line each, and the staging stays set-major, so the reduction, and every
+// result, is unchanged.  The two orders are separate instantiations of the member pass, chosen per
+// group.  Each set thread fetches its own reach through its first member.
 template <typename T, int MAXA, int MPT, bool EXT>
 __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelArgs<T> &a,
                                     GroupLdsA<T, MAXA, MPT> &L) {
@@ -499,7 +508,12 @@ __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelAr
     const int32_t m0 = a.mem_off[ti], m1 = a.mem_off[ti + 1];
     const int32_t s0 = a.slot_off[ti], nA = a.slot_off[ti + 1] - s0;
     const int pl = a.iset_player[ti];
-    const int32_t h0 = a.mnode[m0] & MEMBER_NODE_MASK;
+    const bool perm = a.grp_perm[g] != 0;
+    // the set's first member: in a set-major list at m0 (lines the member pass reads anyway; the
+    // 8-byte member records would cost one extra line per set); in a node-order list, from them
+    int32_t h0;
+    if (perm) h0 = a.mem[m0].x & MEMBER_NODE_MASK;
+    else h0 = a.mnode[m0] & MEMBER_NODE_MASK;
     const T *__restrict__ r1 = a.r1;
     const T *__restrict__ r2 = a.r2;
     const T *__restrict__ sig = a.sigma;
@@ -548,19 +562,24 @@ __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelAr
     T r[MAXA];
 #pragma unroll
     for (int k = 0; k < MAXA; k++) r[k] = T(0);
-    with_action_bound<MAXA>(ga, [&](auto nag) {
+    auto member_pass = [&](auto nag, auto permc) {
         constexpr int NA = decltype(nag)::value;
+        constexpr bool PERM = decltype(permc)::value;
         for (int32_t cb = mbeg; cb < mend; cb += CHUNK) {
             const int32_t ce = min(cb + CHUNK, mend);
             bool in[MPT];
-            int32_t hn[MPT], st[MPT], sb[MPT], na[MPT];
+            int32_t hn[MPT], pj[MPT], st[MPT], sb[MPT], na[MPT];
 #pragma unroll
             for (int u = 0; u < MPT; u++) {
                 const int32_t j = u * BLOCK + tid;
                 in[u] = cb + j < ce;
                 const int32_t jj = in[u] ? j : 0;
+                // thread j takes the group's j-th listed member; in a node-order group pj is its
+                // slot in the set-major staging
                 hn[u] = a.mnode[cb + jj];
-                st[u] = L.mset[jj];
+                if constexpr (PERM) pj[u] = a.mpos[cb + jj];
+                else pj[u] = jj;
+                st[u] = L.mset[pj[u]];
                 sb[u] = L.slot[st[u]];
                 na[u] = L.slot[st[u] + 1] - sb[u];
             }
@@ -594,7 +613,7 @@ __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelAr
                     vh = k < na[u] ? fma_t(sk, cv[u][k], vh) : vh;
                 }
                 if (!in[u]) continue;
-                const int32_t j = u * BLOCK + tid;
+                const int32_t j = pj[u];
                 a.v[hn[u] & MEMBER_NODE_MASK] = vh;
                 L.po[j] = po[u];
 #pragma unroll
@@ -604,6 +623,10 @@ __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelAr
             if (has_set) reduce_members<T, MAXA, NA>(L.po, L.diff, max(m0, cb) - cb, min(m1, ce) - cb, r);
             __syncthreads();
         }
+    };
+    with_action_bound<MAXA>(ga, [&](auto nag) {
+        if (perm) member_pass(nag, std::true_type{});
+        else member_pass(nag, std::false_type{});
     });
     if constexpr (ROWS && MAXA <= 4) {
         // The group's slots [S0, S1) are contiguous: move their regrets, strategy sums and strategy
@@ -1088,7 +1111,7 @@ static LevelArgs<T> level_args(const DevGame &g) {
     a.grp_iset_off = g.grp_iset_off; a.slot_off = g.slot_off; a.mem_off = g.mem_off; a.mem = g.mem;
     a.iset_player = g.iset_player; a.kid_off = g.kid_off; a.kid = g.kid; a.chance_node = g.chance_node;
     a.bigc_node = g.bigc_node;
-    a.koff = g.koff; a.mnode = g.mnode;
+    a.koff = g.koff; a.mnode = g.mnode; a.mpos = g.mpos; a.grp_perm = g.grp_perm;
     a.v = (T *)g.v;
     a.r1 = (T *)g.reach;
     a.r2 = (T *)g.reach + g.N;

@@ -83,6 +83,7 @@ struct cfr_handle {
     int64_t E = 0, Z = 0;
     double pot = 1.0;
     int64_t device_bytes = 0;
+    std::vector<double> perm_members;  // per depth: members of update groups listed in node order
     std::vector<void *> allocs;
     // graph state
     hipStream_t cap_stream = nullptr;
@@ -141,6 +142,68 @@ static void parallel_games(int n, F &&fn) {
             for (int s = next.fetch_add(1); s < n; s = next.fetch_add(1)) fn(s);
         });
     for (auto &t : pool) t.join();
+}
+
+// The affine update's member list (mnode).  A group keeps its members in set-major order, unless
+// listing them in node order makes a wave's 64 consecutive members touch at most half as many
+// 32-node spans (cache lines of FP32 values) -- the case where the group's sets interleave, as a
+// player-2 set's members, strided by the opponent's hand count, do.  Such a group is flagged in
+// perm[g] and mpos gives each listed member's set-major position in its group (groups of several
+// sets hold at most one staging chunk, so it fits 16 bits).  perm_members[d] counts the members of
+// flagged groups of depth d (their extra position reads are design bytes).
+static void member_lists(const DeviceLayout &D, std::vector<int32_t> &mnode, std::vector<uint16_t> &mpos,
+                         std::vector<int8_t> &perm, std::vector<double> &perm_members) {
+    const int64_t Ndec = (int64_t)D.mem_node.size();
+    mnode = D.mem_node;
+    mpos.assign((size_t)Ndec, 0);
+    const int32_t G = (int32_t)D.grp_iset_off.size() - 1;
+    perm.assign((size_t)std::max(G, 1), 0);
+    constexpr int32_t SPAN = 4096;   // groups per task
+    parallel_games((G + SPAN - 1) / SPAN, [&](int task) {
+        std::vector<int32_t> idx;
+        auto spans = [](const int32_t *nodes, int32_t n) {
+            int64_t c = 0;
+            for (int32_t w = 0; w < n; w += 64) {
+                int32_t seen[64];
+                int ns = 0;
+                for (int32_t k = w; k < std::min(n, w + 64); k++) {
+                    const int32_t line = (nodes[k] & MEMBER_NODE_MASK) >> 5;
+                    bool dup = false;
+                    for (int t = 0; t < ns && !dup; t++) dup = seen[t] == line;
+                    if (!dup) seen[ns++] = line;
+                }
+                c += ns;
+            }
+            return c;
+        };
+        std::vector<int32_t> sorted_nodes;
+        for (int32_t g = task * SPAN; g < std::min(G, (task + 1) * SPAN); g++) {
+            const int32_t i0 = D.grp_iset_off[(size_t)g], i1 = D.grp_iset_off[(size_t)g + 1];
+            const int32_t mb = D.mem_off[(size_t)i0], me = D.mem_off[(size_t)i1], n = me - mb;
+            for (int32_t k = 0; k < n; k++) mpos[(size_t)(mb + k)] = (uint16_t)(k & 0xffff);
+            if (i1 - i0 == 1) continue;
+            const int32_t *list = D.mem_node.data() + mb;
+            idx.resize((size_t)n);
+            for (int32_t k = 0; k < n; k++) idx[(size_t)k] = k;
+            std::sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
+                return (list[x] & MEMBER_NODE_MASK) < (list[y] & MEMBER_NODE_MASK);
+            });
+            sorted_nodes.resize((size_t)n);
+            for (int32_t k = 0; k < n; k++) sorted_nodes[(size_t)k] = list[idx[(size_t)k]];
+            if (2 * spans(sorted_nodes.data(), n) > spans(list, n)) continue;
+            perm[(size_t)g] = 1;
+            for (int32_t k = 0; k < n; k++) {
+                mnode[(size_t)(mb + k)] = sorted_nodes[(size_t)k];
+                mpos[(size_t)(mb + k)] = (uint16_t)idx[(size_t)k];
+            }
+        }
+    });
+    const int md = (int)D.grp_depth_off.size() - 2;
+    perm_members.assign((size_t)std::max(md + 1, 1), 0.0);
+    for (int d = 0; d <= md; d++)
+        for (int32_t g = D.grp_depth_off[(size_t)d]; g < D.grp_depth_off[(size_t)d + 1]; g++)
+            if (perm[(size_t)g])
+                perm_members[(size_t)d] += D.mem_off[(size_t)D.grp_iset_off[(size_t)g + 1]] - D.mem_off[(size_t)D.grp_iset_off[(size_t)g]];
 }
 
 // Per-launch event timing for cfr_profile: class 0 tick, 1 forward, 2 level.
@@ -255,8 +318,11 @@ void model_bytes(cfr_handle *h, const DeviceLayout &D) {
         // decision members: id, edge offset, value write, opponent reach; edges: child (index), value;
         // sets: member and slot offsets, player, own reach; slots: sigma read + write, R read + write,
         // sbar read + write
-        // (affine layouts: a 4-byte member record, no child index per edge, one offset per slot)
-        if (h->g.affine) lv += (4 + 2 * es) * Md[d] + es * Ed[d] + (9 + es) * Id[d] + (4 * es + 20) * Ad[d];
+        // (affine layouts: a 4-byte member record, plus a 2-byte staging position in node-order
+        // groups; no child index per edge, one offset per slot)
+        if (h->g.affine)
+            lv += (4 + 2 * es) * Md[d] + es * Ed[d] + (9 + es) * Id[d] + (4 * es + 20) * Ad[d] +
+                  2.0 * ((size_t)d < h->perm_members.size() ? h->perm_members[(size_t)d] : 0.0);
         else lv += (8 + 2 * es) * Md[d] + (kb + es) * Ed[d] + (9 + es) * Id[d] + (4 * es + 16) * Ad[d];
         // chance nodes: list entry, edge offset, value write; edges: child (index), value
         for (int32_t j = D.chance_off[d]; j < D.chance_off[d + 1]; j++) {
@@ -760,6 +826,8 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     if (g.affine) {
         ALLOC(g.koff, A > 0 ? A : 1);
         ALLOC(g.mnode, Ndec > 0 ? Ndec : 1);
+        ALLOC(g.mpos, Ndec > 0 ? Ndec : 1);
+        ALLOC(g.grp_perm, std::max<int64_t>((int64_t)DL.grp_iset_off.size() - 1, 1));
     }
     ALLOC(g.iset_player, I);
     g.G = (int32_t)DL.grp_iset_off.size() - 1;
@@ -813,7 +881,13 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     }
     if (g.affine) {
         UP(g.koff, koff);
-        UP(g.mnode, DL.mem_node);
+        std::vector<int32_t> mnode;
+        std::vector<uint16_t> mpos;
+        std::vector<int8_t> perm;
+        member_lists(DL, mnode, mpos, perm, h->perm_members);
+        UP(g.mnode, mnode);
+        UP(g.mpos, mpos);
+        UP(g.grp_perm, perm);
     }
     UP(g.iset_player, DL.iset_player);
     UP(g.grp_iset_off, DL.grp_iset_off);
