@@ -266,6 +266,7 @@ __global__ __launch_bounds__(256) void k_colsum(const uint16_t *X, int rows, int
     const int r0 = blockIdx.x * chunk, r1 = min(rows, r0 + chunk);
     for (int n = threadIdx.x; n < N; n += 256) {
         float s = 0.f;
+#pragma unroll 8
         for (int r = r0; r < r1; r++) s += from_bf16(X[(int64_t)r * N + n]);
         part[(int64_t)blockIdx.x * N + n] = s;
     }
@@ -276,6 +277,7 @@ __global__ void k_reduce(const float *part, int nb, int64_t stride, int n, float
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     float s = 0.f;
+#pragma unroll 8
     for (int b = 0; b < nb; b++) s += part[(int64_t)b * stride + j];
     out[j] = s;
 }
@@ -781,7 +783,7 @@ cfr_status cfr_mlp_create(const cfr_mlp_desc *desc, cfr_mlp **out) {
 #define MA(p, c) do { st = malloc_dev(n, &(p), (c)); if (st != CFR_OK) { free_mlp(n); return st; } } while (0)
     MA(n->theta, n->P); MA(n->grad, n->P); MA(n->m, n->P); MA(n->v, n->P); MA(n->theta16, n->P);
     MA(n->part, std::max<int64_t>(std::max<int64_t>((int64_t)n->splits_max * maxw, (int64_t)HEAD_BLOCKS * (hid * 4 + 5)),
-                                  (R + 255) / 256 * hid));
+                                  (R + 15) / 16 * hid));
     {
         int64_t off = 0;
         for (int l = 0; l < d.n_hidden; l++) { n->wt_off[l] = off; off += (int64_t)n->fin[(size_t)l] * hid; }
@@ -943,7 +945,7 @@ cfr_status cfr_mlp_backward(cfr_mlp *n, const void *x, const float *target, cons
                                                                         n->grad + n->woff[(size_t)l]);
         MHIP(hipGetLastError());
         // bias gradient
-        const int cchunk = 256;
+        const int cchunk = 16;   // R / 16 blocks: enough to fill the device
         const int cb = (R + cchunk - 1) / cchunk;
         k_colsum<<<cb, 256, 0, s>>>(n->dA[cur], R, fo, cchunk, n->part);
         MHIP(hipGetLastError());
