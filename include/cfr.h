@@ -157,6 +157,9 @@ typedef struct {
     int64_t kernels_per_iteration; /* launches in one iteration (the operation-count gate) */
     double  pot;
     int32_t child_addressing;      /* update pass: 0 implicit (BFS), 1 explicit child list, 2 affine offsets */
+    int32_t node_order_groups;     /* affine update groups whose members are listed in node order (their sets
+                                      interleave); 0 in the counts of cfr_layout_host and cfr_get_layout */
+    int64_t node_order_members;    /* members of those groups */
 } cfr_counts_t;
 
 /* Canonical compiled arrays (host copies), all in canonical numbering:

@@ -62,7 +62,8 @@ class cfr_counts_t(ctypes.Structure):
                 ("max_depth", ctypes.c_int32), ("blocks", ctypes.c_int32), ("max_actions", ctypes.c_int32),
                 ("br_supported", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
                 ("kernels_per_iteration", ctypes.c_int64), ("pot", ctypes.c_double),
-                ("child_addressing", ctypes.c_int32)]
+                ("child_addressing", ctypes.c_int32), ("node_order_groups", ctypes.c_int32),
+                ("node_order_members", ctypes.c_int64)]
 
 
 class cfr_layout(ctypes.Structure):

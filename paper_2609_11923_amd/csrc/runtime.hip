@@ -84,6 +84,8 @@ struct cfr_handle {
     double pot = 1.0;
     int64_t device_bytes = 0;
     std::vector<double> perm_members;  // per depth: members of update groups listed in node order
+    int32_t node_order_groups = 0;
+    int64_t node_order_members = 0;
     std::vector<void *> allocs;
     // graph state
     hipStream_t cap_stream = nullptr;
@@ -885,6 +887,8 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
         std::vector<uint16_t> mpos;
         std::vector<int8_t> perm;
         member_lists(DL, mnode, mpos, perm, h->perm_members);
+        for (int8_t f : perm) h->node_order_groups += f;
+        for (double m : h->perm_members) h->node_order_members += (int64_t)m;
         UP(g.mnode, mnode);
         UP(g.mpos, mpos);
         UP(g.grp_perm, perm);
@@ -1228,6 +1232,8 @@ cfr_status cfr_counts(cfr_handle *h, cfr_counts_t *c) {
     c->max_actions = h->g.max_actions; c->br_supported = h->br_ok ? 1 : 0;
     c->device_bytes = h->device_bytes; c->kernels_per_iteration = h->launches; c->pot = h->pot;
     c->child_addressing = h->g.affine ? 2 : h->g.explicit_kids ? 1 : 0;
+    c->node_order_groups = h->node_order_groups;
+    c->node_order_members = h->node_order_members;
     return CFR_OK;
 }
 

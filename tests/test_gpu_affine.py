@@ -108,3 +108,29 @@ def test_layout_without_offsets_falls_back_to_the_child_list():
 def test_bfs_layout_reports_implicit_children():
     s = cfr.Solver(gg.leduc(3, 2), layout=cfr.CFR_LAYOUT_BFS)
     assert s.counts["child_addressing"] == 0
+
+
+@pytest.mark.parametrize("rule", ["cfr+", "dcfr-alt", "pcfr+"])
+@pytest.mark.parametrize("precision", list(PREC))
+def test_node_order_groups_equal_the_child_list_path(precision, rule):
+    """Subgames with many hands per player: player-2 sets interleave inside a public-state block, so the
+    compile lists some update groups' members in node order (with their set-major positions).  Those
+    groups reproduce the explicit child-list path bitwise, under the level launches and the persistent
+    launch."""
+    games = [gg.subgame(**{k: v for k, v in sp.items() if k != "target"})
+             for sp in gg.random_subgames(4, seed=8, lo=1e5, hi=3e5)]
+    r, o = RULES[rule]
+    a = cfr.Solver(games, rule=r, order=o, precision=PREC[precision])
+    b = cfr.Solver(games, rule=r, order=o, precision=PREC[precision], affine=False)
+    c = cfr.Solver(games, rule=r, order=o, precision=PREC[precision], persistent=True, wg_nodes=16384)
+    note(f"[node order] {precision} {rule}: {a.counts['node_order_groups']} groups, "
+         f"{a.counts['node_order_members']} members of {a.counts['decision_nodes']}")
+    assert a.counts["node_order_groups"] > 0 and a.counts["node_order_members"] > 0
+    assert b.counts["node_order_groups"] == 0
+    for s in (a, b, c):
+        s.iterate(23)
+    Ra, Sa = a.state()
+    for x in (b, c):
+        Rx, Sx = x.state()
+        assert np.array_equal(Ra, Rx) and np.array_equal(Sa, Sx)
+    assert np.array_equal(a.batch_exploitability()[0], b.batch_exploitability()[0])
