@@ -685,8 +685,14 @@ __device__ __forceinline__ void update_group(int32_t g, const RuleArgs &ru, cons
     else group_update<T, MAXA, MPT, EXPLICIT, EXT>(g, ru, a, L);
 }
 
+// FP64 state with at most 4 actions and the lean rule tail: ask for 6 waves per SIMD (78 registers, no
+// spills; the LDS of 6 workgroups fits) instead of the 5 that 86 registers allow.  The discounted and
+// predictive tails would spill under that bound, and FP32 is held to 5 by its LDS.
+template <typename T, int MAXA, bool EXT>
+constexpr int level_min_waves() { return (sizeof(T) == 8 && MAXA <= 4 && !EXT) ? 6 : 1; }
+
 template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT, bool AFF>
-__global__ void __launch_bounds__(BLOCK) k_level(int32_t gbeg, int32_t ngroups, int32_t bbeg, int32_t nbig,
+__global__ void __launch_bounds__(BLOCK, (level_min_waves<T, MAXA, EXT>())) k_level(int32_t gbeg, int32_t ngroups, int32_t bbeg, int32_t nbig,
                                                  int32_t cbeg, int32_t nchance, LevelArgs<T> a,
                                                  const int32_t *__restrict__ tcount, int rule, int linear, int upd) {
     __shared__ LevelLds<T, MAXA, MPT, EXPLICIT, AFF> L;
