@@ -740,6 +740,17 @@ def main():
     if "time_to_target" in m:
         t = dict(m["time_to_target"], rule="CFR+, simultaneous, linear averaging", state=out["config"]["state"])
         out["time_to_target_single_game"] = t
+        if not args.no_rules and args.precision == "fp32":
+            # the same game under the rule that reaches the target soonest on the subgame batch
+            t0 = time.perf_counter()
+            sv = cfr.Solver(game, rule=cfr.CFR_RULE_DCFR, order=cfr.CFR_ORDER_ALTERNATING)
+            compile_s = time.perf_counter() - t0
+            r = time_to_target(sv, torch, pot, log, args.ttt_max_iters, label=f"{args.workload} dcfr-alt")
+            sv.close()
+            del sv
+            torch.cuda.empty_cache()
+            out["time_to_target_single_game_rules"] = {
+                "DCFR alternating": dict(r, state=out["config"]["state"], compile_s=compile_s)}
     del game
     torch.cuda.empty_cache()
     if args.workload == "large" and not args.no_sweep:
