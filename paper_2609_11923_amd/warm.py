@@ -94,7 +94,7 @@ def make_training_set(specs, iters, torch, probe=0, chunk=256, precision=CFR_PRE
         ta = time.perf_counter()
         games = subgames(specs[c0:c0 + chunk])
         tb = time.perf_counter()
-        s = Solver(games, precision=precision, **(solver_kw or {}))
+        s = Solver(games, precision=precision, iters_per_graph=10, **(solver_kw or {}))
         rows = Rows(games, torch)
         tc = time.perf_counter()
         rows.features(s, probe=probe)       # the probe is the first `probe` iterations of this solve
@@ -254,7 +254,8 @@ def batch_solver(games, torch, schedule=LEVEL_SYNC, precision=CFR_PRECISION_FP32
     """A compiled batch on the given schedule (None: autotuned).  Warm and cold arms share the
     handle, so they always run the same schedule and rule (solver_kw: rule, order)."""
     log(f"[warm] compiling {len(games)} games")
-    s = Solver(games, precision=precision, **(solver_kw or {}))
+    # ten iterations per captured graph (remainders run the one-iteration graph)
+    s = Solver(games, precision=precision, iters_per_graph=10, **(solver_kw or {}))
     if schedule is None:
         schedule = s.autotune(tune_iters, stream=torch.cuda.Stream())
         log(f"[warm] autotune: {schedule}")
@@ -346,15 +347,15 @@ def evaluate(games, torch, mlp, scale, t_max, control=None, probe=0, schedule=LE
 
 
 def alone_ms_per_iteration(games, torch, iters=50, log=print):
-    """Milliseconds per iteration of each game solved on its own (one handle, hipGraph replay):
-    the per-game cost of plain one-at-a-time solving.  A batch reproduces each game's iterates
-    bitwise, so its crossing iterations carry over unchanged."""
+    """Milliseconds per iteration of each game solved on its own (one handle, hipGraph replay of ten
+    iterations per graph, as the batch runs): the per-game cost of plain one-at-a-time solving.  A
+    batch reproduces each game's iterates bitwise, so its crossing iterations carry over unchanged."""
     out = np.zeros(len(games))
     stream = torch.cuda.Stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     for k, g in enumerate(games):
-        s = Solver(g)
-        s.iterate(3, stream=stream)       # direct iteration + capture
+        s = Solver(g, iters_per_graph=10)
+        s.iterate(13, stream=stream)      # direct iteration + capture of both graphs
         ev[0].record(stream)
         s.iterate(iters, stream=stream)
         ev[1].record(stream)
