@@ -195,6 +195,34 @@ def run_batch(cfr, torch, games, iters, precision, log, tune_iters=20, warm=None
     pots = np.array([g.pot for g in games])
     cross = crossing_iterations(checkpoints, expl, 1e-3 * pots.min())
     ms_it = ms / iters
+    # the same solve with every game retired at the checkpoint where it reached the threshold
+    # (training segments event-timed, best responses excluded)
+    from paper_2609_11923_amd.warm import retiring_time_to_all
+    s.set_schedule(cfr.CFR_SCHEDULE_LEVEL, 0)   # retiring games needs the level-synchronous schedule
+    s.reset()
+    if warm is not None:
+        s.set_regrets(warm, stream=stream)
+    active = np.ones(len(games), np.uint8)
+    seg, used, expl_r, done = [], [], [], 0
+    for c in checkpoints:
+        ev0.record(stream)
+        s.iterate(c - done, stream=stream)
+        ev1.record(stream)
+        ev1.synchronize()
+        seg.append(ev0.elapsed_time(ev1))
+        done = c
+        used.append(c)
+        expl_r.append(s.batch_exploitability(stream=stream)[0])
+        active &= (expl_r[-1] > 1e-3 * pots.min()).astype(np.uint8)
+        if not active.any():
+            break
+        s.set_active(active, stream=stream)
+    cross_r = crossing_iterations(used, expl_r, 1e-3 * pots.min())
+    retiring = {"time_to_1e3pot_all_ms": retiring_time_to_all(cross_r, used, seg, 0.0),
+                "crossings_equal": bool(np.allclose(cross_r, cross, rtol=0, atol=1e-9, equal_nan=True)),
+                "segment_ms": seg, "checkpoints": used,
+                "what": "each game retired (cfr_set_active) at the checkpoint where it reached 1e-3 pot"}
+    log(f"[bench] batch with retiring games: all at 1e-3 pot after {retiring['time_to_1e3pot_all_ms']} ms")
     s.close()
     alone = alone_ms_per_iteration(games, torch, log=log)
     fin = np.isfinite(cross)
@@ -213,6 +241,7 @@ def run_batch(cfr, torch, games, iters, precision, log, tune_iters=20, warm=None
         time_to_1e3pot_all_ms=float(np.max(cross) * ms_it) if np.isfinite(cross).all() else None,
         time_to_1e3pot_median_ms=float(np.median(cross) * ms_it),
         checkpoint_iterations=int(max_iters),
+        retiring=retiring,
         one_at_a_time={
             "what": "each game alone on its own handle (hipGraph replay, ten iterations per graph), run to its own "
                     "crossing iteration; "
@@ -531,7 +560,7 @@ def run_warm(cfr, torch, args, log):
     log("[warm] evaluating on the held-out test batch")
     test_games, _ = batch_games(args.batch_games, args.seed)
     ev = warm.evaluate(test_games, torch, mlp, scale, args.warm_max_iters, control=control, probe=args.warm_probe,
-                       solver_kw=kw, add=args.warm_add, log=log)
+                       solver_kw=kw, add=args.warm_add, log=log, retire=True)
     cold, wst = ev["cold"]["_cross"], ev["warm"]["_cross"]
     both = np.isfinite(cold) & np.isfinite(wst)
     # throughput of the network on the matrix cores: one forward over every test set's row
@@ -790,6 +819,16 @@ def main():
             "model": "crossing iterations (log-log interpolated between checkpoints) x measured ms per iteration, "
                      "plus the warm start's measured time",
         }
+        rc_ = out["warm_start"]["cold"].get("retiring", {}).get("time_ms_all")
+        rw_ = out["warm_start"]["warm"].get("retiring", {}).get("time_ms_all")
+        if rc_ and rw_:
+            # each game retired once it reached the target (the one-at-a-time baseline stops each game
+            # at its own crossing too)
+            out["time_to_target"]["retiring"] = {
+                "batched_cold_ms": rc_, "batched_warm_ms": rw_,
+                "reduction_batched_warm_vs_plain_cold": 1.0 - rw_ / plain if plain else None,
+                "reduction_batched_warm_vs_batched_cold": 1.0 - rw_ / rc_,
+            }
         sw_c = out["warm_start"]["cold"].get("stopwatch")
         sw_w = out["warm_start"]["warm"].get("stopwatch")
         if sw_c and sw_w:

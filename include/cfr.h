@@ -347,6 +347,19 @@ cfr_status cfr_set_root_chance(cfr_handle *h, int32_t game, const double *prob, 
 cfr_status cfr_set_root_ranges(cfr_handle *h, int32_t game, const double *r1, int64_t n1, const double *r2, int64_t n2,
                                void *stream);
 
+/* Retire games of a batch, or bring them back (the batched form is not in the paper; its concluding
+ * remarks motivate repeated subgame solves, and a solve stops once its subgame is good enough):
+ * active[n] (host, n = the number of games) 0 retires a game.  cfr_iterate then skips a retired
+ * game's forward tiles, update groups and chance nodes, so its state (regrets, strategy sums,
+ * strategy, values) stays as it was while the other games iterate, bitwise as if it were not in
+ * the batch; the shared counter still advances, so a game brought back continues with the current
+ * iteration's averaging weight.  Exploitability and strategies are still reported for every game.
+ * Level-synchronous schedule only: CFR_EUNSUPPORTED under the persistent or LDS schedule, and
+ * while a game is retired cfr_set_schedule to those, cfr_autotune and persistent iterations are
+ * refused (CFR_ESTATE).  cfr_reset brings every game back.  A single game cannot be retired
+ * (CFR_EUNSUPPORTED for active[0] = 0).  Waits for the copy on `stream`. */
+cfr_status cfr_set_active(cfr_handle *h, const uint8_t *active, int32_t n, void *stream);
+
 /* Sizes and per-iteration launch count of a compiled game. */
 cfr_status cfr_counts(cfr_handle *h, cfr_counts_t *out);
 

@@ -94,7 +94,8 @@ _lib = None
 
 # exported symbols of include/cfr.h (the ABI tests check the library exports each one)
 EXPORTS = ["cfr_default_options", "cfr_layout_host", "cfr_layout_free", "cfr_compile", "cfr_compile_batch",
-           "cfr_batch_size", "cfr_batch_exploitability", "cfr_autotune", "cfr_set_schedule", "cfr_iterate",
+           "cfr_batch_size", "cfr_batch_exploitability", "cfr_autotune", "cfr_set_schedule", "cfr_set_active",
+           "cfr_iterate",
            "cfr_iterations", "cfr_strategy", "cfr_exploitability", "cfr_reset", "cfr_get_state", "cfr_set_regrets",
            "cfr_counts", "cfr_profile", "cfr_debug_rebind", "cfr_destroy", "cfr_last_error",
            "cfr_mlp_default_desc", "cfr_mlp_create", "cfr_mlp_num_params", "cfr_mlp_set_params", "cfr_mlp_get",
@@ -128,6 +129,7 @@ def load():
         "cfr_compile_batch": (S, [ctypes.POINTER(cfr_game_desc), ctypes.c_int32, ctypes.POINTER(cfr_options),
                                   ctypes.POINTER(_P)]),
         "cfr_batch_size": (S, [_P, ctypes.POINTER(ctypes.c_int32), _P]),
+        "cfr_set_active": (S, [_P, _P, ctypes.c_int32, _P]),
         "cfr_batch_exploitability": (S, [_P, _P, _P, _P, _P, _P, ctypes.c_int32]),
         "cfr_autotune": (S, [_P, ctypes.c_int64, _P, ctypes.c_char_p, ctypes.POINTER(cfr_tune_result)]),
         "cfr_set_schedule": (S, [_P, ctypes.c_int32, ctypes.c_int32]),
@@ -319,6 +321,12 @@ def cfr_persistent_plan_host(nodes, wg_nodes: int, max_w: int) -> dict:
 
 def cfr_set_schedule(h, persistent: int, wg_nodes: int = 0):
     _check(load().cfr_set_schedule(h, int(persistent), int(wg_nodes)))
+
+
+def cfr_set_active(h, active, stream=None):
+    """Retire (0) or bring back (1) the games of a batch; active has one entry per game."""
+    a = np.ascontiguousarray(np.asarray(active, dtype=np.uint8))
+    _check(load().cfr_set_active(h, a.ctypes.data_as(_P), int(a.size), stream))
 
 
 def cfr_iterate(h, n: int, stream=None):
@@ -590,6 +598,11 @@ class Solver:
 
     def set_schedule(self, persistent: int, wg_nodes: int = 0):
         cfr_set_schedule(self.h, persistent, wg_nodes)
+
+    def set_active(self, active, stream=None):
+        """Retire games of the batch (0) or bring them back (1): retired games keep their state while
+        the others iterate."""
+        cfr_set_active(self.h, active, self._stream(stream))
 
     def batch_exploitability(self, stream=None):
         """(expl, br1, br2, value) arrays with one entry per game."""

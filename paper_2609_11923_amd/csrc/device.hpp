@@ -61,6 +61,13 @@ struct DevGame {
     int32_t *chance_node = nullptr;          // device: internal chance nodes by depth (small fan-out)
     const int32_t *bigc_off = nullptr;       // [max_depth+2] big-fan-out chance nodes of depth d
     int32_t *bigc_node = nullptr;            // device: chance nodes with fan-out above BIG_FANOUT
+    // batches (nullptr for a single game): whether each game iterates (cfr_set_active), the game of
+    // each update group, chance node and big chance node, and the first and last game of each
+    // forward tile (depth d's tiles start at fwd_tile_base[d], a host array)
+    int8_t *game_active = nullptr;           // device [n_games]
+    int32_t *grp_game = nullptr, *chance_game = nullptr, *bigc_game = nullptr;
+    int2 *fwd_games = nullptr;
+    const int64_t *fwd_tile_base = nullptr;
     // iteration state, element type float or double (fp64)
     void *v = nullptr;            // [N]   player-1 chance-weighted values; terminals hold the template
     void *reach = nullptr;        // [2N]  lane 0: player 1 reach, lane 1: player 2 reach
@@ -85,7 +92,7 @@ struct IterFlags {
 };
 
 // one level of the forward reach pass: nodes [lo, hi) of one depth; tick != nullptr bumps the counter
-hipError_t launch_forward(const DevGame &g, int32_t lo, int32_t hi, int32_t *tick, hipStream_t s);
+hipError_t launch_forward(const DevGame &g, int d, int32_t lo, int32_t hi, int32_t *tick, hipStream_t s);
 // one level of the backward value pass fused with the update of the information sets on it
 // (regrets, clamp, average, regret matching of the next strategy)
 hipError_t launch_level(const DevGame &g, int d, IterFlags f, hipStream_t s);

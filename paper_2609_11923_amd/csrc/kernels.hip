@@ -80,10 +80,19 @@ __device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t n) {
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_forward(int32_t lo, int32_t hi, const int2 *__restrict__ up,
                                                    const T *__restrict__ sigma, T *__restrict__ r1,
-                                                   T *__restrict__ r2, int32_t *tick) {
+                                                   T *__restrict__ r2, int32_t *tick,
+                                                   const int8_t *__restrict__ active,
+                                                   const int2 *__restrict__ tile_games) {
     if (tick && blockIdx.x == 0 && threadIdx.x == 0) tick[0] += 1;
     if (hi <= lo) return;
     const int32_t tile = xcd_tile((int32_t)blockIdx.x, (int32_t)gridDim.x);
+    if (active) {
+        // a tile whose games are all retired is skipped (recomputing it would rewrite the same reach)
+        const int2 gr = tile_games[tile];
+        bool any = false;
+        for (int32_t q = gr.x; q <= gr.y && !any; q++) any = active[q] != 0;
+        if (!any) return;
+    }
     const int32_t base = lo + tile * (BLOCK * FWD_NPT) + (int32_t)threadIdx.x;
     int2 u[FWD_NPT];
 #pragma unroll
@@ -112,6 +121,8 @@ struct LevelArgs {
     const int2 *mem;
     const int8_t *iset_player;
     const int32_t *kid_off, *kid, *chance_node, *bigc_node;
+    const int8_t *active;          // batches: whether each game iterates (nullptr: all)
+    const int32_t *grp_game, *chance_game, *bigc_game;
     const int32_t *koff, *mnode;   // affine layouts: per-slot child offset, compact member list
     const uint16_t *mpos;          // affine layouts: set-major position of each member of a node-order group
     const int8_t *grp_perm;        // affine layouts: 1 where a group's member list is in node order
@@ -697,17 +708,22 @@ __global__ void __launch_bounds__(BLOCK, (level_min_waves<T, MAXA, EXT>())) k_le
                                                  const int32_t *__restrict__ tcount, int rule, int linear, int upd) {
     __shared__ LevelLds<T, MAXA, MPT, EXPLICIT, AFF> L;
     const int32_t blk = (int32_t)blockIdx.x;
+    // a retired game of a batch is skipped whole (its values feed only its own parents)
     if (blk >= ngroups + nbig) {
         const int32_t j = (blk - ngroups - nbig) * BLOCK + (int32_t)threadIdx.x;
-        if (j < nchance) chance_value<T, EXPLICIT>(a.chance_node[cbeg + j], a);
+        if (j < nchance && (!a.active || a.active[a.chance_game[cbeg + j]]))
+            chance_value<T, EXPLICIT>(a.chance_node[cbeg + j], a);
         return;
     }
     if (blk >= ngroups) {
+        if (a.active && !a.active[a.bigc_game[bbeg + blk - ngroups]]) return;
         big_chance_value<T, EXPLICIT>(a.bigc_node[bbeg + blk - ngroups], a, L.po);
         return;
     }
+    const int32_t grp = gbeg + xcd_tile(blk, ngroups);
+    if (a.active && !a.active[a.grp_game[grp]]) return;
     const RuleArgs ru = rule_args(rule, linear, upd, tcount[0]);
-    update_group<T, MAXA, MPT, EXPLICIT, EXT, AFF>(gbeg + xcd_tile(blk, ngroups), ru, a, L);
+    update_group<T, MAXA, MPT, EXPLICIT, EXT, AFF>(grp, ru, a, L);
 }
 
 // Per-game barrier among the W blocks of one game.  Thread 0 publishes the block's writes
@@ -1097,18 +1113,20 @@ __global__ void __launch_bounds__(BLOCK) k_br_backward(int32_t lo, int32_t hi, c
 // ---- launchers ------------------------------------------------------------
 
 template <typename T>
-static hipError_t forward_t(const DevGame &g, int32_t lo, int32_t hi, int32_t *tick, hipStream_t s) {
+static hipError_t forward_t(const DevGame &g, int32_t lo, int32_t hi, int32_t *tick, const int2 *fwd_tiles,
+                           hipStream_t s) {
     T *r = (T *)g.reach;
     // one block still runs the counter bump
     const unsigned blocks = hi > lo ? (unsigned)((hi - lo + BLOCK * FWD_NPT - 1) / (BLOCK * FWD_NPT)) : 1u;
     hipLaunchKernelGGL(k_forward<T>, dim3(blocks), dim3(BLOCK), 0, s, lo, hi, g.up, (const T *)g.sigma, r,
-                       r + g.N, tick);
+                       r + g.N, tick, (const int8_t *)g.game_active, fwd_tiles);
     return hipGetLastError();
 }
 
-hipError_t launch_forward(const DevGame &g, int32_t lo, int32_t hi, int32_t *tick, hipStream_t s) {
+hipError_t launch_forward(const DevGame &g, int d, int32_t lo, int32_t hi, int32_t *tick, hipStream_t s) {
     if (hi <= lo && !tick) return hipSuccess;
-    return g.fp64 ? forward_t<double>(g, lo, hi, tick, s) : forward_t<float>(g, lo, hi, tick, s);
+    const int2 *tiles = g.game_active ? g.fwd_games + g.fwd_tile_base[d] : nullptr;
+    return g.fp64 ? forward_t<double>(g, lo, hi, tick, tiles, s) : forward_t<float>(g, lo, hi, tick, tiles, s);
 }
 
 template <typename T>
@@ -1118,6 +1136,7 @@ static LevelArgs<T> level_args(const DevGame &g) {
     a.iset_player = g.iset_player; a.kid_off = g.kid_off; a.kid = g.kid; a.chance_node = g.chance_node;
     a.bigc_node = g.bigc_node;
     a.koff = g.koff; a.mnode = g.mnode; a.mpos = g.mpos; a.grp_perm = g.grp_perm;
+    a.active = g.game_active; a.grp_game = g.grp_game; a.chance_game = g.chance_game; a.bigc_game = g.bigc_game;
     a.v = (T *)g.v;
     a.r1 = (T *)g.reach;
     a.r2 = (T *)g.reach + g.N;

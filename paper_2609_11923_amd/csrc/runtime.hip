@@ -84,6 +84,10 @@ struct cfr_handle {
     double pot = 1.0;
     int64_t device_bytes = 0;
     std::vector<double> perm_members;  // per depth: members of update groups listed in node order
+    // batches: per-game activity (cfr_set_active) and the forward tiles' first tile per depth
+    std::vector<int8_t> active;
+    std::vector<int64_t> fwd_tile_base;
+    bool any_inactive = false;
     int32_t node_order_groups = 0;
     int64_t node_order_members = 0;
     std::vector<void *> allocs;
@@ -286,7 +290,7 @@ cfr_status enqueue_iteration(cfr_handle *h, hipStream_t s, int64_t *count, Launc
         if (alt) f.upd = 1 << half;
         if (kind == 0) HIP_TRY(launch_tick(g, s));
         else if (kind == 1)
-            HIP_TRY(launch_forward(g, h->depth_off[d], h->int_end[d], d == 1 && half == 0 ? g.t : nullptr, s));
+            HIP_TRY(launch_forward(g, d, h->depth_off[d], h->int_end[d], d == 1 && half == 0 ? g.t : nullptr, s));
         else HIP_TRY(launch_level(g, d, f, s));
         if (tm) {
             tm->cls.push_back(-1);
@@ -897,6 +901,51 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     UP(g.grp_iset_off, DL.grp_iset_off);
     UP(g.chance_node, DL.chance_node);
     UP(g.bigc_node, DL.bigc_node);
+    if (DL.n_games > 1) {
+        // the game of every update group, chance node and big chance node, and the first and last
+        // game of every forward tile (BLOCK * 4 nodes of one depth), for retiring games
+        const int ng = DL.n_games, MD = (int)DL.depth_off.size() - 2;
+        auto range = [&](int s_, int d, int f) { return DL.game_range[((size_t)s_ * (MD + 1) + d) * GR_FIELDS + f]; };
+        std::vector<int32_t> gg((size_t)std::max<int64_t>(g.G, 1), 0), cg(std::max<size_t>(DL.chance_node.size(), 1), 0),
+            bg(std::max<size_t>(DL.bigc_node.size(), 1), 0);
+        for (int s_ = 0; s_ < ng; s_++)
+            for (int d = 0; d <= MD; d++) {
+                for (int32_t x = range(s_, d, 2); x < range(s_, d, 3); x++) gg[(size_t)x] = s_;
+                for (int32_t x = range(s_, d, 4); x < range(s_, d, 5); x++) cg[(size_t)x] = s_;
+                for (int32_t x = range(s_, d, 6); x < range(s_, d, 7); x++) bg[(size_t)x] = s_;
+            }
+        constexpr int32_t TILE = 1024;   // k_forward's nodes per workgroup
+        h->fwd_tile_base.assign((size_t)MD + 2, 0);
+        std::vector<int2> tiles;
+        for (int d = 0; d <= MD; d++) {
+            h->fwd_tile_base[(size_t)d] = (int64_t)tiles.size();
+            const int32_t lo = DL.depth_off[(size_t)d], hi = DL.int_end[(size_t)d];
+            int s_ = 0;
+            for (int32_t a0 = lo; a0 < hi; a0 += TILE) {
+                const int32_t a1 = std::min(hi, a0 + TILE) - 1;
+                while (s_ + 1 < ng && range(s_, d, 1) <= a0) s_++;
+                int e_ = s_;
+                while (e_ + 1 < ng && range(e_, d, 1) <= a1) e_++;
+                tiles.push_back(make_int2(s_, e_));
+            }
+        }
+        h->fwd_tile_base[(size_t)MD + 1] = (int64_t)tiles.size();
+        if (tiles.empty()) tiles.push_back(make_int2(0, 0));
+        h->active.assign((size_t)ng, 1);
+#define BA(ptr, cnt) do { st = dev_alloc(h, &(ptr), (cnt)); if (st != CFR_OK) { free_handle(h); return st; } } while (0)
+        BA(g.grp_game, (int64_t)gg.size());
+        BA(g.chance_game, (int64_t)cg.size());
+        BA(g.bigc_game, (int64_t)bg.size());
+        BA(g.fwd_games, (int64_t)tiles.size());
+        BA(g.game_active, (int64_t)ng);
+#undef BA
+        UP(g.grp_game, gg);
+        UP(g.chance_game, cg);
+        UP(g.bigc_game, bg);
+        UP(g.fwd_games, tiles);
+        UP(g.game_active, h->active);
+        g.fwd_tile_base = h->fwd_tile_base.data();
+    }
     UP(h->canon_off, canon_off);
     UP(h->canon_player, canon_player);
     if (o.lifecycle) {
@@ -976,10 +1025,37 @@ cfr_status cfr_reset(cfr_handle *h) {
     HIP_TRY(hipMemsetAsync(g.sbar, 0, (size_t)(g.A > 0 ? g.A : 1) * sizeof(double), s));
     HIP_TRY(hipMemsetAsync(g.t, 0, sizeof(int32_t), s));
     if (h->pp.err) HIP_TRY(hipMemsetAsync(h->pp.err, 0, sizeof(int32_t), s));
+    if (g.game_active && h->any_inactive) {
+        // a fresh solve iterates every game again
+        h->active.assign(h->active.size(), 1);
+        HIP_TRY(hipMemcpyAsync(g.game_active, h->active.data(), h->active.size(), hipMemcpyHostToDevice, s));
+        h->any_inactive = false;
+    }
     HIP_TRY(launch_regret_matching(g, s));
     HIP_TRY(hipStreamSynchronize(s));
     h->iters = 0;
     h->broken = false;
+    return CFR_OK;
+}
+
+cfr_status cfr_set_active(cfr_handle *h, const uint8_t *active, int32_t n, void *stream) {
+    if (!h || !active) return fail(CFR_EINVAL, "NULL argument");
+    if (n != h->n_games) return fail(CFR_EINVAL, "n must equal the number of games " + std::to_string(h->n_games));
+    if (h->n_games == 1) {
+        if (!active[0]) return fail(CFR_EUNSUPPORTED, "a single game cannot be retired (do not iterate it)");
+        return CFR_OK;
+    }
+    bool any = false;
+    for (int32_t s_ = 0; s_ < n; s_++) any |= active[s_] == 0;
+    if (any && (h->persistent || h->lds))
+        return fail(CFR_EUNSUPPORTED, "retiring games needs the level-synchronous schedule (cfr_set_schedule)");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    hipStream_t s = (hipStream_t)stream;
+    // the staging copy stays valid: the handle owns it and the copy is waited for before returning
+    for (int32_t s_ = 0; s_ < n; s_++) h->active[(size_t)s_] = active[s_] ? 1 : 0;
+    HIP_TRY(hipMemcpyAsync(h->g.game_active, h->active.data(), (size_t)n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    h->any_inactive = any;
     return CFR_OK;
 }
 
@@ -990,6 +1066,8 @@ cfr_status cfr_iterate(cfr_handle *h, int64_t n, void *stream) {
     HIP_TRY(hipSetDevice(h->opt.device));
     hipStream_t s = (hipStream_t)stream;
     if (h->broken) return fail(CFR_ESTATE, "a persistent launch stopped part-way; call cfr_reset first");
+    if (h->any_inactive && (h->persistent || h->lds))
+        return fail(CFR_ESTATE, "retired games need the level-synchronous schedule; reactivate them first");
     if (h->persistent || h->lds) return persistent_iterate(h, n, s);
     if (h->captured && h->pinned != persistent_ptrs(h))
         return fail(CFR_ESTATE, "a persistent buffer changed since graph capture; refusing to replay");
@@ -1332,6 +1410,8 @@ cfr_status cfr_persistent_plan_host(const int64_t *nodes, int32_t n, int32_t wg_
 cfr_status cfr_set_schedule(cfr_handle *h, int32_t persistent, int32_t wg_nodes) {
     if (!h) return fail(CFR_EINVAL, "handle is NULL");
     if (persistent < CFR_SCHEDULE_LEVEL || persistent > CFR_SCHEDULE_LDS) return fail(CFR_EINVAL, "unknown schedule");
+    if (persistent != CFR_SCHEDULE_LEVEL && h->any_inactive)
+        return fail(CFR_ESTATE, "some games are retired: the persistent and LDS schedules iterate every game");
     HIP_TRY(hipSetDevice(h->opt.device));
     HIP_TRY(hipDeviceSynchronize());
     if (persistent == CFR_SCHEDULE_PERSISTENT) {
@@ -1354,6 +1434,7 @@ static std::string tune_key(const cfr_handle *h) {
 
 cfr_status cfr_autotune(cfr_handle *h, int64_t iters, void *stream, const char *cache_path, cfr_tune_result *out) {
     if (!h || iters <= 0) return fail(CFR_EINVAL, "bad argument");
+    if (h->any_inactive) return fail(CFR_ESTATE, "some games are retired: reactivate them (or cfr_reset) first");
     HIP_TRY(hipSetDevice(h->opt.device));
     hipStream_t s = (hipStream_t)stream;
     const std::string key = tune_key(h);

@@ -183,12 +183,15 @@ def loss_of(mlp: Mlp, X, T, W, N, torch):
     return tot / max(wt, 1e-30)
 
 
-def solve_curves(s: Solver, rows: Rows, torch, checkpoints, mlp=None, scale=0.0, probe=0, add=False, log=None):
+def solve_curves(s: Solver, rows: Rows, torch, checkpoints, mlp=None, scale=0.0, probe=0, add=False, log=None,
+                 retire_thr=None, seg_ms=None):
     """One batch solve from scratch on solver s, with exploitability checkpoints at absolute
     iteration counts (a warm start's probe iterations count).  Timed on the stream with events:
     the warm start (feature pass, probe iterations, network, injection) and the iterations; the
-    best-response evaluations at the checkpoints are not timed.  Returns (expl [checkpoints,
-    games], warm_ms, iter_ms, the checkpoints used)."""
+    best-response evaluations at the checkpoints are not timed.  With retire_thr, a game whose
+    exploitability is at most retire_thr at a checkpoint is retired (cfr_set_active) and no longer
+    iterated; seg_ms (a list) then receives the measured milliseconds of every segment between
+    checkpoints.  Returns (expl [checkpoints, games], warm_ms, iter_ms, the checkpoints used)."""
     stream = torch.cuda.Stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     warm_ms = 0.0
@@ -204,17 +207,48 @@ def solve_curves(s: Solver, rows: Rows, torch, checkpoints, mlp=None, scale=0.0,
     done = probe if mlp is not None else 0
     checkpoints = [int(c) for c in checkpoints if c > done]
     expl, iter_ms = [], 0.0
+    active = np.ones(s.n_games, np.uint8)
     for c in checkpoints:
         ev[0].record(stream)
         s.iterate(int(c) - done, stream=stream)
         ev[1].record(stream)
         ev[1].synchronize()
-        iter_ms += ev[0].elapsed_time(ev[1])
+        ms = ev[0].elapsed_time(ev[1])
+        iter_ms += ms
+        if seg_ms is not None:
+            seg_ms.append(ms)
         done = int(c)
         expl.append(s.batch_exploitability(stream=stream)[0])
+        if retire_thr is not None:
+            active &= (expl[-1] > retire_thr).astype(np.uint8)
+            if not active.any():
+                break
+            s.set_active(active, stream=stream)
         if log is not None:
-            log(f"[warm]   iteration {done}: median expl {np.median(expl[-1]):.3e}")
-    return np.array(expl), warm_ms, iter_ms, checkpoints
+            log(f"[warm]   iteration {done}: median expl {np.median(expl[-1]):.3e}"
+                + (f", {int(active.sum())} games iterating" if retire_thr is not None else ""))
+    if retire_thr is not None:
+        s.set_active(np.ones(s.n_games, np.uint8), stream=stream)
+    return np.array(expl), warm_ms, iter_ms, checkpoints[:len(expl)]
+
+
+def retiring_time_to_all(cross, checkpoints, seg_ms, warm_ms, skip=0):
+    """Wall time until the last game reaches the threshold when games retire at the checkpoint where
+    they reached it: the warm start, the measured segments before the last game's bracketing segment
+    and, of that segment, the share up to the last game's (interpolated) crossing iteration.  None if
+    a game never got there."""
+    if not np.isfinite(cross).all() or not len(seg_ms):
+        return None
+    last = float(np.max(cross))
+    starts = [skip] + list(checkpoints[:-1])
+    t = warm_ms
+    for a, b, ms in zip(starts, checkpoints, seg_ms):
+        if last >= b:
+            t += ms
+        else:
+            t += ms * max(last - a, 0.0) / max(b - a, 1)
+            break
+    return float(t)
 
 
 def stopwatch(s: Solver, rows: Rows, torch, iters, mlp=None, scale=0.0, probe=0, add=False, thr=None):
@@ -316,7 +350,7 @@ def choose_scale(games, torch, mlp, scales, t_max, probe=0, schedule=LEVEL_SYNC,
 
 
 def evaluate(games, torch, mlp, scale, t_max, control=None, probe=0, schedule=LEVEL_SYNC, solver_kw=None, add=False,
-             log=print):
+             log=print, retire=False):
     """Cold, warm and (optional) control-network solves of the same batch with the same compiled
     handle and schedule; per-game iterations and wall time to exploitability <= 1e-3 pot."""
     s, schedule = batch_solver(games, torch, schedule=schedule, solver_kw=solver_kw, log=log)
@@ -335,6 +369,17 @@ def evaluate(games, torch, mlp, scale, t_max, control=None, probe=0, schedule=LE
         # iterations count from the start (probe included); the probe's time is inside warm_ms
         skip = probe if net is not None else 0
         out[name] = summarize(cross, iter_ms / (used[-1] - skip), warm_ms, skip)
+        if retire and not schedule.get("persistent"):
+            # the same solve, each game retired at the checkpoint where it reached the threshold
+            s.reset()
+            seg = []
+            e2, warm2, _, used2 = solve_curves(s, rows, torch, cps, mlp=net, scale=c, probe=probe, add=add,
+                                              log=log, retire_thr=thr, seg_ms=seg)
+            cross2 = crossing_iterations(used2, e2, thr)
+            out[name]["retiring"] = {
+                "time_ms_all": retiring_time_to_all(cross2, used2, seg, warm2, skip),
+                "crossings_equal": bool(np.allclose(cross2, cross, rtol=0, atol=1e-9, equal_nan=True)),
+                "segment_ms": [float(x) for x in seg], "checkpoints": [int(x) for x in used2]}
         out[name]["expl_final_median"] = float(np.median(e[-1]))
         out[name]["_cross"] = cross
         if np.isfinite(cross).all():

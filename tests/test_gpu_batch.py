@@ -157,3 +157,66 @@ def test_autotune_picks_a_schedule_and_resets(tmp_path):
     t = cfr.Solver(games, precision=cfr.CFR_PRECISION_FP64)
     r2 = t.autotune(10, cache_path=cache)
     assert r2["candidates"] == 0 and r2["persistent"] == r["persistent"]
+
+
+@pytest.mark.parametrize("order", ["sim", "alt"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_retired_games_keep_their_state_and_the_rest_are_unchanged(precision, order):
+    """cfr_set_active: after 12 iterations games 1, 4 and 6 retire; 20 more iterations leave their
+    regrets, strategy sums and strategy bitwise where they were, while the active games' iterates equal
+    those of an uninterrupted run of the whole batch bitwise (games are independent; the shared
+    counter advances alike).  Brought back, a retired game iterates again; cfr_reset brings every game
+    back; the persistent schedule is refused while a game is retired."""
+    games = mixed_batch()
+    p = cfr.CFR_PRECISION_FP32 if precision == "fp32" else cfr.CFR_PRECISION_FP64
+    o = cfr.CFR_ORDER_ALTERNATING if order == "alt" else cfr.CFR_ORDER_SIMULTANEOUS
+    a = cfr.Solver(games, precision=p, order=o, iters_per_graph=5)
+    b = cfr.Solver(games, precision=p, order=o)
+    base = a.slot_base
+    for s in (a, b):
+        s.iterate(12)
+    R12, S12 = a.state()
+    cur12 = a.strategy()
+    retired = [1, 4, 6]
+    mask = np.ones(len(games), np.uint8)
+    mask[retired] = 0
+    a.set_active(mask)
+    with pytest.raises(cfr.CfrError) as e:
+        a.set_schedule(cfr.CFR_SCHEDULE_PERSISTENT, 4096)
+    assert e.value.status == cfr.CFR_ESTATE
+    a.iterate(20)
+    b.iterate(20)
+    Ra, Sa = a.state()
+    Rb, Sb = b.state()
+    cura, curb = a.strategy(), b.strategy()
+    for k in range(len(games)):
+        sl = slice(base[k], base[k + 1])
+        if k in retired:
+            assert np.array_equal(Ra[sl], R12[sl]) and np.array_equal(Sa[sl], S12[sl]), k
+            assert np.array_equal(cura[sl], cur12[sl]), k
+        else:
+            assert np.array_equal(Ra[sl], Rb[sl]) and np.array_equal(Sa[sl], Sb[sl]), k
+            assert np.array_equal(cura[sl], curb[sl]), k
+    ea = a.batch_exploitability()[0]
+    assert np.isfinite(ea).all()
+    a.set_active(np.ones(len(games), np.uint8))
+    a.iterate(3)
+    R3, _ = a.state()
+    assert not np.array_equal(R3[base[1]:base[2]], R12[base[1]:base[2]])
+    a.set_active(mask)
+    a.reset()
+    a.iterate(5)
+    c = cfr.Solver(games, precision=p, order=o)
+    c.iterate(5)
+    assert np.array_equal(a.state()[0], c.state()[0])
+
+
+def test_single_game_cannot_be_retired():
+    s = cfr.Solver(gg.kuhn())
+    s.set_active([1])
+    with pytest.raises(cfr.CfrError) as e:
+        s.set_active([0])
+    assert e.value.status == cfr.CFR_EUNSUPPORTED
+    with pytest.raises(cfr.CfrError) as e:
+        s.set_active([1, 1])
+    assert e.value.status == cfr.CFR_EINVAL

@@ -41,7 +41,7 @@ def test_trained_network_beats_cold_start_and_untrained_network():
     ctl = cfr.Mlp()
     ctl.set_params(theta0)
     test = warm.subgames(gg.random_subgames(64, seed=12, lo=1e3, hi=1e5, game_seed=6))
-    ev = warm.evaluate(test, torch, net, 0.5, 3000, control=ctl, probe=PROBE, add=True, log=note)
+    ev = warm.evaluate(test, torch, net, 0.5, 3000, control=ctl, probe=PROBE, add=True, log=note, retire=True)
     cold, wst, unt = ev["cold"]["_cross"], ev["warm"]["_cross"], ev["control_untrained_net"]["_cross"]
     note(f"[warm test] median iterations: cold {np.median(cold):.1f}, warm {np.median(wst):.1f}, "
          f"untrained {np.median(unt):.1f}; warm faster on {np.mean(wst < cold):.2f} of games")
@@ -52,6 +52,14 @@ def test_trained_network_beats_cold_start_and_untrained_network():
     # wall time includes the feature pass, probe, network and injection
     assert ev["warm"]["time_ms_median"] < ev["cold"]["time_ms_median"]
     for arm in ("cold", "warm"):
+        # retiring each game at the checkpoint where it reached the target changes no crossing and,
+        # when every game got there, shortens the time until the last one did
+        rt = ev[arm]["retiring"]
+        assert rt["crossings_equal"]
+        if rt["time_ms_all"] is not None and ev[arm]["time_ms_all"] is not None:
+            note(f"[warm test] {arm}: all at the target after {ev[arm]['time_ms_all']:.1f} ms, "
+                 f"{rt['time_ms_all']:.1f} ms retiring")
+            assert rt["time_ms_all"] <= ev[arm]["time_ms_all"] * 1.02
         sw = ev[arm].get("stopwatch")
         if sw is not None:
             # run straight through to the last crossing, (almost) every game is at the threshold
