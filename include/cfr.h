@@ -349,11 +349,13 @@ cfr_status cfr_set_root_ranges(cfr_handle *h, int32_t game, const double *r1, in
 
 /* Retire games of a batch, or bring them back (the batched form is not in the paper; its concluding
  * remarks motivate repeated subgame solves, and a solve stops once its subgame is good enough):
- * active[n] (host, n = the number of games) 0 retires a game.  cfr_iterate then skips a retired
- * game's forward tiles, update groups and chance nodes, so its state (regrets, strategy sums,
- * strategy, values) stays as it was while the other games iterate, bitwise as if it were not in
- * the batch; the shared counter still advances, so a game brought back continues with the current
- * iteration's averaging weight.  Exploitability and strategies are still reported for every game.
+ * active[n] (host, n = the number of games) 0 retires a game.  cfr_iterate then launches only the
+ * active games' update groups and chance nodes and the forward tiles that hold an active game (lists
+ * built here; the iteration graphs are captured again on the next cfr_iterate), so a retired game's
+ * state (regrets, strategy sums, strategy, values) stays as it was while the other games iterate,
+ * bitwise as if it were not in the batch; the shared counter still advances, so a game brought back
+ * continues with the current iteration's averaging weight.  cfr_profile's byte figures keep counting
+ * every game.  Exploitability and strategies are still reported for every game.
  * Level-synchronous schedule only: CFR_EUNSUPPORTED under the persistent or LDS schedule, and
  * while a game is retired cfr_set_schedule to those, cfr_autotune and persistent iterations are
  * refused (CFR_ESTATE).  cfr_reset brings every game back.  A single game cannot be retired

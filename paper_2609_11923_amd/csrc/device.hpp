@@ -61,13 +61,13 @@ struct DevGame {
     int32_t *chance_node = nullptr;          // device: internal chance nodes by depth (small fan-out)
     const int32_t *bigc_off = nullptr;       // [max_depth+2] big-fan-out chance nodes of depth d
     int32_t *bigc_node = nullptr;            // device: chance nodes with fan-out above BIG_FANOUT
-    // batches (nullptr for a single game): whether each game iterates (cfr_set_active), the game of
-    // each update group, chance node and big chance node, and the first and last game of each
-    // forward tile (depth d's tiles start at fwd_tile_base[d], a host array)
-    int8_t *game_active = nullptr;           // device [n_games]
-    int32_t *grp_game = nullptr, *chance_game = nullptr, *bigc_game = nullptr;
-    int2 *fwd_games = nullptr;
-    const int64_t *fwd_tile_base = nullptr;
+    // batches with retired games (cfr_set_active): the work that still runs, per depth -- forward
+    // tiles (index within the depth's tiles), update groups, chance nodes and big chance nodes --
+    // listed on the device at [off[d], off[d] + cnt[d]) of each list (host offsets and counts);
+    // use_lists = 0 while every game iterates (the identity)
+    int use_lists = 0;
+    int32_t *fwd_list = nullptr, *grp_list = nullptr, *chance_list = nullptr, *bigc_list = nullptr;
+    const int64_t *fwd_off = nullptr, *grp_off = nullptr, *chance_off_l = nullptr, *bigc_off_l = nullptr;
     // iteration state, element type float or double (fp64)
     void *v = nullptr;            // [N]   player-1 chance-weighted values; terminals hold the template
     void *reach = nullptr;        // [2N]  lane 0: player 1 reach, lane 1: player 2 reach

@@ -81,18 +81,13 @@ template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_forward(int32_t lo, int32_t hi, const int2 *__restrict__ up,
                                                    const T *__restrict__ sigma, T *__restrict__ r1,
                                                    T *__restrict__ r2, int32_t *tick,
-                                                   const int8_t *__restrict__ active,
-                                                   const int2 *__restrict__ tile_games) {
+                                                   const int32_t *__restrict__ tiles) {
     if (tick && blockIdx.x == 0 && threadIdx.x == 0) tick[0] += 1;
     if (hi <= lo) return;
-    const int32_t tile = xcd_tile((int32_t)blockIdx.x, (int32_t)gridDim.x);
-    if (active) {
-        // a tile whose games are all retired is skipped (recomputing it would rewrite the same reach)
-        const int2 gr = tile_games[tile];
-        bool any = false;
-        for (int32_t q = gr.x; q <= gr.y && !any; q++) any = active[q] != 0;
-        if (!any) return;
-    }
+    // with retired games only the listed tiles run (a tile shared with a retired game rewrites that
+    // game's reach with the same values: its strategy no longer changes)
+    const int32_t x = xcd_tile((int32_t)blockIdx.x, (int32_t)gridDim.x);
+    const int32_t tile = tiles ? tiles[x] : x;
     const int32_t base = lo + tile * (BLOCK * FWD_NPT) + (int32_t)threadIdx.x;
     int2 u[FWD_NPT];
 #pragma unroll
@@ -121,8 +116,7 @@ struct LevelArgs {
     const int2 *mem;
     const int8_t *iset_player;
     const int32_t *kid_off, *kid, *chance_node, *bigc_node;
-    const int8_t *active;          // batches: whether each game iterates (nullptr: all)
-    const int32_t *grp_game, *chance_game, *bigc_game;
+    const int32_t *grp_list, *chance_list, *bigc_list;   // batches with retired games (nullptr: all)
     const int32_t *koff, *mnode;   // affine layouts: per-slot child offset, compact member list
     const uint16_t *mpos;          // affine layouts: set-major position of each member of a node-order group
     const int8_t *grp_perm;        // affine layouts: 1 where a group's member list is in node order
@@ -708,20 +702,20 @@ __global__ void __launch_bounds__(BLOCK, (level_min_waves<T, MAXA, EXT>())) k_le
                                                  const int32_t *__restrict__ tcount, int rule, int linear, int upd) {
     __shared__ LevelLds<T, MAXA, MPT, EXPLICIT, AFF> L;
     const int32_t blk = (int32_t)blockIdx.x;
-    // a retired game of a batch is skipped whole (its values feed only its own parents)
+    // with retired games in a batch the ranges index lists of the work that still runs (a retired
+    // game's values feed only its own parents)
     if (blk >= ngroups + nbig) {
         const int32_t j = (blk - ngroups - nbig) * BLOCK + (int32_t)threadIdx.x;
-        if (j < nchance && (!a.active || a.active[a.chance_game[cbeg + j]]))
-            chance_value<T, EXPLICIT>(a.chance_node[cbeg + j], a);
+        if (j < nchance) chance_value<T, EXPLICIT>(a.chance_node[a.chance_list ? a.chance_list[cbeg + j] : cbeg + j], a);
         return;
     }
     if (blk >= ngroups) {
-        if (a.active && !a.active[a.bigc_game[bbeg + blk - ngroups]]) return;
-        big_chance_value<T, EXPLICIT>(a.bigc_node[bbeg + blk - ngroups], a, L.po);
+        const int32_t b = bbeg + blk - ngroups;
+        big_chance_value<T, EXPLICIT>(a.bigc_node[a.bigc_list ? a.bigc_list[b] : b], a, L.po);
         return;
     }
-    const int32_t grp = gbeg + xcd_tile(blk, ngroups);
-    if (a.active && !a.active[a.grp_game[grp]]) return;
+    const int32_t x = gbeg + xcd_tile(blk, ngroups);
+    const int32_t grp = a.grp_list ? a.grp_list[x] : x;
     const RuleArgs ru = rule_args(rule, linear, upd, tcount[0]);
     update_group<T, MAXA, MPT, EXPLICIT, EXT, AFF>(grp, ru, a, L);
 }
@@ -1113,20 +1107,24 @@ __global__ void __launch_bounds__(BLOCK) k_br_backward(int32_t lo, int32_t hi, c
 // ---- launchers ------------------------------------------------------------
 
 template <typename T>
-static hipError_t forward_t(const DevGame &g, int32_t lo, int32_t hi, int32_t *tick, const int2 *fwd_tiles,
-                           hipStream_t s) {
+static hipError_t forward_t(const DevGame &g, int32_t lo, int32_t hi, int32_t *tick, const int32_t *fwd_tiles,
+                           int64_t n_tiles, hipStream_t s) {
     T *r = (T *)g.reach;
     // one block still runs the counter bump
-    const unsigned blocks = hi > lo ? (unsigned)((hi - lo + BLOCK * FWD_NPT - 1) / (BLOCK * FWD_NPT)) : 1u;
+    if (fwd_tiles && n_tiles == 0) hi = lo;
+    const unsigned blocks = hi <= lo ? 1u : fwd_tiles ? (unsigned)n_tiles
+                                                       : (unsigned)((hi - lo + BLOCK * FWD_NPT - 1) / (BLOCK * FWD_NPT));
     hipLaunchKernelGGL(k_forward<T>, dim3(blocks), dim3(BLOCK), 0, s, lo, hi, g.up, (const T *)g.sigma, r,
-                       r + g.N, tick, (const int8_t *)g.game_active, fwd_tiles);
+                       r + g.N, tick, fwd_tiles);
     return hipGetLastError();
 }
 
 hipError_t launch_forward(const DevGame &g, int d, int32_t lo, int32_t hi, int32_t *tick, hipStream_t s) {
     if (hi <= lo && !tick) return hipSuccess;
-    const int2 *tiles = g.game_active ? g.fwd_games + g.fwd_tile_base[d] : nullptr;
-    return g.fp64 ? forward_t<double>(g, lo, hi, tick, tiles, s) : forward_t<float>(g, lo, hi, tick, tiles, s);
+    const int32_t *tiles = g.use_lists ? g.fwd_list + g.fwd_off[d] : nullptr;
+    const int64_t nt = g.use_lists ? g.fwd_off[d + 1] - g.fwd_off[d] : 0;
+    if (g.use_lists && nt == 0 && !tick) return hipSuccess;
+    return g.fp64 ? forward_t<double>(g, lo, hi, tick, tiles, nt, s) : forward_t<float>(g, lo, hi, tick, tiles, nt, s);
 }
 
 template <typename T>
@@ -1136,7 +1134,9 @@ static LevelArgs<T> level_args(const DevGame &g) {
     a.iset_player = g.iset_player; a.kid_off = g.kid_off; a.kid = g.kid; a.chance_node = g.chance_node;
     a.bigc_node = g.bigc_node;
     a.koff = g.koff; a.mnode = g.mnode; a.mpos = g.mpos; a.grp_perm = g.grp_perm;
-    a.active = g.game_active; a.grp_game = g.grp_game; a.chance_game = g.chance_game; a.bigc_game = g.bigc_game;
+    a.grp_list = g.use_lists ? g.grp_list : nullptr;
+    a.chance_list = g.use_lists ? g.chance_list : nullptr;
+    a.bigc_list = g.use_lists ? g.bigc_list : nullptr;
     a.v = (T *)g.v;
     a.r1 = (T *)g.reach;
     a.r2 = (T *)g.reach + g.N;
@@ -1147,9 +1147,13 @@ static LevelArgs<T> level_args(const DevGame &g) {
 
 template <typename T, int MAXA, int MPT, bool EX, bool XT, bool AF>
 static hipError_t level_t(const DevGame &g, int d, IterFlags f, hipStream_t s) {
-    const int32_t gbeg = g.grp_depth_off[d], ng = g.grp_depth_off[d + 1] - gbeg;
-    const int32_t cbeg = g.chance_off[d], nc = g.chance_off[d + 1] - cbeg;
-    const int32_t bbeg = g.bigc_off[d], nb = g.bigc_off[d + 1] - bbeg;
+    // all work of depth d, or with retired games the listed part of it
+    const int32_t gbeg = g.use_lists ? (int32_t)g.grp_off[d] : g.grp_depth_off[d];
+    const int32_t ng = g.use_lists ? (int32_t)(g.grp_off[d + 1] - g.grp_off[d]) : g.grp_depth_off[d + 1] - gbeg;
+    const int32_t cbeg = g.use_lists ? (int32_t)g.chance_off_l[d] : g.chance_off[d];
+    const int32_t nc = g.use_lists ? (int32_t)(g.chance_off_l[d + 1] - g.chance_off_l[d]) : g.chance_off[d + 1] - cbeg;
+    const int32_t bbeg = g.use_lists ? (int32_t)g.bigc_off_l[d] : g.bigc_off[d];
+    const int32_t nb = g.use_lists ? (int32_t)(g.bigc_off_l[d + 1] - g.bigc_off_l[d]) : g.bigc_off[d + 1] - bbeg;
     const unsigned blocks = (unsigned)ng + (unsigned)nb + grid_for(nc);
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL((k_level<T, MAXA, MPT, EX, XT, AF>), dim3(blocks), dim3(BLOCK), 0, s, gbeg, ng, bbeg, nb, cbeg,

@@ -84,9 +84,12 @@ struct cfr_handle {
     double pot = 1.0;
     int64_t device_bytes = 0;
     std::vector<double> perm_members;  // per depth: members of update groups listed in node order
-    // batches: per-game activity (cfr_set_active) and the forward tiles' first tile per depth
+    // batches: per-game activity (cfr_set_active); each depth's forward tiles (first tile per depth,
+    // each tile's first and last game) and the lists of the work that still runs, per depth
     std::vector<int8_t> active;
     std::vector<int64_t> fwd_tile_base;
+    std::vector<int2> fwd_games;
+    std::vector<int64_t> fwd_off, grp_off, chance_off_l, bigc_off_l;
     bool any_inactive = false;
     int32_t node_order_groups = 0;
     int64_t node_order_members = 0;
@@ -387,6 +390,17 @@ cfr_status capture(cfr_handle *h, int iters, hipGraph_t *graph, hipGraphExec_t *
     *graph = gr;
     *exec = ex;
     return CFR_OK;
+}
+
+// Destroy the captured iteration graphs; the next cfr_iterate captures them again.
+void drop_graphs(cfr_handle *h) {
+    if (h->exec1) (void)hipGraphExecDestroy(h->exec1);
+    if (h->execk) (void)hipGraphExecDestroy(h->execk);
+    if (h->graph1) (void)hipGraphDestroy(h->graph1);
+    if (h->graphk) (void)hipGraphDestroy(h->graphk);
+    h->exec1 = h->execk = nullptr;
+    h->graph1 = h->graphk = nullptr;
+    h->captured = false;
 }
 
 void free_handle(cfr_handle *h) {
@@ -902,23 +916,15 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     UP(g.chance_node, DL.chance_node);
     UP(g.bigc_node, DL.bigc_node);
     if (DL.n_games > 1) {
-        // the game of every update group, chance node and big chance node, and the first and last
-        // game of every forward tile (BLOCK * 4 nodes of one depth), for retiring games
+        // the first and last game of every forward tile (BLOCK * 4 nodes of one depth) and room for the
+        // lists of the work that still runs once games retire (cfr_set_active)
         const int ng = DL.n_games, MD = (int)DL.depth_off.size() - 2;
         auto range = [&](int s_, int d, int f) { return DL.game_range[((size_t)s_ * (MD + 1) + d) * GR_FIELDS + f]; };
-        std::vector<int32_t> gg((size_t)std::max<int64_t>(g.G, 1), 0), cg(std::max<size_t>(DL.chance_node.size(), 1), 0),
-            bg(std::max<size_t>(DL.bigc_node.size(), 1), 0);
-        for (int s_ = 0; s_ < ng; s_++)
-            for (int d = 0; d <= MD; d++) {
-                for (int32_t x = range(s_, d, 2); x < range(s_, d, 3); x++) gg[(size_t)x] = s_;
-                for (int32_t x = range(s_, d, 4); x < range(s_, d, 5); x++) cg[(size_t)x] = s_;
-                for (int32_t x = range(s_, d, 6); x < range(s_, d, 7); x++) bg[(size_t)x] = s_;
-            }
         constexpr int32_t TILE = 1024;   // k_forward's nodes per workgroup
         h->fwd_tile_base.assign((size_t)MD + 2, 0);
-        std::vector<int2> tiles;
+        h->fwd_games.clear();
         for (int d = 0; d <= MD; d++) {
-            h->fwd_tile_base[(size_t)d] = (int64_t)tiles.size();
+            h->fwd_tile_base[(size_t)d] = (int64_t)h->fwd_games.size();
             const int32_t lo = DL.depth_off[(size_t)d], hi = DL.int_end[(size_t)d];
             int s_ = 0;
             for (int32_t a0 = lo; a0 < hi; a0 += TILE) {
@@ -926,25 +932,22 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
                 while (s_ + 1 < ng && range(s_, d, 1) <= a0) s_++;
                 int e_ = s_;
                 while (e_ + 1 < ng && range(e_, d, 1) <= a1) e_++;
-                tiles.push_back(make_int2(s_, e_));
+                h->fwd_games.push_back(make_int2(s_, e_));
             }
         }
-        h->fwd_tile_base[(size_t)MD + 1] = (int64_t)tiles.size();
-        if (tiles.empty()) tiles.push_back(make_int2(0, 0));
+        h->fwd_tile_base[(size_t)MD + 1] = (int64_t)h->fwd_games.size();
         h->active.assign((size_t)ng, 1);
+        for (auto *v : {&h->fwd_off, &h->grp_off, &h->chance_off_l, &h->bigc_off_l}) v->assign((size_t)MD + 2, 0);
 #define BA(ptr, cnt) do { st = dev_alloc(h, &(ptr), (cnt)); if (st != CFR_OK) { free_handle(h); return st; } } while (0)
-        BA(g.grp_game, (int64_t)gg.size());
-        BA(g.chance_game, (int64_t)cg.size());
-        BA(g.bigc_game, (int64_t)bg.size());
-        BA(g.fwd_games, (int64_t)tiles.size());
-        BA(g.game_active, (int64_t)ng);
+        BA(g.fwd_list, std::max<int64_t>((int64_t)h->fwd_games.size(), 1));
+        BA(g.grp_list, std::max<int64_t>(g.G, 1));
+        BA(g.chance_list, std::max<int64_t>((int64_t)DL.chance_node.size(), 1));
+        BA(g.bigc_list, std::max<int64_t>((int64_t)DL.bigc_node.size(), 1));
 #undef BA
-        UP(g.grp_game, gg);
-        UP(g.chance_game, cg);
-        UP(g.bigc_game, bg);
-        UP(g.fwd_games, tiles);
-        UP(g.game_active, h->active);
-        g.fwd_tile_base = h->fwd_tile_base.data();
+        g.fwd_off = h->fwd_off.data();
+        g.grp_off = h->grp_off.data();
+        g.chance_off_l = h->chance_off_l.data();
+        g.bigc_off_l = h->bigc_off_l.data();
     }
     UP(h->canon_off, canon_off);
     UP(h->canon_player, canon_player);
@@ -1025,11 +1028,12 @@ cfr_status cfr_reset(cfr_handle *h) {
     HIP_TRY(hipMemsetAsync(g.sbar, 0, (size_t)(g.A > 0 ? g.A : 1) * sizeof(double), s));
     HIP_TRY(hipMemsetAsync(g.t, 0, sizeof(int32_t), s));
     if (h->pp.err) HIP_TRY(hipMemsetAsync(h->pp.err, 0, sizeof(int32_t), s));
-    if (g.game_active && h->any_inactive) {
-        // a fresh solve iterates every game again
+    if (h->any_inactive) {
+        // a fresh solve iterates every game again (the graphs are captured anew)
         h->active.assign(h->active.size(), 1);
-        HIP_TRY(hipMemcpyAsync(g.game_active, h->active.data(), h->active.size(), hipMemcpyHostToDevice, s));
         h->any_inactive = false;
+        h->g.use_lists = 0;
+        drop_graphs(h);
     }
     HIP_TRY(launch_regret_matching(g, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -1051,10 +1055,46 @@ cfr_status cfr_set_active(cfr_handle *h, const uint8_t *active, int32_t n, void 
         return fail(CFR_EUNSUPPORTED, "retiring games needs the level-synchronous schedule (cfr_set_schedule)");
     HIP_TRY(hipSetDevice(h->opt.device));
     hipStream_t s = (hipStream_t)stream;
-    // the staging copy stays valid: the handle owns it and the copy is waited for before returning
-    for (int32_t s_ = 0; s_ < n; s_++) h->active[(size_t)s_] = active[s_] ? 1 : 0;
-    HIP_TRY(hipMemcpyAsync(h->g.game_active, h->active.data(), (size_t)n, hipMemcpyHostToDevice, s));
+    // queued iterations read the lists and graphs replaced below
     HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipDeviceSynchronize());
+    for (int32_t s_ = 0; s_ < n; s_++) h->active[(size_t)s_] = active[s_] ? 1 : 0;
+    if (any) {
+        // per depth, the forward tiles with an active game and the active games' update groups, chance
+        // nodes and big chance nodes
+        const int MD = (int)h->fwd_off.size() - 2;
+        const int ng = h->n_games;
+        auto range = [&](int s_, int d, int f) { return h->game_range[((size_t)s_ * (MD + 1) + d) * GR_FIELDS + f]; };
+        std::vector<int32_t> fl, gl, cl, bl;
+        for (int d = 0; d <= MD; d++) {
+            h->fwd_off[(size_t)d] = (int64_t)fl.size();
+            h->grp_off[(size_t)d] = (int64_t)gl.size();
+            h->chance_off_l[(size_t)d] = (int64_t)cl.size();
+            h->bigc_off_l[(size_t)d] = (int64_t)bl.size();
+            for (int64_t t = h->fwd_tile_base[(size_t)d]; t < h->fwd_tile_base[(size_t)d + 1]; t++) {
+                const int2 gr = h->fwd_games[(size_t)t];
+                bool on = false;
+                for (int q = gr.x; q <= gr.y && !on; q++) on = h->active[(size_t)q] != 0;
+                if (on) fl.push_back((int32_t)(t - h->fwd_tile_base[(size_t)d]));
+            }
+            for (int s_ = 0; s_ < ng; s_++) {
+                if (!h->active[(size_t)s_]) continue;
+                for (int32_t x = range(s_, d, 2); x < range(s_, d, 3); x++) gl.push_back(x);
+                for (int32_t x = range(s_, d, 4); x < range(s_, d, 5); x++) cl.push_back(x);
+                for (int32_t x = range(s_, d, 6); x < range(s_, d, 7); x++) bl.push_back(x);
+            }
+        }
+        h->fwd_off[(size_t)MD + 1] = (int64_t)fl.size();
+        h->grp_off[(size_t)MD + 1] = (int64_t)gl.size();
+        h->chance_off_l[(size_t)MD + 1] = (int64_t)cl.size();
+        h->bigc_off_l[(size_t)MD + 1] = (int64_t)bl.size();
+        if (!fl.empty()) HIP_TRY(hipMemcpy(h->g.fwd_list, fl.data(), fl.size() * 4, hipMemcpyHostToDevice));
+        if (!gl.empty()) HIP_TRY(hipMemcpy(h->g.grp_list, gl.data(), gl.size() * 4, hipMemcpyHostToDevice));
+        if (!cl.empty()) HIP_TRY(hipMemcpy(h->g.chance_list, cl.data(), cl.size() * 4, hipMemcpyHostToDevice));
+        if (!bl.empty()) HIP_TRY(hipMemcpy(h->g.bigc_list, bl.data(), bl.size() * 4, hipMemcpyHostToDevice));
+    }
+    if (any || h->any_inactive) drop_graphs(h);   // the launch shapes change: capture again
+    h->g.use_lists = any ? 1 : 0;
     h->any_inactive = any;
     return CFR_OK;
 }
