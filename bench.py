@@ -337,7 +337,7 @@ def run_rules(cfr, torch, games, log, max_iters=4000):
     games, compiled per rule, level-synchronous graph, FP32 state).  Iterations count full
     iterations (an alternating one runs both players' halves); wall time uses each rule's own
     measured time per iteration."""
-    from paper_2609_11923_amd.warm import crossing_iterations, geometric_checkpoints
+    from paper_2609_11923_amd.warm import crossing_iterations, geometric_checkpoints, retiring_time_to_all
     pots = np.array([g.pot for g in games])
     cps = geometric_checkpoints(max_iters)
     out = {}
@@ -359,13 +359,32 @@ def run_rules(cfr, torch, games, log, max_iters=4000):
             ms += ev0.elapsed_time(ev1)
             done = c
             expl.append(s.batch_exploitability(stream=stream)[0])
-        s.close()
         cross = crossing_iterations(cps, expl, 1e-3 * pots.min())
+        # the same solve with each game retired at the checkpoint where it reached the target
+        s.reset()
+        active = np.ones(len(games), np.uint8)
+        seg, used, expl_r, done = [], [], [], 0
+        for c in cps:
+            ev0.record(stream)
+            s.iterate(c - done, stream=stream)
+            ev1.record(stream)
+            ev1.synchronize()
+            seg.append(ev0.elapsed_time(ev1))
+            done = c
+            used.append(c)
+            expl_r.append(s.batch_exploitability(stream=stream)[0])
+            active &= (expl_r[-1] > 1e-3 * pots.min()).astype(np.uint8)
+            if not active.any():
+                break
+            s.set_active(active, stream=stream)
+        s.close()
+        cross_r = crossing_iterations(used, expl_r, 1e-3 * pots.min())
         ms_it = ms / cps[-1]
         fin = np.isfinite(cross)
         out[name] = dict(ms_per_iteration=ms_it, reached=int(fin.sum()), iterations_median=float(np.median(cross)),
                          time_to_1e3pot_median_ms=float(np.median(cross) * ms_it),
                          time_to_1e3pot_all_ms=float(np.max(cross) * ms_it) if fin.all() else None,
+                         time_to_1e3pot_all_ms_retiring=retiring_time_to_all(cross_r, used, seg, 0.0),
                          expl_at_max_median=float(np.median(expl[-1])))
         log(f"[bench] rule {name}: {out[name]}")
     return out
