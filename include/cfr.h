@@ -359,7 +359,8 @@ cfr_status cfr_set_root_ranges(cfr_handle *h, int32_t game, const double *r1, in
  * Level-synchronous schedule only: CFR_EUNSUPPORTED under the persistent or LDS schedule, and
  * while a game is retired cfr_set_schedule to those, cfr_autotune and persistent iterations are
  * refused (CFR_ESTATE).  cfr_reset brings every game back.  A single game cannot be retired
- * (CFR_EUNSUPPORTED for active[0] = 0).  Waits for the copy on `stream`. */
+ * (CFR_EUNSUPPORTED for active[0] = 0).  Synchronises the device (queued iterations read the lists
+ * and graphs it replaces) and returns with the new lists in place; `stream` is waited for first. */
 cfr_status cfr_set_active(cfr_handle *h, const uint8_t *active, int32_t n, void *stream);
 
 /* Sizes and per-iteration launch count of a compiled game. */
