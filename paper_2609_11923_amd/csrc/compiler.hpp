@@ -97,7 +97,10 @@ struct DeviceLayout {
 constexpr int GR_FIELDS = 8;  // node lo/hi, group lo/hi, chance lo/hi, big chance lo/hi
 constexpr int BIG_FANOUT = 64;
 
-constexpr int GROUP_SETS = 256;
+// sets per update group: 128 keeps the affine update's LDS rows (child offsets, strategy row, set
+// offsets) small enough for six FP32 blocks per compute unit (large game: 4 % faster per
+// iteration than 256 sets, FP64 unchanged).  At most the 256-thread block (one thread per set).
+constexpr int GROUP_SETS = 128;
 // members per update group (members per thread times the 256-thread block): with at most 4 actions
 // per set four per thread for FP32 state and two for FP64 (whose LDS staging is twice as large),
 // else one.  The update kernels' members per thread must match.

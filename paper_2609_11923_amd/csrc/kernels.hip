@@ -18,11 +18,14 @@
 // reproducible run to run (no float atomics).
 #include <type_traits>
 
+#include "compiler.hpp"
 #include "device.hpp"
 
 namespace cfrx {
 
 constexpr int BLOCK = 256;
+// one thread per set of an update group; uint8 member-to-set indices
+static_assert(GROUP_SETS <= BLOCK && GROUP_SETS <= 256, "update group sets");
 
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 
@@ -354,7 +357,7 @@ struct GroupLds {
 };
 
 // One update group: consecutive information sets of one depth with at most MPT * BLOCK members
-// and BLOCK sets.  Phase 1 (one thread per member h, coalesced over the member list):
+// and GROUP_SETS sets.  Phase 1 (one thread per member h, coalesced over the member list):
 //   v(h) = sum_a sigma^t(I, a) v(h.a)   -- written to v: the backward value pass at h
 //   stage pi_{-i}(h) and v(h.a) - v(h) in LDS.
 // Phase 2 (one thread per set I): reduce the set's members from LDS in ascending member order,
@@ -456,10 +459,10 @@ struct GroupLdsA {
     static constexpr int RA = ROWS ? MAXA : 1;
     T po[MPT * BLOCK];
     alignas(16) T diff[MPT * BLOCK * MAXA];
-    alignas(16) int32_t ko[BLOCK * RA];
-    alignas(16) T sg[BLOCK * RA];
-    int32_t moff[BLOCK + 1];
-    int32_t slot[BLOCK + 1];
+    alignas(16) int32_t ko[GROUP_SETS * RA];
+    alignas(16) T sg[GROUP_SETS * RA];
+    int32_t moff[GROUP_SETS + 1];
+    int32_t slot[GROUP_SETS + 1];
     int32_t wmax[BLOCK / 64];
     uint8_t mset[MPT * BLOCK];
 };
