@@ -851,7 +851,7 @@ def main():
         sw_c = out["warm_start"]["cold"].get("stopwatch")
         sw_w = out["warm_start"]["warm"].get("stopwatch")
         if sw_c and sw_w:
-            # the same two solves run straight through to the last game's crossing and timed whole
+            # the same two solves run straight through until every game is at the target, timed whole
             out["time_to_target"]["stopwatch"] = {
                 "batched_cold": sw_c, "batched_warm": sw_w,
                 "reduction_batched_warm_vs_plain_cold": 1.0 - sw_w["ms_events"] / plain if plain else None,

@@ -147,6 +147,10 @@ typedef struct {
                               read the child list */
     int keep_layout;       /* 1: keep every game's canonical arrays on the host for cfr_get_layout (about
                               30 bytes per node of host memory; default 0) */
+    int group_sets;        /* sets per update group of the backward/update pass: 0 (default) chooses 128
+                              or 256 from the game's (or batch's) set sizes, 128 or 256 forces it; any
+                              other value fails with CFR_EINVAL.  Results do not depend on it (each
+                              set's reduction order is fixed), only the speed does. */
 } cfr_options;
 
 /* Sizes of a compiled game.  blocks = number of depth levels that hold edges (D of eq. blocks). */
@@ -160,6 +164,9 @@ typedef struct {
     int32_t node_order_groups;     /* affine update groups whose members are listed in node order (their sets
                                       interleave); 0 in the counts of cfr_layout_host and cfr_get_layout */
     int64_t node_order_members;    /* members of those groups */
+    int32_t group_sets;            /* sets per update group (128 or 256); 0 in the counts of cfr_layout_host
+                                      and cfr_get_layout */
+    int32_t update_groups;         /* update groups (one workgroup each per iteration); 0 there too */
 } cfr_counts_t;
 
 /* Canonical compiled arrays (host copies), all in canonical numbering:

@@ -48,7 +48,7 @@ class cfr_options(ctypes.Structure):
                 ("iters_per_graph", ctypes.c_int), ("layout", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("device", ctypes.c_int), ("test_fail_capture", ctypes.c_int), ("precision", ctypes.c_int),
                 ("persistent", ctypes.c_int), ("wg_nodes", ctypes.c_int), ("lifecycle", ctypes.c_int),
-                ("affine", ctypes.c_int), ("keep_layout", ctypes.c_int)]
+                ("affine", ctypes.c_int), ("keep_layout", ctypes.c_int), ("group_sets", ctypes.c_int)]
 
 
 class cfr_tune_result(ctypes.Structure):
@@ -63,7 +63,8 @@ class cfr_counts_t(ctypes.Structure):
                 ("br_supported", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
                 ("kernels_per_iteration", ctypes.c_int64), ("pot", ctypes.c_double),
                 ("child_addressing", ctypes.c_int32), ("node_order_groups", ctypes.c_int32),
-                ("node_order_members", ctypes.c_int64)]
+                ("node_order_members", ctypes.c_int64), ("group_sets", ctypes.c_int32),
+                ("update_groups", ctypes.c_int32)]
 
 
 class cfr_layout(ctypes.Structure):
@@ -512,7 +513,7 @@ class Solver:
     def __init__(self, game, rule=CFR_RULE_CFR_PLUS, averaging=CFR_AVG_LINEAR, order=CFR_ORDER_SIMULTANEOUS,
                  iters_per_graph=1, layout=CFR_LAYOUT_PUBLIC, use_graph=True, device=0, test_fail_capture=False,
                  precision=CFR_PRECISION_FP32, persistent=False, wg_nodes=0, lifecycle=False, affine=True,
-                 keep_layout=False):
+                 keep_layout=False, group_sets=0):
         o = cfr_default_options()
         o.rule, o.averaging, o.order = rule, averaging, order
         o.iters_per_graph, o.layout, o.use_graph = iters_per_graph, layout, int(use_graph)
@@ -522,6 +523,7 @@ class Solver:
         o.lifecycle = int(lifecycle)
         o.affine = int(affine)
         o.keep_layout = int(keep_layout)
+        o.group_sets = int(group_sets)
         self.options = o
         if isinstance(game, (list, tuple)):
             self.h = cfr_compile_batch(game, o)

@@ -240,8 +240,68 @@ inline int32_t edge_code(int owner, bool internal, int32_t slot) {
 }
 }  // namespace
 
-cfr_status build_device_layout(const Layout &L, int kind, int group_actions, bool fp64, DeviceLayout &D,
-                               std::string &err) {
+namespace {
+// Groups of D with at most cap members and `sets` sets; the offsets are stored when iset_off is given.
+int64_t form_groups(const DeviceLayout &D, int32_t cap, int32_t sets, std::vector<int32_t> *iset_off,
+                    std::vector<int32_t> *depth_off) {
+    const int md = (int)D.iset_depth_off.size() - 2;
+    if (iset_off) {
+        iset_off->assign(1, 0);
+        depth_off->assign((size_t)md + 2, 0);
+    }
+    int64_t G = 0;
+    for (int d = 0; d <= md; d++) {
+        int32_t members = 0, n = 0;
+        for (int32_t i = D.iset_depth_off[d]; i < D.iset_depth_off[d + 1]; i++) {
+            const int32_t m = D.mem_off[i + 1] - D.mem_off[i];
+            if (n > 0 && (members + m > cap || n + 1 > sets)) {
+                if (iset_off) iset_off->push_back(i);
+                G++;
+                members = 0; n = 0;
+            }
+            members += m; n++;
+        }
+        if (n > 0) {
+            if (iset_off) iset_off->push_back(D.iset_depth_off[d + 1]);
+            G++;
+        }
+        if (iset_off) (*depth_off)[d + 1] = (int32_t)iset_off->size() - 1;
+    }
+    return G;
+}
+}  // namespace
+
+cfr_status set_update_groups(DeviceLayout &D, int32_t sets, std::string &err) {
+    const int32_t cap = D.group_cap;
+    D.groups_by_bound[0] = form_groups(D, cap, 128, nullptr, nullptr);
+    D.groups_by_bound[1] = form_groups(D, cap, GROUP_SETS_MAX, nullptr, nullptr);
+    if (sets == 0) sets = choose_group_sets(D.groups_by_bound[0], D.groups_by_bound[1]);
+    if (sets != 128 && sets != GROUP_SETS_MAX) {
+        err = "update groups hold at most 128 or 256 sets";
+        return CFR_EINVAL;
+    }
+    D.group_sets = sets;
+    form_groups(D, cap, sets, &D.grp_iset_off, &D.grp_depth_off);
+    // the update kernels stream a group through LDS in chunks of `cap` members and map members to
+    // sets for the first chunk only: a group that needs several chunks must hold a single set
+    for (size_t gi = 0; gi + 1 < D.grp_iset_off.size(); gi++) {
+        const int32_t i0 = D.grp_iset_off[gi], i1 = D.grp_iset_off[gi + 1];
+        if (i1 - i0 > 1 && D.mem_off[i1] - D.mem_off[i0] > cap) {
+            err = "internal: an update group of several sets exceeds one staging chunk";
+            return CFR_EINVAL;
+        }
+    }
+    const int md = (int)D.grp_depth_off.size() - 2;
+    if (D.n_games == 1 && D.game_range.size() == (size_t)(md + 1) * GR_FIELDS)
+        for (int d = 0; d <= md; d++) {
+            D.game_range[(size_t)d * GR_FIELDS + 2] = D.grp_depth_off[d];
+            D.game_range[(size_t)d * GR_FIELDS + 3] = D.grp_depth_off[d + 1];
+        }
+    return CFR_OK;
+}
+
+cfr_status build_device_layout(const Layout &L, int kind, int group_actions, bool fp64, int group_sets,
+                               DeviceLayout &D, std::string &err) {
     try {
         const int64_t N = L.N, I = L.I, A = L.A;
         const int md = L.max_depth;
@@ -389,31 +449,9 @@ cfr_status build_device_layout(const Layout &L, int kind, int group_actions, boo
         }
         D.kid_off[N] = pub ? e : L.child_off[N];
         // update groups in device information-set order, never spanning two depths
-        D.grp_iset_off.assign(1, 0);
-        D.grp_depth_off.assign((size_t)md + 2, 0);
-        const int32_t cap = group_members(group_actions > L.max_actions ? group_actions : L.max_actions, fp64);
-        for (int d = 0; d <= md; d++) {
-            int32_t members = 0, sets = 0;
-            for (int32_t i = D.iset_depth_off[d]; i < D.iset_depth_off[d + 1]; i++) {
-                int32_t m = D.mem_off[i + 1] - D.mem_off[i];
-                if (sets > 0 && (members + m > cap || sets + 1 > GROUP_SETS)) {
-                    D.grp_iset_off.push_back(i);
-                    members = 0; sets = 0;
-                }
-                members += m; sets++;
-            }
-            if (sets > 0) D.grp_iset_off.push_back(D.iset_depth_off[d + 1]);
-            D.grp_depth_off[d + 1] = (int32_t)D.grp_iset_off.size() - 1;
-        }
-        // the update kernels stream a group through LDS in chunks of `cap` members and map members to
-        // sets for the first chunk only: a group that needs several chunks must hold a single set
-        for (size_t gi = 0; gi + 1 < D.grp_iset_off.size(); gi++) {
-            const int32_t i0 = D.grp_iset_off[gi], i1 = D.grp_iset_off[gi + 1];
-            if (i1 - i0 > 1 && D.mem_off[i1] - D.mem_off[i0] > cap) {
-                err = "internal: an update group of several sets exceeds one staging chunk";
-                return CFR_EINVAL;
-            }
-        }
+        D.group_cap = group_members(group_actions > L.max_actions ? group_actions : L.max_actions, fp64);
+        cfr_status gst = set_update_groups(D, group_sets, err);
+        if (gst != CFR_OK) return gst;
         // internal chance nodes by depth
         D.chance_off.assign((size_t)md + 2, 0);
         D.bigc_off.assign((size_t)md + 2, 0);
@@ -521,6 +559,17 @@ cfr_status build_forest(std::vector<Layout> &Ls, std::vector<DeviceLayout> &Ds, 
             F = std::move(Ds[0]);
             Ds.clear();
             return CFR_OK;
+        }
+        // the games share the kernels' LDS sizing: one group bound and capacity for all
+        F.group_cap = Ds[0].group_cap;
+        F.group_sets = Ds[0].group_sets;
+        for (int s = 0; s < n; s++) {
+            if (Ds[s].group_sets != F.group_sets || Ds[s].group_cap != F.group_cap) {
+                err = "internal: the games of a batch differ in their update group bounds";
+                return CFR_EINVAL;
+            }
+            F.groups_by_bound[0] += Ds[s].groups_by_bound[0];
+            F.groups_by_bound[1] += Ds[s].groups_by_bound[1];
         }
         int MD = 0;
         for (int s = 0; s < n; s++) MD = std::max(MD, (int)Ds[s].depth_off.size() - 2);

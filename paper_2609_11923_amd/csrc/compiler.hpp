@@ -42,6 +42,11 @@ struct Layout {
 // Validate and compile.  Returns CFR_OK or CFR_EINVAL / CFR_ENOMEM with a message in err.
 cfr_status build_layout(const cfr_game_desc *g, Layout &out, std::string &err);
 
+// Sets per update group: at most the 256-thread block (one thread per set).  A game (or batch) uses
+// a bound of 128 or 256 (DeviceLayout::group_sets); the affine update sizes its per-set LDS rows by
+// it, so the smaller bound leaves room for more resident blocks.
+constexpr int GROUP_SETS_MAX = 256;
+
 // The node order the kernels run on.  Depth ranges are those of the canonical layout; inside
 // each depth the nodes are permuted:
 //   BFS     canonical order (children of a node are consecutive ids, so child lists stay
@@ -71,12 +76,15 @@ struct DeviceLayout {
     std::vector<double> tmpl64;          // [N]
     std::vector<int32_t> slot_canon_to_dev; // [A], empty when identical
     std::vector<int32_t> node_dev;       // [N] device id of canonical node k (Layout::keep_maps only)
-    // update groups: runs of consecutive information sets of one depth with at most group_members
-    // members and at most GROUP_SETS sets in total (a set with more members forms a group of its
+    // update groups: runs of consecutive information sets of one depth with at most group_cap
+    // members and at most group_sets sets in total (a set with more members forms a group of its
     // own); group g holds sets [grp_iset_off[g], grp_iset_off[g + 1]); the groups of depth d are
     // [grp_depth_off[d], grp_depth_off[d + 1])
     std::vector<int32_t> grp_iset_off;
     std::vector<int32_t> grp_depth_off;  // [max_depth + 2]
+    int32_t group_cap = 0;               // members per group (group_members)
+    int32_t group_sets = GROUP_SETS_MAX; // sets per group, 128 or 256
+    int64_t groups_by_bound[2] = {0, 0}; // groups this layout forms with at most 128 / 256 sets
     // internal chance nodes by depth: chance_node[chance_off[d] .. chance_off[d + 1]) for fan-out
     // <= BIG_FANOUT (one thread each), bigc_node[bigc_off[d] .. bigc_off[d + 1]) above it (one
     // workgroup each)
@@ -97,19 +105,28 @@ struct DeviceLayout {
 constexpr int GR_FIELDS = 8;  // node lo/hi, group lo/hi, chance lo/hi, big chance lo/hi
 constexpr int BIG_FANOUT = 64;
 
-// sets per update group: 128 keeps the affine update's LDS rows (child offsets, strategy row, set
-// offsets) small enough for six FP32 blocks per compute unit (large game: 4 % faster per
-// iteration than 256 sets, FP64 unchanged).  At most the 256-thread block (one thread per set).
-constexpr int GROUP_SETS = 128;
 // members per update group (members per thread times the 256-thread block): with at most 4 actions
 // per set four per thread for FP32 state and two for FP64 (whose LDS staging is twice as large),
 // else one.  The update kernels' members per thread must match.
 inline int group_members(int max_actions, bool fp64) { return max_actions <= 4 ? (fp64 ? 512 : 1024) : 256; }
 
 // group_actions: the action bound the update groups are sized for (>= L.max_actions); fp64: the state
-// type of the kernels, which sets the group capacity (group_members)
-cfr_status build_device_layout(const Layout &L, int layout_kind, int group_actions, bool fp64, DeviceLayout &out,
-                               std::string &err);
+// type of the kernels, which sets the group capacity (group_members); group_sets: the set bound of the
+// update groups, 128 or 256, or 0 to choose it from this game alone (choose_group_sets)
+cfr_status build_device_layout(const Layout &L, int layout_kind, int group_actions, bool fp64, int group_sets,
+                               DeviceLayout &out, std::string &err);
+
+// (Re)form D's update groups with at most D.group_cap members and `sets` sets each, runs of consecutive
+// information sets of one depth (a set with more members forms a group of its own); also refreshes
+// the group fields of a single game's range table.  Counts for both bounds are in D.groups_by_bound.
+cfr_status set_update_groups(DeviceLayout &D, int32_t sets, std::string &err);
+
+// The set bound for update groups that number g128 with at most 128 sets and g256 with at most 256:
+// 128 unless it splits groups that the member capacity alone would keep whole (more than 30 % more
+// groups).  Measured on the large card game (FP32 state): with about 8 members per set 128 is 4 %
+// faster per iteration (6 resident blocks per compute unit instead of 5), with 6.2 members per set
+// (29 % more groups) 1 % faster, with 4.4 (81 % more groups) 4 % slower and with 3.3 7 % slower.
+inline int32_t choose_group_sets(int64_t g128, int64_t g256) { return g128 * 10 <= g256 * 13 ? 128 : GROUP_SETS_MAX; }
 
 // Affine children: in an explicit layout, when every member h of every information set reaches its
 // child under action a at h + koff[slot a] (one offset per slot, shared by the set's members), fill

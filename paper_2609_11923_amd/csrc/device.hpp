@@ -39,6 +39,7 @@ struct DevGame {
     // affine layouts (explicit, and child a of every member h of a set is h + koff[slot a]): the
     // update pass reads the per-slot offsets and a compact member list instead of kid[] and mem[]
     int affine = 0;
+    int32_t group_sets = 256;     // sets per update group (128 or 256): sizes the affine update's LDS rows
     int32_t *koff = nullptr;      // [A]   child offset of each slot (affine only)
     // member node | MEMBER_P2 bit, per update group in set-major order, or in node order where that
     // touches far fewer cache lines (grp_perm[g] = 1; mpos then gives each member's set-major position

@@ -25,7 +25,7 @@ namespace cfrx {
 
 constexpr int BLOCK = 256;
 // one thread per set of an update group; uint8 member-to-set indices
-static_assert(GROUP_SETS <= BLOCK && GROUP_SETS <= 256, "update group sets");
+static_assert(GROUP_SETS_MAX <= BLOCK && GROUP_SETS_MAX <= 256, "update group sets");
 
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 
@@ -449,20 +449,21 @@ __device__ void group_update(int32_t g, const RuleArgs &ru, const LevelArgs<T> &
     set_update<T, MAXA, EXT>(ru, a, s0, nA, pl, (double)own[a.mem[m0].x & MEMBER_NODE_MASK], r);
 }
 
-// LDS staging of one update group in an affine layout: the set offsets, the set of each member
-// of the chunk and (FP32 state, up to 16 actions) each set's child offsets and strategy row,
-// besides the member values of group_update.  For FP64 the rows would cost a resident block per
-// compute unit (measured slower), so members read them through the cache instead.
-template <typename T, int MAXA, int MPT>
+// LDS staging of one update group in an affine layout: the slot offsets of its sets, the set of each
+// member of the chunk and (FP32 state, up to 16 actions) each set's child offsets and strategy row,
+// besides the member values of group_update.  The rows hold GS sets, the game's group bound (128 or
+// 256): with 128 an FP32 block's LDS fits six per compute unit instead of five.  For FP64 the rows
+// would cost a resident block per compute unit (measured slower), so members read them through the
+// cache instead.
+template <typename T, int MAXA, int MPT, int GS>
 struct GroupLdsA {
     static constexpr bool ROWS = MAXA <= 16 && sizeof(T) == 4;
     static constexpr int RA = ROWS ? MAXA : 1;
     T po[MPT * BLOCK];
     alignas(16) T diff[MPT * BLOCK * MAXA];
-    alignas(16) int32_t ko[GROUP_SETS * RA];
-    alignas(16) T sg[GROUP_SETS * RA];
-    int32_t moff[GROUP_SETS + 1];
-    int32_t slot[GROUP_SETS + 1];
+    alignas(16) int32_t ko[GS * RA];
+    alignas(16) T sg[GS * RA];
+    int32_t slot[GS + 1];
     int32_t wmax[BLOCK / 64];
     uint8_t mset[MPT * BLOCK];
 };
@@ -502,11 +503,11 @@ __device__ __forceinline__ void with_action_bound(int32_t n, F &&f) {
 // instead of one cache line each, and the staging stays set-major, so the reduction, and every
 // result, is unchanged.  The two orders are separate instantiations of the member pass, chosen per
 // group.  Each set thread fetches its own reach through its first member.
-template <typename T, int MAXA, int MPT, bool EXT>
+template <typename T, int MAXA, int MPT, bool EXT, int GS>
 __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelArgs<T> &a,
-                                    GroupLdsA<T, MAXA, MPT> &L) {
+                                    GroupLdsA<T, MAXA, MPT, GS> &L) {
     constexpr int CHUNK = MPT * BLOCK;
-    constexpr bool ROWS = GroupLdsA<T, MAXA, MPT>::ROWS;
+    constexpr bool ROWS = GroupLdsA<T, MAXA, MPT, GS>::ROWS;
     const int tid = threadIdx.x;
     const int32_t i0 = a.grp_iset_off[g], i1 = a.grp_iset_off[g + 1];
     const int32_t nsets = i1 - i0;
@@ -554,7 +555,6 @@ __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelAr
     }
     if ((tid & 63) == 0) L.wmax[tid >> 6] = wa;
     if (has_set) {
-        L.moff[tid] = m0;
         L.slot[tid] = s0;
         if (tid == nsets - 1) L.slot[nsets] = s0 + nA;
         // member -> set map of the first chunk: a group of several sets fits one chunk, and a group
@@ -683,27 +683,31 @@ __device__ void group_update_affine(int32_t g, const RuleArgs &ru, const LevelAr
     }
 }
 
-template <typename T, int MAXA, int MPT, bool EXPLICIT, bool AFF>
-using LevelLds = std::conditional_t<AFF, GroupLdsA<T, MAXA, MPT>, GroupLds<T, MAXA, MPT>>;
+// AF: 0 the child-list update, 1 the affine update with rows for 256 sets per group, 2 the affine
+// update with rows for 128 (FP32 state, at most 4 actions)
+constexpr int aff_sets(int AF) { return AF == 2 ? 128 : GROUP_SETS_MAX; }
 
-template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT, bool AFF>
+template <typename T, int MAXA, int MPT, bool EXPLICIT, int AF>
+using LevelLds = std::conditional_t<AF != 0, GroupLdsA<T, MAXA, MPT, aff_sets(AF)>, GroupLds<T, MAXA, MPT>>;
+
+template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT, int AF>
 __device__ __forceinline__ void update_group(int32_t g, const RuleArgs &ru, const LevelArgs<T> &a,
-                                             LevelLds<T, MAXA, MPT, EXPLICIT, AFF> &L) {
-    if constexpr (AFF) group_update_affine<T, MAXA, MPT, EXT>(g, ru, a, L);
+                                             LevelLds<T, MAXA, MPT, EXPLICIT, AF> &L) {
+    if constexpr (AF != 0) group_update_affine<T, MAXA, MPT, EXT, aff_sets(AF)>(g, ru, a, L);
     else group_update<T, MAXA, MPT, EXPLICIT, EXT>(g, ru, a, L);
 }
 
 // FP64 state with at most 4 actions and the lean rule tail: ask for 6 waves per SIMD (78 registers, no
 // spills; the LDS of 6 workgroups fits) instead of the 5 that 86 registers allow.  The discounted and
-// predictive tails would spill under that bound, and FP32 is held to 5 by its LDS.
+// predictive tails would spill under that bound.  FP32 needs no bound: its registers allow 6 and its
+// LDS too with 128-set groups (5 with 256).
 template <typename T, int MAXA, bool EXT>
 constexpr int level_min_waves() { return (sizeof(T) == 8 && MAXA <= 4 && !EXT) ? 6 : 1; }
-
-template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT, bool AFF>
+template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT, int AF>
 __global__ void __launch_bounds__(BLOCK, (level_min_waves<T, MAXA, EXT>())) k_level(int32_t gbeg, int32_t ngroups, int32_t bbeg, int32_t nbig,
                                                  int32_t cbeg, int32_t nchance, LevelArgs<T> a,
                                                  const int32_t *__restrict__ tcount, int rule, int linear, int upd) {
-    __shared__ LevelLds<T, MAXA, MPT, EXPLICIT, AFF> L;
+    __shared__ LevelLds<T, MAXA, MPT, EXPLICIT, AF> L;
     const int32_t blk = (int32_t)blockIdx.x;
     // with retired games in a batch the ranges index lists of the work that still runs (a retired
     // game's values feed only its own parents)
@@ -720,7 +724,7 @@ __global__ void __launch_bounds__(BLOCK, (level_min_waves<T, MAXA, EXT>())) k_le
     const int32_t x = gbeg + xcd_tile(blk, ngroups);
     const int32_t grp = a.grp_list ? a.grp_list[x] : x;
     const RuleArgs ru = rule_args(rule, linear, upd, tcount[0]);
-    update_group<T, MAXA, MPT, EXPLICIT, EXT, AFF>(grp, ru, a, L);
+    update_group<T, MAXA, MPT, EXPLICIT, EXT, AF>(grp, ru, a, L);
 }
 
 // Per-game barrier among the W blocks of one game.  Thread 0 publishes the block's writes
@@ -767,12 +771,12 @@ __device__ __forceinline__ bool game_barrier(int32_t *ctr, int32_t W, int32_t &e
 // nodes and meet at the game's barrier between levels.  Iteration t0 + k (k = 1..n_iter) uses the
 // same arithmetic, in the same order per set, as the level-synchronous kernels.  Returns false once
 // a barrier reported an error.
-template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT, bool AFF>
+template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT, int AF>
 __device__ bool persistent_game(int32_t gm, int32_t rank, int32_t W, const int32_t *__restrict__ game_range,
                                 const int32_t *__restrict__ game_depth, int32_t MD, int32_t n_iter,
                                 const int2 *__restrict__ up, const LevelArgs<T> &a, int32_t t0, int32_t *barrier,
                                 int32_t *err, int64_t timeout_ticks, int rule, int linear, int alternating,
-                                LevelLds<T, MAXA, MPT, EXPLICIT, AFF> &L) {
+                                LevelLds<T, MAXA, MPT, EXPLICIT, AF> &L) {
     const int32_t *gr = game_range + (size_t)gm * (MD + 1) * GR_FIELDS_DEV;
     const int32_t Ds = game_depth[gm];
     const int tid = threadIdx.x;
@@ -789,7 +793,7 @@ __device__ bool persistent_game(int32_t gm, int32_t rank, int32_t W, const int32
             }
             for (int32_t d = Ds - 1; d >= 0; d--) {
                 const int32_t *r = gr + d * GR_FIELDS_DEV;
-                for (int32_t g = r[2] + rank; g < r[3]; g += W) update_group<T, MAXA, MPT, EXPLICIT, EXT, AFF>(g, ru, a, L);
+                for (int32_t g = r[2] + rank; g < r[3]; g += W) update_group<T, MAXA, MPT, EXPLICIT, EXT, AF>(g, ru, a, L);
                 for (int32_t b = r[6] + rank; b < r[7]; b += W) big_chance_value<T, EXPLICIT>(a.bigc_node[b], a, L.po);
                 for (int32_t j = r[4] + rank * BLOCK + tid; j < r[5]; j += W * BLOCK) chance_value<T, EXPLICIT>(a.chance_node[j], a);
                 if (!game_barrier(barrier + gm, W, epoch, err, timeout_ticks)) return false;
@@ -806,7 +810,7 @@ __device__ bool persistent_game(int32_t gm, int32_t rank, int32_t W, const int32
 // tickets.  A game's barrier therefore waits only for ranks claimed by workgroups already running,
 // and the others are claimed next by whichever workgroup frees up: the launch needs one game's
 // workgroups resident at once, not the whole grid, and any grid size is correct.
-template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT, bool AFF>
+template <typename T, int MAXA, int MPT, bool EXPLICIT, bool EXT, int AF>
 __global__ void __launch_bounds__(BLOCK) k_persistent(const int4 *__restrict__ tickets, const int32_t *__restrict__ q_off,
                                                       int32_t *claim, const int32_t *__restrict__ game_range,
                                                       const int32_t *__restrict__ game_depth, int32_t MD, int32_t n_iter,
@@ -814,7 +818,7 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(const int4 *__restrict__ t
                                                       const int32_t *__restrict__ tcount, int32_t *barrier,
                                                       int32_t *err, int64_t timeout_ticks, int rule, int linear,
                                                       int alternating) {
-    __shared__ LevelLds<T, MAXA, MPT, EXPLICIT, AFF> L;
+    __shared__ LevelLds<T, MAXA, MPT, EXPLICIT, AF> L;
     __shared__ int32_t s_ticket;
     const int32_t t0 = tcount[0];
     // XCC_ID hardware register (bits 3:0): the XCD this workgroup runs on
@@ -829,7 +833,7 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(const int4 *__restrict__ t
             __syncthreads();
             if (t >= qn) break;
             const int4 wt = tickets[qlo + t];
-            if (!persistent_game<T, MAXA, MPT, EXPLICIT, EXT, AFF>(wt.x, wt.y, wt.z, game_range, game_depth, MD, n_iter, up,
+            if (!persistent_game<T, MAXA, MPT, EXPLICIT, EXT, AF>(wt.x, wt.y, wt.z, game_range, game_depth, MD, n_iter, up,
                                                                 a, t0, barrier, err, timeout_ticks, rule, linear,
                                                                 alternating, L))
                 return;
@@ -1148,7 +1152,7 @@ static LevelArgs<T> level_args(const DevGame &g) {
     return a;
 }
 
-template <typename T, int MAXA, int MPT, bool EX, bool XT, bool AF>
+template <typename T, int MAXA, int MPT, bool EX, bool XT, int AF>
 static hipError_t level_t(const DevGame &g, int d, IterFlags f, hipStream_t s) {
     // all work of depth d, or with retired games the listed part of it
     const int32_t gbeg = g.use_lists ? (int32_t)g.grp_off[d] : g.grp_depth_off[d];
@@ -1159,8 +1163,8 @@ static hipError_t level_t(const DevGame &g, int d, IterFlags f, hipStream_t s) {
     const int32_t nb = g.use_lists ? (int32_t)(g.bigc_off_l[d + 1] - g.bigc_off_l[d]) : g.bigc_off[d + 1] - bbeg;
     const unsigned blocks = (unsigned)ng + (unsigned)nb + grid_for(nc);
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_level<T, MAXA, MPT, EX, XT, AF>), dim3(blocks), dim3(BLOCK), 0, s, gbeg, ng, bbeg, nb, cbeg,
-                       nc, level_args<T>(g), g.t, f.rule, f.linear, f.upd);
+    hipLaunchKernelGGL((k_level<T, MAXA, MPT, EX, XT, AF>), dim3(blocks), dim3(BLOCK), 0, s,
+                       gbeg, ng, bbeg, nb, cbeg, nc, level_args<T>(g), g.t, f.rule, f.linear, f.upd);
     return hipGetLastError();
 }
 
@@ -1170,25 +1174,36 @@ inline bool ext_rule(int rule) { return rule == CFR_RULE_DCFR || rule == CFR_RUL
 // Instantiation selector shared by the level and persistent launches: state type, action bound
 // (members per thread must match the group capacity the compiler used, group_members: four for
 // FP32 state with at most 4 actions, two for FP64, else one), child addressing (implicit,
-// explicit, affine) and rule class.
-template <typename T, bool EX, bool XT, bool AF, typename F>
+// explicit, affine; AF, see aff_sets) and rule class.
+template <typename T, bool EX, bool XT, int AF, typename F>
 static auto by_actions(const DevGame &g, F &&f) {
-    if (g.max_actions <= 4) return f.template operator()<T, 4, sizeof(T) == 4 ? 4 : 2, EX, XT, AF>();
-    if (g.max_actions <= 16) return f.template operator()<T, 16, 1, EX, XT, AF>();
-    return f.template operator()<T, 64, 1, EX, XT, AF>();
+    static_assert(AF != 2 || sizeof(T) == 4, "128-set rows are an FP32 instantiation");
+    if constexpr (AF == 2) {
+        return f.template operator()<T, 4, 4, EX, XT, 2>();
+    } else {
+        if (g.max_actions <= 4) return f.template operator()<T, 4, sizeof(T) == 4 ? 4 : 2, EX, XT, AF>();
+        if (g.max_actions <= 16) return f.template operator()<T, 16, 1, EX, XT, AF>();
+        return f.template operator()<T, 64, 1, EX, XT, AF>();
+    }
 }
 
 template <typename T, typename F>
 static auto by_kind(const DevGame &g, int rule, F &&f) {
     const bool x = ext_rule(rule);
-    if (g.affine) return x ? by_actions<T, true, true, true>(g, f) : by_actions<T, true, false, true>(g, f);
-    if (g.explicit_kids) return x ? by_actions<T, true, true, false>(g, f) : by_actions<T, true, false, false>(g, f);
-    return x ? by_actions<T, false, true, false>(g, f) : by_actions<T, false, false, false>(g, f);
+    if (g.affine) {
+        // FP32 state, at most 4 actions, groups of at most 128 sets: the instantiation with 128-set rows
+        if constexpr (sizeof(T) == 4)
+            if (g.max_actions <= 4 && g.group_sets == 128)
+                return x ? by_actions<T, true, true, 2>(g, f) : by_actions<T, true, false, 2>(g, f);
+        return x ? by_actions<T, true, true, 1>(g, f) : by_actions<T, true, false, 1>(g, f);
+    }
+    if (g.explicit_kids) return x ? by_actions<T, true, true, 0>(g, f) : by_actions<T, true, false, 0>(g, f);
+    return x ? by_actions<T, false, true, 0>(g, f) : by_actions<T, false, false, 0>(g, f);
 }
 
 struct LevelLaunch {
     const DevGame &g; int d; IterFlags f; hipStream_t s;
-    template <typename T, int MAXA, int MPT, bool EX, bool XT, bool AF>
+    template <typename T, int MAXA, int MPT, bool EX, bool XT, int AF>
     hipError_t operator()() const { return level_t<T, MAXA, MPT, EX, XT, AF>(g, d, f, s); }
 };
 
@@ -1199,7 +1214,7 @@ hipError_t launch_level(const DevGame &g, int d, IterFlags f, hipStream_t s) {
 
 struct PersistentLaunch {
     const DevGame &g; const PersistentPlan &p; int32_t T_; IterFlags f; int alt; hipStream_t s;
-    template <typename T, int MAXA, int MPT, bool EX, bool XT, bool AF>
+    template <typename T, int MAXA, int MPT, bool EX, bool XT, int AF>
     hipError_t operator()() const {
         hipLaunchKernelGGL((k_persistent<T, MAXA, MPT, EX, XT, AF>), dim3(p.blocks), dim3(BLOCK), 0, s, p.tickets,
                            p.q_off, p.claim, p.game_range, p.game_depth, p.max_depth, T_, g.up, level_args<T>(g), g.t,
@@ -1225,7 +1240,7 @@ hipError_t launch_persistent(const DevGame &g, const PersistentPlan &p, int32_t 
 struct LdsLaunch {
     const DevGame &g; const int32_t *gr; int32_t T_; IterFlags f; int alt; hipStream_t s; size_t bytes;
     bool prepare;   // true: only raise the kernel's dynamic LDS limit to bytes
-    template <typename T, int MAXA, int MPT, bool EX, bool XT, bool AF>
+    template <typename T, int MAXA, int MPT, bool EX, bool XT, int AF>
     hipError_t operator()() const {
         if constexpr (MAXA > 16) {
             return hipErrorInvalidValue;
@@ -1246,8 +1261,8 @@ struct LdsLaunch {
 template <typename T>
 static hipError_t lds_dispatch(const DevGame &g, const LdsLaunch &L) {
     const bool x = ext_rule(L.f.rule);
-    if (g.explicit_kids) return x ? by_actions<T, true, true, false>(g, L) : by_actions<T, true, false, false>(g, L);
-    return x ? by_actions<T, false, true, false>(g, L) : by_actions<T, false, false, false>(g, L);
+    if (g.explicit_kids) return x ? by_actions<T, true, true, 0>(g, L) : by_actions<T, true, false, 0>(g, L);
+    return x ? by_actions<T, false, true, 0>(g, L) : by_actions<T, false, false, 0>(g, L);
 }
 
 hipError_t prepare_lds(const DevGame &g, int rule, size_t *bytes) {
@@ -1267,7 +1282,7 @@ hipError_t launch_lds(const DevGame &g, const int32_t *game_range, int32_t T_, I
 }
 
 struct PersistentFn {
-    template <typename T, int MAXA, int MPT, bool EX, bool XT, bool AF>
+    template <typename T, int MAXA, int MPT, bool EX, bool XT, int AF>
     const void *operator()() const { return reinterpret_cast<const void *>(&k_persistent<T, MAXA, MPT, EX, XT, AF>); }
 };
 

@@ -697,6 +697,8 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     if (o.iters_per_graph < 1 || o.iters_per_graph > 1000) return fail(CFR_EINVAL, "iters_per_graph must be in [1, 1000]");
     if (o.precision != CFR_PRECISION_FP32 && o.precision != CFR_PRECISION_FP64) return fail(CFR_EINVAL, "unknown precision");
     if (o.persistent < CFR_SCHEDULE_LEVEL || o.persistent > CFR_SCHEDULE_LDS) return fail(CFR_EINVAL, "unknown schedule");
+    if (o.group_sets != 0 && o.group_sets != 128 && o.group_sets != GROUP_SETS_MAX)
+        return fail(CFR_EINVAL, "group_sets must be 0, 128 or 256");
     std::string err;
     cfr_status st = CFR_OK;
     // canonical layouts first: the update groups of every game are sized for the batch's action bound
@@ -769,8 +771,8 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
         std::vector<DeviceLayout> Ds((size_t)n);
         parallel_games(n, [&](int s) {
             try {
-                sts[s] = build_device_layout(Ls[s], o.layout, max_actions, o.precision == CFR_PRECISION_FP64, Ds[s],
-                                             errs[s]);
+                sts[s] = build_device_layout(Ls[s], o.layout, max_actions, o.precision == CFR_PRECISION_FP64,
+                                             o.group_sets, Ds[s], errs[s]);
             } catch (...) {
                 sts[s] = CFR_ENOMEM;
                 errs[s] = "host compile failed";
@@ -780,6 +782,20 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
             if (sts[s] != CFR_OK) return fail(sts[s], n > 1 ? "game " + std::to_string(s) + ": " + errs[s] : errs[s]);
             if (o.lifecycle) lifecycle_records(games[s], Ls[s], Ds[s], lc);
             if (n > 1 && !o.keep_layout) Ls[s] = Layout();  // free the canonical arrays early
+        }
+        if (n > 1 && o.group_sets == 0) {
+            // one set bound for the batch, chosen from its group counts as a whole
+            int64_t g128 = 0, g256 = 0;
+            for (int s = 0; s < n; s++) {
+                g128 += Ds[s].groups_by_bound[0];
+                g256 += Ds[s].groups_by_bound[1];
+            }
+            const int32_t gs = choose_group_sets(g128, g256);
+            for (int s = 0; s < n; s++) {
+                if (Ds[s].group_sets == gs) continue;
+                st = set_update_groups(Ds[s], gs, err);
+                if (st != CFR_OK) return fail(st, "game " + std::to_string(s) + ": " + err);
+            }
         }
         if (o.keep_layout) kept.swap(Ls);   // the merge releases the canonical arrays it is given
         st = build_forest(Ls, Ds, DL, err);
@@ -827,6 +843,7 @@ static cfr_status compile_games(const cfr_game_desc *games, int n, const cfr_opt
     h->es = g.fp64 ? 8 : 4;
     std::vector<int32_t> koff;
     g.affine = o.affine && slot_child_offsets(DL, koff) ? 1 : 0;
+    g.group_sets = DL.group_sets;
 
     std::vector<int2> up((size_t)N);
     for (int64_t k = 0; k < N; k++) up[k] = make_int2(DL.up_parent[k], DL.up_code[k]);
@@ -1352,6 +1369,8 @@ cfr_status cfr_counts(cfr_handle *h, cfr_counts_t *c) {
     c->child_addressing = h->g.affine ? 2 : h->g.explicit_kids ? 1 : 0;
     c->node_order_groups = h->node_order_groups;
     c->node_order_members = h->node_order_members;
+    c->group_sets = h->g.group_sets;
+    c->update_groups = h->g.G;
     return CFR_OK;
 }
 

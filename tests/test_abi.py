@@ -124,9 +124,10 @@ def test_invalid_games_rejected(bad, needle):
     assert needle in str(e.value)
 
 
-def test_options_rejected_before_device():
+@pytest.mark.parametrize("field,value", [("iters_per_graph", 0), ("group_sets", 64), ("group_sets", 512)])
+def test_options_rejected_before_device(field, value):
     o = cfr.cfr_default_options()
-    o.iters_per_graph = 0
+    setattr(o, field, value)
     with pytest.raises(cfr.CfrError) as e:
         cfr.cfr_compile(gg.kuhn(), o)
     assert e.value.status == cfr.CFR_EINVAL
@@ -136,6 +137,7 @@ def test_default_options():
     o = cfr.cfr_default_options()
     assert (o.rule, o.averaging, o.order, o.iters_per_graph, o.layout, o.use_graph, o.precision) == \
         (0, 0, 0, 1, cfr.CFR_LAYOUT_PUBLIC, 1, cfr.CFR_PRECISION_FP32)
+    assert o.group_sets == 0   # chosen per game
 
 
 def test_big_set_games_reach_the_staging_paths():

@@ -134,3 +134,43 @@ def test_node_order_groups_equal_the_child_list_path(precision, rule):
         Rx, Sx = x.state()
         assert np.array_equal(Ra, Rx) and np.array_equal(Sa, Sx)
     assert np.array_equal(a.batch_exploitability()[0], b.batch_exploitability()[0])
+
+
+@pytest.mark.parametrize("precision", list(PREC))
+@pytest.mark.parametrize("name", ["leduc13x2", "random_wide", "subgames6", "cards_k2"])
+def test_group_set_bound_leaves_iterates_unchanged(name, precision):
+    """Update groups hold at most 128 or 256 sets: chosen from the game's group counts under both
+    bounds (128 unless it makes more than 30 % more groups), or forced.  The bound decides which
+    workgroup updates a set and how much LDS the affine rows take, never a set's arithmetic, so every
+    bound gives bitwise equal iterates, under the level launches and the persistent launch."""
+    if name == "cards_k2":
+        # two hands per player: about two members per set, so 128-set groups would split most groups
+        h1, h2 = gg.sample_hands(2, 0)
+        game = gg.large(2, seed=0, hands=(h1, h2))
+    else:
+        game = GAMES[name]()
+    r, o = RULES["dcfr-alt"]
+    sol = {}
+    for gs in (0, 128, 256):
+        sol[gs] = cfr.Solver(game, rule=r, order=o, precision=PREC[precision], group_sets=gs)
+    c = {gs: s.counts for gs, s in sol.items()}
+    note(f"[group sets] {name} {precision}: auto {c[0]['group_sets']}, groups {c[128]['update_groups']} "
+         f"(128) / {c[256]['update_groups']} (256)")
+    assert c[128]["group_sets"] == 128 and c[256]["group_sets"] == 256
+    assert c[128]["update_groups"] >= c[256]["update_groups"]
+    auto = 128 if c[128]["update_groups"] * 10 <= c[256]["update_groups"] * 13 else 256
+    assert c[0]["group_sets"] == auto and c[0]["update_groups"] == c[auto]["update_groups"]
+    if name == "cards_k2":
+        assert auto == 256
+    if name == "leduc13x2":
+        assert auto == 128
+    pers = {gs: cfr.Solver(game, rule=r, order=o, precision=PREC[precision], group_sets=gs, persistent=True,
+                           wg_nodes=16384) for gs in (128, 256)}
+    for s in list(sol.values()) + list(pers.values()):
+        s.iterate(9)
+    R0, S0 = sol[0].state()
+    for s in [sol[128], sol[256], pers[128], pers[256]]:
+        R, S = s.state()
+        assert np.array_equal(R, R0) and np.array_equal(S, S0)
+    for s in list(sol.values()) + list(pers.values()):
+        s.close()

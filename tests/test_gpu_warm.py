@@ -62,6 +62,8 @@ def test_trained_network_beats_cold_start_and_untrained_network():
             assert rt["time_ms_all"] <= ev[arm]["time_ms_all"] * 1.02
         sw = ev[arm].get("stopwatch")
         if sw is not None:
-            # run straight through to the last crossing, (almost) every game is at the threshold
+            # run straight through past the last crossing, every game is at the threshold, within a few
+            # per cent of the interpolated crossing
             note(f"[warm test] {arm} stopwatch: {sw}")
-            assert sw["ms_events"] > 0 and sw["reached"] >= sw["games"] - 2
+            assert sw["ms_events"] > 0 and sw["reached"] == sw["games"]
+            assert sw["iterations"] <= sw["interpolated_iterations"] * 1.1 + 6
