@@ -163,6 +163,7 @@ def run_batch(cfr, torch, games, iters, precision, log, tune_iters=20, warm=None
     t0 = time.perf_counter()
     s = cfr.Solver(games, precision=precision, iters_per_graph=BATCH_ITERS_PER_GRAPH)
     t_compile = time.perf_counter() - t0
+    s_counts = s.counts
     tune = s.autotune(tune_iters, stream=stream)
     log(f"[bench] batch autotune: {tune}")
     if warm is not None:
@@ -229,7 +230,8 @@ def run_batch(cfr, torch, games, iters, precision, log, tune_iters=20, warm=None
     seq_ms = float(np.sum(cross[fin] * alone[fin]))
     bat_ms = float(np.max(cross[fin]) * ms_it) if fin.any() else None
     return dict(
-        compile_s=t_compile, schedule=tune, iterations=iters, ms_total=ms, ms_per_iteration=ms_it,
+        compile_s=t_compile, schedule=tune, group_sets=int(s_counts["group_sets"]),
+        update_groups=int(s_counts["update_groups"]), iterations=iters, ms_total=ms, ms_per_iteration=ms_it,
         roofline=roof, design_bytes_per_iteration=design_iter,
         hbm_gbps_design_bytes=physical_rate(design_iter, ms_it),
         frac_design_bytes=physical_rate(design_iter, ms_it) / HBM_PEAK_GBPS, kernels=kernels,
@@ -274,7 +276,8 @@ def run_batch_steps(cfr, torch, args, log):
     ev1.synchronize()
     ms_it = ev0.elapsed_time(ev1) / args.steps
     out = dict(schedule=args.batch_schedule, iters_per_graph=args.iters_per_graph, ms_per_iteration=ms_it, n_games=len(games),
-               edges=int(sum(g.n_edges for g in games)))
+               edges=int(sum(g.n_edges for g in games)), group_sets=int(s.counts["group_sets"]),
+               update_groups=int(s.counts["update_groups"]))
     if args.batch_schedule == "level":
         kernels = s.profile(args.profile_iters, stream=stream)
         design_iter = sum(k["bytes_per_iteration"] for k in kernels)
@@ -769,7 +772,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": desc, "nodes": int(c["nodes"]), "edges": int(c["edges"]), "infosets": int(c["infosets"]),
-            "slots": int(c["slots"]), "blocks": int(c["blocks"]), "rule": "CFR+, simultaneous, linear averaging",
+            "slots": int(c["slots"]), "blocks": int(c["blocks"]), "update_groups": int(c["update_groups"]),
+            "group_sets": int(c["group_sets"]), "rule": "CFR+, simultaneous, linear averaging",
             "state": ("FP64" if args.precision == "fp64" else "FP32") + " reach/values/regrets/strategy, FP64 strategy sums",
             "graph": f"{args.iters_per_graph} iteration(s) per hipGraph",
         },
