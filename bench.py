@@ -197,33 +197,30 @@ def run_batch(cfr, torch, games, iters, precision, log, tune_iters=20, warm=None
     cross = crossing_iterations(checkpoints, expl, 1e-3 * pots.min())
     ms_it = ms / iters
     # the same solve with every game retired at the checkpoint where it reached the threshold
-    # (training segments event-timed, best responses excluded)
-    from paper_2609_11923_amd.warm import retiring_time_to_all
+    # (training segments event-timed, best responses excluded), the last few games moved to handles of
+    # their own on the LDS-resident schedule; and without that move
+    from paper_2609_11923_amd.warm import retiring_solve, retiring_time_to_all
     s.set_schedule(cfr.CFR_SCHEDULE_LEVEL, 0)   # retiring games needs the level-synchronous schedule
-    s.reset()
-    if warm is not None:
-        s.set_regrets(warm, stream=stream)
-    active = np.ones(len(games), np.uint8)
-    seg, used, expl_r, done = [], [], [], 0
-    for c in checkpoints:
-        ev0.record(stream)
-        s.iterate(c - done, stream=stream)
-        ev1.record(stream)
-        ev1.synchronize()
-        seg.append(ev0.elapsed_time(ev1))
-        done = c
-        used.append(c)
-        expl_r.append(s.batch_exploitability(stream=stream)[0])
-        active &= (expl_r[-1] > 1e-3 * pots.min()).astype(np.uint8)
-        if not active.any():
-            break
-        s.set_active(active, stream=stream)
-    cross_r = crossing_iterations(used, expl_r, 1e-3 * pots.min())
-    retiring = {"time_to_1e3pot_all_ms": retiring_time_to_all(cross_r, used, seg, 0.0),
-                "crossings_equal": bool(np.allclose(cross_r, cross, rtol=0, atol=1e-9, equal_nan=True)),
-                "segment_ms": seg, "checkpoints": used,
-                "what": "each game retired (cfr_set_active) at the checkpoint where it reached 1e-3 pot"}
-    log(f"[bench] batch with retiring games: all at 1e-3 pot after {retiring['time_to_1e3pot_all_ms']} ms")
+    retiring = {}
+    for move in (True, False):
+        s.reset()
+        if warm is not None:
+            s.set_regrets(warm, stream=stream)
+        expl_r, used, seg, rec = retiring_solve(s, games, torch, checkpoints, 1e-3 * pots.min(), stream,
+                                                move_tail=move)
+        cross_r = crossing_iterations(used, expl_r, 1e-3 * pots.min())
+        r = {"time_to_1e3pot_all_ms": retiring_time_to_all(cross_r, used, seg, 0.0),
+             "crossings_equal": bool(np.allclose(cross_r, cross, rtol=0, atol=1e-9, equal_nan=True)),
+             "segment_ms": seg, "checkpoints": used}
+        if move:
+            retiring = dict(r, tail_moved=rec,
+                            what="each game retired (cfr_set_active) at the checkpoint where it reached 1e-3 pot; "
+                                 "the last <= 8 games, once all fit, finish on LDS-resident handles of their own "
+                                 "(host time of that move included)")
+        else:
+            retiring["without_tail_move"] = r
+    log(f"[bench] batch with retiring games: all at 1e-3 pot after {retiring['time_to_1e3pot_all_ms']} ms "
+        f"({retiring['without_tail_move']['time_to_1e3pot_all_ms']} ms without moving the tail)")
     s.close()
     alone = alone_ms_per_iteration(games, torch, log=log)
     fin = np.isfinite(cross)
@@ -340,7 +337,8 @@ def run_rules(cfr, torch, games, log, max_iters=4000):
     games, compiled per rule, level-synchronous graph, FP32 state).  Iterations count full
     iterations (an alternating one runs both players' halves); wall time uses each rule's own
     measured time per iteration."""
-    from paper_2609_11923_amd.warm import crossing_iterations, geometric_checkpoints, retiring_time_to_all
+    from paper_2609_11923_amd.warm import (crossing_iterations, geometric_checkpoints, retiring_solve,
+                                           retiring_time_to_all)
     pots = np.array([g.pot for g in games])
     cps = geometric_checkpoints(max_iters)
     out = {}
@@ -363,23 +361,10 @@ def run_rules(cfr, torch, games, log, max_iters=4000):
             done = c
             expl.append(s.batch_exploitability(stream=stream)[0])
         cross = crossing_iterations(cps, expl, 1e-3 * pots.min())
-        # the same solve with each game retired at the checkpoint where it reached the target
+        # the same solve with each game retired at the checkpoint where it reached the target (the last
+        # few games finish on LDS-resident handles of their own)
         s.reset()
-        active = np.ones(len(games), np.uint8)
-        seg, used, expl_r, done = [], [], [], 0
-        for c in cps:
-            ev0.record(stream)
-            s.iterate(c - done, stream=stream)
-            ev1.record(stream)
-            ev1.synchronize()
-            seg.append(ev0.elapsed_time(ev1))
-            done = c
-            used.append(c)
-            expl_r.append(s.batch_exploitability(stream=stream)[0])
-            active &= (expl_r[-1] > 1e-3 * pots.min()).astype(np.uint8)
-            if not active.any():
-                break
-            s.set_active(active, stream=stream)
+        expl_r, used, seg, _ = retiring_solve(s, games, torch, cps, 1e-3 * pots.min(), stream)
         s.close()
         cross_r = crossing_iterations(used, expl_r, 1e-3 * pots.min())
         ms_it = ms / cps[-1]

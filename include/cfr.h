@@ -328,6 +328,16 @@ cfr_status cfr_set_state(cfr_handle *h, const double *regrets, const double *str
  * under another rule.  Synchronises `stream`. */
 cfr_status cfr_get_prediction(cfr_handle *h, double *prediction, int64_t len, void *stream);
 
+/* The state of one game of a batch: its cumulative regrets (eq. regret), strategy sums (eq. rm) and,
+ * under PCFR+, prediction, as host FP64 arrays of len = the game's slot count, in that game's canonical
+ * slot order (slots [slot_base[game], slot_base[game + 1]) of cfr_batch_size).  Only that game's slots
+ * are copied.  Any pointer may be NULL; CFR_EINVAL for a game out of range, another len, or a
+ * prediction under another rule.  Synchronises `stream`.  With cfr_set_state (and the batch's
+ * iteration count) on a handle compiled from that game alone the game continues bitwise as it would in
+ * the batch: a batch's last small games can move to the LDS-resident schedule. */
+cfr_status cfr_get_game_state(cfr_handle *h, int32_t game, double *regrets, double *strategy_sum,
+                              double *prediction, int64_t len, void *stream);
+
 /* In-place re-solve (paper Appendix H, set_payoffs and set_root_chance; Table 'tab:lifecycle'):
  * rewrite the chance-folded template v_tmpl(z) = pi_c(z) u(z) of one game of the handle (game in
  * [0, n_games)) without reallocating anything, so a captured graph stays valid.  The solver state

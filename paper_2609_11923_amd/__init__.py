@@ -103,7 +103,7 @@ EXPORTS = ["cfr_default_options", "cfr_layout_host", "cfr_layout_free", "cfr_com
            "cfr_mlp_forward", "cfr_mlp_backward", "cfr_mlp_adam", "cfr_mlp_train_step", "cfr_mlp_destroy",
            "cfr_num_infosets", "cfr_features", "cfr_regret_unit", "cfr_warm_start", "cfr_set_payoffs",
            "cfr_set_root_chance", "cfr_set_root_ranges", "cfr_set_state", "cfr_get_prediction", "cfr_get_layout",
-           "cfr_persistent_plan_host", "cfr_mlp_forward_noalloc"]
+           "cfr_persistent_plan_host", "cfr_mlp_forward_noalloc", "cfr_get_game_state"]
 
 
 def load():
@@ -169,6 +169,7 @@ def load():
         "cfr_set_root_ranges": (S, [_P, ctypes.c_int32, _P, ctypes.c_int64, _P, ctypes.c_int64, _P]),
         "cfr_set_state": (S, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int64, _P]),
         "cfr_get_prediction": (S, [_P, _P, ctypes.c_int64, _P]),
+        "cfr_get_game_state": (S, [_P, ctypes.c_int32, _P, _P, _P, ctypes.c_int64, _P]),
         "cfr_get_layout": (S, [_P, ctypes.c_int32, ctypes.POINTER(cfr_layout)]),
         "cfr_persistent_plan_host": (S, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P,
                                          ctypes.POINTER(ctypes.c_int32)]),
@@ -377,6 +378,15 @@ def cfr_get_prediction(h, length: int, stream=None):
     return p[:length]
 
 
+def cfr_get_game_state(h, game: int, length: int, prediction: bool = False, stream=None):
+    """(regrets, strategy sums[, prediction]) of one game of a batch, FP64, that game's canonical order."""
+    r, s = np.zeros(max(length, 1), np.float64), np.zeros(max(length, 1), np.float64)
+    p = np.zeros(max(length, 1), np.float64) if prediction else None
+    _check(load().cfr_get_game_state(h, int(game), _ptr(r), _ptr(s), _ptr(p) if p is not None else None,
+                                     int(length), stream))
+    return (r[:length], s[:length]) + ((p[:length],) if p is not None else ())
+
+
 def cfr_counts(h) -> dict:
     c = cfr_counts_t()
     _check(load().cfr_counts(h, ctypes.byref(c)))
@@ -572,6 +582,11 @@ class Solver:
 
     def prediction(self, stream=None) -> np.ndarray:
         return cfr_get_prediction(self.h, self.A, self._stream(stream))
+
+    def game_state(self, game: int, prediction: bool = False, stream=None):
+        """(regrets, strategy sums[, prediction]) of game `game` of the batch, in its canonical order."""
+        n = int(self.slot_base[game + 1] - self.slot_base[game]) if 0 <= game < self.n_games else 0
+        return cfr_get_game_state(self.h, game, n, prediction, self._stream(stream))
 
     def layout(self, game: int = 0) -> dict:
         return cfr_get_layout(self.h, game)

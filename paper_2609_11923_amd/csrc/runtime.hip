@@ -1279,6 +1279,53 @@ cfr_status cfr_set_state(cfr_handle *h, const double *regrets, const double *str
     return CFR_OK;
 }
 
+cfr_status cfr_get_game_state(cfr_handle *h, int32_t game, double *regrets, double *strategy_sum,
+                              double *prediction, int64_t len, void *stream) {
+    if (!h) return fail(CFR_EINVAL, "handle is NULL");
+    if (game < 0 || game >= h->n_games) return fail(CFR_EINVAL, "game out of range");
+    const int64_t b = h->game_slot_base[(size_t)game], e = h->game_slot_base[(size_t)game + 1];
+    if (len != e - b) return fail(CFR_EINVAL, "len must equal the game's slot count " + std::to_string(e - b));
+    if (prediction && !h->g.pred) return fail(CFR_EINVAL, "only PCFR+ keeps a prediction");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    hipStream_t s = (hipStream_t)stream;
+    if (len == 0) return CFR_OK;
+    // the game's device slots, sorted, copied run by run (a game's sets are contiguous per depth)
+    const bool ident = h->slot_map.empty();
+    std::vector<int32_t> dev((size_t)len);
+    for (int64_t q = b; q < e; q++) dev[(size_t)(q - b)] = ident ? (int32_t)q : h->slot_map[(size_t)q];
+    std::vector<int32_t> sorted(dev);
+    std::sort(sorted.begin(), sorted.end());
+    const size_t es = h->es;
+    std::vector<unsigned char> rb(regrets ? (size_t)len * es : 0), pb(prediction ? (size_t)len * es : 0);
+    std::vector<double> sb(strategy_sum ? (size_t)len : 0);
+    for (size_t k0 = 0; k0 < sorted.size();) {
+        size_t k1 = k0 + 1;
+        while (k1 < sorted.size() && sorted[k1] == sorted[k1 - 1] + 1) k1++;
+        const size_t x0 = (size_t)sorted[k0], n = k1 - k0;
+        if (regrets)
+            HIP_TRY(hipMemcpyAsync(rb.data() + k0 * es, (const unsigned char *)h->g.R + x0 * es, n * es,
+                                   hipMemcpyDeviceToHost, s));
+        if (strategy_sum)
+            HIP_TRY(hipMemcpyAsync(sb.data() + k0, h->g.sbar + x0, n * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (prediction)
+            HIP_TRY(hipMemcpyAsync(pb.data() + k0 * es, (const unsigned char *)h->g.pred + x0 * es, n * es,
+                                   hipMemcpyDeviceToHost, s));
+        k0 = k1;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    auto val = [&](const std::vector<unsigned char> &v, size_t k) {
+        if (h->g.fp64) { double x; std::memcpy(&x, v.data() + k * 8, 8); return x; }
+        float x; std::memcpy(&x, v.data() + k * 4, 4); return (double)x;
+    };
+    for (int64_t q = 0; q < len; q++) {
+        const size_t k = (size_t)(std::lower_bound(sorted.begin(), sorted.end(), dev[(size_t)q]) - sorted.begin());
+        if (regrets) regrets[q] = val(rb, k);
+        if (strategy_sum) strategy_sum[q] = sb[k];
+        if (prediction) prediction[q] = val(pb, k);
+    }
+    return CFR_OK;
+}
+
 cfr_status cfr_get_prediction(cfr_handle *h, double *prediction, int64_t len, void *stream) {
     if (!h || (!prediction && len > 0)) return fail(CFR_EINVAL, "NULL argument");
     if (len != h->g.A) return fail(CFR_EINVAL, "len must equal the slot count " + std::to_string(h->g.A));

@@ -16,7 +16,7 @@ import time
 
 import numpy as np
 
-from . import (CFR_FEATURES, CFR_PRECISION_FP32, Mlp, Solver)
+from . import (CFR_FEATURES, CFR_PRECISION_FP32, CFR_RULE_PCFR_PLUS, CFR_SCHEDULE_LDS, CfrError, Mlp, Solver)
 
 THRESHOLD = 1e-3  # of the pot
 
@@ -59,6 +59,7 @@ class Rows:
 
     def __init__(self, games, torch, device="cuda:0"):
         import gamegen as gg
+        self.games = games
         bs, hs, ss, na = [], [], [], []
         self.game_off = [0]
         for g in games:
@@ -184,14 +185,16 @@ def loss_of(mlp: Mlp, X, T, W, N, torch):
 
 
 def solve_curves(s: Solver, rows: Rows, torch, checkpoints, mlp=None, scale=0.0, probe=0, add=False, log=None,
-                 retire_thr=None, seg_ms=None):
+                 retire_thr=None, seg_ms=None, tail_out=None):
     """One batch solve from scratch on solver s, with exploitability checkpoints at absolute
     iteration counts (a warm start's probe iterations count).  Timed on the stream with events:
     the warm start (feature pass, probe iterations, network, injection) and the iterations; the
     best-response evaluations at the checkpoints are not timed.  With retire_thr, a game whose
     exploitability is at most retire_thr at a checkpoint is retired (cfr_set_active) and no longer
-    iterated; seg_ms (a list) then receives the measured milliseconds of every segment between
-    checkpoints.  Returns (expl [checkpoints, games], warm_ms, iter_ms, the checkpoints used)."""
+    iterated, and the last few games finish on handles of their own (retiring_solve); seg_ms (a list)
+    then receives the measured milliseconds of every segment between checkpoints and tail_out (a dict)
+    the record of that move.  Returns (expl [checkpoints, games], warm_ms, iter_ms, the checkpoints
+    used)."""
     stream = torch.cuda.Stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     warm_ms = 0.0
@@ -206,8 +209,15 @@ def solve_curves(s: Solver, rows: Rows, torch, checkpoints, mlp=None, scale=0.0,
         warm_ms = ev[0].elapsed_time(ev[1])
     done = probe if mlp is not None else 0
     checkpoints = [int(c) for c in checkpoints if c > done]
+    if retire_thr is not None:
+        expl, used, seg, rec = retiring_solve(s, rows.games, torch, checkpoints, retire_thr, stream, start=done,
+                                              log=log)
+        if seg_ms is not None:
+            seg_ms.extend(seg)
+        if tail_out is not None and rec is not None:
+            tail_out.update(rec)
+        return expl, warm_ms, float(sum(seg)), used
     expl, iter_ms = [], 0.0
-    active = np.ones(s.n_games, np.uint8)
     for c in checkpoints:
         ev[0].record(stream)
         s.iterate(int(c) - done, stream=stream)
@@ -219,17 +229,137 @@ def solve_curves(s: Solver, rows: Rows, torch, checkpoints, mlp=None, scale=0.0,
             seg_ms.append(ms)
         done = int(c)
         expl.append(s.batch_exploitability(stream=stream)[0])
-        if retire_thr is not None:
-            active &= (expl[-1] > retire_thr).astype(np.uint8)
+        if log is not None:
+            log(f"[warm]   iteration {done}: median expl {np.median(expl[-1]):.3e}")
+    return np.array(expl), warm_ms, iter_ms, checkpoints[:len(expl)]
+
+
+# a retiring solve moves its last games to handles of their own once at most this many are left and
+# every one fits the LDS-resident schedule; they run on up to TAIL_STREAMS streams at once
+TAIL_GAMES = 8
+TAIL_STREAMS = 4
+
+
+class TinyTail:
+    """The last games of a retiring batch solve, each on a handle of its own on the LDS-resident
+    schedule (one workgroup runs whole iterations with the game's state in LDS: no launch per depth,
+    where the batch's level launches would run near-empty).  Each game's state (cfr_get_game_state) and
+    the batch's iteration count go into its handle (cfr_set_state), so it continues bitwise as it would
+    in the batch.  The handles iterate concurrently on a few streams forked from and joined back into
+    the caller's stream.  Raises CfrError (after adding the game to `too_big`) when a game does not fit."""
+
+    def __init__(self, s: Solver, games, idx, torch, stream, too_big: set):
+        o = s.options
+        pred = o.rule == CFR_RULE_PCFR_PLUS
+        t = s.iterations
+        self.h = {}
+        self.torch = torch
+        for i in (int(x) for x in idx):
+            try:
+                h = Solver(games[i], rule=o.rule, averaging=o.averaging, order=o.order, precision=o.precision,
+                           persistent=CFR_SCHEDULE_LDS, device=o.device)
+            except CfrError:
+                too_big.add(i)
+                self.close()
+                raise
+            self.h[i] = h
+            st = s.game_state(i, prediction=pred, stream=stream)
+            h.set_state(st[0], st[1], t, st[2] if pred else None)
+        self.streams = [torch.cuda.Stream() for _ in range(min(TAIL_STREAMS, len(self.h)))]
+        # largest game first onto the least loaded stream: games that share a stream run one after the other
+        load = [0] * len(self.streams)
+        self.lane = {}
+        for i in sorted(self.h, key=lambda j: -games[j].n_nodes):
+            q = int(np.argmin(load))
+            self.lane[i] = q
+            load[q] += games[i].n_nodes
+
+    def iterate(self, n: int, stream):
+        torch = self.torch
+        fork = torch.cuda.Event()
+        fork.record(stream)
+        for st in self.streams:
+            st.wait_event(fork)
+        for i, h in self.h.items():
+            h.iterate(n, stream=self.streams[self.lane[i]])
+        for st in self.streams:
+            join = torch.cuda.Event()
+            join.record(st)
+            stream.wait_event(join)
+
+    def exploitability(self, stream) -> dict:
+        return {i: h.exploitability(stream=stream)[0] for i, h in self.h.items()}
+
+    def retire(self, i: int):
+        self.h.pop(i).close()
+
+    def close(self):
+        for h in self.h.values():
+            h.close()
+        self.h = {}
+
+
+def retiring_solve(s: Solver, games, torch, checkpoints, thr, stream, start=0, move_tail=True, log=None):
+    """Iterate the batch on solver s from iteration `start` to each checkpoint, retiring (cfr_set_active)
+    every game whose exploitability is at most thr at a checkpoint.  With move_tail, once at most
+    TAIL_GAMES games are left and all fit the LDS-resident schedule they move to TinyTail handles and
+    finish there (same iterates, no launch per depth).  Each segment between checkpoints is event-timed
+    on `stream`; the host time of the move (compiles, state copies) is added to the segment after it.
+    Best responses are not timed.  The batch's games are all active again on return, its state is that
+    of the batch (a moved game's later iterations are not in it).  Returns (expl [checkpoints, games],
+    checkpoints used, segment ms, record of the move or None)."""
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    active = np.ones(s.n_games, np.uint8)
+    expl, used, seg = [], [], []
+    tail, rec, too_big, pending_ms = None, None, set(), 0.0
+    done = int(start)
+    try:
+        for c in (int(x) for x in checkpoints if x > start):
+            ev[0].record(stream)
+            if tail is not None:
+                tail.iterate(c - done, stream)
+            else:
+                s.iterate(c - done, stream=stream)
+            ev[1].record(stream)
+            ev[1].synchronize()
+            seg.append(ev[0].elapsed_time(ev[1]) + pending_ms)
+            pending_ms = 0.0
+            done = c
+            used.append(c)
+            if tail is None:
+                e = np.array(s.batch_exploitability(stream=stream)[0])
+            else:
+                e = expl[-1].copy()
+                for i, x in tail.exploitability(stream).items():
+                    e[i] = x
+            expl.append(e)
+            active &= (e > thr).astype(np.uint8)
+            if log is not None:
+                log(f"[warm]   iteration {done}: median expl {np.median(e):.3e}, {int(active.sum())} games iterating"
+                    + (" (moved to LDS-resident handles)" if tail is not None else ""))
             if not active.any():
                 break
+            if tail is not None:
+                for i in [i for i in tail.h if not active[i]]:
+                    tail.retire(i)
+                continue
+            idx = np.flatnonzero(active)
+            if move_tail and len(idx) <= TAIL_GAMES and not too_big.intersection(int(i) for i in idx):
+                t0 = time.perf_counter()
+                try:
+                    tail = TinyTail(s, games, idx, torch, stream, too_big)
+                except CfrError:
+                    tail = None
+                if tail is not None:
+                    pending_ms = (time.perf_counter() - t0) * 1e3
+                    rec = {"at_iteration": done, "games": [int(i) for i in idx], "move_host_ms": pending_ms}
+                    continue
             s.set_active(active, stream=stream)
-        if log is not None:
-            log(f"[warm]   iteration {done}: median expl {np.median(expl[-1]):.3e}"
-                + (f", {int(active.sum())} games iterating" if retire_thr is not None else ""))
-    if retire_thr is not None:
+    finally:
+        if tail is not None:
+            tail.close()
         s.set_active(np.ones(s.n_games, np.uint8), stream=stream)
-    return np.array(expl), warm_ms, iter_ms, checkpoints[:len(expl)]
+    return np.array(expl), used, seg, rec
 
 
 def retiring_time_to_all(cross, checkpoints, seg_ms, warm_ms, skip=0):
@@ -388,14 +518,15 @@ def evaluate(games, torch, mlp, scale, t_max, control=None, probe=0, schedule=LE
         if retire and not schedule.get("persistent"):
             # the same solve, each game retired at the checkpoint where it reached the threshold
             s.reset()
-            seg = []
+            seg, tail = [], {}
             e2, warm2, _, used2 = solve_curves(s, rows, torch, cps, mlp=net, scale=c, probe=probe, add=add,
-                                              log=log, retire_thr=thr, seg_ms=seg)
+                                              log=log, retire_thr=thr, seg_ms=seg, tail_out=tail)
             cross2 = crossing_iterations(used2, e2, thr)
             out[name]["retiring"] = {
                 "time_ms_all": retiring_time_to_all(cross2, used2, seg, warm2, skip),
                 "crossings_equal": bool(np.allclose(cross2, cross, rtol=0, atol=1e-9, equal_nan=True)),
-                "segment_ms": [float(x) for x in seg], "checkpoints": [int(x) for x in used2]}
+                "segment_ms": [float(x) for x in seg], "checkpoints": [int(x) for x in used2],
+                "tail_moved": tail or None}
         out[name]["expl_final_median"] = float(np.median(e[-1]))
         out[name]["_cross"] = cross
         if np.isfinite(cross).all():

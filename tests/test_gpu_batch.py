@@ -220,3 +220,84 @@ def test_single_game_cannot_be_retired():
     with pytest.raises(cfr.CfrError) as e:
         s.set_active([1, 1])
     assert e.value.status == cfr.CFR_EINVAL
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("rule", ["cfr+", "pcfr+", "dcfr-alt"])
+def test_a_game_moves_out_of_the_batch_bitwise(precision, rule):
+    """cfr_get_game_state returns each game's slice of the batch state (and the PCFR+ prediction)
+    bitwise.  Set on a handle of that game alone (cfr_set_state, the batch's iteration count), on the
+    LDS-resident schedule, the game then iterates bitwise as it does in the batch."""
+    rules = {"cfr+": (cfr.CFR_RULE_CFR_PLUS, cfr.CFR_ORDER_SIMULTANEOUS),
+             "pcfr+": (cfr.CFR_RULE_PCFR_PLUS, cfr.CFR_ORDER_SIMULTANEOUS),
+             "dcfr-alt": (cfr.CFR_RULE_DCFR, cfr.CFR_ORDER_ALTERNATING)}
+    r, o = rules[rule]
+    p = cfr.CFR_PRECISION_FP32 if precision == "fp32" else cfr.CFR_PRECISION_FP64
+    pred = rule == "pcfr+"
+    games = mixed_batch()
+    a = cfr.Solver(games, rule=r, order=o, precision=p)
+    a.iterate(14)
+    R, S = a.state()
+    P = a.prediction() if pred else None
+    base = a.slot_base
+    for k in range(len(games)):
+        sl = slice(base[k], base[k + 1])
+        st = a.game_state(k, prediction=pred)
+        assert np.array_equal(st[0], R[sl]) and np.array_equal(st[1], S[sl]), k
+        if pred:
+            assert np.array_equal(st[2], P[sl]), k
+    movers = [0, 2, 3]   # Kuhn, a small random game, the worked example: all fit the LDS schedule
+    hs = {}
+    for k in movers:
+        st = a.game_state(k, prediction=pred)
+        h = cfr.Solver(games[k], rule=r, order=o, precision=p, persistent=cfr.CFR_SCHEDULE_LDS)
+        h.set_state(st[0], st[1], a.iterations, st[2] if pred else None)
+        hs[k] = h
+    a.iterate(9)
+    R2, S2 = a.state()
+    for k, h in hs.items():
+        h.iterate(9)
+        Rh, Sh = h.state()
+        sl = slice(base[k], base[k + 1])
+        assert h.iterations == a.iterations
+        assert np.array_equal(Rh, R2[sl]) and np.array_equal(Sh, S2[sl]), k
+        h.close()
+    with pytest.raises(cfr.CfrError) as e:
+        a.game_state(len(games))
+    assert e.value.status == cfr.CFR_EINVAL
+    with pytest.raises(cfr.CfrError) as e:
+        cfr.cfr_get_game_state(a.h, 0, int(base[1] - base[0]) + 1)
+    assert e.value.status == cfr.CFR_EINVAL
+    if not pred:
+        with pytest.raises(cfr.CfrError) as e:
+            a.game_state(0, prediction=True)
+        assert e.value.status == cfr.CFR_EINVAL
+
+
+def test_retiring_solve_moves_its_tail_with_the_same_crossings():
+    """A retiring solve (games retired at the checkpoint where they reach the target) moves its last
+    <= 8 games to LDS-resident handles of their own: the exploitability at every checkpoint, hence every
+    crossing iteration, equals that of the same solve kept in the batch; afterwards the batch has every
+    game active again."""
+    import torch
+    from paper_2609_11923_amd.warm import crossing_iterations, geometric_checkpoints, retiring_solve
+    games = subgames(14, seed=3)
+    pots = np.array([g.pot for g in games])
+    thr = 1e-3 * pots.min()
+    cps = geometric_checkpoints(3000)
+    s = cfr.Solver(games)
+    stream = torch.cuda.Stream()
+    e1, u1, seg1, rec = retiring_solve(s, games, torch, cps, thr, stream)
+    s.reset()
+    e2, u2, seg2, rec2 = retiring_solve(s, games, torch, cps, thr, stream, move_tail=False)
+    note(f"[tail] moved {rec}; segments {[round(x, 2) for x in seg1]} vs {[round(x, 2) for x in seg2]}")
+    assert rec is not None and rec2 is None and 0 < len(rec["games"]) <= 8
+    assert u1 == u2
+    np.testing.assert_allclose(e1, e2, rtol=1e-12, atol=0)
+    c1, c2 = crossing_iterations(u1, e1, thr), crossing_iterations(u2, e2, thr)
+    assert np.isfinite(c1).all() and np.allclose(c1, c2, rtol=0, atol=1e-9)
+    s.reset()
+    s.iterate(4)
+    t = cfr.Solver(games)
+    t.iterate(4)
+    assert np.array_equal(s.state()[0], t.state()[0])
