@@ -246,7 +246,8 @@ class TinyTail:
     where the batch's level launches would run near-empty).  Each game's state (cfr_get_game_state) and
     the batch's iteration count go into its handle (cfr_set_state), so it continues bitwise as it would
     in the batch.  The handles iterate concurrently on a few streams forked from and joined back into
-    the caller's stream.  Raises CfrError (after adding the game to `too_big`) when a game does not fit."""
+    the caller's stream.  Raises CfrError (after adding the game to `too_big` and closing the handles made)
+    when a game does not fit or cannot take the state."""
 
     def __init__(self, s: Solver, games, idx, torch, stream, too_big: set):
         o = s.options
@@ -258,13 +259,13 @@ class TinyTail:
             try:
                 h = Solver(games[i], rule=o.rule, averaging=o.averaging, order=o.order, precision=o.precision,
                            persistent=CFR_SCHEDULE_LDS, device=o.device)
+                self.h[i] = h
+                st = s.game_state(i, prediction=pred, stream=stream)
+                h.set_state(st[0], st[1], t, st[2] if pred else None)
             except CfrError:
-                too_big.add(i)
+                too_big.add(i)   # not movable: the solve keeps it in the batch
                 self.close()
                 raise
-            self.h[i] = h
-            st = s.game_state(i, prediction=pred, stream=stream)
-            h.set_state(st[0], st[1], t, st[2] if pred else None)
         self.streams = [torch.cuda.Stream() for _ in range(min(TAIL_STREAMS, len(self.h)))]
         # largest game first onto the least loaded stream: games that share a stream run one after the other
         load = [0] * len(self.streams)
