@@ -170,3 +170,22 @@ def test_no_move_while_more_than_eight_games_remain(fakes):
     # all ten cross together between 800 and 1600: never at most eight left before the end
     assert rec is None and FakeHandle.made == []
     assert np.isfinite(warm.crossing_iterations(used, e, 1.0)).all()
+
+
+def test_stopwatch_reruns_until_every_game_is_there(monkeypatch):
+    """stopwatch_to_all starts at the interpolated last crossing and reruns the whole timed solve with
+    2 % more iterations (plus one) until every game is below the threshold, at most `runs` times."""
+    calls = []
+
+    def fake_stopwatch(s, rows, torch, n, **kw):
+        calls.append(n)
+        return {"iterations": n, "ms_events": n * 0.25, "reached": 256 if n >= 2300 else 255, "games": 256}
+
+    monkeypatch.setattr(warm, "stopwatch", fake_stopwatch)
+    sw = warm.stopwatch_to_all(None, None, None, 2235)
+    assert calls == [2235, 2281, 2328]        # ceil(n * 1.02) + 1 each time
+    assert sw["reached"] == 256 and sw["iterations"] == 2328
+    assert sw["interpolated_iterations"] == 2235 and sw["runs"] == 3
+    calls.clear()
+    sw = warm.stopwatch_to_all(None, None, None, 100, runs=2)
+    assert calls == [100, 103] and sw["runs"] == 2 and sw["reached"] == 255   # capped: reported as is
