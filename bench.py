@@ -222,7 +222,8 @@ def run_batch(cfr, torch, games, iters, precision, log, tune_iters=20, warm=None
     log(f"[bench] batch with retiring games: all at 1e-3 pot after {retiring['time_to_1e3pot_all_ms']} ms "
         f"({retiring['without_tail_move']['time_to_1e3pot_all_ms']} ms without moving the tail)")
     s.close()
-    alone = alone_ms_per_iteration(games, torch, log=log)
+    lds_won = []
+    alone = alone_ms_per_iteration(games, torch, log=log, lds=lds_won)
     fin = np.isfinite(cross)
     seq_ms = float(np.sum(cross[fin] * alone[fin]))
     bat_ms = float(np.max(cross[fin]) * ms_it) if fin.any() else None
@@ -242,9 +243,11 @@ def run_batch(cfr, torch, games, iters, precision, log, tune_iters=20, warm=None
         checkpoint_iterations=int(max_iters),
         retiring=retiring,
         one_at_a_time={
-            "what": "each game alone on its own handle (hipGraph replay, ten iterations per graph), run to its own "
-                    "crossing iteration; "
-                    "the batch reproduces each game's iterates bitwise, so crossing iterations are shared",
+            "what": "each game alone on its own handle (hipGraph replay, ten iterations per graph, or the "
+                    "LDS-resident schedule where the game fits and it is faster), run to its own crossing "
+                    "iteration; the batch reproduces each game's iterates bitwise, so crossing iterations are "
+                    "shared",
+            "games_on_lds_schedule": len(lds_won),
             "ms_per_iteration_median": float(np.median(alone)), "ms_per_iteration_sum": float(np.sum(alone)),
             "games_counted": int(fin.sum()),
             "time_to_1e3pot_all_ms": seq_ms,

@@ -539,22 +539,44 @@ def evaluate(games, torch, mlp, scale, t_max, control=None, probe=0, schedule=LE
     return out
 
 
-def alone_ms_per_iteration(games, torch, iters=50, log=print):
-    """Milliseconds per iteration of each game solved on its own (one handle, hipGraph replay of ten
-    iterations per graph, as the batch runs): the per-game cost of plain one-at-a-time solving.  A
-    batch reproduces each game's iterates bitwise, so its crossing iterations carry over unchanged."""
+# above this many nodes a game cannot fit one workgroup's 160 KB of LDS (three 4-byte values per node
+# alone): not worth a compile to find out
+LDS_NODES_MAX = 16384
+
+
+def alone_ms_per_iteration(games, torch, iters=50, log=print, lds=None):
+    """Milliseconds per iteration of each game solved on its own: hipGraph replay of ten iterations per
+    graph (as the batch runs), or, where the game fits one workgroup's LDS and it is faster, the
+    LDS-resident schedule -- the per-game cost of plain one-at-a-time solving with the better of the
+    two.  A batch reproduces each game's iterates bitwise, so its crossing iterations carry over
+    unchanged.  lds (a list), if given, receives the indices of the games the LDS schedule won."""
     out = np.zeros(len(games))
     stream = torch.cuda.Stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    for k, g in enumerate(games):
-        s = Solver(g, iters_per_graph=10)
-        s.iterate(13, stream=stream)      # direct iteration + capture of both graphs
+
+    def timed(s):
+        s.iterate(13, stream=stream)      # direct iteration + capture of the graphs
         ev[0].record(stream)
         s.iterate(iters, stream=stream)
         ev[1].record(stream)
         ev[1].synchronize()
-        out[k] = ev[0].elapsed_time(ev[1]) / iters
         s.close()
+        return ev[0].elapsed_time(ev[1]) / iters
+
+    for k, g in enumerate(games):
+        out[k] = timed(Solver(g, iters_per_graph=10))
+        s = None
+        if g.n_nodes <= LDS_NODES_MAX:
+            try:
+                s = Solver(g, persistent=CFR_SCHEDULE_LDS)
+            except CfrError:
+                s = None                  # does not fit one workgroup's LDS
+        if s is not None:
+            ms = timed(s)
+            if ms < out[k]:
+                out[k] = ms
+                if lds is not None:
+                    lds.append(k)
         if (k + 1) % 64 == 0:
             log(f"[warm] timed {k + 1}/{len(games)} games alone")
     return out
